@@ -1,0 +1,226 @@
+#!/usr/bin/env python
+"""Benchmark of the fast-hyperspectral-reconstruction hot path on one GPU.
+
+One step = the whole path over one synthetic scan already resident in HBM:
+  -log normalisation of the counts (eq. 2)
+  -> NMF subspace decomposition until the relative objective (f - f*)/f*
+     reaches 1e-4 (eq. 4): multiplicative-update bulk, then exact ANLS
+     polish on the float32 p
+  -> 20 CGLS iterations (20 A / A^T pairs) on all K channels (eq. 5, h = 0)
+  -> expansion of one slice to every bin (eq. 6).
+
+value = view*pixel*bins of the scan / step time.  The NMF-only rate, the
+projector voxel-rays/s and each kernel's share are reported beside it.
+f* (the stationary objective of the instance) is computed before timing by
+running the same float32 path to stationarity.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mid|tiny]
+                [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+REL_OBJ = 1e-4
+CGLS_ITERS = 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mid", choices=["mid", "tiny"])
+    ap.add_argument("--bulk-iters", type=int, default=200)
+    ap.add_argument("--polish-rounds", type=int, default=60)
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "the hot path's multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2410_22500_amd import hsn
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    sc = synth.config_scan(args.workload)
+    K = sc.n_mat
+    n_p, n_k = sc.n_p, sc.n_bins
+    vpb = n_p * n_k
+    log(f"workload {args.workload}: N_v={sc.n_views} N_r={sc.n_rows} N_c={sc.n_cols} N_k={n_k} K={K} "
+        f"({vpb:.3e} vpb), generated in {time.time() - t0:.1f}s")
+    y = torch.from_numpy(sc.y.view(np.int16)).to(dev)
+    yo = torch.from_numpy(sc.yo.view(np.int16)).to(dev)
+    V0n, D0n = synth.random_factors(n_p, n_k, K, 1000 + sc.n_views)
+    V0 = torch.from_numpy(V0n.astype(np.float32)).to(dev)
+    D0 = torch.from_numpy(D0n.astype(np.float32)).to(dev)
+    V = torch.empty_like(V0)
+    D = torch.empty_like(D0)
+
+    # f*: the same float32 path run to stationarity (not timed).
+    p, _, _, _ = hsn.hsn_normalize(y, yo)
+    V.copy_(V0)
+    D.copy_(D0)
+    st = hsn.hsn_subspace_nmf(p, None, n_k, V, D, max_iter=args.bulk_iters, check_every=args.bulk_iters,
+                              polish_rounds=400)
+    hist = np.array(st["history"])
+    f_star = float(hist.min())
+    log(f"f* = {f_star:.9e} after {st['iters']} MU + {st['polish_done']} ANLS; "
+        f"last rel change {abs(hist[-2] - hist[-1]) / hist[-1]:.2e}")
+
+    def step(record=None):
+        p, _, _, _ = hsn.hsn_normalize(y, yo)
+        V.copy_(V0)
+        D.copy_(D0)
+        s = hsn.hsn_subspace_nmf(p, None, n_k, V, D, max_iter=args.bulk_iters, check_every=args.check_every,
+                                 polish_rounds=args.polish_rounds, rel_obj_tol=REL_OBJ, f_ref=f_star)
+        sino = V.view(sc.n_views, sc.n_rows, sc.n_cols, K)
+        x = hsn.hsn_cgls(sino, CGLS_ITERS)
+        hsn.hsn_rehydrate(x.view(-1, K), D, vox=(0, sc.n_cols * sc.n_cols), bins=(0, n_k))
+        if record is not None:
+            record.append(s)
+        return s
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    hsn.hsn_profile_enable(True)
+    for kk in (hsn.KERN_NMF_PASS, hsn.KERN_PROJECT, hsn.KERN_BACKPROJECT, hsn.KERN_NORMALIZE):
+        hsn.hsn_profile_read(kk, reset=True)
+    recs = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step(recs)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    hsn.hsn_profile_enable(False)
+    ms_step = ms_total / args.steps
+    nmf_ms = float(np.mean([r["ms"] for r in recs]))
+    reached = all(r["rel_obj"] <= REL_OBJ for r in recs)
+    pass_ms, pass_n = hsn.hsn_profile_read(hsn.KERN_NMF_PASS)
+    prj_ms, prj_n = hsn.hsn_profile_read(hsn.KERN_PROJECT)
+    bpj_ms, bpj_n = hsn.hsn_profile_read(hsn.KERN_BACKPROJECT)
+    nrm_ms, nrm_n = hsn.hsn_profile_read(hsn.KERN_NORMALIZE)
+
+    # Algorithmic bytes of the pass launches: one read of float32 p per pass,
+    # plus the K-vectors per row (MU: V read + V write; NV: N_V write; ND: V read).
+    it, pol = recs[-1]["iters"], recs[-1]["polish_done"]
+    pbytes = 4.0 * n_p * n_k
+    vbytes = 4.0 * n_p * K
+    alg_bytes = sum(r["iters"] * (pbytes + 2 * vbytes) + r["polish_done"] * 2 * (pbytes + vbytes) for r in recs)
+    launches = sum(r["iters"] + 2 * r["polish_done"] for r in recs)
+    if launches != pass_n:
+        log(f"warning: {pass_n} timed pass launches, {launches} expected")
+    avg_pass_ms = pass_ms / pass_n
+    achieved = alg_bytes / launches / (avg_pass_ms * 1e-3) / 1e9
+    vox_rays = sc.n_views * sc.n_rows * sc.n_cols * sc.n_cols * K
+
+    out = {
+        "metric": "view*pixel*bins decomposed/s at rel obj 1e-4 (whole hot-path step)",
+        "value": vpb / (ms_step * 1e-3),
+        "unit": "vpb/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded phantom, Bragg-edge-like spectra, Poisson counts)",
+        "config": {"workload": f"{args.workload}: {sc.n_rows} slices x {sc.n_cols}^2, {sc.n_views} views, "
+                               f"{n_k} bins, K={K}, flux {sc.flux:g}",
+                   "nmf": f"fp32 MU bulk (check every {args.check_every}) + ANLS polish to rel obj {REL_OBJ:g}",
+                   "recon": f"CGLS {CGLS_ITERS} pairs", "parallelism": "single GPU"},
+        "nmf": {"vpb_per_s": vpb / (nmf_ms * 1e-3), "ms": nmf_ms, "mu_iters": it, "polish_rounds": pol,
+                "rel_obj": recs[-1]["rel_obj"], "reached": reached, "f_star": f_star},
+        "projector": {"voxel_rays_per_s_A": vox_rays / (prj_ms / prj_n * 1e-3),
+                      "voxel_rays_per_s_AT": vox_rays / (bpj_ms / bpj_n * 1e-3),
+                      "ms_A": prj_ms / prj_n, "ms_AT": bpj_ms / bpj_n},
+        "normalize_ms": nrm_ms / max(nrm_n, 1),
+        "roofline": {"kernel": "nmf pass (float32, pass_f32_kernel)", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": avg_pass_ms, "launches": pass_n,
+                     "alg_bytes_per_launch": alg_bytes / launches},
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, V0n, D0n, it, pol)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(sc, V0n, D0n, mu_iters, polish_rounds):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload:
+    the rows of detector row 0 (1 of N_r slices).  Normalisation, CGLS and
+    the expansion run in full on the sample; the NMF runs up to 20 MU
+    iterations and 3 ANLS rounds, and its time is extrapolated per
+    iteration to the counts the GPU needed.  Rate in vpb/s of the sample."""
+    from threadpoolctl import threadpool_info
+    from oracle import cgls as ocgls
+    from oracle import expand as oexp
+    from oracle import nmf as onmf
+    from oracle.normalize import normalize as onorm
+
+    K = sc.n_mat
+    ysub = sc.y[:, :1]
+    yosub = sc.yo[:1]
+    rows = np.arange(sc.n_p).reshape(sc.n_views, sc.n_rows, sc.n_cols)[:, 0].ravel()
+    t0 = time.perf_counter()
+    p, _, _ = onorm(ysub, yosub)
+    t_norm = time.perf_counter() - t0
+    V, D = V0n[rows].astype(np.float32).astype(np.float64), D0n.astype(np.float32).astype(np.float64)
+    n_mu = min(mu_iters, 20)
+    t0 = time.perf_counter()
+    V, D, _, _ = onmf.mu_run(p, V, D, n_mu)
+    t_mu = (time.perf_counter() - t0) / max(n_mu, 1)
+    n_an = min(polish_rounds, 3)
+    t0 = time.perf_counter()
+    for _ in range(n_an):
+        V, D, _, _ = onmf.anls_round(p, V, D)
+    t_an = (time.perf_counter() - t0) / max(n_an, 1)
+    t0 = time.perf_counter()
+    sino = V.reshape(sc.n_views, 1, sc.n_cols, K)
+    x = ocgls.cgls(sino, sc.n_cols, CGLS_ITERS)
+    oexp.rehydrate(x.reshape(-1, K), D)
+    t_rec = time.perf_counter() - t0
+    t = t_norm + t_mu * mu_iters + t_an * polish_rounds + t_rec
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    vpb = p.shape[0] * p.shape[1]
+    return {"value": vpb / t, "unit": "vpb/s", "cores": threads, "kind": "oracle",
+            "sample": f"detector row 0 of {sc.n_rows} ({p.shape[0]} x {p.shape[1]}): normalise, {mu_iters} MU "
+                      f"(timed {n_mu}, per-iteration extrapolated), {polish_rounds} ANLS (timed {n_an}), "
+                      f"CGLS {CGLS_ITERS}, expansion; {t:.1f}s total on {os.cpu_count()} host cpus "
+                      f"({platform.processor() or platform.machine()})",
+            "seconds": t}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,218 @@
+/*
+ * hsn.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of fast hyperspectral neutron tomography (arXiv 2410.22500):
+ *
+ *   -log normalisation (eq. 2, Appendix A)
+ *   -> NMF subspace decomposition p ~ V D^T (eq. 4)
+ *   -> K-channel parallel-beam projector A and adjoint A^T (eq. 3, eq. 5)
+ *   -> per-channel least-squares reconstruction (eq. 5 with h = 0)
+ *   -> subspace expansion x^h = x^s D^T (eq. 6)
+ *
+ * Conventions for every entry point
+ *   - Array arguments are DEVICE pointers owned by the caller unless the
+ *     comment says "host".  The library never frees, retains or reallocates
+ *     a caller buffer past the call.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *     is ordered on it; outputs are valid once the stream has synchronised.
+ *     Calls that return host-side statistics synchronise the stream.
+ *   - Every call validates its arguments on the host before any launch and
+ *     returns an hsn_status; on error nothing has been written and
+ *     hsn_last_error(ctx) holds a message.  The library never aborts or prints.
+ *   - Matrices are row-major with the last index fastest.  Pitches are in
+ *     elements.  p rows are ordered (view, detector row, detector column), the
+ *     paper's index order v, r, c; p columns are wavelength bins k.
+ *   - Concurrent calls on one context must be serialised by the caller.
+ */
+#ifndef HSN_H
+#define HSN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HSN_OK = 0,
+  HSN_ERR_INVALID_ARG = 1,  /* NULL where required, bad enum, bad pitch/alignment */
+  HSN_ERR_SHAPE = 2,        /* sizes out of the supported range */
+  HSN_ERR_UNSUPPORTED = 3,  /* valid request this build does not implement */
+  HSN_ERR_OOM = 4,          /* workspace allocation failed */
+  HSN_ERR_DEVICE = 5,       /* a HIP runtime call failed */
+  HSN_ERR_NUMERIC = 6       /* NaN/Inf detected in a result */
+} hsn_status;
+
+typedef struct hsn_ctx hsn_ctx;
+
+/* Create a context bound to HIP device `device`; it owns the workspace. */
+hsn_status hsn_create(hsn_ctx **ctx, int device);
+void hsn_destroy(hsn_ctx *ctx);
+/* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
+const char *hsn_last_error(const hsn_ctx *ctx);
+/* Library ABI version (major*100 + minor). */
+int hsn_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Normalisation: eq. (2) p = -ln(y / y^o), with the Appendix A offset.  */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int64_t n_views; /* N_v */
+  int64_t n_rows;  /* N_r detector rows (= slices) */
+  int64_t n_cols;  /* N_c detector columns */
+  int64_t n_bins;  /* N_k wavelength bins */
+} hsn_dims;
+
+enum { HSN_U16 = 0, HSN_F32 = 1 };
+
+/*
+ * p[(v*N_r + r)*N_c + c][k] = -ln( max(y, f) / max(y^o, f) ) - b[v][k], then
+ * clipped at 0 when clip_nonneg != 0.  (eq. 2; offset b from Appendix A.)
+ *
+ *   y       [N_v][N_r][N_c][N_k] counts, dtype y_dtype (HSN_U16 or HSN_F32)
+ *   y_open  [N_r][N_c][N_k] open-beam counts, dtype y_open_dtype
+ *   bg_mask optional [N_r][N_c] uint8, non-zero on background pixels B.  When
+ *           given, b[v][k] = mean over B of the unclipped -ln(y/y^o)
+ *           (Appendix A); when NULL, b = 0.  B must be non-empty.
+ *   count_floor  f >= 0 applied to both counts (the log of 0 is undefined).
+ *   p       [N_p][ldp] float32 output, ldp >= N_k.  May be NULL if p_bf16 is given.
+ *   p_bf16  optional [N_p][ldb] bfloat16 (bits, round-to-nearest-even) copy
+ *           for the BF16 NMF path; ldb >= N_k, ldb % 32 == 0; columns
+ *           N_k..ldb-1 are written with zeros.  16-byte aligned.
+ *   offset_b optional [N_v][N_k] float32 output of b (requires bg_mask).
+ *   sumsq   optional device double: sum of p^2 over the float32 p values.
+ */
+hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *dims,
+                         const void *y, int y_dtype, const void *y_open, int y_open_dtype,
+                         const uint8_t *bg_mask, float count_floor, int clip_nonneg,
+                         float *p, int64_t ldp, uint16_t *p_bf16, int64_t ldb,
+                         float *offset_b, double *sumsq, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Subspace extraction: eq. (4) (V, D) = argmin_{V,D>=0} ||p - V D^T||^2 */
+/* ------------------------------------------------------------------ */
+
+enum { HSN_ALGO_MU = 0,    /* Lee-Seung multiplicative updates, V then D */
+       HSN_ALGO_ANLS = 1 };/* exact row-wise NNLS for V, then for D       */
+enum { HSN_PREC_FP32 = 0,  /* float32 p, float32 arithmetic               */
+       HSN_PREC_BF16 = 1 };/* bfloat16 p on MFMA, float32 accumulation;
+                              the polish rounds then use the float32 p    */
+enum { HSN_INIT_USER = 0 };/* V and D hold the start on entry             */
+
+typedef struct {
+  int k;              /* K = N_s, 1..8 */
+  int algo;           /* HSN_ALGO_* for the bulk iterations */
+  int precision;      /* HSN_PREC_* for the bulk iterations */
+  int init;           /* HSN_INIT_* */
+  int max_iter;       /* bulk iterations, >= 0 */
+  int check_every;    /* objective evaluated every this many iterations (>= 1) */
+  int polish_rounds;  /* ANLS rounds on the float32 p after the bulk (>= 0) */
+  double rel_obj_tol; /* stop when (f - f_ref)/f_ref <= tol; ignored if f_ref <= 0 */
+  double f_ref;       /* reference objective f* (> 0 enables the stop test) */
+} hsn_nmf_opts;
+
+typedef struct {
+  int iters;          /* bulk iterations done */
+  int polish_done;    /* polish rounds done */
+  double objective;   /* last evaluated objective (see below) */
+  double rel_obj;     /* (objective - f_ref)/f_ref, or NaN without f_ref */
+  double *history;    /* host, optional: evaluated objectives in order */
+  int history_cap;    /* capacity of history */
+  int history_len;    /* entries written */
+  float ms;           /* device time of the call */
+} hsn_nmf_stats;
+
+/*
+ * Runs the bulk iterations, then the polish rounds, on V [N_p][K] and
+ * D [N_k][K] (float32, in/out, both strictly positive on entry for MU).
+ * Each evaluated objective is f(V_{t+1}, D_t) = ||p - V_{t+1} D_t^T||_F^2 over
+ * the float32 p (BF16 bulk iterations: over the bfloat16 p), computed from
+ * the residual inside the pass, i.e. the objective after the V half-step; for
+ * both algorithms it is non-increasing in exact arithmetic.
+ *   p      [N_p][ldp] float32, ldp % 4 == 0, 16-byte aligned (needed for FP32
+ *          bulk and for any polish round; may be NULL otherwise)
+ *   p_bf16 [N_p][ldb] bfloat16 with zero padding, ldb % 32 == 0 (BF16 bulk)
+ * Returns HSN_OK also when max_iter is reached before the tolerance.  stats
+ * (host) may be NULL; filling it synchronises the stream.
+ */
+hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp,
+                            const uint16_t *p_bf16, int64_t ldb,
+                            int64_t n_p, int64_t n_k, float *V, float *D,
+                            const hsn_nmf_opts *opts, hsn_nmf_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Projector A (eq. 3 / eq. 5), K channels, all slices in one launch.   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Parallel beam, detector row r sees image slice r (N_c x N_c pixels, pitch
+ * 1, centres at index - (N_c-1)/2).  Matrix entries (Joseph interpolation
+ * written as a footprint, identical in A and A^T):
+ *   a_{(v,c),(j,i)} = (1/w_v) max(0, 1 - |d|/w_v),
+ *   d = s_c - (x_i cos t_v + y_j sin t_v),  w_v = max(|cos t_v|, |sin t_v|).
+ * Volume x [N_r][N_c][N_c][K] (slice, image row j, column i, channel);
+ * sinogram s [N_v][N_r][N_c][K] (the V layout of hsn_subspace_nmf).
+ */
+typedef struct {
+  int64_t n_views;       /* N_v */
+  int64_t n_slices;      /* N_r */
+  int64_t n_cols;        /* N_c (= image size) */
+  int k;                 /* channels, 1..8 */
+  const double *angles;  /* host [N_v] radians, or NULL for t_v = v*pi/N_v */
+} hsn_geom;
+
+/* s = alpha * A x + beta * s  (beta == 0: s is not read). */
+hsn_status hsn_project(hsn_ctx *ctx, const hsn_geom *g, const float *x, float *s,
+                       float alpha, float beta, void *stream);
+/* x = alpha * A^T s + beta * x  (beta == 0: x is not read). */
+hsn_status hsn_backproject(hsn_ctx *ctx, const hsn_geom *g, const float *s, float *x,
+                           float alpha, float beta, void *stream);
+
+/*
+ * eq. (5) with h = 0: x_j = argmin ||V_j - A x_j||^2 for every channel j by
+ * CGLS from x = 0, n_iter iterations (one A and one A^T each), all channels
+ * at once with per-channel scalars kept on the device (no host sync).
+ *   sino [N_v][N_r][N_c][K] in, x [N_r][N_c][N_c][K] out,
+ *   resid optional [n_iter+1][K] float64: ||b - A x_i|| per channel.
+ */
+hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sino, float *x,
+                    int n_iter, double *resid, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Subspace expansion: eq. (6) x^h = x^s D^T over a voxel x bin range.   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * xh[v - vox_begin][b - bin_begin] = sum_j xs[v][j] * D[b][j]
+ * for v in [vox_begin, vox_end), b in [bin_begin, bin_end).
+ *   xs [n_x][K], D [n_k][K] float32; xh [vox_end-vox_begin][ldh] float32,
+ *   ldh >= bin_end - bin_begin.
+ */
+hsn_status hsn_rehydrate(hsn_ctx *ctx, const float *xs, const float *D, int64_t n_x, int64_t n_k,
+                         int k, int64_t vox_begin, int64_t vox_end, int64_t bin_begin,
+                         int64_t bin_end, float *xh, int64_t ldh, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Kernel timing for roofline reports.                                   */
+/* ------------------------------------------------------------------ */
+
+enum {
+  HSN_KERN_NMF_PASS = 0,    /* every streaming pass over p inside hsn_subspace_nmf */
+  HSN_KERN_PROJECT = 1,     /* the forward projector kernel */
+  HSN_KERN_BACKPROJECT = 2, /* the adjoint projector kernel */
+  HSN_KERN_NORMALIZE = 3,   /* the normalisation stream kernel */
+  HSN_KERN_COUNT = 4
+};
+
+/* When on != 0, every launch of the kernels above is bracketed by a pair of
+ * hipEvents recorded on the launch's stream (small overhead per launch). */
+hsn_status hsn_profile_enable(hsn_ctx *ctx, int on);
+/* Synchronises the recorded events of `kernel` and returns the summed device
+ * time (ms) and launch count since the last reset; reset != 0 clears them. */
+hsn_status hsn_profile_read(hsn_ctx *ctx, int kernel, double *total_ms, int64_t *launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSN_H */

@@ -1,0 +1,157 @@
+// Pieces shared by the NMF passes (float32 VALU pass, bfloat16 MFMA pass)
+// and the per-iteration reduction / factor-update kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace hsn {
+
+// Row-local update rules of one NMF half-step.
+enum PassMode {
+  kModeMU = 0,  // fused: N_V = P D, Lee-Seung V update, then N_D += P^T V_new
+  kModeNV = 1,  // N_V = P D only (written out; the rows are solved separately)
+  kModeND = 2,  // N_D += P^T V_new only (V_new given)
+};
+
+// Workspace of one decomposition (all device pointers).
+struct NmfWork {
+  double *gd;        // [8*8]   G_D = D^T D
+  double *gv;        // [8*8]   G_V = V^T V
+  double *chol;      // [256][36] packed Cholesky factors of principal submatrices
+  float *part_nd;    // [n_wg][n_k][K] per-workgroup partials of P^T V
+  double *part_gv;   // [n_wg][K*K]
+  double *part_obj;  // [n_wg]
+  double *red_nd;    // [kSplit][n_k][K]
+  double *red_gv;    // [kSplit][K*K]
+  double *red_obj;   // [kSplit]
+  float *nv;         // [n_p][K] N_V for the row-wise NNLS
+  double *hist;      // [hist_cap] objective history (device)
+  int n_wg;
+};
+
+constexpr int kSplit = 16;       // first-level groups of the partial reduction
+constexpr int kCholStride = 36;  // packed lower triangle of an 8x8 matrix
+
+__host__ __device__ constexpr int tri(int a) { return a * (a + 1) / 2; }
+
+// Cholesky factor (packed lower, compact index order) of G[S,S], S = bits of
+// mask.  Returns false if G[S,S] is not numerically positive definite.
+__device__ inline bool chol_sub(const double *G, int K, unsigned mask, double *L) {
+  int idx[8];
+  int s = 0;
+  for (int i = 0; i < K; ++i)
+    if (mask & (1u << i)) idx[s++] = i;
+  for (int a = 0; a < s; ++a) {
+    for (int b = 0; b <= a; ++b) {
+      double v = G[idx[a] * K + idx[b]];
+      for (int c = 0; c < b; ++c) v -= L[tri(a) + c] * L[tri(b) + c];
+      if (a == b) {
+        if (!(v > 0.0)) return false;
+        L[tri(a) + a] = sqrt(v);
+      } else {
+        L[tri(a) + b] = v / L[tri(b) + b];
+      }
+    }
+  }
+  return true;
+}
+
+// Non-negative least squares in Gram form, min_{x >= 0} 1/2 x'Gx - h'x, by
+// the Lawson-Hanson active-set method with the float64 Cholesky factor of
+// the passive set taken from `chol` (indexed by the passive-set bit mask; a
+// factor whose first entry is NaN marks a singular set, which is never
+// entered).  Same steps, tie breaks and tolerances as the float64 oracle.
+template <int K>
+__device__ inline void nnls_gram_row(const double *__restrict__ G, const double *__restrict__ chol, const double (&h)[K],
+                                     double (&x)[K]) {
+  constexpr double tol = 1e-12;
+  double scale = 1e-300;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    x[i] = 0.0;
+    scale = fmax(scale, fabs(h[i]));
+  }
+  unsigned passive = 0;
+  double w[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) w[i] = h[i];
+  for (int outer = 0; outer < 4 * K + 8; ++outer) {
+    int jmax = -1;
+    double wmax = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+      if (!(passive & (1u << i)) && w[i] > wmax) {
+        wmax = w[i];
+        jmax = i;
+      }
+    if (jmax < 0 || !(wmax > tol * scale)) break;
+    if (isnan(chol[(passive | (1u << jmax)) * kCholStride])) break;  // singular: stop at the current point
+    passive |= 1u << jmax;
+    for (int inner = 0; inner <= K; ++inner) {
+      // z = solve on the passive set
+      double z[K];
+      {
+        const double *L = chol + size_t(passive) * kCholStride;
+        double t[K];
+        int a = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          z[i] = 0.0;
+          if (passive & (1u << i)) {
+            double v = h[i];
+            for (int c = 0; c < a; ++c) v -= L[tri(a) + c] * t[c];
+            t[a] = v / L[tri(a) + a];
+            ++a;
+          }
+        }
+        const int s = a;
+        // back substitution L^T y = t, written into z at the compact positions
+        double y[K];
+        for (int aa = s - 1; aa >= 0; --aa) {
+          double v = t[aa];
+          for (int c = aa + 1; c < s; ++c) v -= L[tri(c) + aa] * y[c];
+          y[aa] = v / L[tri(aa) + aa];
+        }
+        a = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+          if (passive & (1u << i)) z[i] = y[a++];
+      }
+      bool feasible = true;
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+        if ((passive & (1u << i)) && !(z[i] > 0.0)) feasible = false;
+      if (feasible) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) x[i] = z[i];
+        break;
+      }
+      double alpha = INFINITY;
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+        if ((passive & (1u << i)) && !(z[i] > 0.0)) alpha = fmin(alpha, x[i] / (x[i] - z[i]));
+      double xmax = 0.0;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        x[i] = x[i] + alpha * (z[i] - x[i]);
+        xmax = fmax(xmax, fabs(x[i]));
+      }
+      const double thr = tol * fmax(1.0, xmax);
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+        if ((passive & (1u << i)) && !(x[i] > thr)) passive &= ~(1u << i);
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+        if (!(passive & (1u << i))) x[i] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      double v = h[i];
+#pragma unroll
+      for (int c = 0; c < K; ++c) v -= G[i * K + c] * x[c];
+      w[i] = v;
+    }
+  }
+}
+
+}  // namespace hsn

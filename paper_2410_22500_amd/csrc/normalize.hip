@@ -1,0 +1,216 @@
+// -log normalisation (eq. 2) with the Appendix A offset correction.
+//
+//   p = -ln( max(y, f) / max(y^o, f) ) - b[v][k],  optionally clipped at 0,
+//   b[v][k] = mean over background pixels B of the unclipped -ln(y / y^o).
+//
+// One HBM stream: counts in, float32 p and (optionally) its bfloat16 copy
+// out, with per-block float64 partials of sum(p^2) reduced in a fixed order.
+#include "common.hpp"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSumBlocks = 2048;  // fixed grid so that the sum(p^2) order is fixed
+
+template <typename T>
+__device__ __forceinline__ float ld_count(const T *a, int64_t i);
+template <>
+__device__ __forceinline__ float ld_count<uint16_t>(const uint16_t *a, int64_t i) { return float(a[i]); }
+template <>
+__device__ __forceinline__ float ld_count<float>(const float *a, int64_t i) { return a[i]; }
+
+// -ln(y/y^o) evaluated as ln(y^o/y): one rounding in the ratio, one in the log.
+__device__ __forceinline__ float neglog(float y, float yo, float floor_) {
+  return logf(fmaxf(yo, floor_) / fmaxf(y, floor_));
+}
+
+// b[v][k] = (1/|B|) sum_{(r,c) in B} -ln(y/y^o).  Grid (k-blocks, N_v);
+// each thread walks the pixels in order, so the sum is deterministic.
+template <typename TY, typename TO>
+__global__ __launch_bounds__(kThreads) void offset_kernel(const TY *__restrict__ y, const TO *__restrict__ yo,
+                                                          const uint8_t *__restrict__ mask, int64_t n_pix,
+                                                          int64_t nk, float floor_, float *__restrict__ b) {
+  const int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  const int64_t v = blockIdx.y;
+  if (k >= nk) return;
+  double acc = 0.0;
+  int64_t cnt = 0;
+  for (int64_t px = 0; px < n_pix; ++px) {
+    if (!mask[px]) continue;
+    const float pv = neglog(ld_count(y, (v * n_pix + px) * nk + k), ld_count(yo, px * nk + k), floor_);
+    acc += double(pv);
+    ++cnt;
+  }
+  b[v * nk + k] = float(acc / double(cnt > 0 ? cnt : 1));
+}
+
+// Main stream.  Thread item = 8 consecutive bins of one row.
+template <typename TY, typename TO, bool VEC>
+__global__ __launch_bounds__(kThreads) void normalize_kernel(
+    const TY *__restrict__ y, const TO *__restrict__ yo, int64_t n_rows, int64_t n_pix, int64_t nk,
+    const float *__restrict__ b, float floor_, int clip, float *__restrict__ p, int64_t ldp,
+    uint16_t *__restrict__ pb, int64_t ldb, double *__restrict__ partial) {
+  const int64_t width = (pb && ldb > nk) ? ldb : nk;
+  const int64_t chunks = (width + 7) / 8;
+  const int64_t items = n_rows * chunks;
+  double ss = 0.0;
+  for (int64_t it = int64_t(blockIdx.x) * kThreads + threadIdx.x; it < items;
+       it += int64_t(gridDim.x) * kThreads) {
+    const int64_t row = it / chunks;
+    const int64_t k0 = (it - row * chunks) * 8;
+    const int64_t v = row / n_pix;
+    const int64_t px = row - v * n_pix;
+    float out[8];
+    if (VEC && k0 + 8 <= nk) {
+      // 16-byte loads of 8 uint16 counts (alignment checked on the host).
+      const uint4 yv = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(y) + row * nk + k0);
+      const uint4 ov = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(yo) + px * nk + k0);
+      const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w};
+      const uint32_t ow[4] = {ov.x, ov.y, ov.z, ov.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float yc = float((yw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+        const float oc = float((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+        out[e] = neglog(yc, oc, floor_);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t k = k0 + e;
+        out[e] = (k < nk) ? neglog(ld_count(y, row * nk + k), ld_count(yo, px * nk + k), floor_) : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = k0 + e;
+      float pv = out[e];
+      if (k < nk) {
+        if (b) pv -= b[v * nk + k];
+        if (clip) pv = fmaxf(pv, 0.0f);
+      } else {
+        pv = 0.0f;
+      }
+      out[e] = pv;
+      ss += double(pv) * double(pv);
+    }
+    if (p) {
+      if (VEC && k0 + 8 <= nk) {
+        float4 *dst = reinterpret_cast<float4 *>(p + row * ldp + k0);
+        dst[0] = make_float4(out[0], out[1], out[2], out[3]);
+        dst[1] = make_float4(out[4], out[5], out[6], out[7]);
+      } else {
+        for (int e = 0; e < 8; ++e)
+          if (k0 + e < nk) p[row * ldp + k0 + e] = out[e];
+      }
+    }
+    if (pb) {
+      if (VEC && k0 + 8 <= ldb) {
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          w[e] = uint32_t(hsn::f32_to_bf16_bits(out[2 * e])) | (uint32_t(hsn::f32_to_bf16_bits(out[2 * e + 1])) << 16);
+        *reinterpret_cast<uint4 *>(pb + row * ldb + k0) = make_uint4(w[0], w[1], w[2], w[3]);
+      } else {
+        for (int e = 0; e < 8; ++e)
+          if (k0 + e < ldb) pb[row * ldb + k0 + e] = hsn::f32_to_bf16_bits(out[e]);
+      }
+    }
+  }
+  // Block reduction of the float64 sum of squares, fixed order.
+  __shared__ double red[kThreads / 64];
+  ss = hsn::wave_sum_all(ss);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+    partial[blockIdx.x] = t;
+  }
+}
+
+__global__ void sum_partials_kernel(const double *__restrict__ partial, int n, double *__restrict__ out) {
+  __shared__ double red[kThreads / 64];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) t += partial[i];
+  t = hsn::wave_sum_all(t);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    *out = s;
+  }
+}
+
+template <typename TY, typename TO>
+hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo, const uint8_t *mask,
+                      float floor_, int clip, float *p, int64_t ldp, uint16_t *pb, int64_t ldb,
+                      float *offset_b, double *sumsq, hipStream_t st) {
+  const int64_t n_pix = d->n_rows * d->n_cols;
+  const int64_t n_rows = d->n_views * n_pix;
+  const int64_t nk = d->n_bins;
+  size_t need = hsn::Carver::need({sizeof(double) * kSumBlocks, mask ? sizeof(float) * d->n_views * nk : 0});
+  hsn_status s = hsn::ensure_ws(ctx, need);
+  if (s != HSN_OK) return s;
+  hsn::Carver cv(ctx->ws);
+  double *partial = cv.take<double>(kSumBlocks);
+  float *b = nullptr;
+  if (mask) {
+    b = offset_b ? offset_b : cv.take<float>(d->n_views * nk);
+    dim3 grid(unsigned((nk + kThreads - 1) / kThreads), unsigned(d->n_views));
+    offset_kernel<TY, TO><<<grid, kThreads, 0, st>>>(y, yo, mask, n_pix, nk, floor_, b);
+    HSN_LAUNCHED(ctx);
+  }
+  const bool vec = std::is_same<TY, uint16_t>::value && std::is_same<TO, uint16_t>::value && nk % 8 == 0 &&
+                   (reinterpret_cast<uintptr_t>(y) % 16 == 0) && (reinterpret_cast<uintptr_t>(yo) % 16 == 0) &&
+                   (!p || (ldp % 4 == 0 && reinterpret_cast<uintptr_t>(p) % 16 == 0)) &&
+                   (!pb || reinterpret_cast<uintptr_t>(pb) % 16 == 0);
+  hsn::prof_begin(ctx, HSN_KERN_NORMALIZE, st);
+  if (vec)
+    normalize_kernel<TY, TO, true><<<kSumBlocks, kThreads, 0, st>>>(y, yo, n_rows, n_pix, nk, b, floor_, clip, p,
+                                                                    ldp, pb, ldb, partial);
+  else
+    normalize_kernel<TY, TO, false><<<kSumBlocks, kThreads, 0, st>>>(y, yo, n_rows, n_pix, nk, b, floor_, clip, p,
+                                                                     ldp, pb, ldb, partial);
+  hsn::prof_end(ctx, HSN_KERN_NORMALIZE, st);
+  HSN_LAUNCHED(ctx);
+  if (sumsq) {
+    sum_partials_kernel<<<1, kThreads, 0, st>>>(partial, kSumBlocks, sumsq);
+    HSN_LAUNCHED(ctx);
+  }
+  return HSN_OK;
+}
+
+}  // namespace
+
+extern "C" hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype,
+                                    const void *y_open, int y_open_dtype, const uint8_t *bg_mask,
+                                    float count_floor, int clip_nonneg, float *p, int64_t ldp, uint16_t *p_bf16,
+                                    int64_t ldb, float *offset_b, double *sumsq, void *stream) {
+  if (!ctx) return HSN_ERR_INVALID_ARG;
+  if (!d || !y || !y_open) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: dims, y and y_open are required");
+  if (!p && !p_bf16) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: at least one of p, p_bf16 is required");
+  if (d->n_views <= 0 || d->n_rows <= 0 || d->n_cols <= 0 || d->n_bins <= 0)
+    return hsn::fail(ctx, HSN_ERR_SHAPE, "normalize: all dimensions must be positive");
+  if ((y_dtype != HSN_U16 && y_dtype != HSN_F32) || (y_open_dtype != HSN_U16 && y_open_dtype != HSN_F32))
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: dtype must be HSN_U16 or HSN_F32");
+  if (p && ldp < d->n_bins) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: ldp < n_bins");
+  if (p_bf16 && (ldb < d->n_bins || ldb % 32 != 0 || reinterpret_cast<uintptr_t>(p_bf16) % 16 != 0))
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: ldb must be >= n_bins, a multiple of 32, 16-byte aligned");
+  if (offset_b && !bg_mask) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: offset_b requires bg_mask");
+  if (!(count_floor >= 0.0f)) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: count_floor must be >= 0");
+  hsn::DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool yu = y_dtype == HSN_U16, ou = y_open_dtype == HSN_U16;
+  if (yu && ou)
+    return launch_all(ctx, d, (const uint16_t *)y, (const uint16_t *)y_open, bg_mask, count_floor, clip_nonneg, p,
+                      ldp, p_bf16, ldb, offset_b, sumsq, st);
+  if (yu && !ou)
+    return launch_all(ctx, d, (const uint16_t *)y, (const float *)y_open, bg_mask, count_floor, clip_nonneg, p, ldp,
+                      p_bf16, ldb, offset_b, sumsq, st);
+  if (!yu && ou)
+    return launch_all(ctx, d, (const float *)y, (const uint16_t *)y_open, bg_mask, count_floor, clip_nonneg, p, ldp,
+                      p_bf16, ldb, offset_b, sumsq, st);
+  return launch_all(ctx, d, (const float *)y, (const float *)y_open, bg_mask, count_floor, clip_nonneg, p, ldp,
+                    p_bf16, ldb, offset_b, sumsq, st);
+}

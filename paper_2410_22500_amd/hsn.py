@@ -1,0 +1,249 @@
+"""Thin ctypes binding of libhsn.so (include/hsn.h).
+
+Argument marshalling only: torch supplies device memory and the current
+HIP stream; every step of the computation runs in the library's kernels.
+There is no fallback: if libhsn.so is missing or fails to load, importing
+this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsn.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_22500_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+# status codes
+OK, ERR_INVALID_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_OOM, ERR_DEVICE, ERR_NUMERIC = range(7)
+U16, F32 = 0, 1
+ALGO_MU, ALGO_ANLS = 0, 1
+PREC_FP32, PREC_BF16 = 0, 1
+INIT_USER = 0
+
+KERN_NMF_PASS, KERN_PROJECT, KERN_BACKPROJECT, KERN_NORMALIZE = range(4)
+
+
+class Dims(C.Structure):
+    _fields_ = [("n_views", C.c_int64), ("n_rows", C.c_int64), ("n_cols", C.c_int64), ("n_bins", C.c_int64)]
+
+
+class NmfOpts(C.Structure):
+    _fields_ = [("k", C.c_int), ("algo", C.c_int), ("precision", C.c_int), ("init", C.c_int),
+                ("max_iter", C.c_int), ("check_every", C.c_int), ("polish_rounds", C.c_int),
+                ("rel_obj_tol", C.c_double), ("f_ref", C.c_double)]
+
+
+class NmfStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("polish_done", C.c_int), ("objective", C.c_double), ("rel_obj", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int),
+                ("ms", C.c_float)]
+
+
+class Geom(C.Structure):
+    _fields_ = [("n_views", C.c_int64), ("n_slices", C.c_int64), ("n_cols", C.c_int64), ("k", C.c_int),
+                ("angles", C.POINTER(C.c_double))]
+
+
+_P = C.c_void_p
+_lib.hsn_create.argtypes = [C.POINTER(_P), C.c_int]
+_lib.hsn_create.restype = C.c_int
+_lib.hsn_destroy.argtypes = [_P]
+_lib.hsn_destroy.restype = None
+_lib.hsn_last_error.argtypes = [_P]
+_lib.hsn_last_error.restype = C.c_char_p
+_lib.hsn_version.restype = C.c_int
+_lib.hsn_normalize.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, _P, C.c_float, C.c_int,
+                               _P, C.c_int64, _P, C.c_int64, _P, _P, _P]
+_lib.hsn_normalize.restype = C.c_int
+_lib.hsn_subspace_nmf.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64, _P, _P,
+                                  C.POINTER(NmfOpts), C.POINTER(NmfStats), _P]
+_lib.hsn_subspace_nmf.restype = C.c_int
+_lib.hsn_project.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_float, C.c_float, _P]
+_lib.hsn_project.restype = C.c_int
+_lib.hsn_backproject.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_float, C.c_float, _P]
+_lib.hsn_backproject.restype = C.c_int
+_lib.hsn_cgls.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_int, _P, _P]
+_lib.hsn_cgls.restype = C.c_int
+_lib.hsn_rehydrate.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_int, C.c_int64, C.c_int64, C.c_int64,
+                               C.c_int64, _P, C.c_int64, _P]
+_lib.hsn_rehydrate.restype = C.c_int
+_lib.hsn_profile_enable.argtypes = [_P, C.c_int]
+_lib.hsn_profile_enable.restype = C.c_int
+_lib.hsn_profile_read.argtypes = [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+_lib.hsn_profile_read.restype = C.c_int
+
+
+class HsnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hsn status {status}: {msg}")
+        self.status = status
+
+
+_ctx = {}
+
+
+def context(device: int = 0):
+    if device not in _ctx:
+        h = _P()
+        st = _lib.hsn_create(C.byref(h), device)
+        if st != OK:
+            raise HsnError(st, f"hsn_create(device={device}) failed")
+        _ctx[device] = h
+    return _ctx[device]
+
+
+def _check(st: int, ctx) -> None:
+    if st != OK:
+        raise HsnError(st, _lib.hsn_last_error(ctx).decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else _P(t.data_ptr())
+
+
+def _stream(dev) -> _P:
+    return _P(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _dev(t: torch.Tensor) -> int:
+    if not t.is_cuda:
+        raise ValueError("hsn: tensors must live on a GPU")
+    return t.device.index or 0
+
+
+def _geom(n_views, n_slices, n_cols, k, angles):
+    g = Geom(n_views, n_slices, n_cols, k, None)
+    keep = None
+    if angles is not None:
+        keep = (C.c_double * n_views)(*[float(a) for a in angles])
+        g.angles = C.cast(keep, C.POINTER(C.c_double))
+    return g, keep
+
+
+def round_up(x: int, m: int) -> int:
+    return (x + m - 1) // m * m
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def hsn_normalize(y: torch.Tensor, yo: torch.Tensor, bg_mask: Optional[torch.Tensor] = None,
+                  count_floor: float = 1.0, clip: bool = True, want_f32: bool = True, want_bf16: bool = False,
+                  want_offset: bool = False, ldp: Optional[int] = None, ldb: Optional[int] = None):
+    """y [N_v][N_r][N_c][N_k] (uint16 as int16/uint16 bits or float32), yo [N_r][N_c][N_k].
+    Returns (p [N_p][ldp] f32 or None, p_bf16 [N_p][ldb] int16 bits or None, b or None, sumsq f64 scalar)."""
+    dev = _dev(y)
+    ctx = context(dev)
+    n_v, n_r, n_c, n_k = y.shape
+    dims = Dims(n_v, n_r, n_c, n_k)
+    yd = F32 if y.dtype == torch.float32 else U16
+    od = F32 if yo.dtype == torch.float32 else U16
+    n_p = n_v * n_r * n_c
+    ldp = ldp or round_up(n_k, 4)
+    ldb = ldb or round_up(n_k, 32)
+    p = torch.empty((n_p, ldp), dtype=torch.float32, device=y.device) if want_f32 else None
+    pb = torch.empty((n_p, ldb), dtype=torch.int16, device=y.device) if want_bf16 else None
+    b = torch.empty((n_v, n_k), dtype=torch.float32, device=y.device) if (want_offset and bg_mask is not None) else None
+    ss = torch.empty((), dtype=torch.float64, device=y.device)
+    _check(_lib.hsn_normalize(ctx, C.byref(dims), _ptr(y), yd, _ptr(yo), od, _ptr(bg_mask), float(count_floor),
+                              int(clip), _ptr(p), ldp, _ptr(pb), ldb, _ptr(b), _ptr(ss), _stream(dev)), ctx)
+    return p, pb, b, ss
+
+
+def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], n_k: int, V: torch.Tensor,
+                     D: torch.Tensor, algo: int = ALGO_MU, precision: int = PREC_FP32, max_iter: int = 100,
+                     check_every: int = 10, polish_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0,
+                     history_cap: int = 4096) -> dict:
+    """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device)."""
+    dev = _dev(V)
+    ctx = context(dev)
+    n_p, k = V.shape
+    opts = NmfOpts(k, algo, precision, INIT_USER, max_iter, check_every, polish_rounds, rel_obj_tol, f_ref)
+    hist = (C.c_double * max(history_cap, 1))()
+    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0)
+    ldp = p.stride(0) if p is not None else 0
+    ldb = p_bf16.stride(0) if p_bf16 is not None else 0
+    _check(_lib.hsn_subspace_nmf(ctx, _ptr(p), ldp, _ptr(p_bf16), ldb, n_p, n_k, _ptr(V), _ptr(D), C.byref(opts),
+                                 C.byref(stats), _stream(dev)), ctx)
+    return dict(iters=stats.iters, polish_done=stats.polish_done, objective=stats.objective, rel_obj=stats.rel_obj,
+                history=[hist[i] for i in range(stats.history_len)], ms=stats.ms)
+
+
+def hsn_project(x: torch.Tensor, n_views: int, angles: Optional[Sequence[float]] = None, alpha: float = 1.0,
+                beta: float = 0.0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x [N_r][N][N][K] -> s [N_v][N_r][N][K]."""
+    dev = _dev(x)
+    ctx = context(dev)
+    n_r, n, _, k = x.shape
+    g, keep = _geom(n_views, n_r, n, k, angles)
+    if out is None:
+        out = torch.empty((n_views, n_r, n, k), dtype=torch.float32, device=x.device)
+    _check(_lib.hsn_project(ctx, C.byref(g), _ptr(x), _ptr(out), alpha, beta, _stream(dev)), ctx)
+    return out
+
+
+def hsn_backproject(s: torch.Tensor, angles: Optional[Sequence[float]] = None, alpha: float = 1.0, beta: float = 0.0,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """s [N_v][N_r][N][K] -> x [N_r][N][N][K]."""
+    dev = _dev(s)
+    ctx = context(dev)
+    n_v, n_r, n, k = s.shape
+    g, keep = _geom(n_v, n_r, n, k, angles)
+    if out is None:
+        out = torch.empty((n_r, n, n, k), dtype=torch.float32, device=s.device)
+    _check(_lib.hsn_backproject(ctx, C.byref(g), _ptr(s), _ptr(out), alpha, beta, _stream(dev)), ctx)
+    return out
+
+
+def hsn_cgls(sino: torch.Tensor, n_iter: int, angles: Optional[Sequence[float]] = None, resid: bool = False):
+    """Per-channel CGLS from x = 0: sino [N_v][N_r][N][K] -> x [N_r][N][N][K] (and residual norms)."""
+    dev = _dev(sino)
+    ctx = context(dev)
+    n_v, n_r, n, k = sino.shape
+    g, keep = _geom(n_v, n_r, n, k, angles)
+    x = torch.empty((n_r, n, n, k), dtype=torch.float32, device=sino.device)
+    rh = torch.empty((n_iter + 1, k), dtype=torch.float64, device=sino.device) if resid else None
+    _check(_lib.hsn_cgls(ctx, C.byref(g), _ptr(sino), _ptr(x), n_iter, _ptr(rh), _stream(dev)), ctx)
+    return (x, rh) if resid else x
+
+
+def hsn_rehydrate(xs: torch.Tensor, D: torch.Tensor, vox=None, bins=None) -> torch.Tensor:
+    """x^h = x^s D^T over [vox[0], vox[1]) x [bins[0], bins[1])."""
+    dev = _dev(xs)
+    ctx = context(dev)
+    n_x, k = xs.shape
+    n_k = D.shape[0]
+    vb, ve = vox if vox is not None else (0, n_x)
+    bb, be = bins if bins is not None else (0, n_k)
+    out = torch.empty((ve - vb, be - bb), dtype=torch.float32, device=xs.device)
+    _check(_lib.hsn_rehydrate(ctx, _ptr(xs), _ptr(D), n_x, n_k, k, vb, ve, bb, be, _ptr(out), be - bb,
+                              _stream(dev)), ctx)
+    return out
+
+
+def bf16_bits_to_float(t: torch.Tensor) -> torch.Tensor:
+    """View int16 bfloat16 bits as float32 (for checks)."""
+    return (t.to(torch.int32) << 16).view(torch.float32) if t.dtype == torch.int16 else t
+
+
+def hsn_profile_enable(on: bool = True, device: int = 0) -> None:
+    ctx = context(device)
+    _check(_lib.hsn_profile_enable(ctx, int(on)), ctx)
+
+
+def hsn_profile_read(kernel: int, reset: bool = True, device: int = 0):
+    """(summed device ms, launches) of one kernel kind since the last reset."""
+    ctx = context(device)
+    ms = C.c_double(0.0)
+    n = C.c_int64(0)
+    _check(_lib.hsn_profile_read(ctx, kernel, C.byref(ms), C.byref(n), int(reset)), ctx)
+    return ms.value, n.value

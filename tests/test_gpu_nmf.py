@@ -1,0 +1,145 @@
+"""GPU parity of the NMF (eq. 4) against the FP64 oracle.
+
+Float32 path: one multiplicative-update step from a shared state, V and D
+within 1e-5 relative (Frobenius); 200 steps on the tiny workload, the
+product V D^T and every evaluated objective within 1e-5 (the factors
+themselves may drift along the flat directions of the factorisation, so
+they are compared per step only).  ANLS rounds: exact row-wise NNLS, unique
+minimisers, so V and D are compared directly."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import nmf as onmf
+from oracle.normalize import normalize as onorm
+from tests.gpu_util import rel_fro, show, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _tiny_p():
+    sc = synth.config_scan("tiny")
+    p, _, _ = onorm(sc.y, sc.yo)
+    return p
+
+
+def _p_dev(p, ldp=None):
+    n_p, n_k = p.shape
+    ldp = ldp or (n_k + 3) // 4 * 4
+    buf = torch.zeros((n_p, ldp), dtype=torch.float32, device="cuda")
+    buf[:, :n_k] = torch.from_numpy(p.astype(np.float32)).cuda()
+    return buf
+
+
+def _as32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("shape,k", [((5760, 256), 3), ((1001, 37), 1), ((777, 1500), 8), ((2048, 1024), 4),
+                                     ((95, 2048), 5)])
+def test_mu_one_step(hsn, shape, k):
+    n_p, n_k = shape
+    g = np.random.Generator(np.random.PCG64(n_p + n_k + k))
+    if shape == (5760, 256):
+        p = _tiny_p()
+    else:
+        p = np.maximum(g.uniform(0, 1, (n_p, k)) @ g.uniform(0, 1, (k, n_k)) + 0.1 * g.standard_normal((n_p, n_k)), 0)
+    V0, D0 = synth.random_factors(n_p, n_k, k, 7)
+    V0, D0, p = _as32(V0), _as32(D0), _as32(p)
+    show("mu one step", n_p=n_p, n_k=n_k, k=k)
+    V1, D1, fh, ff = onmf.mu_step(p, V0, D0)
+    V = to_dev(V0, torch.float32)
+    D = to_dev(D0, torch.float32)
+    st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, max_iter=1, check_every=1)
+    assert rel_fro(V.cpu().numpy(), V1) <= 1e-5
+    assert rel_fro(D.cpu().numpy(), D1) <= 1e-5
+    assert abs(st["history"][0] - fh) <= 1e-5 * fh
+
+
+def test_mu_200_steps_tiny(hsn):
+    p = _as32(_tiny_p())
+    n_p, n_k = p.shape
+    V0, D0 = synth.random_factors(n_p, n_k, 3, 8)
+    V0, D0 = _as32(V0), _as32(D0)
+    show("mu 200 tiny")
+    Vr, Dr, fh, _ = onmf.mu_run(p, V0, D0, 200)
+    V = to_dev(V0, torch.float32)
+    D = to_dev(D0, torch.float32)
+    st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, max_iter=200, check_every=1)
+    h = np.array(st["history"])
+    assert len(h) == 200
+    np.testing.assert_allclose(h, fh, rtol=1e-5)
+    assert rel_fro(V.cpu().numpy() @ D.cpu().numpy().T, Vr @ Dr.T) <= 1e-5
+    assert np.all(np.diff(h) <= 1e-6 * h[0])
+
+
+@pytest.mark.parametrize("shape,k", [((5760, 256), 3), ((503, 1100), 6)])
+def test_anls_round(hsn, shape, k):
+    n_p, n_k = shape
+    g = np.random.Generator(np.random.PCG64(k))
+    if shape == (5760, 256):
+        p = _tiny_p()
+    else:
+        p = np.maximum(g.uniform(0, 1, (n_p, k)) @ g.uniform(0, 1, (k, n_k)) + 0.1 * g.standard_normal((n_p, n_k)), 0)
+    p = _as32(p)
+    V0, D0 = synth.random_factors(n_p, n_k, k, 9)
+    V0, D0 = _as32(V0), _as32(D0)
+    show("anls round", n_p=n_p, n_k=n_k, k=k)
+    V1, D1, fh, ff = onmf.anls_round(p, V0, D0)
+    V = to_dev(V0, torch.float32)
+    D = to_dev(D0, torch.float32)
+    st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, algo=hsn.ALGO_ANLS, max_iter=1, check_every=1)
+    assert rel_fro(V.cpu().numpy(), V1) <= 1e-5
+    assert rel_fro(D.cpu().numpy(), D1) <= 1e-5
+    assert abs(st["history"][0] - fh) <= 1e-5 * fh
+
+
+def test_polish_after_mu_reaches_reference(hsn):
+    # MU bulk then ANLS polish on the float32 p: the objective decreases
+    # monotonically and reaches the oracle's stationary value.
+    p = _as32(_tiny_p())
+    n_p, n_k = p.shape
+    V0, D0 = synth.random_factors(n_p, n_k, 3, 10)
+    V0, D0 = _as32(V0), _as32(D0)
+    f_star, _, _ = onmf.stationary_reference(p, V0.copy(), D0.copy())
+    V = to_dev(V0, torch.float32)
+    D = to_dev(D0, torch.float32)
+    show("mu+polish tiny")
+    st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, max_iter=50, check_every=10, polish_rounds=40,
+                              rel_obj_tol=1e-4, f_ref=f_star)
+    assert st["rel_obj"] <= 1e-4
+    h = np.array(st["history"])
+    assert np.all(np.diff(h) <= 1e-6 * h[0])
+
+
+def test_mu_mid_config_one_step(hsn):
+    # Full mid-size workload (122880 x 1024, K = 4) in the benchmark's launch shape.
+    sc = synth.config_scan("mid")
+    p, _, _ = onorm(sc.y, sc.yo)
+    p = _as32(p)
+    n_p, n_k = p.shape
+    V0, D0 = synth.random_factors(n_p, n_k, 4, 11)
+    V0, D0 = _as32(V0), _as32(D0)
+    show("mu one step mid")
+    V1, D1, fh, _ = onmf.mu_step(p, V0, D0)
+    V = to_dev(V0, torch.float32)
+    D = to_dev(D0, torch.float32)
+    st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, max_iter=1, check_every=1)
+    assert rel_fro(V.cpu().numpy(), V1) <= 1e-5
+    assert rel_fro(D.cpu().numpy(), D1) <= 1e-5
+    assert abs(st["history"][0] - fh) <= 1e-5 * fh
+
+
+def test_bad_arguments_raise(hsn):
+    V = torch.ones((10, 3), device="cuda")
+    D = torch.ones((20, 3), device="cuda")
+    p = torch.ones((10, 22), device="cuda")       # pitch 22 is not a multiple of 4
+    with pytest.raises(hsn.HsnError) as e:
+        hsn.hsn_subspace_nmf(p, None, 20, V, D, max_iter=1)
+    assert e.value.status == hsn.ERR_INVALID_ARG
+    V9 = torch.ones((10, 9), device="cuda")
+    D9 = torch.ones((20, 9), device="cuda")
+    with pytest.raises(hsn.HsnError) as e:
+        hsn.hsn_subspace_nmf(torch.ones((10, 20), device="cuda"), None, 20, V9, D9, max_iter=1)
+    assert e.value.status == hsn.ERR_SHAPE
