@@ -92,8 +92,9 @@ hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *dims,
 /* Subspace extraction: eq. (4) (V, D) = argmin_{V,D>=0} ||p - V D^T||^2 */
 /* ------------------------------------------------------------------ */
 
-enum { HSN_ALGO_MU = 0,    /* Lee-Seung multiplicative updates, V then D */
-       HSN_ALGO_ANLS = 1 };/* exact row-wise NNLS for V, then for D       */
+enum { HSN_ALGO_MU = 0,    /* Lee-Seung multiplicative updates, V then D      */
+       HSN_ALGO_ANLS = 1,  /* exact row-wise NNLS for V, then for D            */
+       HSN_ALGO_HALS = 2 };/* HALS column sweeps (the paper's Fast HALS), V then D */
 enum { HSN_PREC_FP32 = 0,  /* float32 p, float32 arithmetic               */
        HSN_PREC_BF16 = 1 };/* bfloat16 p on MFMA, float32 accumulation;
                               the polish rounds then use the float32 p    */
@@ -101,12 +102,13 @@ enum { HSN_INIT_USER = 0 };/* V and D hold the start on entry             */
 
 typedef struct {
   int k;              /* K = N_s, 1..8 */
-  int algo;           /* HSN_ALGO_* for the bulk iterations */
+  int algo;           /* HSN_ALGO_* for the bulk iterations (bf16 bulk: MU or HALS) */
   int precision;      /* HSN_PREC_* for the bulk iterations */
   int init;           /* HSN_INIT_* */
   int max_iter;       /* bulk iterations, >= 0 */
   int check_every;    /* objective evaluated every this many iterations (>= 1) */
-  int polish_rounds;  /* ANLS rounds on the float32 p after the bulk (>= 0) */
+  int polish_rounds;  /* rounds on the float32 p after the bulk (>= 0) */
+  int polish_algo;    /* HSN_ALGO_ANLS or HSN_ALGO_HALS for the polish rounds */
   double rel_obj_tol; /* stop when (f - f_ref)/f_ref <= tol; ignored if f_ref <= 0 */
   double f_ref;       /* reference objective f* (> 0 enables the stop test) */
 } hsn_nmf_opts;

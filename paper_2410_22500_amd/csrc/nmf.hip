@@ -22,15 +22,16 @@ void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st
                      int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, float *part_nd,
                      double *part_gv, double *part_obj);
 void launch_gram(int K, hipStream_t st, const float *F, int64_t n, double *G, double *chol, int want_chol);
-void launch_reduce_update(int K, int mode_d, bool obj, hipStream_t st, const NmfWork &w, int n_k, float *D,
+void launch_reduce_update(int K, int mode_d, bool obj, hipStream_t st, const NmfWork &w, int n_wg, int n_k, float *D,
                           double *hist_slot);
 void launch_nnls_rows(int K, hipStream_t st, const float *NV, const double *GD, const double *chol, float *V,
                       int64_t n_p, int n_blocks);
 // bfloat16 MFMA pass (nmf_bf16.hip); returns false if the shape is unsupported.
-bool launch_pass_bf16(int K, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p,
-                      int n_k, float *V, const float *D, const double *GD, float *part_nd, double *part_gv,
-                      double *part_obj);
+bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
+                      int64_t n_p, int n_k, float *V, const float *D, const double *GD, uint4 *scratch,
+                      float *part_nd, double *part_gv, double *part_obj);
 int pass_bf16_wgs(hsn_ctx *ctx, int64_t n_p);
+size_t bf16_scratch_bytes(int64_t ldb);
 
 namespace {
 
@@ -42,22 +43,26 @@ struct Run {
   int n_k;
   NmfWork w;
   int hist_len = 0;
+  int wg_f32 = 0, wg_bf16 = 0;  // persistent grid sizes of the two passes
+  uint4 *bf16_scratch = nullptr;
 };
 
-hsn_status mu_iteration(Run &R, bool bf16, const float *p, int64_t ldp, const uint16_t *pb, int64_t ldb, float *V,
-                        float *D, bool obj) {
+// One fused iteration (MU or HALS row rule): a single streaming read of p.
+hsn_status fused_iteration(Run &R, int mode, bool bf16, const float *p, int64_t ldp, const uint16_t *pb, int64_t ldb,
+                           float *V, float *D, bool obj) {
   launch_gram(R.K, R.st, D, R.n_k, R.w.gd, R.w.chol, 0);
+  const int n_wg = bf16 ? R.wg_bf16 : R.wg_f32;
   prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
   if (bf16) {
-    if (!launch_pass_bf16(R.K, obj, R.w.n_wg, R.st, pb, ldb, R.n_p, R.n_k, V, D, R.w.gd, R.w.part_nd, R.w.part_gv,
-                          R.w.part_obj))
-      return fail(R.ctx, HSN_ERR_UNSUPPORTED, "bf16 pass: unsupported shape");
+    if (!launch_pass_bf16(R.K, mode, obj, n_wg, R.st, pb, ldb, R.n_p, R.n_k, V, D, R.w.gd, R.bf16_scratch,
+                          R.w.part_nd, R.w.part_gv, R.w.part_obj))
+      return fail(R.ctx, HSN_ERR_UNSUPPORTED, "bf16 pass: unsupported shape (ldb <= 2048, k <= 8)");
   } else {
-    launch_pass_f32(R.K, kModeMU, obj, R.n_k > 1024 ? 2 : 1, R.w.n_wg, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D,
-                    R.w.gd, R.w.part_nd, R.w.part_gv, R.w.part_obj);
+    launch_pass_f32(R.K, mode, obj, R.n_k > 1024 ? 2 : 1, n_wg, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd,
+                    R.w.part_nd, R.w.part_gv, R.w.part_obj);
   }
   prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  launch_reduce_update(R.K, kModeMU, obj, R.st, R.w, R.n_k, D, obj ? R.w.hist + R.hist_len : nullptr);
+  launch_reduce_update(R.K, mode, obj, R.st, R.w, n_wg, R.n_k, D, obj ? R.w.hist + R.hist_len : nullptr);
   if (obj) ++R.hist_len;
   HSN_LAUNCHED(R.ctx);
   return HSN_OK;
@@ -67,16 +72,16 @@ hsn_status anls_round(Run &R, const float *p, int64_t ldp, float *V, float *D) {
   const int nq = R.n_k > 1024 ? 2 : 1;
   launch_gram(R.K, R.st, D, R.n_k, R.w.gd, R.w.chol, 1);
   prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  launch_pass_f32(R.K, kModeNV, false, nq, R.w.n_wg, R.st, p, ldp, R.n_p, R.n_k, V, R.w.nv, D, R.w.gd, R.w.part_nd,
+  launch_pass_f32(R.K, kModeNV, false, nq, R.wg_f32, R.st, p, ldp, R.n_p, R.n_k, V, R.w.nv, D, R.w.gd, R.w.part_nd,
                   R.w.part_gv, R.w.part_obj);
   prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
   const int nb = int(std::min<int64_t>((R.n_p + 255) / 256, 8 * int64_t(R.ctx->num_cu)));
   launch_nnls_rows(R.K, R.st, R.w.nv, R.w.gd, R.w.chol, V, R.n_p, nb);
   prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  launch_pass_f32(R.K, kModeND, true, nq, R.w.n_wg, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd, R.w.part_nd,
+  launch_pass_f32(R.K, kModeND, true, nq, R.wg_f32, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd, R.w.part_nd,
                   R.w.part_gv, R.w.part_obj);
   prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  launch_reduce_update(R.K, kModeNV, true, R.st, R.w, R.n_k, D, R.w.hist + R.hist_len);
+  launch_reduce_update(R.K, kModeNV, true, R.st, R.w, R.wg_f32, R.n_k, D, R.w.hist + R.hist_len);
   ++R.hist_len;
   HSN_LAUNCHED(R.ctx);
   return HSN_OK;
@@ -99,7 +104,10 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   if (!o) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: opts is NULL");
   if (o->k < 1 || o->k > 8) return fail(ctx, HSN_ERR_SHAPE, "nmf: k must be in 1..8 (got %d)", o->k);
   if (n_p < 1 || n_k < 1 || n_k > 2048) return fail(ctx, HSN_ERR_SHAPE, "nmf: need n_p >= 1 and 1 <= n_k <= 2048");
-  if (o->algo != HSN_ALGO_MU && o->algo != HSN_ALGO_ANLS) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: bad algo");
+  if (o->algo != HSN_ALGO_MU && o->algo != HSN_ALGO_ANLS && o->algo != HSN_ALGO_HALS)
+    return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: bad algo");
+  if (o->polish_rounds > 0 && o->polish_algo != HSN_ALGO_ANLS && o->polish_algo != HSN_ALGO_HALS)
+    return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: polish_algo must be HSN_ALGO_ANLS or HSN_ALGO_HALS");
   if (o->precision != HSN_PREC_FP32 && o->precision != HSN_PREC_BF16)
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: bad precision");
   if (o->init != HSN_INIT_USER) return fail(ctx, HSN_ERR_UNSUPPORTED, "nmf: only HSN_INIT_USER is available");
@@ -107,8 +115,8 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: max_iter >= 0, check_every >= 1, polish_rounds >= 0 required");
   if (!V || !D) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: V and D are required");
   const bool bf16 = o->precision == HSN_PREC_BF16;
-  if (bf16 && o->algo != HSN_ALGO_MU)
-    return fail(ctx, HSN_ERR_UNSUPPORTED, "nmf: the bfloat16 bulk runs multiplicative updates only");
+  if (bf16 && o->algo == HSN_ALGO_ANLS)
+    return fail(ctx, HSN_ERR_UNSUPPORTED, "nmf: the bfloat16 bulk runs MU or HALS");
   const bool need_f32 = (!bf16 && o->max_iter > 0) || o->polish_rounds > 0;
   if (need_f32) {
     if (!p) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: float32 p is required");
@@ -127,15 +135,17 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int K = o->k;
   const int64_t n_tiles = (n_p + 7) / 8;
-  int n_wg = int(std::min<int64_t>(n_tiles, 2 * int64_t(ctx->num_cu)));
-  if (bf16) n_wg = std::max(n_wg, pass_bf16_wgs(ctx, n_p));
+  const int wg_f32 = int(std::min<int64_t>(n_tiles, 2 * int64_t(ctx->num_cu)));
+  const int wg_bf16 = bf16 ? pass_bf16_wgs(ctx, n_p) : 0;
+  const int n_wg = std::max(wg_f32, wg_bf16);
   const int hist_cap = o->max_iter + o->polish_rounds + 2;
+  const bool need_nv = o->algo == HSN_ALGO_ANLS || (o->polish_rounds > 0 && o->polish_algo == HSN_ALGO_ANLS);
   const size_t need = Carver::need({sizeof(double) * 64, sizeof(double) * 64, sizeof(double) * 256 * kCholStride,
                                     sizeof(float) * size_t(n_wg) * n_k * K, sizeof(double) * size_t(n_wg) * K * K,
                                     sizeof(double) * n_wg, sizeof(double) * kSplit * size_t(n_k) * K,
                                     sizeof(double) * kSplit * K * K, sizeof(double) * kSplit,
-                                    o->polish_rounds > 0 || o->algo == HSN_ALGO_ANLS ? sizeof(float) * n_p * K : 0,
-                                    sizeof(double) * hist_cap});
+                                    need_nv ? sizeof(float) * n_p * K : 0,
+                                    sizeof(double) * hist_cap, bf16 ? bf16_scratch_bytes(ldb) : 0});
   hsn_status rc = ensure_ws(ctx, need);
   if (rc != HSN_OK) return rc;
   Carver cv(ctx->ws);
@@ -149,9 +159,12 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   R.w.red_nd = cv.take<double>(kSplit * size_t(n_k) * K);
   R.w.red_gv = cv.take<double>(kSplit * K * K);
   R.w.red_obj = cv.take<double>(kSplit);
-  R.w.nv = (o->polish_rounds > 0 || o->algo == HSN_ALGO_ANLS) ? cv.take<float>(n_p * K) : nullptr;
+  R.w.nv = need_nv ? cv.take<float>(n_p * K) : nullptr;
   R.w.hist = cv.take<double>(hist_cap);
   R.w.n_wg = n_wg;
+  R.wg_f32 = wg_f32;
+  R.wg_bf16 = wg_bf16;
+  if (bf16) R.bf16_scratch = cv.take<uint4>(bf16_scratch_bytes(ldb) / sizeof(uint4));
 
   if (stats) HSN_HIP(ctx, hipEventRecord(ctx->ev0, st));
   const bool stop_test = o->f_ref > 0.0;
@@ -160,10 +173,10 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   bool reached = false;
   for (; it < o->max_iter && !reached; ++it) {
     const bool obj = ((it + 1) % o->check_every == 0) || (it + 1 == o->max_iter);
-    if (o->algo == HSN_ALGO_MU)
-      rc = mu_iteration(R, bf16, p, ldp, p_bf16, ldb, V, D, obj);
-    else
+    if (o->algo == HSN_ALGO_ANLS)
       rc = anls_round(R, p, ldp, V, D);
+    else
+      rc = fused_iteration(R, o->algo == HSN_ALGO_MU ? kModeMU : kModeHALS, bf16, p, ldp, p_bf16, ldb, V, D, obj);
     if (rc != HSN_OK) return rc;
     if (obj && stop_test) {
       if ((rc = read_last(R, &last)) != HSN_OK) return rc;
@@ -172,7 +185,9 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   }
   int polished = 0;
   for (; polished < o->polish_rounds; ++polished) {
-    if ((rc = anls_round(R, p, ldp, V, D)) != HSN_OK) return rc;
+    rc = (o->polish_algo == HSN_ALGO_ANLS) ? anls_round(R, p, ldp, V, D)
+                                           : fused_iteration(R, kModeHALS, false, p, ldp, nullptr, 0, V, D, true);
+    if (rc != HSN_OK) return rc;
     if (stop_test) {
       if ((rc = read_last(R, &last)) != HSN_OK) return rc;
       if ((last - o->f_ref) / o->f_ref <= o->rel_obj_tol) {

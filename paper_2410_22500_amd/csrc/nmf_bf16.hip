@@ -1,10 +1,372 @@
-// bfloat16 MFMA NMF pass (placeholder until the MFMA kernel lands).
+// bfloat16 NMF pass over p on the matrix cores (eq. 4), float32 accumulation.
+//
+// One persistent 512-thread workgroup per CU walks tiles of 16 rows of the
+// bfloat16 copy of p (row pitch ldb, zero-padded to a multiple of 32 bins).
+// Wave w owns a contiguous range of 32-bin k-steps for the whole pass.  Per
+// tile:
+//   1. the wave writes its bins of the 16 rows (loaded coalesced, 1 KB per
+//      instruction, prefetched one tile ahead) into a row-major LDS tile;
+//   2. N_V = P D on MFMA 16x16x32: A = 16 rows x 32 bins from LDS, B = D split
+//      into bfloat16 hi/lo halves packed as 16 columns [D_hi | D_lo], so one
+//      instruction gives both products and N_V = C[:, j] + C[:, 8 + j];
+//   3. the per-wave N_V partials are summed in LDS (fixed order) and the row
+//      rule (Lee-Seung MU or HALS) updates V in float64 registers;
+//   4. N_D += P^T V_new on MFMA 16x16x16: A = P^T (16 bins x 16 rows, read
+//      transposed from the LDS tile), B = [V_hi | V_lo]; the accumulators
+//      stay in registers for the whole pass;
+//   5. on objective iterations, V_new D^T is rebuilt on MFMA 16x16x32 from
+//      [V_hi | V_lo | V_hi] x [D_hi ; D_hi ; D_lo] and ||P - V_new D^T||^2 is
+//      accumulated against the same bfloat16 P values.
+// p is read from HBM exactly once per iteration; everything else stays on chip.
 #include "nmf_common.hpp"
 
 namespace hsn {
-bool launch_pass_bf16(int, bool, int, hipStream_t, const uint16_t *, int64_t, int64_t, int, float *, const float *,
-                      const double *, float *, double *, double *) {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBThreads = 512;
+constexpr int kBWaves = kBThreads / 64;
+constexpr int kBRows = 16;
+constexpr int kMaxLdb = 2048;
+constexpr int kKSW = kMaxLdb / 32 / kBWaves;  // max k-steps per wave
+
+__host__ __device__ inline int bf16_pitch(int64_t ldb) { return int(2 * ldb + 8); }
+
+struct Bf16Lds {
+  int tile, db1, red, vsp, vnw, gd, obj, total;
+};
+
+__host__ __device__ inline Bf16Lds bf16_lds_layout(int64_t ldb, int K) {
+  Bf16Lds L;
+  int o = 0;
+  L.tile = o;
+  o += kBRows * bf16_pitch(ldb);
+  o = (o + 15) & ~15;
+  L.db1 = o;
+  o += int(ldb / 32) * 64 * 16;
+  L.red = o;
+  o += kBWaves * 16 * 16 * 4;
+  L.vsp = o;
+  o += 16 * 16 * 2;
+  L.vnw = o;
+  o += 16 * 8 * 4;
+  L.gd = o;
+  o += 64 * 8;
+  L.obj = o;
+  o += kBWaves * 8;
+  L.total = o;
+  (void)K;
+  return L;
+}
+
+__device__ __forceinline__ uint16_t bf_hi(float f) { return f32_to_bf16_bits(f); }
+__device__ __forceinline__ uint16_t bf_lo(float f) { return f32_to_bf16_bits(f - bf16_bits_to_f32(f32_to_bf16_bits(f))); }
+
+// Operand images of D for one pass.
+//   db1[s][lane]: GEMM1 B operand of k-step s: column n = lane % 16, bins
+//                 32 s + 8 (lane / 16) + e; n < 8 -> hi(D[k][n]), else lo(D[k][n-8]).
+//   db3[b][lane]: reconstruction B operand of bin block b: bin 16 b + lane % 16,
+//                 contraction group g = lane / 16: g 0,1 -> hi(D[bin][e]), g 2 -> lo, g 3 -> 0.
+__global__ void bf16_prep_kernel(const float *__restrict__ D, int n_k, int K, int64_t ldb, uint4 *__restrict__ db1,
+                                 uint4 *__restrict__ db3) {
+  const int64_t nks = ldb / 32, nbb = ldb / 16;
+  const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int lane = int(id & 63);
+  uint16_t v[8];
+  if (id < nks * 64) {
+    const int64_t s = id >> 6;
+    const int n = lane & 15, j = n & 7;
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = 32 * s + 8 * (lane >> 4) + e;
+      const float d = (j < K && k < n_k) ? D[k * K + j] : 0.0f;
+      v[e] = (n < 8) ? bf_hi(d) : bf_lo(d);
+    }
+    db1[id] = make_uint4(v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
+                         v[6] | (uint32_t(v[7]) << 16));
+  } else if (id < nks * 64 + nbb * 64) {
+    const int64_t b = (id - nks * 64) >> 6;
+    const int64_t bin = 16 * b + (lane & 15);
+    const int g = lane >> 4;
+    for (int e = 0; e < 8; ++e) {
+      const float d = (e < K && bin < n_k) ? D[bin * K + e] : 0.0f;
+      v[e] = (g == 3) ? 0 : (g == 2 ? bf_lo(d) : bf_hi(d));
+    }
+    db3[id - nks * 64] = make_uint4(v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16),
+                                    v[4] | (uint32_t(v[5]) << 16), v[6] | (uint32_t(v[7]) << 16));
+  }
+}
+
+template <int K, int MODE, bool OBJ>
+__global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__restrict__ Pb, int64_t ldb,
+                                                              int64_t n_p, int n_k, float *__restrict__ V,
+                                                              const uint4 *__restrict__ db1g,
+                                                              const uint4 *__restrict__ db3g,
+                                                              const double *__restrict__ GD,
+                                                              float *__restrict__ part_nd,
+                                                              double *__restrict__ part_gv,
+                                                              double *__restrict__ part_obj) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const Bf16Lds L = bf16_lds_layout(ldb, K);
+  char *tileL = smem + L.tile;
+  uint4 *db1L = reinterpret_cast<uint4 *>(smem + L.db1);
+  float *red = reinterpret_cast<float *>(smem + L.red);        // [8][16][16]
+  uint16_t *vsp = reinterpret_cast<uint16_t *>(smem + L.vsp);  // [16][16]  [V_hi | V_lo]
+  float *vnw = reinterpret_cast<float *>(smem + L.vnw);        // [16][8]
+  double *gd_s = reinterpret_cast<double *>(smem + L.gd);
+  double *obj_s = reinterpret_cast<double *>(smem + L.obj);
+
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int pitch = bf16_pitch(ldb);
+  const int nks = int(ldb / 32);
+  const int s0 = (w * nks) / kBWaves, s1 = ((w + 1) * nks) / kBWaves, nw = s1 - s0;
+  const int cpr = 4 * nw;  // 16-byte chunks per row in this wave's bins
+
+  for (int i = t; i < nks * 64; i += kBThreads) db1L[i] = db1g[i];
+  for (int i = t; i < 16 * 16; i += kBThreads) vsp[i] = 0;
+  if (t < K * K) gd_s[t] = GD[t];
+
+  f32x4 acc2[2 * kKSW];
+#pragma unroll
+  for (int b = 0; b < 2 * kKSW; ++b) acc2[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double gv = 0.0, obj = 0.0;
+
+  uint4 pr[kKSW];
+  auto load_tile = [&](int64_t row0) {
+#pragma unroll
+    for (int i = 0; i < kKSW; ++i) {
+      if (i < nw) {
+        const int c = lane + 64 * i;
+        const int r = c / cpr, cc = c - (c / cpr) * cpr;
+        const int64_t row = row0 + r;
+        pr[i] = (row < n_p) ? *reinterpret_cast<const uint4 *>(Pb + row * ldb + 32 * s0 + 8 * cc)
+                            : make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+  };
+
+  const int64_t n_tiles = (n_p + kBRows - 1) / kBRows;
+  int64_t tile = blockIdx.x;
+  if (tile < n_tiles) load_tile(tile * kBRows);
+  __syncthreads();
+
+  for (; tile < n_tiles; tile += gridDim.x) {
+    const int64_t row0 = tile * kBRows;
+    // 1. this wave's bins of the tile -> LDS (8-byte stores: the padded pitch
+    //    keeps the transposed reads below free of bank conflicts)
+#pragma unroll
+    for (int i = 0; i < kKSW; ++i) {
+      if (i < nw) {
+        const int c = lane + 64 * i;
+        const int r = c / cpr, cc = c - (c / cpr) * cpr;
+        uint2 *dst = reinterpret_cast<uint2 *>(tileL + r * pitch + 2 * (32 * s0 + 8 * cc));
+        dst[0] = make_uint2(pr[i].x, pr[i].y);
+        dst[1] = make_uint2(pr[i].z, pr[i].w);
+      }
+    }
+    // prefetch the next tile into the same registers
+    if (tile + gridDim.x < n_tiles) load_tile((tile + gridDim.x) * kBRows);
+    __syncthreads();
+
+    // 2. N_V partial over this wave's bins
+    f32x4 acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < kKSW; ++i) {
+      if (i < nw) {
+        const int s = s0 + i;
+        const uint2 *src = reinterpret_cast<const uint2 *>(tileL + (lane & 15) * pitch + 2 * (32 * s + 8 * (lane >> 4)));
+        const uint2 lo = src[0], hi = src[1];
+        const uint4 av = make_uint4(lo.x, lo.y, hi.x, hi.y);
+        const uint4 bv = db1L[s * 64 + lane];
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                       acc1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[(w * 16 + 4 * (lane >> 4) + i) * 16 + (lane & 15)] = acc1[i];
+    __syncthreads();
+
+    // 3. row rule
+    if (MODE == kModeHALS) {
+      if (t < kBRows) {
+        const int r = t;
+        const int64_t row = row0 + r;
+        double h[K], x[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          float s = 0.0f;
+#pragma unroll
+          for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + r) * 16 + j] + red[(ww * 16 + r) * 16 + 8 + j];
+          h[j] = s;
+          x[j] = (row < n_p) ? double(V[row * K + j]) : 0.0;
+        }
+        hals_row<K>(gd_s, h, x);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float vn = (row < n_p) ? float(x[j]) : 0.0f;
+          if (row < n_p) V[row * K + j] = vn;
+          vnw[r * 8 + j] = vn;
+          vsp[r * 16 + j] = bf_hi(vn);
+          vsp[r * 16 + 8 + j] = bf_lo(vn);
+        }
+      }
+    } else if (t < kBRows * K) {
+      const int r = t / K, j = t - (t / K) * K;
+      const int64_t row = row0 + r;
+      float s = 0.0f;
+#pragma unroll
+      for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + r) * 16 + j] + red[(ww * 16 + r) * 16 + 8 + j];
+      float vn = 0.0f;
+      if (row < n_p) {
+        float vr[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) vr[i] = V[row * K + i];
+        double den = 0.0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) den += double(vr[i]) * gd_s[i * K + j];
+        vn = float(double(vr[j]) * double(s) / fmax(den, 1e-300));
+        V[row * K + j] = vn;
+      }
+      vnw[r * 8 + j] = vn;
+      vsp[r * 16 + j] = bf_hi(vn);
+      vsp[r * 16 + 8 + j] = bf_lo(vn);
+    }
+    __syncthreads();
+
+    // 4. N_D += P^T V_new (and 5. the residual on objective iterations)
+    if (t < K * K) {
+      const int i = t / K, j = t - (t / K) * K;
+      float s = 0.0f;
+#pragma unroll
+      for (int r = 0; r < kBRows; ++r) s = fmaf(vnw[r * 8 + i], vnw[r * 8 + j], s);
+      gv += double(s);
+    }
+    s16x4 b2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b2[q] = short(vsp[(4 * (lane >> 4) + q) * 16 + (lane & 15)]);
+    bf16x8 a3;
+    if (OBJ) {
+      const int g = lane >> 4, row = lane & 15;
+      uint16_t u[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) u[e] = (g == 3) ? 0 : vsp[row * 16 + (g == 1 ? 8 : 0) + e];
+      a3 = __builtin_bit_cast(bf16x8, make_uint4(u[0] | (uint32_t(u[1]) << 16), u[2] | (uint32_t(u[3]) << 16),
+                                                 u[4] | (uint32_t(u[5]) << 16), u[6] | (uint32_t(u[7]) << 16)));
+    }
+    float objf = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kKSW; ++i) {
+      if (i < nw) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int bin0 = 32 * (s0 + i) + 16 * hh;
+          s16x4 a2;
+          const char *col = tileL + 2 * (bin0 + (lane & 15));
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a2[q] = *reinterpret_cast<const short *>(col + (4 * (lane >> 4) + q) * pitch);
+          acc2[2 * i + hh] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, b2, acc2[2 * i + hh], 0, 0, 0);
+          if (OBJ) {
+            const uint4 b3 = db3g[(bin0 / 16) * 64 + lane];
+            f32x4 rec = {0.f, 0.f, 0.f, 0.f};
+            rec = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, __builtin_bit_cast(bf16x8, b3), rec, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float df = bf16_bits_to_f32(uint16_t(a2[q])) - rec[q];
+              objf = fmaf(df, df, objf);
+            }
+          }
+        }
+      }
+    }
+    if (OBJ) obj += double(objf);
+  }
+
+  // Partials: N_D[bin][j] = C[bin][j] + C[bin][8 + j] (lanes n and n + 8).
+  float *dst = part_nd + size_t(blockIdx.x) * n_k * K;
+  const int n = lane & 15;
+#pragma unroll
+  for (int i = 0; i < kKSW; ++i) {
+    if (i < nw) {
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float v = acc2[2 * i + hh][q];
+          const float other = __shfl_xor(v, 8, 64);
+          const int bin = 32 * (s0 + i) + 16 * hh + 4 * (lane >> 4) + q;
+          if (n < K && bin < n_k) dst[size_t(bin) * K + n] = v + other;
+        }
+      }
+    }
+  }
+  if (t < K * K) part_gv[size_t(blockIdx.x) * K * K + t] = gv;
+  if (OBJ) {
+    obj = wave_sum_all(obj);
+    if (lane == 0) obj_s[w] = obj;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int ww = 0; ww < kBWaves; ++ww) s += obj_s[ww];
+      part_obj[blockIdx.x] = s;
+    }
+  }
+}
+
+template <int K, int MODE, bool OBJ>
+static bool launch_bf16_inst(int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p, int n_k,
+                             float *V, const uint4 *db1, const uint4 *db3, const double *GD, float *part_nd,
+                             double *part_gv, double *part_obj) {
+  const int lds = bf16_lds_layout(ldb, K).total;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&pass_bf16_kernel<K, MODE, OBJ>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+      return false;
+    attr_set = true;
+  }
+  pass_bf16_kernel<K, MODE, OBJ><<<n_wg, kBThreads, lds, st>>>(Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
+                                                                part_obj);
+  return true;
+}
+
+template <int K>
+static bool launch_bf16_k(int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p,
+                          int n_k, float *V, const uint4 *db1, const uint4 *db3, const double *GD, float *part_nd,
+                          double *part_gv, double *part_obj) {
+  if (mode == kModeMU)
+    return obj ? launch_bf16_inst<K, kModeMU, true>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
+                                                    part_obj)
+               : launch_bf16_inst<K, kModeMU, false>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
+                                                     part_obj);
+  return obj ? launch_bf16_inst<K, kModeHALS, true>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
+                                                    part_obj)
+             : launch_bf16_inst<K, kModeHALS, false>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
+                                                     part_obj);
+}
+
+size_t bf16_scratch_bytes(int64_t ldb) { return size_t(ldb / 32) * 1024 + size_t(ldb / 16) * 1024; }
+
+bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
+                      int64_t n_p, int n_k, float *V, const float *D, const double *GD, uint4 *scratch,
+                      float *part_nd, double *part_gv, double *part_obj) {
+  if (ldb > kMaxLdb || ldb % 32 != 0 || K < 1 || K > 8 || (mode != kModeMU && mode != kModeHALS)) return false;
+  uint4 *db1 = scratch;
+  uint4 *db3 = scratch + (ldb / 32) * 64;
+  const int64_t n_items = (ldb / 32) * 64 + (ldb / 16) * 64;
+  bf16_prep_kernel<<<unsigned((n_items + 255) / 256), 256, 0, st>>>(D, n_k, K, ldb, db1, db3);
+  switch (K) {
+#define HSN_K(KK) \
+  case KK: return launch_bf16_k<KK>(mode, obj, n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv, part_obj);
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+  }
   return false;
 }
-int pass_bf16_wgs(hsn_ctx *ctx, int64_t) { return ctx->num_cu; }
+
+int pass_bf16_wgs(hsn_ctx *ctx, int64_t n_p) {
+  const int64_t n_tiles = (n_p + kBRows - 1) / kBRows;
+  return int(std::min<int64_t>(n_tiles, ctx->num_cu));
+}
+
 }  // namespace hsn

@@ -11,7 +11,25 @@ enum PassMode {
   kModeMU = 0,  // fused: N_V = P D, Lee-Seung V update, then N_D += P^T V_new
   kModeNV = 1,  // N_V = P D only (written out; the rows are solved separately)
   kModeND = 2,  // N_D += P^T V_new only (V_new given)
+  kModeHALS = 3,  // fused: N_V = P D, HALS column sweep of V, then N_D += P^T V_new
 };
+
+// One HALS sweep of a row x given its right-hand side h and Gram G: for each
+// column j in order, x_j <- max(0, x_j + (h_j - sum_i x_i G_ij) / G_jj), using
+// the already updated x_i (Cichocki-Phan).  Columns with G_jj = 0 are skipped.
+template <int K>
+__device__ __forceinline__ void hals_row(const double *__restrict__ G, const double (&h)[K], double (&x)[K]) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const double gjj = G[j * K + j];
+    if (gjj > 0.0) {
+      double g = h[j];
+#pragma unroll
+      for (int i = 0; i < K; ++i) g -= x[i] * G[i * K + j];
+      x[j] = fmax(0.0, x[j] + g / gjj);
+    }
+  }
+}
 
 // Workspace of one decomposition (all device pointers).
 struct NmfWork {

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
       for (int j = 0; j < K; ++j) nd[q][e][j] = 0.0f;
   double gv = 0.0;
   double obj = 0.0;
-  if (MODE == kModeMU && t < K * K) gd_s[t] = GD[t];
+  if ((MODE == kModeMU || MODE == kModeHALS) && t < K * K) gd_s[t] = GD[t];
   __syncthreads();
 
   const int64_t n_tiles = (n_p + kRows - 1) / kRows;
@@ -81,7 +81,28 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
           if (lane == 63) red[wave][r * K + j] = s;
         }
       __syncthreads();
-      if (t < kRows * K) {
+      if (MODE == kModeHALS) {
+        if (t < kRows) {
+          const int r = t;
+          const int64_t row = row0 + r;
+          double h[K], x[K];
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            float s = 0.0f;
+#pragma unroll
+            for (int w = 0; w < kPassThreads / 64; ++w) s += red[w][r * K + j];
+            h[j] = s;
+            x[j] = (row < n_p) ? double(V[row * K + j]) : 0.0;
+          }
+          hals_row<K>(gd_s, h, x);
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            const float vn = (row < n_p) ? float(x[j]) : 0.0f;
+            if (row < n_p) V[row * K + j] = vn;
+            vnew[r][j] = vn;
+          }
+        }
+      } else if (t < kRows * K) {
         const int r = t / K, j = t - (t / K) * K;
         const int64_t row = row0 + r;
         float s = 0.0f;
@@ -313,6 +334,13 @@ __global__ __launch_bounds__(256) void update_d_kernel(float *__restrict__ D, co
       for (int i = 0; i < K; ++i) den += dr[i] * g_s[i * K + j];
       D[k * K + j] = float(dr[j] * nd[j] / fmax(den, 1e-300));
     }
+  } else if (MODE == kModeHALS) {
+    double x[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) x[j] = D[k * K + j];
+    hals_row<K>(g_s, nd, x);
+#pragma unroll
+    for (int j = 0; j < K; ++j) D[k * K + j] = float(x[j]);
   } else {
     double x[K];
     nnls_gram_row<K>(g_s, chol, nd, x);
@@ -352,6 +380,8 @@ void launch_pass_f32_k(int mode, bool obj, int nq, int n_wg, hipStream_t st, con
   if (nq == 1) {
     if (mode == kModeMU) {
       if (obj) HSN_PASS(1, kModeMU, true); else HSN_PASS(1, kModeMU, false);
+    } else if (mode == kModeHALS) {
+      if (obj) HSN_PASS(1, kModeHALS, true); else HSN_PASS(1, kModeHALS, false);
     } else if (mode == kModeNV) {
       HSN_PASS(1, kModeNV, false);
     } else {
@@ -360,6 +390,8 @@ void launch_pass_f32_k(int mode, bool obj, int nq, int n_wg, hipStream_t st, con
   } else {
     if (mode == kModeMU) {
       if (obj) HSN_PASS(2, kModeMU, true); else HSN_PASS(2, kModeMU, false);
+    } else if (mode == kModeHALS) {
+      if (obj) HSN_PASS(2, kModeHALS, true); else HSN_PASS(2, kModeHALS, false);
     } else if (mode == kModeNV) {
       HSN_PASS(2, kModeNV, false);
     } else {
@@ -388,19 +420,21 @@ void launch_gram(int K, hipStream_t st, const float *F, int64_t n, double *G, do
   }
 }
 
-void launch_reduce_update(int K, int mode_d, bool obj, hipStream_t st, const NmfWork &w, int n_k, float *D,
+void launch_reduce_update(int K, int mode_d, bool obj, hipStream_t st, const NmfWork &w, int n_wg, int n_k, float *D,
                           double *hist_slot) {
   const dim3 grid(unsigned((int64_t(n_k) * K + 255) / 256), kSplit);
   const unsigned ub = unsigned((n_k + 255) / 256);
   switch (K) {
 #define HSN_K(KK)                                                                                             \
   case KK:                                                                                                    \
-    reduce_kernel<KK><<<grid, 256, 0, st>>>(w.part_nd, w.part_gv, w.part_obj, w.n_wg, n_k, obj ? 1 : 0,       \
+    reduce_kernel<KK><<<grid, 256, 0, st>>>(w.part_nd, w.part_gv, w.part_obj, n_wg, n_k, obj ? 1 : 0,         \
                                             w.red_nd, w.red_gv, w.red_obj);                                   \
-    finish_gv_kernel<KK><<<1, 256, 0, st>>>(w.red_gv, w.red_obj, w.gv, w.chol, mode_d == kModeMU ? 0 : 1,     \
+    finish_gv_kernel<KK><<<1, 256, 0, st>>>(w.red_gv, w.red_obj, w.gv, w.chol, mode_d == kModeNV ? 1 : 0,     \
                                             obj ? hist_slot : nullptr);                                       \
     if (mode_d == kModeMU)                                                                                    \
       update_d_kernel<KK, kModeMU><<<ub, 256, 0, st>>>(D, w.red_nd, w.gv, w.chol, n_k);                       \
+    else if (mode_d == kModeHALS)                                                                             \
+      update_d_kernel<KK, kModeHALS><<<ub, 256, 0, st>>>(D, w.red_nd, w.gv, w.chol, n_k);                     \
     else                                                                                                      \
       update_d_kernel<KK, kModeNV><<<ub, 256, 0, st>>>(D, w.red_nd, w.gv, w.chol, n_k);                       \
     break;

@@ -95,6 +95,39 @@ def test_anls_round(hsn, shape, k):
     assert abs(st["history"][0] - fh) <= 1e-5 * fh
 
 
+@pytest.mark.parametrize("shape,k", [((5760, 256), 3), ((1001, 1500), 5), ((333, 64), 8)])
+def test_hals_sweeps(hsn, shape, k):
+    # HALS (the paper's Fast HALS) as the fused pass's row rule: one sweep and
+    # five sweeps from a shared start against the oracle's column sweeps.
+    n_p, n_k = shape
+    g = np.random.Generator(np.random.PCG64(k + 40))
+    if shape == (5760, 256):
+        p = _tiny_p()
+    else:
+        p = np.maximum(g.uniform(0, 1, (n_p, k)) @ g.uniform(0, 1, (k, n_k)) + 0.1 * g.standard_normal((n_p, n_k)), 0)
+    p = _as32(p)
+    V0, D0 = synth.random_factors(n_p, n_k, k, 12)
+    V0, D0 = _as32(V0), _as32(D0)
+    show("hals", n_p=n_p, n_k=n_k, k=k)
+    V1, D1, fh1, _ = onmf.hals_step(p, V0, D0)
+    V = to_dev(V0, torch.float32)
+    D = to_dev(D0, torch.float32)
+    st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, algo=hsn.ALGO_HALS, max_iter=1, check_every=1)
+    assert rel_fro(V.cpu().numpy(), V1) <= 1e-5
+    assert rel_fro(D.cpu().numpy(), D1) <= 1e-5
+    assert abs(st["history"][0] - fh1) <= 1e-5 * fh1
+    Vr, Dr = V0, D0
+    fhs = []
+    for _ in range(5):
+        Vr, Dr, fh, _ = onmf.hals_step(p, Vr, Dr)
+        fhs.append(fh)
+    V = to_dev(V0, torch.float32)
+    D = to_dev(D0, torch.float32)
+    st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, algo=hsn.ALGO_HALS, max_iter=5, check_every=1)
+    np.testing.assert_allclose(st["history"], fhs, rtol=1e-5)
+    assert rel_fro(V.cpu().numpy() @ D.cpu().numpy().T, Vr @ Dr.T) <= 1e-5
+
+
 def test_polish_after_mu_reaches_reference(hsn):
     # MU bulk then ANLS polish on the float32 p: the objective decreases
     # monotonically and reaches the oracle's stationary value.
