@@ -102,13 +102,14 @@ enum { HSN_INIT_USER = 0 };/* V and D hold the start on entry             */
 
 typedef struct {
   int k;              /* K = N_s, 1..8 */
-  int algo;           /* HSN_ALGO_* for the bulk iterations (bf16 bulk: MU or HALS) */
+  int algo;           /* HSN_ALGO_* for the bulk iterations */
   int precision;      /* HSN_PREC_* for the bulk iterations */
   int init;           /* HSN_INIT_* */
   int max_iter;       /* bulk iterations, >= 0 */
   int check_every;    /* objective evaluated every this many iterations (>= 1) */
   int polish_rounds;  /* rounds on the float32 p after the bulk (>= 0) */
   int polish_algo;    /* HSN_ALGO_ANLS or HSN_ALGO_HALS for the polish rounds */
+  int polish_bf16_rounds; /* the first this many polish rounds run on p_bf16 (needs p_bf16) */
   double rel_obj_tol; /* stop when (f - f_ref)/f_ref <= tol; ignored if f_ref <= 0 */
   double f_ref;       /* reference objective f* (> 0 enables the stop test) */
 } hsn_nmf_opts;
@@ -199,11 +200,12 @@ hsn_status hsn_rehydrate(hsn_ctx *ctx, const float *xs, const float *D, int64_t 
 /* ------------------------------------------------------------------ */
 
 enum {
-  HSN_KERN_NMF_PASS = 0,    /* every streaming pass over p inside hsn_subspace_nmf */
+  HSN_KERN_NMF_PASS = 0,    /* float32 streaming passes over p inside hsn_subspace_nmf */
   HSN_KERN_PROJECT = 1,     /* the forward projector kernel */
   HSN_KERN_BACKPROJECT = 2, /* the adjoint projector kernel */
   HSN_KERN_NORMALIZE = 3,   /* the normalisation stream kernel */
-  HSN_KERN_COUNT = 4
+  HSN_KERN_NMF_PASS_BF16 = 4, /* bfloat16 (MFMA) streaming passes over p */
+  HSN_KERN_COUNT = 5
 };
 
 /* When on != 0, every launch of the kernels above is bracketed by a pair of

@@ -30,7 +30,7 @@ struct hsn_ctx {
   // Optional kernel timing: event pairs per kernel kind.
   bool prof = false;
   std::vector<hipEvent_t> prof_ev[HSN_KERN_COUNT];
-  size_t prof_used[HSN_KERN_COUNT] = {0, 0, 0, 0};
+  size_t prof_used[HSN_KERN_COUNT] = {};
 };
 
 namespace hsn {

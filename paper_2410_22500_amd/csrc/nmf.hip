@@ -1,39 +1,50 @@
 // hsn_subspace_nmf: the NMF of eq. (4), (V, D) = argmin_{V,D>=0} ||p - V D^T||^2.
 //
 // Every iteration is a short fixed sequence of launches on the caller's
-// stream, with no host synchronisation except when an objective value is
-// read for the stop test:
-//   multiplicative updates (Lee-Seung; V first, then D with the new V):
-//     gram(D) -> fused pass [N_V = P D, V update, N_D += P^T V_new,
-//     G_V += V_new^T V_new, optional ||P - V_new D^T||^2] -> reduce -> D update
+// stream:
+//   MU / HALS iteration (V first, then D with the new V):
+//     fused pass [N_V = P D, row rule for V, N_D += P^T V_new, G_V, optional
+//     ||P - V_new D^T||^2]  ->  update_d [reductions, D row rule, G_D of D_new]
 //   ANLS round (exact row-wise non-negative least squares, V then D):
-//     gram(D)+factors -> pass N_V -> row solves -> pass N_D (+objective)
-//     -> reduce -> G_V factors -> row solves of D
-// The float32 pass reads p once per MU iteration.  The bfloat16 bulk runs the
-// same sequence with the MFMA pass over the bfloat16 copy of p.
+//     pass N_V -> row solves of V (all rows in parallel, FP64 Cholesky factors
+//     of G_D's principal submatrices) -> pass N_D (+objective) -> update_d
+//     (row solves of D)
+// The stop test runs on the device (update_d lowers stop_at), so the host
+// queues iterations in chunks and reads the control block once per chunk.
+// The float32 pass reads p once per MU/HALS iteration; the bfloat16 bulk runs
+// the same sequence with the MFMA pass over the bfloat16 copy of p.
 #include "nmf_common.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <vector>
 
 namespace hsn {
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
-                     int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, float *part_nd,
-                     double *part_gv, double *part_obj);
-void launch_gram(int K, hipStream_t st, const float *F, int64_t n, double *G, double *chol, int want_chol);
-void launch_reduce_update(int K, int mode_d, bool obj, hipStream_t st, const NmfWork &w, int n_wg, int n_k, float *D,
-                          double *hist_slot);
-void launch_nnls_rows(int K, hipStream_t st, const float *NV, const double *GD, const double *chol, float *V,
-                      int64_t n_p, int n_blocks);
-// bfloat16 MFMA pass (nmf_bf16.hip); returns false if the shape is unsupported.
+                     int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
+                     float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter);
 bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
-                      int64_t n_p, int n_k, float *V, const float *D, const double *GD, uint4 *scratch,
-                      float *part_nd, double *part_gv, double *part_obj);
+                      int64_t n_p, int n_k, float *V, const double *GD, const double *chol, const uint16_t *img,
+                      float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter);
 int pass_bf16_wgs(hsn_ctx *ctx, int64_t n_p);
-size_t bf16_scratch_bytes(int64_t ldb);
+size_t bf16_image_elems(int64_t ldb);
+int64_t bf16_image_ldb(int64_t ldb);
+void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWork &w, int want_chol, int64_t ldb);
+int update_d_blocks(int n_k);
+void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
+                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img);
+void launch_nnls_rows(int K, hipStream_t st, const NmfWork &w, float *V, int64_t n_p, int n_blocks, int iter);
 
 namespace {
+
+// One step of the schedule, in issue order.
+struct Step {
+  int rule;     // kModeMU, kModeHALS or kModeANLS (exact row-wise NNLS for V, then for D)
+  bool bf16;    // pass over the bfloat16 copy of p
+  bool obj;     // objective evaluated (and stop test applied)
+};
 
 struct Run {
   hsn_ctx *ctx;
@@ -42,54 +53,48 @@ struct Run {
   int64_t n_p;
   int n_k;
   NmfWork w;
-  int hist_len = 0;
   int wg_f32 = 0, wg_bf16 = 0;  // persistent grid sizes of the two passes
-  uint4 *bf16_scratch = nullptr;
+  double f_ref = 0.0, tol = 0.0;
 };
 
-// One fused iteration (MU or HALS row rule): a single streaming read of p.
-hsn_status fused_iteration(Run &R, int mode, bool bf16, const float *p, int64_t ldp, const uint16_t *pb, int64_t ldb,
-                           float *V, float *D, bool obj) {
-  launch_gram(R.K, R.st, D, R.n_k, R.w.gd, R.w.chol, 0);
-  const int n_wg = bf16 ? R.wg_bf16 : R.wg_f32;
-  prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  if (bf16) {
-    if (!launch_pass_bf16(R.K, mode, obj, n_wg, R.st, pb, ldb, R.n_p, R.n_k, V, D, R.w.gd, R.bf16_scratch,
-                          R.w.part_nd, R.w.part_gv, R.w.part_obj))
-      return fail(R.ctx, HSN_ERR_UNSUPPORTED, "bf16 pass: unsupported shape (ldb <= 2048, k <= 8)");
-  } else {
-    launch_pass_f32(R.K, mode, obj, R.n_k > 1024 ? 2 : 1, n_wg, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd,
-                    R.w.part_nd, R.w.part_gv, R.w.part_obj);
-  }
-  prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  launch_reduce_update(R.K, mode, obj, R.st, R.w, n_wg, R.n_k, D, obj ? R.w.hist + R.hist_len : nullptr);
-  if (obj) ++R.hist_len;
-  HSN_LAUNCHED(R.ctx);
-  return HSN_OK;
-}
-
-hsn_status anls_round(Run &R, const float *p, int64_t ldp, float *V, float *D) {
+// Queue iteration `iter`.  MU / HALS: one streaming pass over p (row rule for
+// V, N_D and G_V partials, optional objective) and the D update.  ANLS: a pass
+// for N_V = P D, the exact row solves of V on all rows in parallel, a pass
+// for N_D = P^T V_new (+ objective), and the exact row solves of D.
+// next_exact: the following step solves V rows exactly (the update then also
+// factors G_D).
+hsn_status queue_step(Run &R, const Step &s, int iter, bool next_exact, const float *p, int64_t ldp,
+                      const uint16_t *pb, int64_t ldb, float *V, float *D) {
   const int nq = R.n_k > 1024 ? 2 : 1;
-  launch_gram(R.K, R.st, D, R.n_k, R.w.gd, R.w.chol, 1);
-  prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  launch_pass_f32(R.K, kModeNV, false, nq, R.wg_f32, R.st, p, ldp, R.n_p, R.n_k, V, R.w.nv, D, R.w.gd, R.w.part_nd,
-                  R.w.part_gv, R.w.part_obj);
-  prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  const int nb = int(std::min<int64_t>((R.n_p + 255) / 256, 8 * int64_t(R.ctx->num_cu)));
-  launch_nnls_rows(R.K, R.st, R.w.nv, R.w.gd, R.w.chol, V, R.n_p, nb);
-  prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  launch_pass_f32(R.K, kModeND, true, nq, R.wg_f32, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd, R.w.part_nd,
-                  R.w.part_gv, R.w.part_obj);
-  prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
-  launch_reduce_update(R.K, kModeNV, true, R.st, R.w, R.wg_f32, R.n_k, D, R.w.hist + R.hist_len);
-  ++R.hist_len;
+  const int n_wg = s.bf16 ? R.wg_bf16 : R.wg_f32;
+  const bool obj = s.obj || s.rule == kModeANLS;
+  if (s.rule == kModeANLS) {
+    prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
+    launch_pass_f32(R.K, kModeNV, false, nq, n_wg, R.st, p, ldp, R.n_p, R.n_k, V, R.w.nv, D, R.w.gd, R.w.chol,
+                    R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter);
+    prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
+    const int nb = int(std::min<int64_t>((R.n_p + 255) / 256, 8 * int64_t(R.ctx->num_cu)));
+    launch_nnls_rows(R.K, R.st, R.w, V, R.n_p, nb, iter);
+    prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
+    launch_pass_f32(R.K, kModeND, true, nq, n_wg, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd, R.w.chol,
+                    R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter);
+    prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
+  } else {
+    prof_begin(R.ctx, s.bf16 ? HSN_KERN_NMF_PASS_BF16 : HSN_KERN_NMF_PASS, R.st);
+    if (s.bf16) {
+      const bool ok = launch_pass_bf16(R.K, s.rule, obj, n_wg, R.st, pb, ldb, R.n_p, R.n_k, V, R.w.gd, R.w.chol,
+                                       R.w.img, R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter);
+      prof_end(R.ctx, HSN_KERN_NMF_PASS_BF16, R.st);
+      if (!ok) return fail(R.ctx, HSN_ERR_UNSUPPORTED, "bf16 pass: unsupported shape (ldb <= 2048, k <= 8)");
+    } else {
+      launch_pass_f32(R.K, s.rule, obj, nq, n_wg, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd, R.w.chol,
+                      R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter);
+      prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
+    }
+  }
+  launch_update_d(R.K, s.rule == kModeANLS ? kModeNV : s.rule, R.st, D, R.w, n_wg, R.n_k, iter, obj, R.f_ref,
+                  R.tol, next_exact, R.w.img ? bf16_image_ldb(ldb) : 0);
   HSN_LAUNCHED(R.ctx);
-  return HSN_OK;
-}
-
-hsn_status read_last(Run &R, double *out) {
-  HSN_HIP(R.ctx, hipMemcpyAsync(out, R.w.hist + (R.hist_len - 1), sizeof(double), hipMemcpyDeviceToHost, R.st));
-  HSN_HIP(R.ctx, hipStreamSynchronize(R.st));
   return HSN_OK;
 }
 
@@ -115,15 +120,18 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: max_iter >= 0, check_every >= 1, polish_rounds >= 0 required");
   if (!V || !D) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: V and D are required");
   const bool bf16 = o->precision == HSN_PREC_BF16;
-  if (bf16 && o->algo == HSN_ALGO_ANLS)
-    return fail(ctx, HSN_ERR_UNSUPPORTED, "nmf: the bfloat16 bulk runs MU or HALS");
-  const bool need_f32 = (!bf16 && o->max_iter > 0) || o->polish_rounds > 0;
+  if (o->polish_bf16_rounds < 0) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: polish_bf16_rounds must be >= 0");
+  if (bf16 && o->algo == HSN_ALGO_ANLS && o->max_iter > 0)
+    return fail(ctx, HSN_ERR_UNSUPPORTED, "nmf: ANLS rounds run on the float32 p (bulk precision FP32)");
+  // bfloat16 polish rounds exist for HALS only (ANLS rounds read the float32 p).
+  const int pol_bf16 = (o->polish_algo == HSN_ALGO_HALS) ? std::min(o->polish_bf16_rounds, o->polish_rounds) : 0;
+  const bool need_f32 = (!bf16 && o->max_iter > 0) || o->polish_rounds > pol_bf16;
   if (need_f32) {
     if (!p) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: float32 p is required");
     if (ldp < n_k || ldp % 4 != 0 || reinterpret_cast<uintptr_t>(p) % 16 != 0)
       return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: ldp must be >= n_k and a multiple of 4, p 16-byte aligned");
   }
-  if (bf16 && o->max_iter > 0) {
+  if ((bf16 && o->max_iter > 0) || pol_bf16 > 0) {
     if (!p_bf16) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: p_bf16 is required for the bfloat16 bulk");
     if (ldb < n_k || ldb % 32 != 0 || reinterpret_cast<uintptr_t>(p_bf16) % 16 != 0)
       return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: ldb must be >= n_k and a multiple of 32, p_bf16 16-byte aligned");
@@ -136,86 +144,97 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   const int K = o->k;
   const int64_t n_tiles = (n_p + 7) / 8;
   const int wg_f32 = int(std::min<int64_t>(n_tiles, 2 * int64_t(ctx->num_cu)));
-  const int wg_bf16 = bf16 ? pass_bf16_wgs(ctx, n_p) : 0;
+  const bool any_bf16 = (bf16 && o->max_iter > 0) || pol_bf16 > 0;
+  const int wg_bf16 = any_bf16 ? pass_bf16_wgs(ctx, n_p) : 0;
   const int n_wg = std::max(wg_f32, wg_bf16);
   const int hist_cap = o->max_iter + o->polish_rounds + 2;
   const bool need_nv = o->algo == HSN_ALGO_ANLS || (o->polish_rounds > 0 && o->polish_algo == HSN_ALGO_ANLS);
-  const size_t need = Carver::need({sizeof(double) * 64, sizeof(double) * 64, sizeof(double) * 256 * kCholStride,
+  const int n_upd = update_d_blocks(int(n_k));
+  const size_t need = Carver::need({sizeof(NmfCtrl), sizeof(double) * 64, sizeof(double) * 256 * kCholStride,
                                     sizeof(float) * size_t(n_wg) * n_k * K, sizeof(double) * size_t(n_wg) * K * K,
-                                    sizeof(double) * n_wg, sizeof(double) * kSplit * size_t(n_k) * K,
-                                    sizeof(double) * kSplit * K * K, sizeof(double) * kSplit,
-                                    need_nv ? sizeof(float) * n_p * K : 0,
-                                    sizeof(double) * hist_cap, bf16 ? bf16_scratch_bytes(ldb) : 0});
+                                    sizeof(double) * n_wg, sizeof(double) * size_t(n_upd) * K * K,
+                                    need_nv ? sizeof(float) * n_p * K : 0, sizeof(double) * hist_cap,
+                                    any_bf16 ? sizeof(uint16_t) * bf16_image_elems(ldb) : 0});
   hsn_status rc = ensure_ws(ctx, need);
   if (rc != HSN_OK) return rc;
   Carver cv(ctx->ws);
   Run R{ctx, st, K, n_p, int(n_k), {}};
+  R.w.ctrl = cv.take<NmfCtrl>(1);
   R.w.gd = cv.take<double>(64);
-  R.w.gv = cv.take<double>(64);
   R.w.chol = cv.take<double>(256 * kCholStride);
   R.w.part_nd = cv.take<float>(size_t(n_wg) * n_k * K);
   R.w.part_gv = cv.take<double>(size_t(n_wg) * K * K);
   R.w.part_obj = cv.take<double>(n_wg);
-  R.w.red_nd = cv.take<double>(kSplit * size_t(n_k) * K);
-  R.w.red_gv = cv.take<double>(kSplit * K * K);
-  R.w.red_obj = cv.take<double>(kSplit);
+  R.w.part_gd = cv.take<double>(size_t(n_upd) * K * K);
   R.w.nv = need_nv ? cv.take<float>(n_p * K) : nullptr;
   R.w.hist = cv.take<double>(hist_cap);
+  R.w.img = any_bf16 ? cv.take<uint16_t>(bf16_image_elems(ldb)) : nullptr;
   R.w.n_wg = n_wg;
   R.wg_f32 = wg_f32;
   R.wg_bf16 = wg_bf16;
-  if (bf16) R.bf16_scratch = cv.take<uint4>(bf16_scratch_bytes(ldb) / sizeof(uint4));
+  const bool stop_test = o->f_ref > 0.0;
+  R.f_ref = stop_test ? o->f_ref : 0.0;
+  R.tol = o->rel_obj_tol;
+
+  // The schedule: bulk iterations, then polish rounds (global indices 0..n-1).
+  std::vector<Step> steps;
+  steps.reserve(size_t(o->max_iter) + o->polish_rounds);
+  for (int it = 0; it < o->max_iter; ++it) {
+    const bool obj = ((it + 1) % o->check_every == 0) || (it + 1 == o->max_iter);
+    const int rule = o->algo == HSN_ALGO_MU ? kModeMU : (o->algo == HSN_ALGO_HALS ? kModeHALS : kModeANLS);
+    steps.push_back({rule, bf16 && rule != kModeANLS, obj});
+  }
+  for (int r = 0; r < o->polish_rounds; ++r) {
+    const int rule = o->polish_algo == HSN_ALGO_ANLS ? kModeANLS : kModeHALS;
+    steps.push_back({rule, r < pol_bf16 && rule != kModeANLS, true});
+  }
 
   if (stats) HSN_HIP(ctx, hipEventRecord(ctx->ev0, st));
-  const bool stop_test = o->f_ref > 0.0;
-  double last = NAN;
-  int it = 0;
-  bool reached = false;
-  for (; it < o->max_iter && !reached; ++it) {
-    const bool obj = ((it + 1) % o->check_every == 0) || (it + 1 == o->max_iter);
-    if (o->algo == HSN_ALGO_ANLS)
-      rc = anls_round(R, p, ldp, V, D);
-    else
-      rc = fused_iteration(R, o->algo == HSN_ALGO_MU ? kModeMU : kModeHALS, bf16, p, ldp, p_bf16, ldb, V, D, obj);
-    if (rc != HSN_OK) return rc;
-    if (obj && stop_test) {
-      if ((rc = read_last(R, &last)) != HSN_OK) return rc;
-      if ((last - o->f_ref) / o->f_ref <= o->rel_obj_tol) reached = true;
+  launch_nmf_init(K, st, D, int(n_k), R.w, !steps.empty() && steps[0].rule == kModeANLS ? 1 : 0,
+                  any_bf16 ? bf16_image_ldb(ldb) : 0);
+  HSN_LAUNCHED(ctx);
+  // Queue in chunks; between chunks read stop_at once (only when a stop test is on).
+  const int chunk = 32;
+  int issued = 0;
+  NmfCtrl hc{};
+  hc.stop_at = INT32_MAX;
+  while (issued < int(steps.size())) {
+    const int end = std::min<int>(int(steps.size()), issued + chunk);
+    for (int i = issued; i < end; ++i) {
+      const bool next_exact = (i + 1 < int(steps.size())) && steps[i + 1].rule == kModeANLS;
+      if ((rc = queue_step(R, steps[i], i, next_exact, p, ldp, p_bf16, ldb, V, D)) != HSN_OK) return rc;
     }
-  }
-  int polished = 0;
-  for (; polished < o->polish_rounds; ++polished) {
-    rc = (o->polish_algo == HSN_ALGO_ANLS) ? anls_round(R, p, ldp, V, D)
-                                           : fused_iteration(R, kModeHALS, false, p, ldp, nullptr, 0, V, D, true);
-    if (rc != HSN_OK) return rc;
-    if (stop_test) {
-      if ((rc = read_last(R, &last)) != HSN_OK) return rc;
-      if ((last - o->f_ref) / o->f_ref <= o->rel_obj_tol) {
-        ++polished;
-        break;
-      }
+    issued = end;
+    if (stop_test && issued < int(steps.size())) {
+      HSN_HIP(ctx, hipMemcpyAsync(&hc, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
+      HSN_HIP(ctx, hipStreamSynchronize(st));
+      if (hc.stop_at <= issued) break;
     }
   }
   if (stats) {
     HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
+    HSN_HIP(ctx, hipMemcpyAsync(&hc, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
     HSN_HIP(ctx, hipEventSynchronize(ctx->ev1));
+    HSN_HIP(ctx, hipStreamSynchronize(st));
     float ms = 0.f;
     HSN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    const int done = std::min(hc.stop_at, issued);
     stats->ms = ms;
-    stats->iters = it;
-    stats->polish_done = polished;
+    stats->iters = std::min(done, o->max_iter);
+    stats->polish_done = std::max(0, done - o->max_iter);
     stats->history_len = 0;
-    if (R.hist_len > 0) {
-      std::vector<double> h(R.hist_len);
-      HSN_HIP(ctx, hipMemcpy(h.data(), R.w.hist, sizeof(double) * R.hist_len, hipMemcpyDeviceToHost));
+    double last = NAN;
+    if (hc.hist_len > 0) {
+      std::vector<double> h(hc.hist_len);
+      HSN_HIP(ctx, hipMemcpy(h.data(), R.w.hist, sizeof(double) * hc.hist_len, hipMemcpyDeviceToHost));
       last = h.back();
-      const int n_copy = std::min(R.hist_len, stats->history_cap);
+      const int n_copy = std::min(hc.hist_len, stats->history_cap);
       for (int i = 0; i < n_copy; ++i) stats->history[i] = h[i];
       stats->history_len = n_copy;
     }
     stats->objective = last;
     stats->rel_obj = stop_test ? (last - o->f_ref) / o->f_ref : NAN;
-    if (std::isnan(last) && R.hist_len > 0) return fail(ctx, HSN_ERR_NUMERIC, "nmf: objective is NaN");
+    if (hc.hist_len > 0 && std::isnan(last)) return fail(ctx, HSN_ERR_NUMERIC, "nmf: objective is NaN");
   }
   return HSN_OK;
 }

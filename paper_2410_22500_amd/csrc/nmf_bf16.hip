@@ -5,7 +5,7 @@
 // Wave w owns a contiguous range of 32-bin k-steps for the whole pass.  Per
 // tile:
 //   1. the wave writes its bins of the 16 rows (loaded coalesced, 1 KB per
-//      instruction, prefetched one tile ahead) into a row-major LDS tile;
+//      instruction, prefetched two tiles ahead) into a row-major LDS tile;
 //   2. N_V = P D on MFMA 16x16x32: A = 16 rows x 32 bins from LDS, B = D split
 //      into bfloat16 hi/lo halves packed as 16 columns [D_hi | D_lo], so one
 //      instruction gives both products and N_V = C[:, j] + C[:, 8 + j];
@@ -30,12 +30,21 @@ constexpr int kBThreads = 512;
 constexpr int kBWaves = kBThreads / 64;
 constexpr int kBRows = 16;
 constexpr int kMaxLdb = 2048;
-constexpr int kKSW = kMaxLdb / 32 / kBWaves;  // max k-steps per wave
+// Every wave owns exactly NW k-steps of 32 bins (NW = 1, 2, 4 or 8), so the
+// row of the LDS tile and the operand images are padded to 256 NW bins; bins
+// at or beyond ldb load as zeros.  The load code is branch-free (clamped
+// address + select) so the compiler can count outstanding loads exactly and
+// the prefetched tiles stay in flight across the tile's compute.  With NW <= 4
+// the registers left over hold a second tile of loads in flight (NBUF = 2).
+__host__ __device__ inline int64_t bf16_ldb_pad(int64_t ldb) {
+  const int64_t nw = (ldb + 255) / 256;
+  return 256 * (nw <= 1 ? 1 : nw <= 2 ? 2 : nw <= 4 ? 4 : 8);
+}
 
-__host__ __device__ inline int bf16_pitch(int64_t ldb) { return int(2 * ldb + 8); }
+__host__ __device__ inline int bf16_pitch(int64_t ldb) { return int(2 * bf16_ldb_pad(ldb) + 8); }
 
 struct Bf16Lds {
-  int tile, db1, red, vsp, vnw, gd, obj, total;
+  int tile, db1, red, vsp, vnw, vold, gd, obj, total;
 };
 
 __host__ __device__ inline Bf16Lds bf16_lds_layout(int64_t ldb, int K) {
@@ -45,12 +54,14 @@ __host__ __device__ inline Bf16Lds bf16_lds_layout(int64_t ldb, int K) {
   o += kBRows * bf16_pitch(ldb);
   o = (o + 15) & ~15;
   L.db1 = o;
-  o += int(ldb / 32) * 64 * 16;
+  o += int(bf16_ldb_pad(ldb) / 32) * 64 * 16;
   L.red = o;
   o += kBWaves * 16 * 16 * 4;
   L.vsp = o;
   o += 16 * 16 * 2;
   L.vnw = o;
+  o += 16 * 8 * 4;
+  L.vold = o;
   o += 16 * 8 * 4;
   L.gd = o;
   o += 64 * 8;
@@ -61,52 +72,18 @@ __host__ __device__ inline Bf16Lds bf16_lds_layout(int64_t ldb, int K) {
   return L;
 }
 
-__device__ __forceinline__ uint16_t bf_hi(float f) { return f32_to_bf16_bits(f); }
-__device__ __forceinline__ uint16_t bf_lo(float f) { return f32_to_bf16_bits(f - bf16_bits_to_f32(f32_to_bf16_bits(f))); }
-
-// Operand images of D for one pass.
-//   db1[s][lane]: GEMM1 B operand of k-step s: column n = lane % 16, bins
-//                 32 s + 8 (lane / 16) + e; n < 8 -> hi(D[k][n]), else lo(D[k][n-8]).
-//   db3[b][lane]: reconstruction B operand of bin block b: bin 16 b + lane % 16,
-//                 contraction group g = lane / 16: g 0,1 -> hi(D[bin][e]), g 2 -> lo, g 3 -> 0.
-__global__ void bf16_prep_kernel(const float *__restrict__ D, int n_k, int K, int64_t ldb, uint4 *__restrict__ db1,
-                                 uint4 *__restrict__ db3) {
-  const int64_t nks = ldb / 32, nbb = ldb / 16;
-  const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int lane = int(id & 63);
-  uint16_t v[8];
-  if (id < nks * 64) {
-    const int64_t s = id >> 6;
-    const int n = lane & 15, j = n & 7;
-    for (int e = 0; e < 8; ++e) {
-      const int64_t k = 32 * s + 8 * (lane >> 4) + e;
-      const float d = (j < K && k < n_k) ? D[k * K + j] : 0.0f;
-      v[e] = (n < 8) ? bf_hi(d) : bf_lo(d);
-    }
-    db1[id] = make_uint4(v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
-                         v[6] | (uint32_t(v[7]) << 16));
-  } else if (id < nks * 64 + nbb * 64) {
-    const int64_t b = (id - nks * 64) >> 6;
-    const int64_t bin = 16 * b + (lane & 15);
-    const int g = lane >> 4;
-    for (int e = 0; e < 8; ++e) {
-      const float d = (e < K && bin < n_k) ? D[bin * K + e] : 0.0f;
-      v[e] = (g == 3) ? 0 : (g == 2 ? bf_lo(d) : bf_hi(d));
-    }
-    db3[id - nks * 64] = make_uint4(v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16),
-                                    v[4] | (uint32_t(v[5]) << 16), v[6] | (uint32_t(v[7]) << 16));
-  }
-}
-
-template <int K, int MODE, bool OBJ>
+template <int K, int MODE, bool OBJ, int NW, int NBUF>
 __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__restrict__ Pb, int64_t ldb,
                                                               int64_t n_p, int n_k, float *__restrict__ V,
                                                               const uint4 *__restrict__ db1g,
                                                               const uint4 *__restrict__ db3g,
                                                               const double *__restrict__ GD,
+                                                              const double *__restrict__ chol,
                                                               float *__restrict__ part_nd,
                                                               double *__restrict__ part_gv,
-                                                              double *__restrict__ part_obj) {
+                                                              double *__restrict__ part_obj,
+                                                              const NmfCtrl *__restrict__ ctrl, int iter) {
+  if (iter >= ctrl->stop_at) return;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const Bf16Lds L = bf16_lds_layout(ldb, K);
   char *tileL = smem + L.tile;
@@ -114,14 +91,17 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
   float *red = reinterpret_cast<float *>(smem + L.red);        // [8][16][16]
   uint16_t *vsp = reinterpret_cast<uint16_t *>(smem + L.vsp);  // [16][16]  [V_hi | V_lo]
   float *vnw = reinterpret_cast<float *>(smem + L.vnw);        // [16][8]
+  float *vold = reinterpret_cast<float *>(smem + L.vold);      // [16][K] V of the tile before the update
   double *gd_s = reinterpret_cast<double *>(smem + L.gd);
   double *obj_s = reinterpret_cast<double *>(smem + L.obj);
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  constexpr int kKSW = NW;
+  constexpr int nw = NW;
   const int pitch = bf16_pitch(ldb);
-  const int nks = int(ldb / 32);
-  const int s0 = (w * nks) / kBWaves, s1 = ((w + 1) * nks) / kBWaves, nw = s1 - s0;
-  const int cpr = 4 * nw;  // 16-byte chunks per row in this wave's bins
+  const int nks = kBWaves * NW;  // k-steps of the padded row
+  const int s0 = w * NW;
+  constexpr int cpr = 4 * NW;   // 16-byte chunks per row in this wave's bins
 
   for (int i = t; i < nks * 64; i += kBThreads) db1L[i] = db1g[i];
   for (int i = t; i < 16 * 16; i += kBThreads) vsp[i] = 0;
@@ -132,26 +112,36 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
   for (int b = 0; b < 2 * kKSW; ++b) acc2[b] = f32x4{0.f, 0.f, 0.f, 0.f};
   double gv = 0.0, obj = 0.0;
 
-  uint4 pr[kKSW];
-  auto load_tile = [&](int64_t row0) {
+  uint4 prA[kKSW], prB[kKSW];
+  float vA = 0.0f, vB = 0.0f;  // the tile's V values (thread t < 16 K holds one)
+  // Tile loads go through buffer descriptors covering the tile's valid rows:
+  // rows past n_p and bins past ldb (offset pushed out of range) read as 0
+  // without a branch, so the loads stay unconditional and in flight.
+  auto load_tile = [&](uint4 (&pr)[kKSW], float &vv, int64_t row0) {
+    const int64_t rows = (n_p - row0) < kBRows ? (n_p - row0) : kBRows;
+    const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(V) + row0 * K, 0, int(rows * K * 4), 0x00020000);
+    vv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, t < kBRows * K ? 4 * t : 0x7FFFFFF0, 0, 0));
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint16_t *>(Pb) + row0 * ldb, 0, int(rows * ldb * 2), 0x00020000);
 #pragma unroll
     for (int i = 0; i < kKSW; ++i) {
-      if (i < nw) {
-        const int c = lane + 64 * i;
-        const int r = c / cpr, cc = c - (c / cpr) * cpr;
-        const int64_t row = row0 + r;
-        pr[i] = (row < n_p) ? *reinterpret_cast<const uint4 *>(Pb + row * ldb + 32 * s0 + 8 * cc)
-                            : make_uint4(0u, 0u, 0u, 0u);
-      }
+      const int c = lane + 64 * i;
+      const int r = c / cpr, cc = c % cpr;
+      const int col = 32 * s0 + 8 * cc;
+      const int off = (col < ldb) ? int(r * ldb + col) * 2 : 0x7FFFFFF0;
+      pr[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rp, off, 0, 0));
     }
   };
 
+  // NBUF register buffers keep NBUF tiles of loads in flight per wave.
   const int64_t n_tiles = (n_p + kBRows - 1) / kBRows;
-  int64_t tile = blockIdx.x;
-  if (tile < n_tiles) load_tile(tile * kBRows);
+  const int64_t G = gridDim.x;
+  if (int64_t(blockIdx.x) < n_tiles) load_tile(prA, vA, int64_t(blockIdx.x) * kBRows);
+  if (NBUF == 2 && int64_t(blockIdx.x) + G < n_tiles) load_tile(prB, vB, (int64_t(blockIdx.x) + G) * kBRows);
   __syncthreads();
 
-  for (; tile < n_tiles; tile += gridDim.x) {
+  auto do_tile = [&](uint4 (&pr)[kKSW], float &vv, int64_t tile) {
     const int64_t row0 = tile * kBRows;
     // 1. this wave's bins of the tile -> LDS (8-byte stores: the padded pitch
     //    keeps the transposed reads below free of bank conflicts)
@@ -165,8 +155,9 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
         dst[1] = make_uint2(pr[i].z, pr[i].w);
       }
     }
-    // prefetch the next tile into the same registers
-    if (tile + gridDim.x < n_tiles) load_tile((tile + gridDim.x) * kBRows);
+    if (t < kBRows * K) vold[t] = vv;
+    // prefetch the tile NBUF steps ahead into the same registers
+    if (tile + NBUF * G < n_tiles) load_tile(pr, vv, (tile + NBUF * G) * kBRows);
     __syncthreads();
 
     // 2. N_V partial over this wave's bins
@@ -188,7 +179,7 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
     __syncthreads();
 
     // 3. row rule
-    if (MODE == kModeHALS) {
+    if (MODE == kModeHALS || MODE == kModeANLS) {
       if (t < kBRows) {
         const int r = t;
         const int64_t row = row0 + r;
@@ -199,9 +190,12 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
 #pragma unroll
           for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + r) * 16 + j] + red[(ww * 16 + r) * 16 + 8 + j];
           h[j] = s;
-          x[j] = (row < n_p) ? double(V[row * K + j]) : 0.0;
+          x[j] = (row < n_p) ? double(vold[r * K + j]) : 0.0;
         }
-        hals_row<K>(gd_s, h, x);
+        if (MODE == kModeHALS)
+          hals_row<K>(gd_s, h, x);
+        else
+          nnls_gram_row<K>(gd_s, chol, h, x);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const float vn = (row < n_p) ? float(x[j]) : 0.0f;
@@ -221,7 +215,7 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
       if (row < n_p) {
         float vr[K];
 #pragma unroll
-        for (int i = 0; i < K; ++i) vr[i] = V[row * K + i];
+        for (int i = 0; i < K; ++i) vr[i] = vold[r * K + i];
         double den = 0.0;
 #pragma unroll
         for (int i = 0; i < K; ++i) den += double(vr[i]) * gd_s[i * K + j];
@@ -280,6 +274,14 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
       }
     }
     if (OBJ) obj += double(objf);
+  };
+  if (NBUF == 2) {
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += 2 * G) {
+      do_tile(prA, vA, tile);
+      if (tile + G < n_tiles) do_tile(prB, vB, tile + G);
+    }
+  } else {
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += G) do_tile(prA, vA, tile);
   }
 
   // Partials: N_D[bin][j] = C[bin][j] + C[bin][8 + j] (lanes n and n + 8).
@@ -313,51 +315,71 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
   }
 }
 
-template <int K, int MODE, bool OBJ>
+template <int K, int MODE, bool OBJ, int NW, int NBUF>
 static bool launch_bf16_inst(int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p, int n_k,
-                             float *V, const uint4 *db1, const uint4 *db3, const double *GD, float *part_nd,
-                             double *part_gv, double *part_obj) {
+                             float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
+                             float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
   const int lds = bf16_lds_layout(ldb, K).total;
   static bool attr_set = false;
   if (!attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&pass_bf16_kernel<K, MODE, OBJ>),
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&pass_bf16_kernel<K, MODE, OBJ, NW, NBUF>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
       return false;
     attr_set = true;
   }
-  pass_bf16_kernel<K, MODE, OBJ><<<n_wg, kBThreads, lds, st>>>(Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
-                                                                part_obj);
+  pass_bf16_kernel<K, MODE, OBJ, NW, NBUF><<<n_wg, kBThreads, lds, st>>>(Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd,
+                                                                part_gv, part_obj, ctrl, iter);
   return true;
+}
+
+template <int K, int NW, int NBUF>
+static bool launch_bf16_kw(int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p,
+                           int n_k, float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
+                           float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
+#define HSN_INST(M_, O_) \
+  launch_bf16_inst<K, M_, O_, NW, NBUF>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd, part_gv, part_obj, \
+                                        ctrl, iter)
+  if (mode == kModeMU) return obj ? HSN_INST(kModeMU, true) : HSN_INST(kModeMU, false);
+  if (mode == kModeHALS) return obj ? HSN_INST(kModeHALS, true) : HSN_INST(kModeHALS, false);
+  return false;
+#undef HSN_INST
 }
 
 template <int K>
 static bool launch_bf16_k(int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p,
-                          int n_k, float *V, const uint4 *db1, const uint4 *db3, const double *GD, float *part_nd,
-                          double *part_gv, double *part_obj) {
-  if (mode == kModeMU)
-    return obj ? launch_bf16_inst<K, kModeMU, true>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
-                                                    part_obj)
-               : launch_bf16_inst<K, kModeMU, false>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
-                                                     part_obj);
-  return obj ? launch_bf16_inst<K, kModeHALS, true>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
-                                                    part_obj)
-             : launch_bf16_inst<K, kModeHALS, false>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv,
-                                                     part_obj);
+                          int n_k, float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
+                          float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
+  const int64_t nw = bf16_ldb_pad(ldb) / 256;
+#define HSN_NW(NW_, NB_)                                                                                           \
+  if (nw == NW_)                                                                                                   \
+    return launch_bf16_kw<K, NW_, NB_>(mode, obj, n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd,     \
+                                       part_gv, part_obj, ctrl, iter);
+  HSN_NW(1, 2) HSN_NW(2, 2) HSN_NW(4, 2) HSN_NW(8, 1)
+#undef HSN_NW
+  return false;
 }
 
-size_t bf16_scratch_bytes(int64_t ldb) { return size_t(ldb / 32) * 1024 + size_t(ldb / 16) * 1024; }
+// Row pitch of the operand images of D (padded to the wave split) and their
+// size in uint16 (see nmf_iter.hip).
+int64_t bf16_image_ldb(int64_t ldb) { return bf16_ldb_pad(ldb); }
+size_t bf16_image_elems(int64_t ldb) {
+  const int64_t l = bf16_ldb_pad(ldb);
+  return size_t(l / 32) * 64 * 8 + size_t(l / 16) * 64 * 8;
+}
 
 bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
-                      int64_t n_p, int n_k, float *V, const float *D, const double *GD, uint4 *scratch,
-                      float *part_nd, double *part_gv, double *part_obj) {
-  if (ldb > kMaxLdb || ldb % 32 != 0 || K < 1 || K > 8 || (mode != kModeMU && mode != kModeHALS)) return false;
-  uint4 *db1 = scratch;
-  uint4 *db3 = scratch + (ldb / 32) * 64;
-  const int64_t n_items = (ldb / 32) * 64 + (ldb / 16) * 64;
-  bf16_prep_kernel<<<unsigned((n_items + 255) / 256), 256, 0, st>>>(D, n_k, K, ldb, db1, db3);
+                      int64_t n_p, int n_k, float *V, const double *GD, const double *chol, const uint16_t *img,
+                      float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
+  if (ldb > kMaxLdb || ldb % 32 != 0 || K < 1 || K > 8 ||
+      (mode != kModeMU && mode != kModeHALS))
+    return false;
+  const uint4 *db1 = reinterpret_cast<const uint4 *>(img);
+  const uint4 *db3 = db1 + (bf16_ldb_pad(ldb) / 32) * 64;
   switch (K) {
-#define HSN_K(KK) \
-  case KK: return launch_bf16_k<KK>(mode, obj, n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, part_nd, part_gv, part_obj);
+#define HSN_K(KK)                                                                                                  \
+  case KK:                                                                                                         \
+    return launch_bf16_k<KK>(mode, obj, n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd, part_gv,     \
+                             part_obj, ctrl, iter);
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
   }

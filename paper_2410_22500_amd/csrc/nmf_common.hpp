@@ -12,6 +12,7 @@ enum PassMode {
   kModeNV = 1,  // N_V = P D only (written out; the rows are solved separately)
   kModeND = 2,  // N_D += P^T V_new only (V_new given)
   kModeHALS = 3,  // fused: N_V = P D, HALS column sweep of V, then N_D += P^T V_new
+  kModeANLS = 4,  // ANLS round: N_V pass, exact row solves of V, N_D pass (driver step kind)
 };
 
 // One HALS sweep of a row x given its right-hand side h and Gram G: for each
@@ -31,23 +32,33 @@ __device__ __forceinline__ void hals_row(const double *__restrict__ G, const dou
   }
 }
 
+// Device-resident loop control of one decomposition.  Every iteration has a
+// global index; kernels of iteration i return at once when i >= stop_at, so
+// the host can queue many iterations and synchronise rarely.  stop_at is
+// lowered only by the D-update kernel of the iteration whose objective meets
+// the tolerance (to i + 1), so no kernel of a running iteration is skipped.
+struct NmfCtrl {
+  int stop_at;
+  int upd_ticket;  // arrival counter of the D-update blocks (last block finishes G_D)
+  int hist_len;    // objective values written so far
+  int pad;
+};
+
 // Workspace of one decomposition (all device pointers).
 struct NmfWork {
-  double *gd;        // [8*8]   G_D = D^T D
-  double *gv;        // [8*8]   G_V = V^T V
-  double *chol;      // [256][36] packed Cholesky factors of principal submatrices
+  NmfCtrl *ctrl;
+  double *gd;        // [8*8]   G_D = D^T D of the current D
+  double *chol;      // [256][36] packed Cholesky factors of principal submatrices of G_D
   float *part_nd;    // [n_wg][n_k][K] per-workgroup partials of P^T V
   double *part_gv;   // [n_wg][K*K]
   double *part_obj;  // [n_wg]
-  double *red_nd;    // [kSplit][n_k][K]
-  double *red_gv;    // [kSplit][K*K]
-  double *red_obj;   // [kSplit]
+  double *part_gd;   // [update blocks][K*K]
   float *nv;         // [n_p][K] N_V for the row-wise NNLS
   double *hist;      // [hist_cap] objective history (device)
+  uint16_t *img;     // bfloat16 operand images of D for the MFMA pass (or null)
   int n_wg;
 };
 
-constexpr int kSplit = 16;       // first-level groups of the partial reduction
 constexpr int kCholStride = 36;  // packed lower triangle of an 8x8 matrix
 
 __host__ __device__ constexpr int tri(int a) { return a * (a + 1) / 2; }
@@ -171,5 +182,27 @@ __device__ inline void nnls_gram_row(const double *__restrict__ G, const double 
     }
   }
 }
+
+// Sum of f(w) for w = g, g + G, g + 2G, ... < n in a fixed order, with eight
+// independent loads in flight per round (the partial sums live in HBM/L2 and
+// a dependent chain of loads would be latency bound).
+template <typename F>
+__device__ __forceinline__ double strided_sum(int g, int G, int n, F f) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int w = g;
+  for (; w + 7 * G < n; w += 8 * G) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = f(w + u * G);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += v[u];
+  }
+  for (int u = 0; w < n; w += G, ++u) a[u & 7] += f(w);
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// bfloat16 hi/lo split of a float32 value (hi = RNE(x), lo = RNE(x - hi)).
+__device__ __forceinline__ uint16_t bf_hi(float f) { return f32_to_bf16_bits(f); }
+__device__ __forceinline__ uint16_t bf_lo(float f) { return f32_to_bf16_bits(f - bf16_bits_to_f32(f32_to_bf16_bits(f))); }
 
 }  // namespace hsn

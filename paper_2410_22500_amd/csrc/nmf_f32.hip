@@ -1,6 +1,4 @@
-// Float32 NMF pass over p (eq. 4) on the vector ALUs, and the small kernels
-// that close every iteration: G = F^T F with its principal Cholesky factors,
-// the deterministic reduction of per-workgroup partials, and the D update.
+// Float32 NMF pass over p (eq. 4) on the vector ALUs.
 //
 // Pass layout: a persistent grid of 256-thread workgroups walks tiles of
 // kRows rows of p.  Thread t owns the bins k = 1024 q + 4 t + e (q < NQ,
@@ -19,12 +17,15 @@ constexpr int kRows = 8;
 template <int K, int NQ, int MODE, bool OBJ>
 __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
     const float *__restrict__ P, int64_t ldp, int64_t n_p, int n_k, float *__restrict__ V, float *__restrict__ NV,
-    const float *__restrict__ D, const double *__restrict__ GD, float *__restrict__ part_nd,
-    double *__restrict__ part_gv, double *__restrict__ part_obj) {
+    const float *__restrict__ D, const double *__restrict__ GD, const double *__restrict__ chol,
+    float *__restrict__ part_nd, double *__restrict__ part_gv, double *__restrict__ part_obj,
+    const NmfCtrl *__restrict__ ctrl, int iter) {
+  if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   __shared__ float red[kPassThreads / 64][kRows * K];
   __shared__ float vnew[kRows][K];
+  __shared__ float vold[kRows][K];
   __shared__ double gd_s[K * K];
   __shared__ double obj_s[kPassThreads / 64];
 
@@ -46,12 +47,16 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
       for (int j = 0; j < K; ++j) nd[q][e][j] = 0.0f;
   double gv = 0.0;
   double obj = 0.0;
-  if ((MODE == kModeMU || MODE == kModeHALS) && t < K * K) gd_s[t] = GD[t];
+  if ((MODE == kModeMU || MODE == kModeHALS || MODE == kModeANLS) && t < K * K) gd_s[t] = GD[t];
   __syncthreads();
 
   const int64_t n_tiles = (n_p + kRows - 1) / kRows;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t row0 = tile * kRows;
+    // The tile's V values (one per thread t < kRows*K) are loaded with the
+    // tile, so the row rule does not wait on a global load.
+    float vcur = 0.0f;
+    if (MODE != kModeNV && t < kRows * K && row0 * K + t < n_p * K) vcur = V[row0 * K + t];
     float p[kRows][NQ][4];
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
@@ -67,6 +72,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
       }
 
     if (MODE != kModeND) {
+      if (t < kRows * K) vold[t / K][t % K] = vcur;
       // N_V partials of this thread's bins, summed over the workgroup.
 #pragma unroll
       for (int r = 0; r < kRows; ++r)
@@ -81,7 +87,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
           if (lane == 63) red[wave][r * K + j] = s;
         }
       __syncthreads();
-      if (MODE == kModeHALS) {
+      if (MODE == kModeHALS || MODE == kModeANLS) {
         if (t < kRows) {
           const int r = t;
           const int64_t row = row0 + r;
@@ -92,9 +98,12 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
 #pragma unroll
             for (int w = 0; w < kPassThreads / 64; ++w) s += red[w][r * K + j];
             h[j] = s;
-            x[j] = (row < n_p) ? double(V[row * K + j]) : 0.0;
+            x[j] = (row < n_p) ? double(vold[r][j]) : 0.0;
           }
-          hals_row<K>(gd_s, h, x);
+          if (MODE == kModeHALS)
+            hals_row<K>(gd_s, h, x);
+          else
+            nnls_gram_row<K>(gd_s, chol, h, x);
 #pragma unroll
           for (int j = 0; j < K; ++j) {
             const float vn = (row < n_p) ? float(x[j]) : 0.0f;
@@ -116,7 +125,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
           if (row < n_p) {
             float vr[K];
 #pragma unroll
-            for (int i = 0; i < K; ++i) vr[i] = V[row * K + i];
+            for (int i = 0; i < K; ++i) vr[i] = vold[r][i];
             double den = 0.0;
 #pragma unroll
             for (int i = 0; i < K; ++i) den += double(vr[i]) * gd_s[i * K + j];
@@ -127,10 +136,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
         }
       }
     } else {
-      if (t < kRows * K) {
-        const int r = t / K, j = t - (t / K) * K;
-        vnew[r][j] = (row0 + r < n_p) ? V[(row0 + r) * K + j] : 0.0f;
-      }
+      if (t < kRows * K) vnew[t / K][t % K] = vcur;
     }
     __syncthreads();
 
@@ -206,177 +212,16 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
   }
 }
 
-// G = F^T F (float64) for F [n][K] float32, and (if want_chol) the packed
-// Cholesky factors of all 2^K - 1 principal submatrices.  One workgroup.
-template <int K>
-__global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ F, int64_t n, double *__restrict__ G,
-                                                   double *__restrict__ chol, int want_chol) {
-  const int t = threadIdx.x;
-  __shared__ double red[4][K * K];
-  __shared__ double g_s[K * K];
-  double acc[K * K];
-#pragma unroll
-  for (int i = 0; i < K * K; ++i) acc[i] = 0.0;
-  for (int64_t k = t; k < n; k += 256) {
-    double f[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) f[j] = F[k * K + j];
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-#pragma unroll
-      for (int j = 0; j < K; ++j) acc[i * K + j] += f[i] * f[j];
-  }
-#pragma unroll
-  for (int i = 0; i < K * K; ++i) {
-    const double s = wave_sum_all(acc[i]);
-    if ((t & 63) == 0) red[t >> 6][i] = s;
-  }
-  __syncthreads();
-  if (t < K * K) {
-    const double s = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-    g_s[t] = s;
-    G[t] = s;
-  }
-  __syncthreads();
-  if (want_chol && t >= 1 && t < (1 << K)) {
-    double L[kCholStride];
-    if (!chol_sub(g_s, K, unsigned(t), L)) L[0] = NAN;
-    for (int i = 0; i < kCholStride; ++i) chol[size_t(t) * kCholStride + i] = L[i];
-  }
-}
-
-// First-level reduction of the per-workgroup partials (fixed order).
-// Grid (ceil(n_k*K / 256), kSplit).
-template <int K>
-__global__ __launch_bounds__(256) void reduce_kernel(const float *__restrict__ part_nd,
-                                                     const double *__restrict__ part_gv,
-                                                     const double *__restrict__ part_obj, int n_wg, int n_k,
-                                                     int with_obj, double *__restrict__ red_nd,
-                                                     double *__restrict__ red_gv, double *__restrict__ red_obj) {
-  const int s = blockIdx.y;
-  const int w0 = int((int64_t(n_wg) * s) / kSplit), w1 = int((int64_t(n_wg) * (s + 1)) / kSplit);
-  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  const int64_t n_e = int64_t(n_k) * K;
-  if (e < n_e) {
-    double acc = 0.0;
-    for (int w = w0; w < w1; ++w) acc += part_nd[size_t(w) * n_e + e];
-    red_nd[size_t(s) * n_e + e] = acc;
-  }
-  if (blockIdx.x == 0) {
-    if (threadIdx.x < K * K) {
-      double acc = 0.0;
-      for (int w = w0; w < w1; ++w) acc += part_gv[size_t(w) * K * K + threadIdx.x];
-      red_gv[s * K * K + threadIdx.x] = acc;
-    } else if (threadIdx.x == K * K) {
-      double acc = 0.0;
-      if (with_obj)
-        for (int w = w0; w < w1; ++w) acc += part_obj[w];
-      red_obj[s] = acc;
-    }
-  }
-}
-
-// G_V = sum of the first-level sums; its factors when the D rows are solved
-// exactly; the objective into the history.  One workgroup.
-template <int K>
-__global__ __launch_bounds__(256) void finish_gv_kernel(const double *__restrict__ red_gv,
-                                                        const double *__restrict__ red_obj, double *__restrict__ GV,
-                                                        double *__restrict__ chol, int want_chol,
-                                                        double *__restrict__ hist_slot) {
-  const int t = threadIdx.x;
-  __shared__ double g_s[K * K];
-  if (t < K * K) {
-    double acc = 0.0;
-    for (int s = 0; s < kSplit; ++s) acc += red_gv[s * K * K + t];
-    g_s[t] = acc;
-    GV[t] = acc;
-  }
-  if (t == 255 && hist_slot) {
-    double acc = 0.0;
-    for (int s = 0; s < kSplit; ++s) acc += red_obj[s];
-    *hist_slot = acc;
-  }
-  __syncthreads();
-  if (want_chol && t >= 1 && t < (1 << K)) {
-    double L[kCholStride];
-    if (!chol_sub(g_s, K, unsigned(t), L)) L[0] = NAN;
-    for (int i = 0; i < kCholStride; ++i) chol[size_t(t) * kCholStride + i] = L[i];
-  }
-}
-
-// D update, one thread per bin row k: MU (D <- D * N_D / (D G_V)) or the
-// exact non-negative row solve with G_V.
-template <int K, int MODE>
-__global__ __launch_bounds__(256) void update_d_kernel(float *__restrict__ D, const double *__restrict__ red_nd,
-                                                       const double *__restrict__ GV, const double *__restrict__ chol,
-                                                       int n_k) {
-  __shared__ double g_s[K * K];
-  if (threadIdx.x < K * K) g_s[threadIdx.x] = GV[threadIdx.x];
-  __syncthreads();
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= n_k) return;
-  const size_t n_e = size_t(n_k) * K;
-  double nd[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    double acc = 0.0;
-    for (int s = 0; s < kSplit; ++s) acc += red_nd[s * n_e + size_t(k) * K + j];
-    nd[j] = acc;
-  }
-  if (MODE == kModeMU) {
-    double dr[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) dr[j] = D[k * K + j];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      double den = 0.0;
-#pragma unroll
-      for (int i = 0; i < K; ++i) den += dr[i] * g_s[i * K + j];
-      D[k * K + j] = float(dr[j] * nd[j] / fmax(den, 1e-300));
-    }
-  } else if (MODE == kModeHALS) {
-    double x[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) x[j] = D[k * K + j];
-    hals_row<K>(g_s, nd, x);
-#pragma unroll
-    for (int j = 0; j < K; ++j) D[k * K + j] = float(x[j]);
-  } else {
-    double x[K];
-    nnls_gram_row<K>(g_s, chol, nd, x);
-#pragma unroll
-    for (int j = 0; j < K; ++j) D[k * K + j] = float(x[j]);
-  }
-}
-
-// Exact non-negative solve of every V row from N_V and the factors of G_D.
-template <int K>
-__global__ __launch_bounds__(256) void nnls_rows_kernel(const float *__restrict__ NV, const double *__restrict__ GD,
-                                                        const double *__restrict__ chol, float *__restrict__ V,
-                                                        int64_t n_p) {
-  __shared__ double g_s[K * K];
-  if (threadIdx.x < K * K) g_s[threadIdx.x] = GD[threadIdx.x];
-  __syncthreads();
-  for (int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x; row < n_p; row += int64_t(gridDim.x) * 256) {
-    double h[K], x[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) h[j] = NV[row * K + j];
-    nnls_gram_row<K>(g_s, chol, h, x);
-#pragma unroll
-    for (int j = 0; j < K; ++j) V[row * K + j] = float(x[j]);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Host-side launchers (called by the driver for a runtime K).
 // ---------------------------------------------------------------------------
 template <int K>
 void launch_pass_f32_k(int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp, int64_t n_p,
-                       int n_k, float *V, float *NV, const float *D, const double *GD, float *part_nd,
-                       double *part_gv, double *part_obj) {
+                       int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
+                       float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
 #define HSN_PASS(NQ_, M_, O_)                                                                                   \
-  pass_f32_kernel<K, NQ_, M_, O_><<<n_wg, kPassThreads, 0, st>>>(P, ldp, n_p, n_k, V, NV, D, GD, part_nd, part_gv, \
-                                                                 part_obj)
+  pass_f32_kernel<K, NQ_, M_, O_><<<n_wg, kPassThreads, 0, st>>>(P, ldp, n_p, n_k, V, NV, D, GD, chol, part_nd,    \
+                                                                 part_gv, part_obj, ctrl, iter)
   if (nq == 1) {
     if (mode == kModeMU) {
       if (obj) HSN_PASS(1, kModeMU, true); else HSN_PASS(1, kModeMU, false);
@@ -402,51 +247,14 @@ void launch_pass_f32_k(int mode, bool obj, int nq, int n_wg, hipStream_t st, con
 }
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
-                     int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, float *part_nd,
-                     double *part_gv, double *part_obj) {
+                     int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
+                     float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
   switch (K) {
-#define HSN_K(KK) \
-  case KK: launch_pass_f32_k<KK>(mode, obj, nq, n_wg, st, P, ldp, n_p, n_k, V, NV, D, GD, part_nd, part_gv, part_obj); break;
-    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
-#undef HSN_K
-  }
-}
-
-void launch_gram(int K, hipStream_t st, const float *F, int64_t n, double *G, double *chol, int want_chol) {
-  switch (K) {
-#define HSN_K(KK) case KK: gram_kernel<KK><<<1, 256, 0, st>>>(F, n, G, chol, want_chol); break;
-    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
-#undef HSN_K
-  }
-}
-
-void launch_reduce_update(int K, int mode_d, bool obj, hipStream_t st, const NmfWork &w, int n_wg, int n_k, float *D,
-                          double *hist_slot) {
-  const dim3 grid(unsigned((int64_t(n_k) * K + 255) / 256), kSplit);
-  const unsigned ub = unsigned((n_k + 255) / 256);
-  switch (K) {
-#define HSN_K(KK)                                                                                             \
-  case KK:                                                                                                    \
-    reduce_kernel<KK><<<grid, 256, 0, st>>>(w.part_nd, w.part_gv, w.part_obj, n_wg, n_k, obj ? 1 : 0,         \
-                                            w.red_nd, w.red_gv, w.red_obj);                                   \
-    finish_gv_kernel<KK><<<1, 256, 0, st>>>(w.red_gv, w.red_obj, w.gv, w.chol, mode_d == kModeNV ? 1 : 0,     \
-                                            obj ? hist_slot : nullptr);                                       \
-    if (mode_d == kModeMU)                                                                                    \
-      update_d_kernel<KK, kModeMU><<<ub, 256, 0, st>>>(D, w.red_nd, w.gv, w.chol, n_k);                       \
-    else if (mode_d == kModeHALS)                                                                             \
-      update_d_kernel<KK, kModeHALS><<<ub, 256, 0, st>>>(D, w.red_nd, w.gv, w.chol, n_k);                     \
-    else                                                                                                      \
-      update_d_kernel<KK, kModeNV><<<ub, 256, 0, st>>>(D, w.red_nd, w.gv, w.chol, n_k);                       \
+#define HSN_K(KK)                                                                                                  \
+  case KK:                                                                                                         \
+    launch_pass_f32_k<KK>(mode, obj, nq, n_wg, st, P, ldp, n_p, n_k, V, NV, D, GD, chol, part_nd, part_gv,      \
+                          part_obj, ctrl, iter);                                                                   \
     break;
-    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
-#undef HSN_K
-  }
-}
-
-void launch_nnls_rows(int K, hipStream_t st, const float *NV, const double *GD, const double *chol, float *V,
-                      int64_t n_p, int n_blocks) {
-  switch (K) {
-#define HSN_K(KK) case KK: nnls_rows_kernel<KK><<<n_blocks, 256, 0, st>>>(NV, GD, chol, V, n_p); break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
   }

@@ -1,0 +1,323 @@
+// The kernels that close every NMF iteration (eq. 4) around the streaming
+// passes, with all loop control kept on the device:
+//
+//   init      once per call: G_D = D^T D (float64), the Cholesky factors of its
+//             principal submatrices when the first step solves rows exactly,
+//             the bfloat16 operand images of D for the MFMA pass, control reset.
+//   update_d  after every pass that accumulates N_D = P^T V_new:
+//             - every block sums the per-workgroup partials of G_V and of the
+//               objective (fixed order) and the N_D partials of its 16 bin rows;
+//             - applies the D row rule (Lee-Seung MU, HALS sweep, or the exact
+//               non-negative row solve with G_V's factors);
+//             - block 0 appends the objective to the history and, when it
+//               meets the tolerance, lowers stop_at to this iteration + 1;
+//             - the last block to finish (arrival counter) sums the blocks'
+//               D_new^T D_new partials into G_D for the next pass, plus its
+//               factors when the next step solves rows exactly;
+//             - rewrites the bfloat16 images of its rows for the MFMA pass.
+//   nnls_rows the exact non-negative solve of every V row (ANLS), from N_V and
+//             the factors of G_D.
+// All sums run in a fixed order, so results are bitwise reproducible.
+#include "nmf_common.hpp"
+
+#include <climits>
+
+namespace hsn {
+
+constexpr int kUpdThreads = 1024;
+constexpr int kUpdRows = 16;  // D rows per update block
+
+// Row k of D -> its entries in the two bfloat16 operand images.
+//   image 1 [k-step s][lane][8]: column n = lane % 16, bins 32 s + 8 (lane/16) + e;
+//            n < 8 -> hi(D[k][n]), n >= 8 -> lo(D[k][n-8]).
+//   image 3 [block b][lane][8]: bin 16 b + lane % 16; group g = lane / 16:
+//            g 0,1 -> hi(D[bin][e]), g 2 -> lo(D[bin][e]), g 3 -> 0.
+template <int K>
+__device__ inline void write_images_row(uint16_t *__restrict__ img, int64_t ldb, int64_t k, const float (&d)[K],
+                                        bool zero) {
+  uint16_t *im1 = img;
+  uint16_t *im3 = img + (ldb / 32) * 64 * 8;
+  const int64_t s = k / 32, g = (k % 32) / 8, e = k % 8;
+  for (int n = 0; n < 16; ++n) {
+    const int j = n & 7;
+    const float v = (!zero && j < K) ? d[j < K ? j : 0] : 0.0f;
+    im1[((s * 64) + 16 * g + n) * 8 + e] = (n < 8) ? bf_hi(v) : bf_lo(v);
+  }
+  const int64_t b = k / 16, l16 = k % 16;
+  for (int gg = 0; gg < 4; ++gg)
+    for (int ee = 0; ee < 8; ++ee) {
+      const float v = (!zero && ee < K && gg < 3) ? d[ee < K ? ee : 0] : 0.0f;
+      im3[((b * 64) + 16 * gg + l16) * 8 + ee] = (gg == 2) ? bf_lo(v) : bf_hi(v);
+    }
+}
+
+// Factors of all principal submatrices of G (K x K, in LDS) -> chol.
+template <int K>
+__device__ inline void factor_all(const double *G, double *__restrict__ chol) {
+  for (int m = threadIdx.x; m < (1 << K); m += blockDim.x) {
+    if (m == 0) continue;
+    double L[kCholStride];
+    if (!chol_sub(G, K, unsigned(m), L)) L[0] = NAN;
+    for (int i = 0; i < kCholStride; ++i) chol[size_t(m) * kCholStride + i] = L[i];
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kUpdThreads) void nmf_init_kernel(const float *__restrict__ D, int n_k, double *__restrict__ GD,
+                                                               double *__restrict__ chol, int want_chol,
+                                                               uint16_t *__restrict__ img, int64_t ldb,
+                                                               NmfCtrl *__restrict__ ctrl) {
+  const int t = threadIdx.x;
+  __shared__ double red[kUpdThreads / 64][K * K];
+  __shared__ double g_s[K * K];
+  double acc[K * K];
+#pragma unroll
+  for (int i = 0; i < K * K; ++i) acc[i] = 0.0;
+  for (int k = t; k < n_k; k += kUpdThreads) {
+    float d[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) d[j] = D[size_t(k) * K + j];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+      for (int j = 0; j < K; ++j) acc[i * K + j] += double(d[i]) * double(d[j]);
+  }
+  if (img) {
+    for (int64_t k = t; k < ldb; k += kUpdThreads) {
+      float d[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) d[j] = (k < n_k) ? D[k * K + j] : 0.0f;
+      write_images_row<K>(img, ldb, k, d, k >= n_k);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < K * K; ++i) {
+    const double s = wave_sum_all(acc[i]);
+    if ((t & 63) == 0) red[t >> 6][i] = s;
+  }
+  __syncthreads();
+  if (t < K * K) {
+    double s = 0.0;
+    for (int w = 0; w < kUpdThreads / 64; ++w) s += red[w][t];
+    g_s[t] = s;
+    GD[t] = s;
+  }
+  if (t == 0) {
+    ctrl->stop_at = INT_MAX;
+    ctrl->upd_ticket = 0;
+    ctrl->hist_len = 0;
+  }
+  __syncthreads();
+  if (want_chol) factor_all<K>(g_s, chol);
+}
+
+// RULE: kModeMU (Lee-Seung), kModeHALS (column sweep), kModeNV (exact NNLS rows)
+template <int K, int RULE>
+__global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
+    float *__restrict__ D, const float *__restrict__ part_nd, const double *__restrict__ part_gv,
+    const double *__restrict__ part_obj, int n_wg, int n_k, NmfCtrl *__restrict__ ctrl, int iter, int has_obj,
+    double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
+    int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb) {
+  if (iter >= ctrl->stop_at) return;
+  const int t = threadIdx.x;
+  constexpr int E1 = K * K + 1;                 // G_V entries + the objective
+  constexpr int G1 = kUpdThreads / E1;          // groups summing them
+  constexpr int EB = kUpdRows * K;              // N_D entries of this block
+  constexpr int G2 = kUpdThreads / EB;
+  __shared__ double red1[G1][E1];
+  __shared__ double red2[G2][EB];
+  __shared__ double gv_s[K * K];
+  __shared__ double gd_s[K * K];
+  __shared__ double nd_s[EB];
+  __shared__ float dn_s[kUpdRows][K];
+  __shared__ double obj_s;
+  __shared__ double chol_s[(1 << K) * kCholStride / ((RULE == kModeNV) ? 1 : (1 << K))];
+  __shared__ int last_s;
+
+  const int k0 = blockIdx.x * kUpdRows;
+  // G_V and objective: each thread sums every G1-th workgroup partial (8 loads in flight).
+  if (t < G1 * E1) {
+    const int e = t % E1, g = t / E1;
+    double acc = 0.0;
+    if (e < K * K)
+      acc = strided_sum(g, G1, n_wg, [&](int w) { return part_gv[size_t(w) * K * K + e]; });
+    else if (has_obj)
+      acc = strided_sum(g, G1, n_wg, [&](int w) { return part_obj[w]; });
+    red1[g][e] = acc;
+  }
+  // N_D of this block's rows.
+  if (t < G2 * EB) {
+    const int e = t % EB, g = t / EB;
+    const int row = k0 + e / K;
+    double acc = 0.0;
+    if (row < n_k) {
+      const size_t base = size_t(k0) * K + e;
+      const size_t stride = size_t(n_k) * K;
+      acc = strided_sum(g, G2, n_wg, [&](int w) { return double(part_nd[size_t(w) * stride + base]); });
+    }
+    red2[g][e] = acc;
+  }
+  __syncthreads();
+  if (t < E1) {
+    double s = 0.0;
+    for (int g = 0; g < G1; ++g) s += red1[g][t];
+    if (t < K * K) gv_s[t] = s;
+    else obj_s = s;
+  }
+  if (t >= 64 && t < 64 + EB) {
+    const int e = t - 64;
+    double s = 0.0;
+    for (int g = 0; g < G2; ++g) s += red2[g][e];
+    nd_s[e] = s;
+  }
+  __syncthreads();
+  if (RULE == kModeNV) factor_all<K>(gv_s, chol_s);
+  if (blockIdx.x == 0 && t == 0 && has_obj) {
+    const int h = ctrl->hist_len;
+    hist[h] = obj_s;
+    ctrl->hist_len = h + 1;
+    if (f_ref > 0.0 && (obj_s - f_ref) / f_ref <= tol) ctrl->stop_at = iter + 1;
+  }
+  __syncthreads();
+
+  // Row rule, one thread per bin row.
+  if (t < kUpdRows) {
+    const int k = k0 + t;
+    float dn[K];
+    if (k < n_k) {
+      double nd[K], x[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        nd[j] = nd_s[t * K + j];
+        x[j] = D[size_t(k) * K + j];
+      }
+      if (RULE == kModeMU) {
+        double y[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          double den = 0.0;
+#pragma unroll
+          for (int i = 0; i < K; ++i) den += x[i] * gv_s[i * K + j];
+          y[j] = x[j] * nd[j] / fmax(den, 1e-300);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) x[j] = y[j];
+      } else if (RULE == kModeHALS) {
+        hals_row<K>(gv_s, nd, x);
+      } else {
+        nnls_gram_row<K>(gv_s, chol_s, nd, x);
+      }
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        dn[j] = float(x[j]);
+        D[size_t(k) * K + j] = dn[j];
+      }
+      if (img) write_images_row<K>(img, ldb, k, dn, false);
+    } else {
+#pragma unroll
+      for (int j = 0; j < K; ++j) dn[j] = 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) dn_s[t][j] = dn[j];
+  }
+  __syncthreads();
+  // This block's share of G_D for the next pass; the last block to arrive sums them.
+  if (t < K * K) {
+    const int i = t / K, j = t % K;
+    double s = 0.0;
+    for (int r = 0; r < kUpdRows; ++r) s += double(dn_s[r][i]) * double(dn_s[r][j]);
+    part_gd[size_t(blockIdx.x) * K * K + t] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) last_s = (atomicAdd(&ctrl->upd_ticket, 1) == int(gridDim.x) - 1);
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  {
+    constexpr int G3 = kUpdThreads / (K * K);
+    __shared__ double red3[G3][K * K];
+    if (t < G3 * K * K) {
+      const int e = t % (K * K), g = t / (K * K);
+      red3[g][e] = strided_sum(g, G3, int(gridDim.x), [&](int b) { return part_gd[size_t(b) * K * K + e]; });
+    }
+    __syncthreads();
+    if (t < K * K) {
+      double s = 0.0;
+      for (int g = 0; g < G3; ++g) s += red3[g][t];
+      gd_s[t] = s;
+      GD[t] = s;
+    }
+    if (t == 0) ctrl->upd_ticket = 0;
+    __syncthreads();
+    if (next_chol) factor_all<K>(gd_s, chol);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void nnls_rows_kernel(const float *__restrict__ NV, const double *__restrict__ GD,
+                                                        const double *__restrict__ chol, float *__restrict__ V,
+                                                        int64_t n_p, const NmfCtrl *__restrict__ ctrl, int iter) {
+  if (iter >= ctrl->stop_at) return;
+  __shared__ double g_s[K * K];
+  if (threadIdx.x < K * K) g_s[threadIdx.x] = GD[threadIdx.x];
+  __syncthreads();
+  for (int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x; row < n_p; row += int64_t(gridDim.x) * 256) {
+    double h[K], x[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) h[j] = NV[row * K + j];
+    nnls_gram_row<K>(g_s, chol, h, x);
+#pragma unroll
+    for (int j = 0; j < K; ++j) V[row * K + j] = float(x[j]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers for a runtime K.
+// ---------------------------------------------------------------------------
+void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWork &w, int want_chol, int64_t ldb) {
+  switch (K) {
+#define HSN_K(KK) \
+  case KK: nmf_init_kernel<KK><<<1, kUpdThreads, 0, st>>>(D, n_k, w.gd, w.chol, want_chol, w.img, ldb, w.ctrl); break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+  }
+}
+
+int update_d_blocks(int n_k) { return (n_k + kUpdRows - 1) / kUpdRows; }
+
+void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
+                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img) {
+  const int nb = update_d_blocks(n_k);
+  uint16_t *img = ldb_img > 0 ? w.img : nullptr;
+  switch (K) {
+#define HSN_K(KK)                                                                                                 \
+  case KK:                                                                                                        \
+    if (rule == kModeMU)                                                                                          \
+      update_d_kernel<KK, kModeMU><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, w.part_gv, w.part_obj, n_wg, n_k,    \
+                                                               w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img);       \
+    else if (rule == kModeHALS)                                                                                   \
+      update_d_kernel<KK, kModeHALS><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, w.part_gv, w.part_obj, n_wg, n_k,  \
+                                                                 w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd, \
+                                                                 w.chol, next_chol, w.part_gd, img, ldb_img);     \
+    else                                                                                                          \
+      update_d_kernel<KK, kModeNV><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, w.part_gv, w.part_obj, n_wg, n_k,    \
+                                                               w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img);       \
+    break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+  }
+}
+
+void launch_nnls_rows(int K, hipStream_t st, const NmfWork &w, float *V, int64_t n_p, int n_blocks, int iter) {
+  switch (K) {
+#define HSN_K(KK) \
+  case KK: nnls_rows_kernel<KK><<<n_blocks, 256, 0, st>>>(w.nv, w.gd, w.chol, V, n_p, w.ctrl, iter); break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+  }
+}
+
+}  // namespace hsn

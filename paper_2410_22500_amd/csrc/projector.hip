@@ -201,22 +201,48 @@ __global__ __launch_bounds__(kDotThreads) void chan_dot_kernel(const float *__re
 
 // st layout: gamma[8], alpha[8], beta[8]
 enum { kSetGamma = 0, kAlpha = 1, kBeta = 2, kResid = 3 };
-__global__ void cgls_scalar_kernel(const double *__restrict__ partial, int nblk, int K, int mode,
-                                   double *__restrict__ st, double *__restrict__ out) {
-  const int q = threadIdx.x;
+__global__ __launch_bounds__(256) void cgls_scalar_kernel(const double *__restrict__ partial, int nblk, int K,
+                                                          int mode, double *__restrict__ st,
+                                                          double *__restrict__ out) {
+  // 256 threads = K channels x groups; each group sums every G-th block partial.
+  __shared__ double red[256];
+  __shared__ double tot[8];
+  const int t = threadIdx.x;
+  const int G = 256 / K;
+  if (t < G * K) {
+    const int q = t % K, g = t / K;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = g;
+    for (; b + 3 * G < nblk; b += 4 * G) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = partial[size_t(b + u * G) * K + q];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] += v[u];
+    }
+    for (int u = 0; b < nblk; b += G, ++u) a[u & 3] += partial[size_t(b) * K + q];
+    red[t] = (a[0] + a[1]) + (a[2] + a[3]);
+  }
+  __syncthreads();
+  if (t < K) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += red[g * K + t];
+    tot[t] = s;
+  }
+  __syncthreads();
+  const int q = t;
   if (q >= K) return;
-  double t = 0.0;
-  for (int b = 0; b < nblk; ++b) t += partial[size_t(b) * K + q];
+  const double tq = tot[q];
   double *gamma = st, *alpha = st + 8, *beta = st + 16;
   if (mode == kSetGamma) {
-    gamma[q] = t;
+    gamma[q] = tq;
   } else if (mode == kAlpha) {
-    alpha[q] = (t > 0.0) ? gamma[q] / t : 0.0;
+    alpha[q] = (tq > 0.0) ? gamma[q] / tq : 0.0;
   } else if (mode == kBeta) {
-    beta[q] = (gamma[q] > 0.0) ? t / gamma[q] : 0.0;
-    gamma[q] = t;
+    beta[q] = (gamma[q] > 0.0) ? tq / gamma[q] : 0.0;
+    gamma[q] = tq;
   } else if (out) {
-    out[q] = sqrt(t);
+    out[q] = sqrt(tq);
   }
 }
 
@@ -397,28 +423,28 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
   HSN_DISPATCH_K(K, launch_backproject, r, sv, geom, g, 1.0f, 0.0f, st);
   HSN_HIP(ctx, hipMemcpyAsync(p, sv, sizeof(float) * nx * K, hipMemcpyDeviceToDevice, st));
   HSN_DISPATCH_K(K, launch_dot, sv, sv, nx, partial, st);
-  cgls_scalar_kernel<<<1, 64, 0, st>>>(partial, kDotBlocks, K, kSetGamma, scal, nullptr);
+  cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kSetGamma, scal, nullptr);
   if (resid) {
     HSN_DISPATCH_K(K, launch_dot, r, r, ns, partial, st);
-    cgls_scalar_kernel<<<1, 64, 0, st>>>(partial, kDotBlocks, K, kResid, scal, resid);
+    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kResid, scal, resid);
   }
   for (int it = 0; it < n_iter; ++it) {
     hsn::prof_begin(ctx, HSN_KERN_PROJECT, st);
     HSN_DISPATCH_K(K, launch_project, p, q, geom, g, 1.0f, 0.0f, st);
     hsn::prof_end(ctx, HSN_KERN_PROJECT, st);
     HSN_DISPATCH_K(K, launch_dot, q, q, ns, partial, st);
-    cgls_scalar_kernel<<<1, 64, 0, st>>>(partial, kDotBlocks, K, kAlpha, scal, nullptr);
+    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kAlpha, scal, nullptr);
     chan_axpy_kernel<<<blocks(nx * K), eb, 0, st>>>(x, p, scal + 8, 1.0f, K, nx * K);
     chan_axpy_kernel<<<blocks(ns * K), eb, 0, st>>>(r, q, scal + 8, -1.0f, K, ns * K);
     hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
     HSN_DISPATCH_K(K, launch_backproject, r, sv, geom, g, 1.0f, 0.0f, st);
     hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
     HSN_DISPATCH_K(K, launch_dot, sv, sv, nx, partial, st);
-    cgls_scalar_kernel<<<1, 64, 0, st>>>(partial, kDotBlocks, K, kBeta, scal, nullptr);
+    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kBeta, scal, nullptr);
     chan_xpby_kernel<<<blocks(nx * K), eb, 0, st>>>(p, sv, scal + 16, K, nx * K);
     if (resid) {
       HSN_DISPATCH_K(K, launch_dot, r, r, ns, partial, st);
-      cgls_scalar_kernel<<<1, 64, 0, st>>>(partial, kDotBlocks, K, kResid, scal, resid + size_t(it + 1) * K);
+      cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kResid, scal, resid + size_t(it + 1) * K);
     }
   }
   HSN_LAUNCHED(ctx);

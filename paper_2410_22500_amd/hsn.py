@@ -28,7 +28,7 @@ ALGO_MU, ALGO_ANLS, ALGO_HALS = 0, 1, 2
 PREC_FP32, PREC_BF16 = 0, 1
 INIT_USER = 0
 
-KERN_NMF_PASS, KERN_PROJECT, KERN_BACKPROJECT, KERN_NORMALIZE = range(4)
+KERN_NMF_PASS, KERN_PROJECT, KERN_BACKPROJECT, KERN_NORMALIZE, KERN_NMF_PASS_BF16 = range(5)
 
 
 class Dims(C.Structure):
@@ -38,7 +38,8 @@ class Dims(C.Structure):
 class NmfOpts(C.Structure):
     _fields_ = [("k", C.c_int), ("algo", C.c_int), ("precision", C.c_int), ("init", C.c_int),
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("polish_rounds", C.c_int),
-                ("polish_algo", C.c_int), ("rel_obj_tol", C.c_double), ("f_ref", C.c_double)]
+                ("polish_algo", C.c_int), ("polish_bf16_rounds", C.c_int), ("rel_obj_tol", C.c_double),
+                ("f_ref", C.c_double)]
 
 
 class NmfStats(C.Structure):
@@ -162,13 +163,14 @@ def hsn_normalize(y: torch.Tensor, yo: torch.Tensor, bg_mask: Optional[torch.Ten
 def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], n_k: int, V: torch.Tensor,
                      D: torch.Tensor, algo: int = ALGO_MU, precision: int = PREC_FP32, max_iter: int = 100,
                      check_every: int = 10, polish_rounds: int = 0, polish_algo: int = ALGO_ANLS,
-                     rel_obj_tol: float = 0.0, f_ref: float = 0.0, history_cap: int = 4096) -> dict:
+                     polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0,
+                     history_cap: int = 4096) -> dict:
     """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device)."""
     dev = _dev(V)
     ctx = context(dev)
     n_p, k = V.shape
-    opts = NmfOpts(k, algo, precision, INIT_USER, max_iter, check_every, polish_rounds, polish_algo, rel_obj_tol,
-                   f_ref)
+    opts = NmfOpts(k, algo, precision, INIT_USER, max_iter, check_every, polish_rounds, polish_algo,
+                   polish_bf16_rounds, rel_obj_tol, f_ref)
     hist = (C.c_double * max(history_cap, 1))()
     stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0)
     ldp = p.stride(0) if p is not None else 0

@@ -45,7 +45,8 @@ def _problem(shape, k, seed):
 
 
 @pytest.mark.parametrize("shape,k,algo", [((5760, 256), 3, "mu"), ((1001, 2000), 5, "mu"), ((777, 1024), 8, "hals"),
-                                          ((5760, 256), 3, "hals"), ((100, 64), 1, "mu"), ((2053, 512), 4, "mu")])
+                                          ((5760, 256), 3, "hals"), ((100, 64), 1, "mu"), ((2053, 512), 4, "mu"),
+                                          ])
 def test_bf16_one_step(hsn, shape, k, algo):
     n_p, n_k = shape
     p32 = _problem(shape, k, n_k + k)
@@ -55,15 +56,18 @@ def test_bf16_one_step(hsn, shape, k, algo):
     V0 = V0.astype(np.float32).astype(np.float64)
     D0 = D0.astype(np.float32).astype(np.float64)
     show("bf16 one step", n_p=n_p, n_k=n_k, k=k, algo=algo)
-    step = onmf.mu_step if algo == "mu" else onmf.hals_step
+    step = {"mu": onmf.mu_step, "hals": onmf.hals_step, "anls": onmf.anls_round}[algo]
     V1, D1, fh, _ = step(pq, V0, D0)
     V = to_dev(V0, torch.float32)
     D = to_dev(D0, torch.float32)
-    st = hsn.hsn_subspace_nmf(None, pb, n_k, V, D, algo=hsn.ALGO_MU if algo == "mu" else hsn.ALGO_HALS,
-                              precision=hsn.PREC_BF16, max_iter=1, check_every=1)
+    code = {"mu": hsn.ALGO_MU, "hals": hsn.ALGO_HALS, "anls": hsn.ALGO_ANLS}[algo]
+    st = hsn.hsn_subspace_nmf(None, pb, n_k, V, D, algo=code, precision=hsn.PREC_BF16, max_iter=1, check_every=1)
     ev, ed = rel_fro(V.cpu().numpy(), V1), rel_fro(D.cpu().numpy(), D1)
-    show("  err", V=ev, D=ed, f=abs(st["history"][0] - fh) / fh)
-    assert ev <= 2e-5 and ed <= 2e-5
+    # The exact D solve (ANLS) maps the ~2^-17 relative error of the split
+    # products in N_D = P^T V through G_V = V^T V: its bound is cond(G_V) 2^-16.
+    tol_d = 2e-5 if algo != "anls" else max(2e-5, np.linalg.cond(V1.T @ V1) * 2.0 ** -16)
+    show("  err", V=ev, D=ed, tol_d=tol_d, f=abs(st["history"][0] - fh) / fh)
+    assert ev <= 2e-5 and ed <= tol_d
     assert abs(st["history"][0] - fh) <= 2e-5 * fh
 
 
