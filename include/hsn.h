@@ -98,7 +98,10 @@ enum { HSN_ALGO_MU = 0,    /* Lee-Seung multiplicative updates, V then D      */
 enum { HSN_PREC_FP32 = 0,  /* float32 p, float32 arithmetic               */
        HSN_PREC_BF16 = 1 };/* bfloat16 p on MFMA, float32 accumulation;
                               the polish rounds then use the float32 p    */
-enum { HSN_INIT_USER = 0 };/* V and D hold the start on entry             */
+enum { HSN_INIT_USER = 0,  /* V and D hold the start on entry                    */
+       HSN_INIT_NNDSVDA = 1 };/* NNDSVD with zeros filled by mean(p) (Boutsidis &
+                                 Gallopoulos; the paper's initialisation); needs p,
+                                 uses p_bf16 for the Gram P^T P when given      */
 
 typedef struct {
   int k;              /* K = N_s, 1..8 */

@@ -36,6 +36,9 @@ int update_d_blocks(int n_k);
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
                      bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img);
 void launch_nnls_rows(int K, hipStream_t st, const NmfWork &w, float *V, int64_t n_p, int n_blocks, int iter);
+size_t nndsvd_ws_bytes(int64_t n_p, int n_k, int K, int n_split);
+hsn_status nndsvd_init(hsn_ctx *ctx, hipStream_t st, const float *p, int64_t ldp, const uint16_t *pb, int64_t ldb,
+                       int64_t n_p, int n_k, int K, float *V, float *D, void *ws, int n_split);
 
 namespace {
 
@@ -115,7 +118,8 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: polish_algo must be HSN_ALGO_ANLS or HSN_ALGO_HALS");
   if (o->precision != HSN_PREC_FP32 && o->precision != HSN_PREC_BF16)
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: bad precision");
-  if (o->init != HSN_INIT_USER) return fail(ctx, HSN_ERR_UNSUPPORTED, "nmf: only HSN_INIT_USER is available");
+  if (o->init != HSN_INIT_USER && o->init != HSN_INIT_NNDSVDA)
+    return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: bad init");
   if (o->max_iter < 0 || o->check_every < 1 || o->polish_rounds < 0)
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: max_iter >= 0, check_every >= 1, polish_rounds >= 0 required");
   if (!V || !D) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: V and D are required");
@@ -125,7 +129,7 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     return fail(ctx, HSN_ERR_UNSUPPORTED, "nmf: ANLS rounds run on the float32 p (bulk precision FP32)");
   // bfloat16 polish rounds exist for HALS only (ANLS rounds read the float32 p).
   const int pol_bf16 = (o->polish_algo == HSN_ALGO_HALS) ? std::min(o->polish_bf16_rounds, o->polish_rounds) : 0;
-  const bool need_f32 = (!bf16 && o->max_iter > 0) || o->polish_rounds > pol_bf16;
+  const bool need_f32 = (!bf16 && o->max_iter > 0) || o->polish_rounds > pol_bf16 || o->init == HSN_INIT_NNDSVDA;
   if (need_f32) {
     if (!p) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: float32 p is required");
     if (ldp < n_k || ldp % 4 != 0 || reinterpret_cast<uintptr_t>(p) % 16 != 0)
@@ -155,7 +159,16 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
                                     sizeof(double) * n_wg, sizeof(double) * size_t(n_upd) * K * K,
                                     need_nv ? sizeof(float) * n_p * K : 0, sizeof(double) * hist_cap,
                                     any_bf16 ? sizeof(uint16_t) * bf16_image_elems(ldb) : 0});
-  hsn_status rc = ensure_ws(ctx, need);
+  // NNDSVD runs before any NMF kernel on the same stream, so its scratch can
+  // share the workspace with the decomposition's.
+  int n_split = 1;
+  size_t need_init = 0;
+  if (o->init == HSN_INIT_NNDSVDA) {
+    const int64_t n_tb = (n_k + 127) / 128;
+    n_split = int(std::max<int64_t>(1, std::min<int64_t>(1024 / (n_tb * (n_tb + 1) / 2), n_p / 32)));
+    need_init = nndsvd_ws_bytes(n_p, int(n_k), K, n_split);
+  }
+  hsn_status rc = ensure_ws(ctx, std::max(need, need_init));
   if (rc != HSN_OK) return rc;
   Carver cv(ctx->ws);
   Run R{ctx, st, K, n_p, int(n_k), {}};
@@ -190,6 +203,9 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   }
 
   if (stats) HSN_HIP(ctx, hipEventRecord(ctx->ev0, st));
+  if (o->init == HSN_INIT_NNDSVDA &&
+      (rc = nndsvd_init(ctx, st, p, ldp, p_bf16, ldb, n_p, int(n_k), K, V, D, ctx->ws, n_split)) != HSN_OK)
+    return rc;
   launch_nmf_init(K, st, D, int(n_k), R.w, !steps.empty() && steps[0].rule == kModeANLS ? 1 : 0,
                   any_bf16 ? bf16_image_ldb(ldb) : 0);
   HSN_LAUNCHED(ctx);

@@ -26,7 +26,7 @@ OK, ERR_INVALID_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_OOM, ERR_DEVICE, ERR_NUMERI
 U16, F32 = 0, 1
 ALGO_MU, ALGO_ANLS, ALGO_HALS = 0, 1, 2
 PREC_FP32, PREC_BF16 = 0, 1
-INIT_USER = 0
+INIT_USER, INIT_NNDSVDA = 0, 1
 
 KERN_NMF_PASS, KERN_PROJECT, KERN_BACKPROJECT, KERN_NORMALIZE, KERN_NMF_PASS_BF16 = range(5)
 
@@ -164,12 +164,12 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
                      D: torch.Tensor, algo: int = ALGO_MU, precision: int = PREC_FP32, max_iter: int = 100,
                      check_every: int = 10, polish_rounds: int = 0, polish_algo: int = ALGO_ANLS,
                      polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0,
-                     history_cap: int = 4096) -> dict:
+                     init: int = INIT_USER, history_cap: int = 4096) -> dict:
     """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device)."""
     dev = _dev(V)
     ctx = context(dev)
     n_p, k = V.shape
-    opts = NmfOpts(k, algo, precision, INIT_USER, max_iter, check_every, polish_rounds, polish_algo,
+    opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo,
                    polish_bf16_rounds, rel_obj_tol, f_ref)
     hist = (C.c_double * max(history_cap, 1))()
     stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0)
