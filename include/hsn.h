@@ -99,9 +99,14 @@ enum { HSN_PREC_FP32 = 0,  /* float32 p, float32 arithmetic               */
        HSN_PREC_BF16 = 1 };/* bfloat16 p on MFMA, float32 accumulation;
                               the polish rounds then use the float32 p    */
 enum { HSN_INIT_USER = 0,  /* V and D hold the start on entry                    */
-       HSN_INIT_NNDSVDA = 1 };/* NNDSVD with zeros filled by mean(p) (Boutsidis &
+       HSN_INIT_NNDSVDA = 1,  /* NNDSVD with zeros filled by mean(p) (Boutsidis &
                                  Gallopoulos; the paper's initialisation); needs p,
                                  uses p_bf16 for the Gram P^T P when given      */
+       HSN_INIT_MLP = 2 };    /* learned warm start: V0 = opts.mlp(pooled p_bf16),
+                                 D0 = argmin_{D>=0} ||p - V0 D^T|| row by row, exact
+                                 zeros of D0 set to 1e-6 mean(D0); needs p and p_bf16 */
+
+typedef struct hsn_mlp hsn_mlp;
 
 typedef struct {
   int k;              /* K = N_s, 1..8 */
@@ -115,6 +120,7 @@ typedef struct {
   int polish_bf16_rounds; /* the first this many polish rounds run on p_bf16 (needs p_bf16) */
   double rel_obj_tol; /* stop when (f - f_ref)/f_ref <= tol; ignored if f_ref <= 0 */
   double f_ref;       /* reference objective f* (> 0 enables the stop test) */
+  const hsn_mlp *mlp; /* network for HSN_INIT_MLP (its k must equal k), else NULL */
 } hsn_nmf_opts;
 
 typedef struct {
@@ -199,6 +205,87 @@ hsn_status hsn_rehydrate(hsn_ctx *ctx, const float *xs, const float *D, int64_t 
                          int64_t bin_end, float *xh, int64_t ldh, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Learned warm start of eq. (4): spectrum -> K coefficients.            */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The paper starts its NMF from NNDSVD; this network replaces that start
+ * with a prediction of the rows of V.  A ray's spectrum is average-pooled to
+ * 256 bins (bin i covers [floor(i N_k/256), ceil((i+1) N_k/256))), then
+ *   h1 = GELU(x W1 + b1), h2 = GELU(h1 W2 + b2), v = softplus(h2 W3 + b3),
+ * GELU(z) = z Phi(z) (erf form), softplus(z) = log(1 + e^z).  Parameters,
+ * flat float32 in this order (row-major): W1[256][128], b1[128],
+ * W2[128][128], b2[128], W3[128][K], b3[K]; n = 49408 + 129 K.
+ * Precision HSN_PREC_BF16: bfloat16 weights and activations on MFMA with
+ * float32 accumulation (float32 master weights and Adam state);
+ * HSN_PREC_FP32: the same network in float32 throughout.  Inputs x of a
+ * network are [n][256] in its precision: bfloat16 bits for BF16, float32
+ * for FP32.  Training minimises the mean squared error over the batch and
+ * the K outputs with Adam.
+ */
+enum { HSN_MLP_IN = 256, HSN_MLP_HIDDEN = 128 };
+
+int64_t hsn_mlp_n_params(int k);
+/* Creates a network on ctx's device; params_host (host, n floats) or NULL for
+ * all-zero parameters.  The network belongs to the caller (hsn_mlp_destroy). */
+hsn_status hsn_mlp_create(hsn_ctx *ctx, hsn_mlp **mlp, int k, int precision, const float *params_host);
+void hsn_mlp_destroy(hsn_mlp *mlp);
+/* Host copies of the float32 master parameters (synchronous). */
+hsn_status hsn_mlp_get_params(hsn_ctx *ctx, const hsn_mlp *mlp, float *params_host);
+hsn_status hsn_mlp_set_params(hsn_ctx *ctx, hsn_mlp *mlp, const float *params_host);
+int hsn_mlp_k(const hsn_mlp *mlp);
+int hsn_mlp_precision(const hsn_mlp *mlp);
+
+/* x[i][.] = the 256-bin average pooling of row i of p_bf16 [n_p][ldb]
+ * (n_k bins), written as x_dtype: HSN_PREC_BF16 (bits, round to nearest even)
+ * or HSN_PREC_FP32. */
+hsn_status hsn_mlp_pool(hsn_ctx *ctx, const uint16_t *p_bf16, int64_t ldb, int64_t n_p, int64_t n_k,
+                        int x_dtype, void *x, void *stream);
+/* y [n][K] float32 = network(x [n][256]). */
+hsn_status hsn_mlp_forward(hsn_ctx *ctx, const hsn_mlp *mlp, const void *x, int64_t n, float *y, void *stream);
+/* Mean squared error of network(x) against target [n][K] float32 over all n
+ * rows as one batch: *loss (device double) and its gradient grad (device,
+ * n_params float32, parameter order above). */
+hsn_status hsn_mlp_loss_grad(hsn_ctx *ctx, const hsn_mlp *mlp, const void *x, const float *target, int64_t n,
+                             float *grad, double *loss, void *stream);
+
+typedef struct {
+  int epochs;          /* passes over the data */
+  int batch;           /* rows per Adam step (the last batch of an epoch may be short), 1..65536 */
+  float lr, beta1, beta2, eps;  /* Adam */
+  uint64_t seed;       /* shuffle seed: epoch e visits the rows in a seeded permutation */
+} hsn_train_opts;
+
+/* Adam on the mean squared error over shuffled mini-batches of (x, target).
+ * loss_hist (host, optional, [epochs]): mean loss of the batches of each
+ * epoch.  Adam's step counter persists in the network across calls.  Synchronises
+ * the stream once per epoch. */
+hsn_status hsn_mlp_train(hsn_ctx *ctx, hsn_mlp *mlp, const void *x, const float *target, int64_t n,
+                         const hsn_train_opts *opts, double *loss_hist, void *stream);
+/* V0 [n_p][K] float32 = network(pool(p_bf16)): the pooled inputs go through
+ * the context's workspace. */
+hsn_status hsn_mlp_infer(hsn_ctx *ctx, const hsn_mlp *mlp, const uint16_t *p_bf16, int64_t ldb, int64_t n_p,
+                         int64_t n_k, float *V0, void *stream);
+/* Binary file: magic "HSNMLP01", int32 k, int32 precision, int64 Adam step,
+ * then float32 [n] parameters, [n] Adam first and [n] second moments (little
+ * endian), so training can resume. */
+hsn_status hsn_mlp_save(hsn_ctx *ctx, const hsn_mlp *mlp, const char *path);
+hsn_status hsn_mlp_load(hsn_ctx *ctx, hsn_mlp **mlp, const char *path);
+
+/*
+ * Canonical form of an NMF pair (the factorisation is unique only up to
+ * column scaling and permutation): D's columns scaled to unit l2 norm, V's
+ * scaled inversely (zero columns keep scale 1), then columns reordered, in
+ * place.  With library [n_k][K] float32 (device) the order maximises the sum
+ * of cosines between the reordered D columns and the library columns (first
+ * such permutation in lexicographic order); without it, columns are sorted
+ * by descending l2 norm of the scaled V (stable).  These are the coefficient
+ * targets of the warm-start network.
+ */
+hsn_status hsn_canonicalize(hsn_ctx *ctx, float *V, int64_t n_p, float *D, int64_t n_k, int k,
+                            const float *library, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Kernel timing for roofline reports.                                   */
 /* ------------------------------------------------------------------ */
 
@@ -208,7 +295,10 @@ enum {
   HSN_KERN_BACKPROJECT = 2, /* the adjoint projector kernel */
   HSN_KERN_NORMALIZE = 3,   /* the normalisation stream kernel */
   HSN_KERN_NMF_PASS_BF16 = 4, /* bfloat16 (MFMA) streaming passes over p */
-  HSN_KERN_COUNT = 5
+  HSN_KERN_MLP_ROWS = 5,    /* warm-start network: per-row layers (inference; training forward+backward) */
+  HSN_KERN_MLP_WGRAD = 6,   /* warm-start network: weight-gradient contraction over the batch */
+  HSN_KERN_NNDSVD_GRAM = 7, /* NNDSVD start: the Gram P^T P on MFMA */
+  HSN_KERN_COUNT = 8
 };
 
 /* When on != 0, every launch of the kernels above is bracketed by a pair of

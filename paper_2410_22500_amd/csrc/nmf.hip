@@ -37,6 +37,12 @@ void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w
                      bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img);
 void launch_nnls_rows(int K, hipStream_t st, const NmfWork &w, float *V, int64_t n_p, int n_blocks, int iter);
 size_t nndsvd_ws_bytes(int64_t n_p, int n_k, int K, int n_split);
+size_t mlp_pool_bytes(const hsn_mlp *m, int64_t n_p);
+int mlp_k(const hsn_mlp *m);
+int mlp_device(const hsn_mlp *m);
+hsn_status mlp_nmf_start(hsn_ctx *ctx, hipStream_t st, const hsn_mlp *m, const float *p, int64_t ldp,
+                         const uint16_t *pb, int64_t ldb, int64_t n_p, int n_k, float *V, float *D, void *xbuf,
+                         const NmfWork &w, int n_wg);
 hsn_status nndsvd_init(hsn_ctx *ctx, hipStream_t st, const float *p, int64_t ldp, const uint16_t *pb, int64_t ldb,
                        int64_t n_p, int n_k, int K, float *V, float *D, void *ws, int n_split);
 
@@ -118,8 +124,13 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: polish_algo must be HSN_ALGO_ANLS or HSN_ALGO_HALS");
   if (o->precision != HSN_PREC_FP32 && o->precision != HSN_PREC_BF16)
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: bad precision");
-  if (o->init != HSN_INIT_USER && o->init != HSN_INIT_NNDSVDA)
+  if (o->init != HSN_INIT_USER && o->init != HSN_INIT_NNDSVDA && o->init != HSN_INIT_MLP)
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: bad init");
+  if (o->init == HSN_INIT_MLP) {
+    if (!o->mlp) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: HSN_INIT_MLP needs opts.mlp");
+    if (mlp_k(o->mlp) != o->k) return fail(ctx, HSN_ERR_SHAPE, "nmf: the network's k differs from opts.k");
+    if (mlp_device(o->mlp) != ctx->device) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: network on another device");
+  }
   if (o->max_iter < 0 || o->check_every < 1 || o->polish_rounds < 0)
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: max_iter >= 0, check_every >= 1, polish_rounds >= 0 required");
   if (!V || !D) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: V and D are required");
@@ -129,13 +140,13 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     return fail(ctx, HSN_ERR_UNSUPPORTED, "nmf: ANLS rounds run on the float32 p (bulk precision FP32)");
   // bfloat16 polish rounds exist for HALS only (ANLS rounds read the float32 p).
   const int pol_bf16 = (o->polish_algo == HSN_ALGO_HALS) ? std::min(o->polish_bf16_rounds, o->polish_rounds) : 0;
-  const bool need_f32 = (!bf16 && o->max_iter > 0) || o->polish_rounds > pol_bf16 || o->init == HSN_INIT_NNDSVDA;
+  const bool need_f32 = (!bf16 && o->max_iter > 0) || o->polish_rounds > pol_bf16 || o->init != HSN_INIT_USER;
   if (need_f32) {
     if (!p) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: float32 p is required");
     if (ldp < n_k || ldp % 4 != 0 || reinterpret_cast<uintptr_t>(p) % 16 != 0)
       return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: ldp must be >= n_k and a multiple of 4, p 16-byte aligned");
   }
-  if ((bf16 && o->max_iter > 0) || pol_bf16 > 0) {
+  if ((bf16 && o->max_iter > 0) || pol_bf16 > 0 || o->init == HSN_INIT_MLP) {
     if (!p_bf16) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: p_bf16 is required for the bfloat16 bulk");
     if (ldb < n_k || ldb % 32 != 0 || reinterpret_cast<uintptr_t>(p_bf16) % 16 != 0)
       return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: ldb must be >= n_k and a multiple of 32, p_bf16 16-byte aligned");
@@ -168,7 +179,10 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     n_split = int(std::max<int64_t>(1, std::min<int64_t>(1024 / (n_tb * (n_tb + 1) / 2), n_p / 32)));
     need_init = nndsvd_ws_bytes(n_p, int(n_k), K, n_split);
   }
-  hsn_status rc = ensure_ws(ctx, std::max(need, need_init));
+  // The learned start pools p into a scratch block placed after the NMF's
+  // arrays (its kernels run before the first NMF kernel reads them).
+  const size_t need_pool = o->init == HSN_INIT_MLP ? mlp_pool_bytes(o->mlp, n_p) + 256 : 0;
+  hsn_status rc = ensure_ws(ctx, std::max(need + need_pool, need_init));
   if (rc != HSN_OK) return rc;
   Carver cv(ctx->ws);
   Run R{ctx, st, K, n_p, int(n_k), {}};
@@ -182,6 +196,7 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   R.w.nv = need_nv ? cv.take<float>(n_p * K) : nullptr;
   R.w.hist = cv.take<double>(hist_cap);
   R.w.img = any_bf16 ? cv.take<uint16_t>(bf16_image_elems(ldb)) : nullptr;
+  void *pool_buf = need_pool ? cv.take<char>(need_pool - 256) : nullptr;
   R.w.n_wg = n_wg;
   R.wg_f32 = wg_f32;
   R.wg_bf16 = wg_bf16;
@@ -205,6 +220,9 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   if (stats) HSN_HIP(ctx, hipEventRecord(ctx->ev0, st));
   if (o->init == HSN_INIT_NNDSVDA &&
       (rc = nndsvd_init(ctx, st, p, ldp, p_bf16, ldb, n_p, int(n_k), K, V, D, ctx->ws, n_split)) != HSN_OK)
+    return rc;
+  if (o->init == HSN_INIT_MLP &&
+      (rc = mlp_nmf_start(ctx, st, o->mlp, p, ldp, p_bf16, ldb, n_p, int(n_k), V, D, pool_buf, R.w, wg_f32)) != HSN_OK)
     return rc;
   launch_nmf_init(K, st, D, int(n_k), R.w, !steps.empty() && steps[0].rule == kModeANLS ? 1 : 0,
                   any_bf16 ? bf16_image_ldb(ldb) : 0);

@@ -441,10 +441,12 @@ hsn_status nndsvd_init(hsn_ctx *ctx, hipStream_t st, const float *p, int64_t ldp
   NmfCtrl *ctrl = cv.take<NmfCtrl>(1);
 
   const dim3 g1(unsigned(n_tb * (n_tb + 1) / 2), unsigned(n_split));
+  prof_begin(ctx, HSN_KERN_NNDSVD_GRAM, st);
   if (pb)
     gram_tile_kernel<false><<<g1, 256, 0, st>>>(pb, ldb, n_p, n_k, n_tb, n_split, part);
   else
     gram_tile_kernel<true><<<g1, 256, 0, st>>>(p, ldp, n_p, n_k, n_tb, n_split, part);
+  prof_end(ctx, HSN_KERN_NNDSVD_GRAM, st);
   gram_sum_kernel<<<unsigned((int64_t(n_k) * n_k + 255) / 256), 256, 0, st>>>(part, n_split, n_tb, n_k, G);
   qinit_kernel<<<unsigned((n_k * L + 255) / 256), 256, 0, st>>>(Q, n_k, L);
   for (int it = 0; it < kSubspaceIters; ++it) {

@@ -26,9 +26,11 @@ OK, ERR_INVALID_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_OOM, ERR_DEVICE, ERR_NUMERI
 U16, F32 = 0, 1
 ALGO_MU, ALGO_ANLS, ALGO_HALS = 0, 1, 2
 PREC_FP32, PREC_BF16 = 0, 1
-INIT_USER, INIT_NNDSVDA = 0, 1
+INIT_USER, INIT_NNDSVDA, INIT_MLP = 0, 1, 2
+MLP_IN, MLP_HIDDEN = 256, 128
 
-KERN_NMF_PASS, KERN_PROJECT, KERN_BACKPROJECT, KERN_NORMALIZE, KERN_NMF_PASS_BF16 = range(5)
+(KERN_NMF_PASS, KERN_PROJECT, KERN_BACKPROJECT, KERN_NORMALIZE, KERN_NMF_PASS_BF16, KERN_MLP_ROWS,
+ KERN_MLP_WGRAD, KERN_NNDSVD_GRAM) = range(8)
 
 
 class Dims(C.Structure):
@@ -39,7 +41,12 @@ class NmfOpts(C.Structure):
     _fields_ = [("k", C.c_int), ("algo", C.c_int), ("precision", C.c_int), ("init", C.c_int),
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("polish_rounds", C.c_int),
                 ("polish_algo", C.c_int), ("polish_bf16_rounds", C.c_int), ("rel_obj_tol", C.c_double),
-                ("f_ref", C.c_double)]
+                ("f_ref", C.c_double), ("mlp", C.c_void_p)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
 
 
 class NmfStats(C.Structure):
@@ -76,6 +83,36 @@ _lib.hsn_cgls.restype = C.c_int
 _lib.hsn_rehydrate.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_int, C.c_int64, C.c_int64, C.c_int64,
                                C.c_int64, _P, C.c_int64, _P]
 _lib.hsn_rehydrate.restype = C.c_int
+_lib.hsn_mlp_n_params.argtypes = [C.c_int]
+_lib.hsn_mlp_n_params.restype = C.c_int64
+_lib.hsn_mlp_create.argtypes = [_P, C.POINTER(_P), C.c_int, C.c_int, _P]
+_lib.hsn_mlp_create.restype = C.c_int
+_lib.hsn_mlp_destroy.argtypes = [_P]
+_lib.hsn_mlp_destroy.restype = None
+_lib.hsn_mlp_get_params.argtypes = [_P, _P, _P]
+_lib.hsn_mlp_get_params.restype = C.c_int
+_lib.hsn_mlp_set_params.argtypes = [_P, _P, _P]
+_lib.hsn_mlp_set_params.restype = C.c_int
+_lib.hsn_mlp_k.argtypes = [_P]
+_lib.hsn_mlp_k.restype = C.c_int
+_lib.hsn_mlp_precision.argtypes = [_P]
+_lib.hsn_mlp_precision.restype = C.c_int
+_lib.hsn_mlp_pool.argtypes = [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int, _P, _P]
+_lib.hsn_mlp_pool.restype = C.c_int
+_lib.hsn_mlp_forward.argtypes = [_P, _P, _P, C.c_int64, _P, _P]
+_lib.hsn_mlp_forward.restype = C.c_int
+_lib.hsn_mlp_loss_grad.argtypes = [_P, _P, _P, _P, C.c_int64, _P, _P, _P]
+_lib.hsn_mlp_loss_grad.restype = C.c_int
+_lib.hsn_mlp_train.argtypes = [_P, _P, _P, _P, C.c_int64, C.POINTER(TrainOpts), _P, _P]
+_lib.hsn_mlp_train.restype = C.c_int
+_lib.hsn_mlp_infer.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_int64, _P, _P]
+_lib.hsn_mlp_infer.restype = C.c_int
+_lib.hsn_mlp_save.argtypes = [_P, _P, C.c_char_p]
+_lib.hsn_mlp_save.restype = C.c_int
+_lib.hsn_mlp_load.argtypes = [_P, C.POINTER(_P), C.c_char_p]
+_lib.hsn_mlp_load.restype = C.c_int
+_lib.hsn_canonicalize.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, C.c_int, _P, _P]
+_lib.hsn_canonicalize.restype = C.c_int
 _lib.hsn_profile_enable.argtypes = [_P, C.c_int]
 _lib.hsn_profile_enable.restype = C.c_int
 _lib.hsn_profile_read.argtypes = [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
@@ -164,13 +201,13 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
                      D: torch.Tensor, algo: int = ALGO_MU, precision: int = PREC_FP32, max_iter: int = 100,
                      check_every: int = 10, polish_rounds: int = 0, polish_algo: int = ALGO_ANLS,
                      polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0,
-                     init: int = INIT_USER, history_cap: int = 4096) -> dict:
+                     init: int = INIT_USER, mlp: Optional["Mlp"] = None, history_cap: int = 4096) -> dict:
     """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device)."""
     dev = _dev(V)
     ctx = context(dev)
     n_p, k = V.shape
     opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo,
-                   polish_bf16_rounds, rel_obj_tol, f_ref)
+                   polish_bf16_rounds, rel_obj_tol, f_ref, mlp.handle if mlp is not None else None)
     hist = (C.c_double * max(history_cap, 1))()
     stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0)
     ldp = p.stride(0) if p is not None else 0
@@ -250,3 +287,133 @@ def hsn_profile_read(kernel: int, reset: bool = True, device: int = 0):
     n = C.c_int64(0)
     _check(_lib.hsn_profile_read(ctx, kernel, C.byref(ms), C.byref(n), int(reset)), ctx)
     return ms.value, n.value
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start
+# ---------------------------------------------------------------------------
+
+def hsn_mlp_n_params(k: int) -> int:
+    return int(_lib.hsn_mlp_n_params(k))
+
+
+class Mlp:
+    """Owner of an hsn_mlp handle (256-128-128-K network on one device)."""
+
+    def __init__(self, handle, device: int):
+        self.handle = handle
+        self.device = device
+        self.k = int(_lib.hsn_mlp_k(handle))
+        self.precision = int(_lib.hsn_mlp_precision(handle))
+        self.n_params = hsn_mlp_n_params(self.k)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.hsn_mlp_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def x_dtype(self):
+        return torch.int16 if self.precision == PREC_BF16 else torch.float32
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.n_params, np.float32)
+        ctx = context(self.device)
+        _check(_lib.hsn_mlp_get_params(ctx, self.handle, _P(out.ctypes.data)), ctx)
+        return out
+
+    def set_params(self, params) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(params, np.float32)
+        if a.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {a.size}")
+        ctx = context(self.device)
+        _check(_lib.hsn_mlp_set_params(ctx, self.handle, _P(a.ctypes.data)), ctx)
+
+
+def hsn_mlp_create(k: int, precision: int = PREC_BF16, params=None, device: int = 0) -> Mlp:
+    import numpy as np
+    ctx = context(device)
+    h = _P()
+    a = None if params is None else np.ascontiguousarray(params, np.float32)
+    if a is not None and a.size != hsn_mlp_n_params(k):
+        raise ValueError("wrong parameter count")
+    _check(_lib.hsn_mlp_create(ctx, C.byref(h), k, precision, None if a is None else _P(a.ctypes.data)), ctx)
+    return Mlp(h, device)
+
+
+def hsn_mlp_pool(p_bf16: torch.Tensor, n_k: int, x_dtype: int = PREC_BF16) -> torch.Tensor:
+    """[N_p][ldb] bfloat16 bits -> [N_p][256] pooled (int16 bits or float32)."""
+    dev = _dev(p_bf16)
+    ctx = context(dev)
+    n_p = p_bf16.shape[0]
+    x = torch.empty((n_p, MLP_IN), dtype=torch.int16 if x_dtype == PREC_BF16 else torch.float32,
+                    device=p_bf16.device)
+    _check(_lib.hsn_mlp_pool(ctx, _ptr(p_bf16), p_bf16.stride(0), n_p, n_k, x_dtype, _ptr(x), _stream(dev)), ctx)
+    return x
+
+
+def hsn_mlp_forward(mlp: Mlp, x: torch.Tensor) -> torch.Tensor:
+    dev = _dev(x)
+    ctx = context(dev)
+    assert x.dtype == mlp.x_dtype and x.shape[1] == MLP_IN and x.is_contiguous()
+    y = torch.empty((x.shape[0], mlp.k), dtype=torch.float32, device=x.device)
+    _check(_lib.hsn_mlp_forward(ctx, mlp.handle, _ptr(x), x.shape[0], _ptr(y), _stream(dev)), ctx)
+    return y
+
+
+def hsn_mlp_loss_grad(mlp: Mlp, x: torch.Tensor, target: torch.Tensor):
+    """(mean squared error, flat gradient [n_params]) over all rows as one batch."""
+    dev = _dev(x)
+    ctx = context(dev)
+    assert x.dtype == mlp.x_dtype and x.is_contiguous() and target.is_contiguous()
+    g = torch.empty(mlp.n_params, dtype=torch.float32, device=x.device)
+    loss = torch.empty((), dtype=torch.float64, device=x.device)
+    _check(_lib.hsn_mlp_loss_grad(ctx, mlp.handle, _ptr(x), _ptr(target), x.shape[0], _ptr(g), _ptr(loss),
+                                  _stream(dev)), ctx)
+    return loss, g
+
+
+def hsn_mlp_train(mlp: Mlp, x: torch.Tensor, target: torch.Tensor, epochs: int, batch: int = 4096,
+                  lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, seed: int = 0):
+    """Adam over shuffled mini-batches; returns the per-epoch mean batch loss."""
+    dev = _dev(x)
+    ctx = context(dev)
+    assert x.dtype == mlp.x_dtype and x.is_contiguous() and target.is_contiguous()
+    o = TrainOpts(epochs, batch, lr, beta1, beta2, eps, seed)
+    hist = (C.c_double * max(epochs, 1))()
+    _check(_lib.hsn_mlp_train(ctx, mlp.handle, _ptr(x), _ptr(target), x.shape[0], C.byref(o),
+                              C.cast(hist, _P), _stream(dev)), ctx)
+    return [hist[i] for i in range(epochs)]
+
+
+def hsn_mlp_infer(mlp: Mlp, p_bf16: torch.Tensor, n_k: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    dev = _dev(p_bf16)
+    ctx = context(dev)
+    n_p = p_bf16.shape[0]
+    if out is None:
+        out = torch.empty((n_p, mlp.k), dtype=torch.float32, device=p_bf16.device)
+    _check(_lib.hsn_mlp_infer(ctx, mlp.handle, _ptr(p_bf16), p_bf16.stride(0), n_p, n_k, _ptr(out),
+                              _stream(dev)), ctx)
+    return out
+
+
+def hsn_mlp_save(mlp: Mlp, path: str) -> None:
+    ctx = context(mlp.device)
+    _check(_lib.hsn_mlp_save(ctx, mlp.handle, os.fsencode(path)), ctx)
+
+
+def hsn_mlp_load(path: str, device: int = 0) -> Mlp:
+    ctx = context(device)
+    h = _P()
+    _check(_lib.hsn_mlp_load(ctx, C.byref(h), os.fsencode(path)), ctx)
+    return Mlp(h, device)
+
+
+def hsn_canonicalize(V: torch.Tensor, D: torch.Tensor, library: Optional[torch.Tensor] = None) -> None:
+    """In place: unit-norm D columns, V scaled inversely, columns matched to library (or by |V|)."""
+    dev = _dev(V)
+    ctx = context(dev)
+    n_p, k = V.shape
+    _check(_lib.hsn_canonicalize(ctx, _ptr(V), n_p, _ptr(D), D.shape[0], k, _ptr(library), _stream(dev)), ctx)

@@ -45,3 +45,19 @@ def test_null_context_is_invalid_arg(lib):
     assert lib.hsn_rehydrate(None, v(), v(), C.c_int64(1), C.c_int64(1), 1, C.c_int64(0), C.c_int64(1),
                              C.c_int64(0), C.c_int64(1), v(), C.c_int64(1), v()) == 1
     assert lib.hsn_last_error(None) == b"null context"
+
+
+def test_mlp_entry_points_validate_on_host(lib):
+    v = C.c_void_p
+    lib.hsn_mlp_n_params.restype = C.c_int64
+    # 256*128 + 128 + 128*128 + 128 + 128*K + K parameters
+    assert lib.hsn_mlp_n_params(4) == 49924
+    assert lib.hsn_mlp_n_params(1) == 49408 + 129
+    assert lib.hsn_mlp_n_params(0) == -1 and lib.hsn_mlp_n_params(9) == -1
+    lib.hsn_mlp_k.argtypes = [v]
+    assert lib.hsn_mlp_k(None) == -1
+    assert lib.hsn_mlp_create(None, v(), 4, 1, v()) == 1
+    assert lib.hsn_mlp_train(None, v(), v(), v(), C.c_int64(1), v(), v(), v()) == 1
+    assert lib.hsn_mlp_infer(None, v(), v(), C.c_int64(0), C.c_int64(0), C.c_int64(1), v(), v()) == 1
+    assert lib.hsn_canonicalize(None, v(), C.c_int64(1), v(), C.c_int64(1), 1, v(), v()) == 1
+    lib.hsn_mlp_destroy(None)

@@ -50,7 +50,7 @@ def _check(Vg, Dg, W, H, gaps):
         ev, ed = rel_fro(Vg[:, j], W[:, j]), rel_fro(Dg[:, j], H[:, j])
         show("  col", j=j, gap=gaps[j], V=ev, D=ed)
         assert ev <= TOL and ed <= TOL
-    return len(det) == len(gaps) - 1
+    return len(det) == len(gaps)
 
 
 def _mu50_matches(hsn, P, pd, n_k, V, D, W, H, tol):
@@ -76,7 +76,7 @@ def test_nndsvda_matches_oracle(hsn, case, k):
     D = torch.zeros((n_k, k), dtype=torch.float32, device="cuda")
     show("nndsvda", case=case, k=k)
     hsn.hsn_subspace_nmf(pd, None, n_k, V, D, init=hsn.INIT_NNDSVDA, max_iter=0)
-    unique = _check(V.cpu().numpy(), D.cpu().numpy(), W, H, _gaps(P, k + 1))
+    unique = _check(V.cpu().numpy(), D.cpu().numpy(), W, H, _gaps(P, k))
     _mu50_matches(hsn, P, pd, n_k, V, D, W, H, 1e-3 if unique else 1e-2)
 
 
@@ -94,7 +94,7 @@ def test_nndsvda_mid_with_bf16_gram(hsn):
     show("nndsvda mid")
     st = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, init=hsn.INIT_NNDSVDA, max_iter=0)
     show("  ms", ms=st["ms"])
-    _check(V.cpu().numpy(), D.cpu().numpy(), W, H, _gaps(P, k + 1))
+    _check(V.cpu().numpy(), D.cpu().numpy(), W, H, _gaps(P, k))
 
 
 def test_nndsvda_needs_fp32_p(hsn):
