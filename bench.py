@@ -2,25 +2,30 @@
 """Benchmark of the fast-hyperspectral-reconstruction hot path on one GPU.
 
 One step = the whole path over one synthetic scan already resident in HBM:
-  -log normalisation of the counts (eq. 2)
+  -log normalisation of the counts (eq. 2), float32 p and its bfloat16 copy
   -> NMF subspace decomposition until the relative objective (f - f*)/f*
-     reaches 1e-4 (eq. 4): multiplicative-update bulk, then exact ANLS
-     polish on the float32 p
+     reaches 1e-4 (eq. 4): learned start (the warm-start network on MFMA over
+     the pooled bfloat16 p, then D0 by exact NNLS), then exact ANLS rounds on
+     the float32 p with FP64 K x K Cholesky solves
   -> 20 CGLS iterations (20 A / A^T pairs) on all K channels (eq. 5, h = 0)
   -> expansion of one slice to every bin (eq. 6).
 
-value = view*pixel*bins of the scan / step time.  The NMF-only rate, the
-projector voxel-rays/s and each kernel's share are reported beside it.
-f* (the stationary objective of the instance) is computed before timing by
-running the same float32 path to stationarity.
+value = view*pixel*bins of the scan / step time.  Before timing (not timed):
+the warm-start network is trained on the GPU on decompositions of 348
+tiny-geometry scans made of the workload's materials (2.0 M spectra), and
+f* is the lowest objective of long reference runs.  Beside the flagship
+path, the plain FP32 path (NNDSVDa start, float32 MU bulk, ANLS polish) and
+the cold BF16 path (NNDSVDa, bfloat16 MFMA MU bulk, ANLS polish) are timed
+to the same relative objective.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mid|tiny]
-                [--no-cpu-baseline]
+                [--mlp-scans N] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -32,8 +37,12 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+VALU_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed)
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 REL_OBJ = 1e-4
 CGLS_ITERS = 20
+BULK = 200
+POLISH_CAP = 1500
 
 
 def parse():
@@ -42,13 +51,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mid", choices=["mid", "tiny"])
-    ap.add_argument("--bulk-iters", type=int, default=200)
-    ap.add_argument("--polish-rounds", type=int, default=600)
-    ap.add_argument("--check-every", type=int, default=200)
-    ap.add_argument("--polish-bf16", type=int, default=0,
-                    help="the first polish rounds run on the bfloat16 copy of p")
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"],
-                    help="bulk iterations on the bfloat16 copy of p (MFMA) or on the float32 p")
+    ap.add_argument("--mlp-scans", type=int, default=348)
+    ap.add_argument("--mlp-epochs", type=int, default=20)
+    ap.add_argument("--compare-steps", type=int, default=2,
+                    help="steps of each comparison path (plain FP32, cold BF16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
 
@@ -61,15 +67,16 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "the hot path's multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+              "how the path would shard is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
     import synth
-    from paper_2410_22500_amd import hsn
+    from paper_2410_22500_amd import hsn, warmstart
 
     dev = torch.device("cuda:0")
     t0 = time.time()
+    cfg = synth.CONFIGS[args.workload]
     sc = synth.config_scan(args.workload)
     K = sc.n_mat
     n_p, n_k = sc.n_p, sc.n_bins
@@ -78,37 +85,44 @@ def main():
         f"({vpb:.3e} vpb), generated in {time.time() - t0:.1f}s")
     y = torch.from_numpy(sc.y.view(np.int16)).to(dev)
     yo = torch.from_numpy(sc.yo.view(np.int16)).to(dev)
-    V0n, D0n = synth.random_factors(n_p, n_k, K, 1000 + sc.n_views)
-    V0 = torch.from_numpy(V0n.astype(np.float32)).to(dev)
-    D0 = torch.from_numpy(D0n.astype(np.float32)).to(dev)
-    V = torch.empty_like(V0)
-    D = torch.empty_like(D0)
+    V = torch.empty((n_p, K), dtype=torch.float32, device=dev)
+    D = torch.empty((n_k, K), dtype=torch.float32, device=dev)
 
-    # f*: the lowest objective reached by long float32 runs of two schedules
-    # (MU then ANLS to stationarity; MU then HALS), not timed.
-    p, _, _, _ = hsn.hsn_normalize(y, yo)
-    refs = []
-    for algo_p, rounds in ((hsn.ALGO_ANLS, 800), (hsn.ALGO_HALS, 3000)):
-        V.copy_(V0)
-        D.copy_(D0)
-        st = hsn.hsn_subspace_nmf(p, None, n_k, V, D, max_iter=args.bulk_iters, check_every=args.bulk_iters,
-                                  polish_rounds=rounds, polish_algo=algo_p)
-        hist = np.array(st["history"])
-        refs.append(float(hist.min()))
-        log(f"reference run polish={algo_p}: min f {hist.min():.9e}, last rel change "
-            f"{abs(hist[-2] - hist[-1]) / hist[-1]:.2e}")
-    f_star = min(refs)
+    # Warm-start network: trained on the workload's material library (not timed).
+    t0 = time.time()
+    X, T, tt = warmstart.make_training_set(args.mlp_scans, k=K, library_seed=cfg["seed"],
+                                           log=lambda s: log(s))
+    mlp, loss_hist, t_train = warmstart.train(X, T, k=K, epochs=args.mlp_epochs)
+    n_train = int(X.shape[0])
+    del X, T
+    log(f"network: {n_train} spectra, training {t_train:.2f}s, loss {loss_hist[0]:.3g} -> {loss_hist[-1]:.3g} "
+        f"(set-up {time.time() - t0:.1f}s)")
 
-    bf16 = args.precision == "bf16"
+    # f*: lowest objective of long float32 reference runs (not timed).
+    p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=True)
+    refs = {}
+    for name, kw in (("nndsvda+mu+anls", dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, polish_algo=hsn.ALGO_ANLS,
+                                              polish_rounds=2000)),
+                     ("nndsvda+mu+hals", dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, polish_algo=hsn.ALGO_HALS,
+                                              polish_rounds=3000)),
+                     ("learned+anls", dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0, polish_algo=hsn.ALGO_ANLS,
+                                           polish_rounds=2000))):
+        st = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, **kw)
+        h = np.array(st["history"])
+        refs[name] = float(h.min())
+        log(f"reference {name}: min f {h.min():.9e}, last rel change {abs(h[-2] - h[-1]) / h[-1]:.2e}")
+    f_star = min(refs.values())
 
-    def step(record=None):
-        p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=bf16)
-        V.copy_(V0)
-        D.copy_(D0)
-        s = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, max_iter=args.bulk_iters, check_every=args.check_every,
-                                 precision=hsn.PREC_BF16 if bf16 else hsn.PREC_FP32,
-                                 polish_rounds=args.polish_rounds, polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ,
-                                 polish_bf16_rounds=args.polish_bf16 if bf16 else 0, f_ref=f_star)
+    paths = {
+        "learned": dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0),
+        "plain_fp32": dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, precision=hsn.PREC_FP32),
+        "cold_bf16": dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, precision=hsn.PREC_BF16),
+    }
+
+    def step(path, record=None):
+        p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=True)
+        s = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, polish_rounds=POLISH_CAP,
+                                 polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star, **paths[path])
         sino = V.view(sc.n_views, sc.n_rows, sc.n_cols, K)
         x = hsn.hsn_cgls(sino, CGLS_ITERS)
         hsn.hsn_rehydrate(x.view(-1, K), D, vox=(0, sc.n_cols * sc.n_cols), bins=(0, n_k))
@@ -116,62 +130,89 @@ def main():
             record.append(s)
         return s
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    def timed(path, steps, profile):
+        if profile:
+            hsn.hsn_profile_enable(True)
+            for kk in range(hsn.KERN_COUNT):
+                hsn.hsn_profile_read(kk, reset=True)
+        recs = []
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            step(path, recs)
+        e1.record()
+        torch.cuda.synchronize()
+        prof = {}
+        if profile:
+            hsn.hsn_profile_enable(False)
+            prof = {kk: hsn.hsn_profile_read(kk) for kk in range(hsn.KERN_COUNT)}
+        return e0.elapsed_time(e1) / steps, recs, prof
 
-    hsn.hsn_profile_enable(True)
-    for kk in (hsn.KERN_NMF_PASS, hsn.KERN_NMF_PASS_BF16, hsn.KERN_PROJECT, hsn.KERN_BACKPROJECT, hsn.KERN_NORMALIZE):
-        hsn.hsn_profile_read(kk, reset=True)
-    recs = []
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step(recs)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_total = e0.elapsed_time(e1)
-    hsn.hsn_profile_enable(False)
-    ms_step = ms_total / args.steps
+    for _ in range(args.warmup):
+        step("learned")
+    ms_step, recs, prof = timed("learned", args.steps, True)
     nmf_ms = float(np.mean([r["ms"] for r in recs]))
     reached = all(r["rel_obj"] <= REL_OBJ for r in recs)
-    pass_ms, pass_n = hsn.hsn_profile_read(hsn.KERN_NMF_PASS)
-    bpass_ms, bpass_n = hsn.hsn_profile_read(hsn.KERN_NMF_PASS_BF16)
-    prj_ms, prj_n = hsn.hsn_profile_read(hsn.KERN_PROJECT)
-    bpj_ms, bpj_n = hsn.hsn_profile_read(hsn.KERN_BACKPROJECT)
-    nrm_ms, nrm_n = hsn.hsn_profile_read(hsn.KERN_NORMALIZE)
+    log(f"learned path: {ms_step:.3f} ms/step, NMF {nmf_ms:.3f} ms, rounds {recs[-1]['polish_done']}, "
+        f"rel obj {recs[-1]['rel_obj']:.3e}")
 
-    # Algorithmic bytes of the streaming passes over p, per kind:
-    #   bfloat16 MU bulk pass: 2 B per element of p + V read and written (8K B per row);
-    #   float32 ANLS round = N_V pass (4 B per element + N_V written) and
-    #   N_D pass (4 B per element + V read).
-    # Launches queued after the stop test fired return at once; they are
-    # counted in the measured time (a few us each), so the rates are conservative.
-    it, pol = recs[-1]["iters"], recs[-1]["polish_done"]
+    compare = {}
+    for path in ("plain_fp32", "cold_bf16"):
+        step(path)
+        ms_p, rp, _ = timed(path, args.compare_steps, False)
+        nm = float(np.mean([r["ms"] for r in rp]))
+        compare[path] = {"ms_per_step": ms_p, "nmf_ms": nm, "nmf_vpb_per_s": vpb / (nm * 1e-3),
+                         "mu_iters": rp[-1]["iters"], "anls_rounds": rp[-1]["polish_done"],
+                         "rel_obj": rp[-1]["rel_obj"], "reached": all(r["rel_obj"] <= REL_OBJ for r in rp)}
+        log(f"{path}: {ms_p:.3f} ms/step, NMF {nm:.3f} ms, {rp[-1]['iters']} MU + {rp[-1]['polish_done']} ANLS, "
+            f"rel obj {rp[-1]['rel_obj']:.3e}")
+
+    # Roofline of each profiled kernel kind over the timed region: algorithmic
+    # bytes (or flops) per launch / average launch time.
+    rounds = sum(r["polish_done"] for r in recs)
     elems = float(n_p) * n_k
-    vbytes = 4.0 * n_p * K
-    kinds = {}
-    b_bytes = sum(r["iters"] for r in recs) * ((2.0 if bf16 else 4.0) * elems + 2 * vbytes)
-    f_bytes = sum(r["polish_done"] for r in recs) * 2 * (4.0 * elems + vbytes)
-    b_launch = sum(r["iters"] for r in recs)
-    f_launch = sum(2 * r["polish_done"] for r in recs)
-    if not bf16:
-        f_bytes, f_launch = f_bytes + b_bytes, f_launch + b_launch
-        b_bytes, b_launch = 0.0, 0
-    if b_launch:
-        kinds["nmf pass bfloat16 MFMA (pass_bf16_kernel, MU bulk)"] = (b_bytes, b_launch, bpass_ms)
-    if f_launch:
-        kinds["nmf pass float32 (pass_f32_kernel, ANLS N_V/N_D)" if bf16 else
-              "nmf pass float32 (pass_f32_kernel)"] = (f_bytes, f_launch, pass_ms)
-    dom = max(kinds, key=lambda k: kinds[k][2])
+    vb = 4.0 * n_p * K
+    taps = 2.0 * float(np.mean([max(abs(math.cos(v * math.pi / sc.n_views)), abs(math.sin(v * math.pi / sc.n_views)))
+                                for v in range(sc.n_views)]))
+    triples = float(sc.n_views) * sc.n_rows * sc.n_cols * sc.n_cols * K
+    mlp_flops_row = 2.0 * (256 * 128 + 128 * 128 + 128 * 16)
+    work = {  # kind -> (name, total algorithmic units over the timed region, bound, unit)
+        hsn.KERN_NORMALIZE: ("normalize_kernel (u16 counts -> f32 p + bf16 p)",
+                             args.steps * (8.0 * elems + 2.0 * sc.n_rows * sc.n_cols * n_k), "hbm"),
+        hsn.KERN_NMF_PASS: ("pass_f32_kernel (N_V / N_D passes over f32 p)",
+                            args.steps * (4.0 * elems + vb) + rounds * 2 * (4.0 * elems + vb), "hbm"),
+        hsn.KERN_MLP_POOL: ("pool_kernel (bf16 p -> 256-bin pooled rows)",
+                            args.steps * (2.0 * elems + 512.0 * n_p), "hbm"),
+        hsn.KERN_MLP_ROWS: ("mlp_rows_kernel (network inference, bf16 MFMA)",
+                            args.steps * mlp_flops_row * n_p, "mfma"),
+        hsn.KERN_PROJECT: ("project_kernel (A, Joseph footprint, K channels)", None, "alu"),
+        hsn.KERN_BACKPROJECT: ("backproject_kernel (A^T)", None, "alu"),
+    }
+    # Float32 passes that did work: one N_D pass for D0 per step and two passes
+    # per ANLS round; passes queued after the stop test fired return at once,
+    # their time stays in the total (so the rate is conservative).
+    real = {hsn.KERN_NMF_PASS: args.steps + 2 * rounds}
     roof = {}
-    for name, (by, nl, ms) in kinds.items():
-        ach = by / (ms * 1e-3) / 1e9
-        roof[name] = {"achieved": ach, "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": ms / nl, "launches": nl,
-                      "alg_bytes_per_launch": by / nl}
-    vox_rays = sc.n_views * sc.n_rows * sc.n_cols * sc.n_cols * K
+    for kk, (name, units, bound) in work.items():
+        ms, n = prof.get(kk, (0.0, 0))
+        if n == 0:
+            continue
+        queued = n
+        n = real.get(kk, n)
+        if bound == "alu":
+            units = n * 2.0 * taps * triples
+        peak, unit = {"hbm": (HBM_PEAK_GBS, "GB/s"), "alu": (VALU_PEAK_TFLOPS, "TFLOP/s"),
+                      "mfma": (MFMA_BF16_PEAK_TFLOPS, "TFLOP/s")}[bound]
+        ach = units / (ms * 1e-3) / (1e9 if unit == "GB/s" else 1e12)
+        roof[name] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                      "avg_launch_ms": ms / n, "launches": n, "queued": queued, "total_ms": ms,
+                      "alg_per_launch": units / n}
+    dom = max(roof, key=lambda k: roof[k]["total_ms"])
+    d = roof[dom]
+    prj = roof.get(work[hsn.KERN_PROJECT][0])
+    bpj = roof.get(work[hsn.KERN_BACKPROJECT][0])
 
     out = {
         "metric": "view*pixel*bins decomposed/s at rel obj 1e-4 (whole hot-path step)",
@@ -184,36 +225,42 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+f32" if bf16 else "f32",
+        "dtype": "bf16+f32",
         "data": "synthetic (seeded phantom, Bragg-edge-like spectra, Poisson counts)",
         "config": {"workload": f"{args.workload}: {sc.n_rows} slices x {sc.n_cols}^2, {sc.n_views} views, "
                                f"{n_k} bins, K={K}, flux {sc.flux:g}",
-                   "nmf": f"{args.precision} bulk: {args.bulk_iters} MU, then ANLS polish ({args.polish_bf16 if bf16 else 0} rounds bf16, rest float32) until rel obj {REL_OBJ:g}",
+                   "nmf": f"learned start (bf16 MFMA network, {n_train} training spectra) + ANLS polish until "
+                          f"rel obj {REL_OBJ:g}",
                    "recon": f"CGLS {CGLS_ITERS} pairs", "parallelism": "single GPU"},
-        "nmf": {"vpb_per_s": vpb / (nmf_ms * 1e-3), "ms": nmf_ms, "mu_iters": it, "polish_rounds": pol,
-                "rel_obj": recs[-1]["rel_obj"], "reached": reached, "f_star": f_star},
-        "projector": {"voxel_rays_per_s_A": vox_rays / (prj_ms / prj_n * 1e-3),
-                      "voxel_rays_per_s_AT": vox_rays / (bpj_ms / bpj_n * 1e-3),
-                      "ms_A": prj_ms / prj_n, "ms_AT": bpj_ms / bpj_n},
-        "normalize_ms": nrm_ms / max(nrm_n, 1),
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": roof[dom]["achieved"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": roof[dom]["frac"], "traffic": None,
-                     "avg_launch_ms": roof[dom]["avg_launch_ms"], "launches": roof[dom]["launches"],
-                     "alg_bytes_per_launch": roof[dom]["alg_bytes_per_launch"], "all_passes": roof},
+        "nmf": {"vpb_per_s": vpb / (nmf_ms * 1e-3), "ms": nmf_ms, "anls_rounds": recs[-1]["polish_done"],
+                "rel_obj": recs[-1]["rel_obj"], "reached": reached, "f_star": f_star, "references": refs},
+        "compare": compare,
+        "speedup_vs_plain_fp32": {"nmf": compare["plain_fp32"]["nmf_ms"] / nmf_ms,
+                                  "step": compare["plain_fp32"]["ms_per_step"] / ms_step},
+        "network": {"train_spectra": n_train, "epochs": args.mlp_epochs, "train_s": t_train,
+                    "loss_first": loss_hist[0], "loss_last": loss_hist[-1]},
+        "projector": {"voxel_rays_per_s_A": triples / (prj["avg_launch_ms"] * 1e-3) if prj else None,
+                      "voxel_rays_per_s_AT": triples / (bpj["avg_launch_ms"] * 1e-3) if bpj else None,
+                      "ms_A": prj["avg_launch_ms"] if prj else None, "ms_AT": bpj["avg_launch_ms"] if bpj else None},
+        "roofline": {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+                     "unit": d["unit"], "frac": d["frac"], "traffic": None,
+                     "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
+                     "alg_per_launch": d["alg_per_launch"], "all_kernels": roof},
     }
-
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, V0n, D0n, it, pol)
+        out["cpu_baseline"] = cpu_baseline(sc, compare["plain_fp32"]["mu_iters"],
+                                           compare["plain_fp32"]["anls_rounds"])
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(sc, V0n, D0n, mu_iters, polish_rounds):
+def cpu_baseline(sc, mu_iters, polish_rounds):
     """The FP64 oracle as it stands, on a bounded sample of the same workload:
-    detector row 0 (1 of N_r slices).  Normalisation, CGLS and the expansion
-    run in full on that slice.  The NMF is timed on the first quarter of the
-    slice's rays (10 MU iterations, 1 ANLS round) and extrapolated linearly
-    in rows and per iteration to the slice and the counts the GPU needed.
-    Rate in vpb/s of the slice."""
+    detector row 0 (1 of N_r slices), running the plain method (NNDSVDa, MU,
+    ANLS) with the iteration counts the plain FP32 GPU path needed.
+    Normalisation, NNDSVDa, CGLS and the expansion run in full on that slice;
+    the NMF iterations are timed on the first quarter of the slice's rays (10
+    MU iterations, 1 ANLS round) and extrapolated linearly in rows and per
+    iteration.  Rate in vpb/s of the slice."""
     from threadpoolctl import threadpool_info
     from oracle import cgls as ocgls
     from oracle import expand as oexp
@@ -223,12 +270,13 @@ def cpu_baseline(sc, V0n, D0n, mu_iters, polish_rounds):
     K = sc.n_mat
     ysub = sc.y[:, :1]
     yosub = sc.yo[:1]
-    rows = np.arange(sc.n_p).reshape(sc.n_views, sc.n_rows, sc.n_cols)[:, 0].ravel()
     t0 = time.perf_counter()
     p, _, _ = onorm(ysub, yosub)
     t_norm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    V, D = onmf.nndsvd(p, K, variant="a")
+    t_init = time.perf_counter() - t0
     q = max(1, p.shape[0] // 4)
-    V, D = V0n[rows].astype(np.float32).astype(np.float64), D0n.astype(np.float32).astype(np.float64)
     n_mu = min(mu_iters, 10)
     t0 = time.perf_counter()
     Vq, Dq, _, _ = onmf.mu_run(p[:q], V[:q], D, n_mu)
@@ -241,14 +289,15 @@ def cpu_baseline(sc, V0n, D0n, mu_iters, polish_rounds):
     x = ocgls.cgls(sino, sc.n_cols, CGLS_ITERS)
     oexp.rehydrate(x.reshape(-1, K), D)
     t_rec = time.perf_counter() - t0
-    t = t_norm + t_mu * mu_iters + t_an * polish_rounds + t_rec
+    t = t_norm + t_init + t_mu * mu_iters + t_an * polish_rounds + t_rec
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     vpb = p.shape[0] * p.shape[1]
     return {"value": vpb / t, "unit": "vpb/s", "cores": threads, "kind": "oracle",
-            "sample": f"detector row 0 of {sc.n_rows} ({p.shape[0]} x {p.shape[1]}): normalise, CGLS {CGLS_ITERS}, "
-                      f"expansion in full; NMF timed on {q} rays ({n_mu} MU, 1 ANLS) and extrapolated to "
-                      f"{mu_iters} MU + {polish_rounds} ANLS on the slice; {t:.1f}s total (estimate) on "
-                      f"{os.cpu_count()} host cpus ({platform.processor() or platform.machine()})",
+            "sample": f"detector row 0 of {sc.n_rows} ({p.shape[0]} x {p.shape[1]}): normalise, NNDSVDa, "
+                      f"CGLS {CGLS_ITERS}, expansion in full; NMF iterations timed on {q} rays ({n_mu} MU, "
+                      f"1 ANLS) and extrapolated to {mu_iters} MU + {polish_rounds} ANLS on the slice; "
+                      f"{t:.1f}s total (estimate) on {os.cpu_count()} host cpus "
+                      f"({platform.processor() or platform.machine()})",
             "seconds": t}
 
 

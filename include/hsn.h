@@ -298,7 +298,8 @@ enum {
   HSN_KERN_MLP_ROWS = 5,    /* warm-start network: per-row layers (inference; training forward+backward) */
   HSN_KERN_MLP_WGRAD = 6,   /* warm-start network: weight-gradient contraction over the batch */
   HSN_KERN_NNDSVD_GRAM = 7, /* NNDSVD start: the Gram P^T P on MFMA */
-  HSN_KERN_COUNT = 8
+  HSN_KERN_MLP_POOL = 8,    /* warm-start network: pooling of p_bf16 rows to 256 bins */
+  HSN_KERN_COUNT = 9
 };
 
 /* When on != 0, every launch of the kernels above is bracketed by a pair of

@@ -761,10 +761,12 @@ hsn_status check_mlp(hsn_ctx *ctx, const hsn_mlp *m) {
 hsn_status mlp_infer_into(hsn_ctx *ctx, const hsn_mlp *m, const uint16_t *pb, int64_t ldb, int64_t n_p, int n_k,
                           float *V0, void *xbuf, hipStream_t st) {
   const int nbp = int(std::min<int64_t>((n_p + kWaves - 1) / kWaves, 16 * int64_t(ctx->num_cu)));
+  prof_begin(ctx, HSN_KERN_MLP_POOL, st);
   if (m->prec == HSN_PREC_BF16)
     pool_kernel<uint16_t><<<nbp, 256, 0, st>>>(pb, ldb, n_p, n_k, static_cast<uint16_t *>(xbuf));
   else
     pool_kernel<float><<<nbp, 256, 0, st>>>(pb, ldb, n_p, n_k, static_cast<float *>(xbuf));
+  prof_end(ctx, HSN_KERN_MLP_POOL, st);
   RowsArgs ra{};
   ra.x = xbuf;
   ra.ldx = kIn;

@@ -227,13 +227,21 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   launch_nmf_init(K, st, D, int(n_k), R.w, !steps.empty() && steps[0].rule == kModeANLS ? 1 : 0,
                   any_bf16 ? bf16_image_ldb(ldb) : 0);
   HSN_LAUNCHED(ctx);
-  // Queue in chunks; between chunks read stop_at once (only when a stop test is on).
-  const int chunk = 32;
-  int issued = 0;
+  // Queue in chunks; between chunks read stop_at once (only when a stop test
+  // is on).  The stop can only fire at a step that evaluates the objective, so
+  // a chunk ends after a number of such steps that starts at 2 and doubles up
+  // to 32: a run that converges early (a learned start) queues few launches
+  // past its stop, a long run pays few host round trips.
+  int issued = 0, chunk_obj = 2;
   NmfCtrl hc{};
   hc.stop_at = INT32_MAX;
   while (issued < int(steps.size())) {
-    const int end = std::min<int>(int(steps.size()), issued + chunk);
+    int end = issued, n_obj = 0;
+    while (end < int(steps.size()) && n_obj < chunk_obj) {
+      if (steps[end].obj || steps[end].rule == kModeANLS) ++n_obj;
+      ++end;
+    }
+    chunk_obj = std::min(2 * chunk_obj, 32);
     for (int i = issued; i < end; ++i) {
       const bool next_exact = (i + 1 < int(steps.size())) && steps[i + 1].rule == kModeANLS;
       if ((rc = queue_step(R, steps[i], i, next_exact, p, ldp, p_bf16, ldb, V, D)) != HSN_OK) return rc;

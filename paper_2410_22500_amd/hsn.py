@@ -30,7 +30,8 @@ INIT_USER, INIT_NNDSVDA, INIT_MLP = 0, 1, 2
 MLP_IN, MLP_HIDDEN = 256, 128
 
 (KERN_NMF_PASS, KERN_PROJECT, KERN_BACKPROJECT, KERN_NORMALIZE, KERN_NMF_PASS_BF16, KERN_MLP_ROWS,
- KERN_MLP_WGRAD, KERN_NNDSVD_GRAM) = range(8)
+ KERN_MLP_WGRAD, KERN_NNDSVD_GRAM, KERN_MLP_POOL) = range(9)
+KERN_COUNT = 9
 
 
 class Dims(C.Structure):
