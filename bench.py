@@ -56,7 +56,31 @@ def parse():
     ap.add_argument("--compare-steps", type=int, default=2,
                     help="steps of each comparison path (plain FP32, cold BF16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time a plain device copy of 1 GiB (reference for HBM counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain device-to-device copy of 1 GiB (float32), 10 times: the
+    reference kernel whose FETCH_SIZE / WRITE_SIZE per dispatch scale the
+    HBM counters of the path's kernels, and the achievable copy bandwidth."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": ms,
+                      "gbs_read_plus_write": 8.0 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def log(*a):
@@ -65,6 +89,9 @@ def log(*a):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
               "how the path would shard is described in DESIGN.md but not built.", file=sys.stderr)

@@ -18,6 +18,7 @@
 // are contiguous, so each tap is one vector load.
 #include "common.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace {
@@ -51,95 +52,153 @@ __device__ __forceinline__ void load_k(const float *__restrict__ p, float (&out)
 }
 
 constexpr int kRayThreads = 128;
+constexpr int kXcds = 8;  // MI355X: 8 XCDs, each with its own L2; workgroups go round-robin over them
+
+// XCD-aware block order: with >= 8 slices, block id b runs on XCD b % 8 and
+// every block of a slice lands on the same XCD (slice = xcd + 8 q), so the
+// slice's image (or sinogram) is read from one L2 by all of its views or
+// rows.  The grid is padded to a multiple of 8 slices; blocks of padding
+// slices exit at once.  Fewer than 8 slices: plain slice-major order.
+struct BlockSlot {
+  int slice, rest;
+};
+__device__ __forceinline__ BlockSlot block_slot(unsigned id, int n_slices, int per_slice) {
+  BlockSlot b;
+  if (n_slices >= kXcds) {
+    const unsigned xcd = id % kXcds, local = id / kXcds;
+    b.slice = int(xcd + kXcds * (local / unsigned(per_slice)));
+    b.rest = int(local % unsigned(per_slice));
+  } else {
+    b.slice = int(id / unsigned(per_slice));
+    b.rest = int(id % unsigned(per_slice));
+  }
+  return b;
+}
+inline unsigned slot_grid(int64_t n_slices, int64_t per_slice) {
+  const int64_t s = n_slices >= kXcds ? (n_slices + kXcds - 1) / kXcds * kXcds : n_slices;
+  return unsigned(s * per_slice);
+}
+
+// Block partial of per-channel sums of squares of the values each thread
+// wrote (fused CGLS dot products): partial[block][q].
+template <int K, int NT>
+__device__ __forceinline__ void block_sumsq(const float (&v)[K], bool valid, double *__restrict__ partial,
+                                            size_t block) {
+  __shared__ double red[NT / 64][K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const double t = hsn::wave_sum_all(valid ? double(v[q]) * double(v[q]) : 0.0);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += red[w][threadIdx.x];
+    partial[block * K + threadIdx.x] = t;
+  }
+}
 
 // s[v][r][c][:] = alpha * sum_taps a * x[r][j][i][:] + beta * s[v][r][c][:]
+//
+// The ray steps along the image axis closer to its direction: rows j for
+// flat views (|cos| >= |sin|), columns i for steep ones.  Steep views read
+// the transposed image xT[r][i][j][:] (= x[r][j][i][:]), so for every view
+// the taps of neighbouring detector columns are neighbouring pixels of one
+// image row and a wave's loads are contiguous.  Steps where the ray is
+// outside the image are skipped by a conservative step range; at the image
+// edge a tap index is clamped and its weight set to 0, which keeps the loop
+// free of branches.  Optional: per-block sums of squares of the outputs.
 template <int K>
-__global__ __launch_bounds__(kRayThreads) void project_kernel(const float *__restrict__ x, float *__restrict__ s,
+__global__ __launch_bounds__(kRayThreads) void project_kernel(const float *__restrict__ x,
+                                                              const float *__restrict__ xT, float *__restrict__ s,
                                                               const ViewGeom *__restrict__ geom, int n_slices,
-                                                              int n, float alpha, float beta) {
-  const int c = blockIdx.x * kRayThreads + threadIdx.x;
-  const int r = blockIdx.y;
-  const int v = blockIdx.z;
-  if (c >= n) return;
+                                                              int n_views, int n, float alpha, float beta,
+                                                              double *__restrict__ sumsq) {
+  const int nx = (n + kRayThreads - 1) / kRayThreads;
+  const BlockSlot bs = block_slot(blockIdx.x, n_slices, n_views * nx);
+  if (bs.slice >= n_slices) return;
+  const int v = bs.rest / nx, cx = bs.rest % nx;
+  const int r = bs.slice;
+  const int c = cx * kRayThreads + threadIdx.x;
   const ViewGeom g = geom[v];
   const double h = 0.5 * double(n - 1);
   const double sc = double(c) - h;
   const float inv_w = float(g.inv_w);
+  const bool steep = fabs(g.sn) > fabs(g.cs);
+  const double a = steep ? g.sn : g.cs, b = steep ? g.cs : g.sn;
+  // crossing position along the other axis at step m: u(m) = u0 + m du
+  const double u0 = (sc + h * b) / a + h;
+  const double du = -b / a;
+  int m_lo = 0, m_hi = n - 1;
+  if (du != 0.0) {
+    const double ma = (-1.0 - u0) / du, mb = (double(n) - u0) / du;
+    // clamped in float64 before the conversion (|du| may be ~1e-16)
+    m_lo = int(fmax(0.0, floor(fmin(ma, mb)) - 1.0));
+    m_hi = int(fmin(double(n - 1), ceil(fmax(ma, mb)) + 1.0));
+  } else if (u0 < -1.0 || u0 >= double(n)) {
+    m_hi = -1;
+  }
   float acc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0.0f;
-  const float *xs = x + size_t(r) * n * n * K;
-  if (fabs(g.cs) >= fabs(g.sn)) {
-    // Step along image rows j; the ray crosses row j at column position u_j.
-    const double u0 = (sc + h * g.sn) / g.cs + h;
-    const double du = -g.sn / g.cs;
-    for (int j = 0; j < n; ++j) {
-      const double u = fma(double(j), du, u0);
+  const float *img = (steep ? xT : x) + size_t(r) * n * n * K;
+  if (c < n) {
+#pragma unroll 4
+    for (int m = m_lo; m <= m_hi; ++m) {
+      const double u = fma(double(m), du, u0);
       const double fl = floor(u);
-      const int i0 = int(fl);
+      const int t0 = int(fl);
       const float f = float(u - fl);
-      if (i0 < -1 || i0 >= n) continue;
-      const float w0 = (1.0f - f) * inv_w, w1 = f * inv_w;
-      const float *row = xs + size_t(j) * n * K;
-      float a[K];
-      if (i0 >= 0) {
-        load_k<K>(row + size_t(i0) * K, a);
+      const float w0 = (t0 >= 0 && t0 < n) ? (1.0f - f) * inv_w : 0.0f;
+      const float w1 = (t0 + 1 >= 0 && t0 + 1 < n) ? f * inv_w : 0.0f;
+      const int i0 = min(max(t0, 0), n - 1), i1 = min(max(t0 + 1, 0), n - 1);
+      const float *row = img + size_t(m) * n * K;
+      float p0[K], p1[K];
+      load_k<K>(row + size_t(i0) * K, p0);
+      load_k<K>(row + size_t(i1) * K, p1);
 #pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] = fmaf(w0, a[q], acc[q]);
-      }
-      if (i0 + 1 < n) {
-        load_k<K>(row + size_t(i0 + 1) * K, a);
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] = fmaf(w1, a[q], acc[q]);
-      }
-    }
-  } else {
-    // Step along image columns i; the ray crosses column i at row position u_i.
-    const double u0 = (sc + h * g.cs) / g.sn + h;
-    const double du = -g.cs / g.sn;
-    for (int i = 0; i < n; ++i) {
-      const double u = fma(double(i), du, u0);
-      const double fl = floor(u);
-      const int j0 = int(fl);
-      const float f = float(u - fl);
-      if (j0 < -1 || j0 >= n) continue;
-      const float w0 = (1.0f - f) * inv_w, w1 = f * inv_w;
-      float a[K];
-      if (j0 >= 0) {
-        load_k<K>(xs + (size_t(j0) * n + i) * K, a);
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] = fmaf(w0, a[q], acc[q]);
-      }
-      if (j0 + 1 < n) {
-        load_k<K>(xs + (size_t(j0 + 1) * n + i) * K, a);
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] = fmaf(w1, a[q], acc[q]);
-      }
+      for (int q = 0; q < K; ++q) acc[q] = fmaf(w1, p1[q], fmaf(w0, p0[q], acc[q]));
     }
   }
-  float *out = s + ((size_t(v) * n_slices + r) * n + c) * K;
+  float res[K];
+  if (c < n) {
+    float *out = s + ((size_t(v) * n_slices + r) * n + c) * K;
 #pragma unroll
-  for (int q = 0; q < K; ++q) out[q] = (beta == 0.0f) ? alpha * acc[q] : fmaf(alpha, acc[q], beta * out[q]);
+    for (int q = 0; q < K; ++q) {
+      res[q] = (beta == 0.0f) ? alpha * acc[q] : fmaf(alpha, acc[q], beta * out[q]);
+      out[q] = res[q];
+    }
+  }
+  if (sumsq) block_sumsq<K, kRayThreads>(res, c < n, sumsq, (size_t(v) * n_slices + r) * nx + cx);
 }
 
 constexpr int kVoxThreads = 128;
 
 // x[r][j][i][:] = alpha * sum_v sum_taps a * s[v][r][c][:] + beta * x[r][j][i][:]
+// Views are unrolled by 4 with branch-free taps (clamped index, weight 0
+// outside the detector) so that several loads are in flight.  Optional:
+// per-block sums of squares of the outputs.
 template <int K>
 __global__ __launch_bounds__(kVoxThreads) void backproject_kernel(const float *__restrict__ s, float *__restrict__ x,
                                                                   const ViewGeom *__restrict__ geom, int n_views,
-                                                                  int n_slices, int n, float alpha, float beta) {
-  const int i = blockIdx.x * kVoxThreads + threadIdx.x;
-  const int j = blockIdx.y;
-  const int r = blockIdx.z;
-  if (i >= n) return;
+                                                                  int n_slices, int n, float alpha, float beta,
+                                                                  double *__restrict__ sumsq) {
+  const int nx = (n + kVoxThreads - 1) / kVoxThreads;
+  const BlockSlot bs = block_slot(blockIdx.x, n_slices, n * nx);
+  if (bs.slice >= n_slices) return;
+  const int j = bs.rest / nx, cx = bs.rest % nx;
+  const int r = bs.slice;
+  const int i = cx * kVoxThreads + threadIdx.x;
+  const bool ok = i < n;
   const double h = 0.5 * double(n - 1);
-  const double xi = double(i) - h, yj = double(j) - h;
+  const double xi = double(ok ? i : 0) - h, yj = double(j) - h;
   float acc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0.0f;
   const size_t view_stride = size_t(n_slices) * n * K;
   const float *sr = s + size_t(r) * n * K;
+#pragma unroll 4
   for (int v = 0; v < n_views; ++v) {
     const ViewGeom g = geom[v];
     const double u = fma(xi, g.cs, fma(yj, g.sn, h));   // detector position of the voxel centre
@@ -147,24 +206,76 @@ __global__ __launch_bounds__(kVoxThreads) void backproject_kernel(const float *_
     const int c0 = int(fl);
     const float f = float(u - fl);                      // |d| of tap c0; tap c0+1 has |d| = 1 - f
     const float inv_w = float(g.inv_w);
-    const float w0 = fmaxf(0.0f, 1.0f - f * inv_w) * inv_w;
-    const float w1 = fmaxf(0.0f, 1.0f - (1.0f - f) * inv_w) * inv_w;
+    const float w0 = (c0 >= 0 && c0 < n) ? fmaxf(0.0f, 1.0f - f * inv_w) * inv_w : 0.0f;
+    const float w1 = (c0 + 1 >= 0 && c0 + 1 < n) ? fmaxf(0.0f, 1.0f - (1.0f - f) * inv_w) * inv_w : 0.0f;
+    const int k0 = min(max(c0, 0), n - 1), k1 = min(max(c0 + 1, 0), n - 1);
     const float *sv = sr + size_t(v) * view_stride;
-    float a[K];
-    if (c0 >= 0 && c0 < n && w0 > 0.0f) {
-      load_k<K>(sv + size_t(c0) * K, a);
+    float p0[K], p1[K];
+    load_k<K>(sv + size_t(k0) * K, p0);
+    load_k<K>(sv + size_t(k1) * K, p1);
 #pragma unroll
-      for (int q = 0; q < K; ++q) acc[q] = fmaf(w0, a[q], acc[q]);
-    }
-    if (c0 + 1 >= 0 && c0 + 1 < n && w1 > 0.0f) {
-      load_k<K>(sv + size_t(c0 + 1) * K, a);
+    for (int q = 0; q < K; ++q) acc[q] = fmaf(w1, p1[q], fmaf(w0, p0[q], acc[q]));
+  }
+  float res[K];
+  if (ok) {
+    float *out = x + ((size_t(r) * n + j) * n + i) * K;
 #pragma unroll
-      for (int q = 0; q < K; ++q) acc[q] = fmaf(w1, a[q], acc[q]);
+    for (int q = 0; q < K; ++q) {
+      res[q] = (beta == 0.0f) ? alpha * acc[q] : fmaf(alpha, acc[q], beta * out[q]);
+      out[q] = res[q];
     }
   }
-  float *out = x + ((size_t(r) * n + j) * n + i) * K;
+  if (sumsq) block_sumsq<K, kVoxThreads>(res, ok, sumsq, (size_t(r) * n + j) * nx + cx);
+}
+
+constexpr int kTile = 32;
+
+// Per slice: xT[r][i][j][:] = x[r][j][i][:] through a 32 x 32 LDS tile.
+// With coef (CGLS direction update), first p = sv + coef[q] * p is formed
+// and written back (coef == NULL: p = sv), then transposed into pT.
+template <int K>
+__global__ __launch_bounds__(256) void xpby_transpose_kernel(float *__restrict__ p, float *__restrict__ pT,
+                                                             const float *__restrict__ sv,
+                                                             const double *__restrict__ coef, int n, int mode) {
+  __shared__ float tile[kTile][kTile + 1][K];
+  const int r = blockIdx.z;
+  const int j0 = blockIdx.y * kTile, i0 = blockIdx.x * kTile;
+  const size_t base = size_t(r) * n * n * K;
+  float cf[K];
 #pragma unroll
-  for (int q = 0; q < K; ++q) out[q] = (beta == 0.0f) ? alpha * acc[q] : fmaf(alpha, acc[q], beta * out[q]);
+  for (int q = 0; q < K; ++q) cf[q] = (mode == 1) ? float(coef[q]) : 0.0f;
+  for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+    const int jj = e / kTile, ii = e % kTile;
+    const int j = j0 + jj, i = i0 + ii;
+    if (j < n && i < n) {
+      const size_t o = base + (size_t(j) * n + i) * K;
+      float val[K];
+      if (mode == 0) {  // plain transpose of p
+        load_k<K>(p + o, val);
+      } else {          // p = sv + coef * p (mode 1), p = sv (mode 2)
+        float a[K], b[K];
+        load_k<K>(sv + o, a);
+        if (mode == 1) load_k<K>(p + o, b);
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          val[q] = (mode == 1) ? fmaf(cf[q], b[q], a[q]) : a[q];
+          p[o + q] = val[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < K; ++q) tile[jj][ii][q] = val[q];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+    const int ii = e / kTile, jj = e % kTile;
+    const int j = j0 + jj, i = i0 + ii;
+    if (j < n && i < n) {
+      float *o = pT + base + (size_t(i) * n + j) * K;
+#pragma unroll
+      for (int q = 0; q < K; ++q) o[q] = tile[jj][ii][q];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -246,23 +357,23 @@ __global__ __launch_bounds__(256) void cgls_scalar_kernel(const double *__restri
   }
 }
 
-// y += sign * coef[ch] * x over n_items K-vectors.
-__global__ void chan_axpy_kernel(float *__restrict__ y, const float *__restrict__ xv, const double *__restrict__ coef,
-                                 float sign, int K, int64_t n) {
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
-    y[e] = fmaf(sign * float(coef[e % K]), xv[e], y[e]);
-}
-
 __global__ void fill_zero_kernel(float *__restrict__ y, int64_t n) {
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
     y[e] = 0.0f;
 }
 
-// p = s + coef[ch] * p
-__global__ void chan_xpby_kernel(float *__restrict__ p, const float *__restrict__ s, const double *__restrict__ coef,
-                                 int K, int64_t n) {
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
-    p[e] = fmaf(float(coef[e % K]), p[e], s[e]);
+// x += coef[ch] * p over nx values, then r -= coef[ch] * q over nr values (one launch).
+__global__ void chan_axpy2_kernel(float *__restrict__ x, const float *__restrict__ p, int64_t nx,
+                                  float *__restrict__ r, const float *__restrict__ q, int64_t nr,
+                                  const double *__restrict__ coef, int K) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < nx + nr; e += int64_t(gridDim.x) * blockDim.x) {
+    if (e < nx) {
+      x[e] = fmaf(float(coef[e % K]), p[e], x[e]);
+    } else {
+      const int64_t f = e - nx;
+      r[f] = fmaf(-float(coef[f % K]), q[f], r[f]);
+    }
+  }
 }
 
 hsn_status check_geom(hsn_ctx *ctx, const hsn_geom *g) {
@@ -272,6 +383,10 @@ hsn_status check_geom(hsn_ctx *ctx, const hsn_geom *g) {
   if (g->k < 1 || g->k > 8) return hsn::fail(ctx, HSN_ERR_SHAPE, "k must be in 1..8 (got %d)", g->k);
   if (g->n_cols > 8192 || g->n_views > 65535 || g->n_slices > 65535)
     return hsn::fail(ctx, HSN_ERR_SHAPE, "geometry too large (n_cols <= 8192, n_views, n_slices <= 65535)");
+  // 1-D launch grids: threads per launch must stay below 2^31.
+  const int64_t sp = (g->n_slices + 7) / 8 * 8, nxc = (g->n_cols + 127) / 128 * 128;
+  if (sp * g->n_views * nxc >= (int64_t(1) << 31) || sp * g->n_cols * nxc >= (int64_t(1) << 31))
+    return hsn::fail(ctx, HSN_ERR_SHAPE, "geometry too large for one launch");
   return HSN_OK;
 }
 
@@ -312,20 +427,51 @@ hsn_status upload_geom(hsn_ctx *ctx, const hsn_geom *g, hipStream_t st, const Vi
   return HSN_OK;
 }
 
+// Launch grids (1-D, padded, see block_slot) and the number of partials the
+// fused sums of squares write (one per real block).
+unsigned project_grid(const hsn_geom *g) {
+  return slot_grid(g->n_slices, g->n_views * ((g->n_cols + kRayThreads - 1) / kRayThreads));
+}
+unsigned backproject_grid(const hsn_geom *g) {
+  return slot_grid(g->n_slices, g->n_cols * ((g->n_cols + kVoxThreads - 1) / kVoxThreads));
+}
+size_t project_partials(const hsn_geom *g) {
+  return size_t(g->n_slices) * g->n_views * ((g->n_cols + kRayThreads - 1) / kRayThreads);
+}
+size_t backproject_partials(const hsn_geom *g) {
+  return size_t(g->n_slices) * g->n_cols * ((g->n_cols + kVoxThreads - 1) / kVoxThreads);
+}
+
 template <int K>
-void launch_project(const float *x, float *s, const ViewGeom *geom, const hsn_geom *g, float alpha, float beta,
-                    hipStream_t st) {
-  const int n = int(g->n_cols);
-  dim3 grid(unsigned((n + kRayThreads - 1) / kRayThreads), unsigned(g->n_slices), unsigned(g->n_views));
-  project_kernel<K><<<grid, kRayThreads, 0, st>>>(x, s, geom, int(g->n_slices), n, alpha, beta);
+void launch_project(const float *x, const float *xT, float *s, const ViewGeom *geom, const hsn_geom *g, float alpha,
+                    float beta, double *sumsq, hipStream_t st) {
+  project_kernel<K><<<project_grid(g), kRayThreads, 0, st>>>(x, xT, s, geom, int(g->n_slices), int(g->n_views),
+                                                             int(g->n_cols), alpha, beta, sumsq);
 }
 
 template <int K>
 void launch_backproject(const float *s, float *x, const ViewGeom *geom, const hsn_geom *g, float alpha, float beta,
-                        hipStream_t st) {
-  const int n = int(g->n_cols);
-  dim3 grid(unsigned((n + kVoxThreads - 1) / kVoxThreads), unsigned(n), unsigned(g->n_slices));
-  backproject_kernel<K><<<grid, kVoxThreads, 0, st>>>(s, x, geom, int(g->n_views), int(g->n_slices), n, alpha, beta);
+                        double *sumsq, hipStream_t st) {
+  backproject_kernel<K><<<backproject_grid(g), kVoxThreads, 0, st>>>(s, x, geom, int(g->n_views),
+                                                                     int(g->n_slices), int(g->n_cols), alpha, beta,
+                                                                     sumsq);
+}
+
+// mode 0: pT = p^T; mode 1: p = sv + coef p, pT = p^T; mode 2: p = sv, pT = p^T.
+template <int K>
+void launch_xpby_t(float *p, float *pT, const float *sv, const double *coef, const hsn_geom *g, int mode,
+                   hipStream_t st) {
+  const unsigned t = unsigned((g->n_cols + kTile - 1) / kTile);
+  xpby_transpose_kernel<K><<<dim3(t, t, unsigned(g->n_slices)), 256, 0, st>>>(p, pT, sv, coef, int(g->n_cols), mode);
+}
+
+bool has_steep_view(const hsn_geom *g) {
+  const int nv = int(g->n_views);
+  for (int v = 0; v < nv; ++v) {
+    const double t = g->angles ? g->angles[v] : double(v) * M_PI / double(nv);
+    if (std::fabs(std::sin(t)) > std::fabs(std::cos(t))) return true;
+  }
+  return false;
 }
 
 #define HSN_DISPATCH_K(k, F, ...)   \
@@ -364,9 +510,17 @@ extern "C" hsn_status hsn_project(hsn_ctx *ctx, const hsn_geom *g, const float *
   hsn::DeviceGuard dg(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const ViewGeom *geom = nullptr;
+  // Steep views read a transposed copy of x (workspace).
+  float *xT = nullptr;
+  if (has_steep_view(g)) {
+    const size_t nxk = size_t(g->n_slices) * g->n_cols * g->n_cols * g->k;
+    if ((rc = hsn::ensure_ws(ctx, sizeof(float) * nxk)) != HSN_OK) return rc;
+    xT = static_cast<float *>(ctx->ws);
+  }
   if ((rc = upload_geom(ctx, g, st, &geom)) != HSN_OK) return rc;
+  if (xT) HSN_DISPATCH_K(g->k, launch_xpby_t, const_cast<float *>(x), xT, nullptr, nullptr, g, 0, st);
   hsn::prof_begin(ctx, HSN_KERN_PROJECT, st);
-  HSN_DISPATCH_K(g->k, launch_project, x, s, geom, g, alpha, beta, st);
+  HSN_DISPATCH_K(g->k, launch_project, x, xT, s, geom, g, alpha, beta, nullptr, st);
   hsn::prof_end(ctx, HSN_KERN_PROJECT, st);
   HSN_LAUNCHED(ctx);
   return HSN_OK;
@@ -384,7 +538,7 @@ extern "C" hsn_status hsn_backproject(hsn_ctx *ctx, const hsn_geom *g, const flo
   const ViewGeom *geom = nullptr;
   if ((rc = upload_geom(ctx, g, st, &geom)) != HSN_OK) return rc;
   hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
-  HSN_DISPATCH_K(g->k, launch_backproject, s, x, geom, g, alpha, beta, st);
+  HSN_DISPATCH_K(g->k, launch_backproject, s, x, geom, g, alpha, beta, nullptr, st);
   hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
   HSN_LAUNCHED(ctx);
   return HSN_OK;
@@ -405,43 +559,46 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
   const int64_t n = g->n_cols;
   const int64_t nx = g->n_slices * n * n;          // voxels
   const int64_t ns = g->n_views * g->n_slices * n; // rays
+  // The sums of squares of A p and A^T r come from the projector epilogues
+  // (one partial per block); ||r|| for the optional residual history from
+  // the dot kernel.
+  const size_t nb_proj = project_partials(g), nb_back = backproject_partials(g);
+  const size_t n_part = std::max<size_t>({nb_proj, nb_back, size_t(kDotBlocks)});
   const size_t need = hsn::Carver::need({sizeof(float) * ns * K, sizeof(float) * ns * K, sizeof(float) * nx * K,
-                                         sizeof(float) * nx * K, sizeof(double) * kDotBlocks * 8,
-                                         sizeof(double) * 24});
+                                         sizeof(float) * nx * K, sizeof(float) * nx * K,
+                                         sizeof(double) * n_part * K, sizeof(double) * 24});
   if ((rc = hsn::ensure_ws(ctx, need)) != HSN_OK) return rc;
   const ViewGeom *geom = nullptr;
   if ((rc = upload_geom(ctx, g, st, &geom)) != HSN_OK) return rc;
   hsn::Carver cv(ctx->ws);
   float *r = cv.take<float>(ns * K), *q = cv.take<float>(ns * K);
-  float *sv = cv.take<float>(nx * K), *p = cv.take<float>(nx * K);
-  double *partial = cv.take<double>(kDotBlocks * 8), *scal = cv.take<double>(24);
+  float *sv = cv.take<float>(nx * K), *p = cv.take<float>(nx * K), *pT = cv.take<float>(nx * K);
+  double *partial = cv.take<double>(n_part * K), *scal = cv.take<double>(24);
   const int eb = 256;
   auto blocks = [&](int64_t m) { return unsigned(std::min<int64_t>((m + eb - 1) / eb, 4096)); };
 
   fill_zero_kernel<<<blocks(nx * K), eb, 0, st>>>(x, nx * K);
   HSN_HIP(ctx, hipMemcpyAsync(r, sino, sizeof(float) * ns * K, hipMemcpyDeviceToDevice, st));
-  HSN_DISPATCH_K(K, launch_backproject, r, sv, geom, g, 1.0f, 0.0f, st);
-  HSN_HIP(ctx, hipMemcpyAsync(p, sv, sizeof(float) * nx * K, hipMemcpyDeviceToDevice, st));
-  HSN_DISPATCH_K(K, launch_dot, sv, sv, nx, partial, st);
-  cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kSetGamma, scal, nullptr);
+  hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
+  HSN_DISPATCH_K(K, launch_backproject, r, sv, geom, g, 1.0f, 0.0f, partial, st);
+  hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
+  cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_back), K, kSetGamma, scal, nullptr);
+  HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, nullptr, g, 2, st);
   if (resid) {
     HSN_DISPATCH_K(K, launch_dot, r, r, ns, partial, st);
     cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kResid, scal, resid);
   }
   for (int it = 0; it < n_iter; ++it) {
     hsn::prof_begin(ctx, HSN_KERN_PROJECT, st);
-    HSN_DISPATCH_K(K, launch_project, p, q, geom, g, 1.0f, 0.0f, st);
+    HSN_DISPATCH_K(K, launch_project, p, pT, q, geom, g, 1.0f, 0.0f, partial, st);
     hsn::prof_end(ctx, HSN_KERN_PROJECT, st);
-    HSN_DISPATCH_K(K, launch_dot, q, q, ns, partial, st);
-    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kAlpha, scal, nullptr);
-    chan_axpy_kernel<<<blocks(nx * K), eb, 0, st>>>(x, p, scal + 8, 1.0f, K, nx * K);
-    chan_axpy_kernel<<<blocks(ns * K), eb, 0, st>>>(r, q, scal + 8, -1.0f, K, ns * K);
+    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_proj), K, kAlpha, scal, nullptr);
+    chan_axpy2_kernel<<<blocks(nx * K + ns * K), eb, 0, st>>>(x, p, nx * K, r, q, ns * K, scal + 8, K);
     hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
-    HSN_DISPATCH_K(K, launch_backproject, r, sv, geom, g, 1.0f, 0.0f, st);
+    HSN_DISPATCH_K(K, launch_backproject, r, sv, geom, g, 1.0f, 0.0f, partial, st);
     hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
-    HSN_DISPATCH_K(K, launch_dot, sv, sv, nx, partial, st);
-    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kBeta, scal, nullptr);
-    chan_xpby_kernel<<<blocks(nx * K), eb, 0, st>>>(p, sv, scal + 16, K, nx * K);
+    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_back), K, kBeta, scal, nullptr);
+    HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, scal + 16, g, 1, st);
     if (resid) {
       HSN_DISPATCH_K(K, launch_dot, r, r, ns, partial, st);
       cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kResid, scal, resid + size_t(it + 1) * K);
