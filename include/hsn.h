@@ -152,6 +152,40 @@ hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp,
                             int64_t n_p, int64_t n_k, float *V, float *D,
                             const hsn_nmf_opts *opts, hsn_nmf_stats *stats, void *stream);
 
+/*
+ * Many independent decompositions (eq. 4) of uneven size in one go: every
+ * phase of an iteration is ONE launch over the workgroups of all instances
+ * (per-instance descriptors and block ranges), and with HSN_BATCH_GRAPH the
+ * iteration chunks are captured once into hipGraphs and replayed.  Schedule
+ * (from opts; opts.k is ignored, each problem has its own k): opts.max_iter
+ * float32 MU iterations (objective every check_every), then up to
+ * opts.polish_rounds ANLS rounds; algo must be HSN_ALGO_MU, precision
+ * HSN_PREC_FP32, init HSN_INIT_USER, polish_algo HSN_ALGO_ANLS.  Instance i
+ * stops on its own when f_ref > 0 and its relative objective reaches
+ * opts.rel_obj_tol; its kernels then return at once.
+ * Flags: HSN_BATCH_GRAPH captures and replays graphs (cached in ctx per batch
+ * shape); HSN_BATCH_AUTOTUNE times candidate workgroup budgets (rows of p per
+ * workgroup) on the first call for a batch shape and keeps the fastest.
+ * Without AUTOTUNE every instance is partitioned exactly as hsn_subspace_nmf
+ * would partition it alone, so its results are bitwise those of that call.
+ * stats: optional host array [n]; ms is the device time of the whole batch.
+ */
+typedef struct {
+  const float *p;   /* [n_p][ldp] float32, ldp >= n_k, ldp % 4 == 0, 16-byte aligned */
+  int64_t ldp;
+  int64_t n_p, n_k; /* 1 <= n_k <= 2048 */
+  int k;            /* 1..8 */
+  float *V;         /* [n_p][k] in/out */
+  float *D;         /* [n_k][k] in/out */
+  double f_ref;     /* > 0 enables this instance's stop test */
+} hsn_nmf_problem;
+
+enum { HSN_BATCH_GRAPH = 1, HSN_BATCH_AUTOTUNE = 2 };
+
+hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nmf_problem *probs,
+                                    const hsn_nmf_opts *opts, int flags, hsn_nmf_stats *stats,
+                                    void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Projector A (eq. 3 / eq. 5), K channels, all slices in one launch.   */
 /* ------------------------------------------------------------------ */

@@ -111,6 +111,8 @@ void hsn_destroy(hsn_ctx *ctx) {
   if (!ctx) return;
   hsn::DeviceGuard g(ctx->device);
   (void)hipDeviceSynchronize();
+  for (hsn::Owned *o : ctx->plans) delete o;
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->geom) (void)hipFree(ctx->geom);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);

@@ -15,6 +15,13 @@
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
+namespace hsn {
+// Device state a context keeps across calls (cached plans); released by hsn_destroy.
+struct Owned {
+  virtual ~Owned() {}
+};
+}  // namespace hsn
+
 struct hsn_ctx {
   int device = 0;
   int num_cu = 256;
@@ -31,6 +38,10 @@ struct hsn_ctx {
   bool prof = false;
   std::vector<hipEvent_t> prof_ev[HSN_KERN_COUNT];
   size_t prof_used[HSN_KERN_COUNT] = {};
+  // Cached batched-decomposition plans (descriptors, workspace, captured graphs).
+  std::vector<hsn::Owned *> plans;
+  // Stream used only to capture graphs (capture is not allowed on the null stream).
+  hipStream_t cap_stream = nullptr;
 };
 
 namespace hsn {

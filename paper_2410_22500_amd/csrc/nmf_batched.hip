@@ -1,0 +1,467 @@
+// hsn_subspace_nmf_batched: many decompositions of eq. (4) of uneven size
+// (rays x bins x K) in one stream of launches.
+//
+// Every phase of an iteration is one launch over the blocks of all
+// instances: the float32 pass (MU, or N_V / N_D for an ANLS round), the
+// row solves of an ANLS round, and the D update.  Each instance owns a range
+// of blocks in each launch, its descriptor (operands, workspace, ranges) and
+// its control block, so its stop test is its own: once it has converged its
+// blocks return at once.  Iteration chunks (check_every MU iterations, or a
+// few ANLS rounds) are captured once into hipGraphs and replayed; the step
+// index comes from the instance's iter_base, advanced on the device at the
+// end of each chunk, so one graph serves every replay.  The plan (descriptors,
+// workspace, graphs, tuned partition) is cached in the context per batch
+// shape.
+//
+// Partition: without autotuning each instance gets the workgroup count the
+// single-instance call would use, so results are bitwise those of
+// hsn_subspace_nmf.  The autotuner times candidate budgets of row tiles per
+// workgroup (fewer, longer workgroups cut the per-workgroup N_D partials that
+// the update must read, which dominate small instances) on a side copy of
+// the state and keeps the fastest.
+#include "nmf_common.hpp"
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace hsn {
+
+size_t batched_pass_lds(int max_k);
+size_t batched_update_lds(int max_k, int rule);
+hipError_t batched_kernel_setup(size_t pass_lds, size_t upd_lds);
+void launch_batched_pass(int mode, bool obj, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
+                         int iter_local);
+void launch_batched_init(int n_inst, int want_chol, hipStream_t st, const BatchInst *d);
+void launch_batched_update(int rule, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
+                           int iter_local, bool has_obj, bool next_chol);
+void launch_batched_rows(int n_blocks, hipStream_t st, const BatchInst *d, int n_inst, int iter_local);
+void launch_batched_advance(int n_inst, int steps, hipStream_t st, const BatchInst *d);
+int update_d_blocks(int n_k);
+
+namespace {
+
+constexpr int kRowsPerTile = 8;  // rows per tile of the float32 pass
+constexpr int kPolishChunk = 4;  // ANLS rounds per replayed chunk
+
+__global__ void set_limit_kernel(const BatchInst *__restrict__ d, int n, int limit) {
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) d[i].ctrl->stop_at = limit;
+}
+
+struct Shape {
+  int64_t n_p, n_k, ldp;
+  int k;
+};
+
+struct Plan : Owned {
+  std::string sig;
+  int n = 0;
+  int max_k = 1;
+  bool need_nv = false;
+  std::vector<Shape> shapes;
+  std::vector<int> wg;            // pass workgroups per instance (chosen)
+  std::vector<int> wg_cap;        // largest candidate (sizes the partials)
+  std::vector<BatchInst> h;       // host copy of the descriptors
+  BatchInst *d = nullptr;         // device descriptors
+  BatchInst *d_tune = nullptr;    // descriptors of the tuning copy
+  NmfCtrl *ctrl = nullptr;        // [n] contiguous (one read per chunk)
+  char *mem = nullptr;            // per-instance workspace
+  size_t mem_bytes = 0;
+  int total_wg = 0, total_ub = 0, total_rb = 0;
+  size_t pass_lds = 0, upd_lds = 0;
+  int hist_cap = 0;
+  std::vector<size_t> hist_off;
+  // captured chunks: key = (kind, steps, flags)
+  struct G {
+    int kind, steps, obj_last, chol_last;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<G> graphs;
+  std::string tune_note;
+  ~Plan() override {
+    for (auto &g : graphs) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    if (mem) (void)hipFree(mem);
+  }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Lays out descriptors for the partition `wgs`; all pointers into p->mem.
+void layout(Plan &pl, const std::vector<int> &wgs, const hsn_nmf_problem *probs, double tol,
+            std::vector<BatchInst> &out, int &tot_wg, int &tot_ub, int &tot_rb, int num_cu) {
+  out.assign(pl.n, BatchInst{});
+  tot_wg = tot_ub = tot_rb = 0;
+  for (int i = 0; i < pl.n; ++i) {
+    const Shape &s = pl.shapes[i];
+    BatchInst &b = out[i];
+    b.P = probs ? probs[i].p : nullptr;
+    b.ldp = s.ldp;
+    b.n_p = s.n_p;
+    b.n_k = int(s.n_k);
+    b.K = s.k;
+    b.nq = s.n_k > 1024 ? 2 : 1;
+    b.V = probs ? probs[i].V : nullptr;
+    b.D = probs ? probs[i].D : nullptr;
+    b.f_ref = (probs && probs[i].f_ref > 0.0) ? probs[i].f_ref : 0.0;
+    b.tol = tol;
+    b.wg0 = tot_wg;
+    b.n_wg = wgs[i];
+    tot_wg += wgs[i];
+    b.ub0 = tot_ub;
+    b.n_ub = update_d_blocks(int(s.n_k));
+    tot_ub += b.n_ub;
+    b.rb0 = tot_rb;
+    b.n_rb = int(std::min<int64_t>((s.n_p + 255) / 256, 8 * int64_t(num_cu)));
+    tot_rb += b.n_rb;
+  }
+}
+
+// Byte offsets of instance i's arrays inside the plan memory (region A).
+struct InstMem {
+  size_t gd, chol, part_nd, part_gv, part_obj, part_gd, nv, hist, dcopy;
+};
+
+std::vector<InstMem> mem_layout(const Plan &pl, size_t &total) {
+  std::vector<InstMem> m(pl.n);
+  size_t off = align256(sizeof(BatchInst) * pl.n) * 2 + align256(sizeof(NmfCtrl) * pl.n) * 2;
+  for (int i = 0; i < pl.n; ++i) {
+    const Shape &s = pl.shapes[i];
+    const int K = s.k;
+    const int nub = update_d_blocks(int(s.n_k));
+    InstMem &x = m[i];
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off = align256(off + bytes);
+      return o;
+    };
+    x.gd = take(sizeof(double) * 64);
+    x.chol = take(sizeof(double) * 256 * kCholStride);
+    x.part_nd = take(sizeof(float) * size_t(pl.wg_cap[i]) * s.n_k * K);
+    x.part_gv = take(sizeof(double) * size_t(pl.wg_cap[i]) * K * K);
+    x.part_obj = take(sizeof(double) * size_t(pl.wg_cap[i]));
+    x.part_gd = take(sizeof(double) * size_t(nub) * K * K);
+    x.nv = pl.need_nv ? take(sizeof(float) * size_t(s.n_p) * K) : 0;
+    x.hist = take(sizeof(double) * size_t(pl.hist_cap));
+    x.dcopy = take(sizeof(float) * size_t(s.n_k) * K);  // tuning: scratch D
+  }
+  total = off + 256;
+  return m;
+}
+
+// Candidate partitions: the single-instance one, then budgets of T row tiles per workgroup.
+std::vector<int> partition(const Plan &pl, int tiles_per_wg, int num_cu) {
+  std::vector<int> w(pl.n);
+  for (int i = 0; i < pl.n; ++i) {
+    const int64_t tiles = (pl.shapes[i].n_p + kRowsPerTile - 1) / kRowsPerTile;
+    if (tiles_per_wg <= 0)
+      w[i] = int(std::min<int64_t>(tiles, 2 * int64_t(num_cu)));
+    else
+      w[i] = int(std::max<int64_t>(1, std::min<int64_t>((tiles + tiles_per_wg - 1) / tiles_per_wg, 2 * int64_t(num_cu))));
+  }
+  return w;
+}
+
+void fill_pointers(Plan &pl, const std::vector<InstMem> &m, std::vector<BatchInst> &v, NmfCtrl *ctrl, bool tune) {
+  for (int i = 0; i < pl.n; ++i) {
+    BatchInst &b = v[i];
+    b.gd = reinterpret_cast<double *>(pl.mem + m[i].gd);
+    b.chol = reinterpret_cast<double *>(pl.mem + m[i].chol);
+    b.part_nd = reinterpret_cast<float *>(pl.mem + m[i].part_nd);
+    b.part_gv = reinterpret_cast<double *>(pl.mem + m[i].part_gv);
+    b.part_obj = reinterpret_cast<double *>(pl.mem + m[i].part_obj);
+    b.part_gd = reinterpret_cast<double *>(pl.mem + m[i].part_gd);
+    b.NV = pl.need_nv ? reinterpret_cast<float *>(pl.mem + m[i].nv) : nullptr;
+    b.hist = reinterpret_cast<double *>(pl.mem + m[i].hist);
+    b.ctrl = ctrl + i;
+    if (tune) {
+      b.D = reinterpret_cast<float *>(pl.mem + m[i].dcopy);
+      b.f_ref = 0.0;
+    }
+  }
+}
+
+// Queues one chunk of `steps` steps of one kind.
+//   kind 0: MU iterations (objective and G_D factors on the last if asked)
+//   kind 1: ANLS rounds
+void queue_chunk(const Plan &pl, const BatchInst *d, hipStream_t st, int kind, int steps, bool obj_last,
+                 bool chol_last) {
+  for (int s = 0; s < steps; ++s) {
+    const bool last = s + 1 == steps;
+    if (kind == 0) {
+      launch_batched_pass(kModeMU, obj_last && last, pl.total_wg, pl.pass_lds, st, d, pl.n, s);
+      launch_batched_update(kModeMU, pl.total_ub, pl.upd_lds, st, d, pl.n, s, obj_last && last, chol_last && last);
+    } else {
+      launch_batched_pass(kModeNV, false, pl.total_wg, pl.pass_lds, st, d, pl.n, s);
+      launch_batched_rows(pl.total_rb, st, d, pl.n, s);
+      launch_batched_pass(kModeND, true, pl.total_wg, pl.pass_lds, st, d, pl.n, s);
+      launch_batched_update(kModeNV, pl.total_ub, pl.upd_lds, st, d, pl.n, s, true, true);
+    }
+  }
+  launch_batched_advance(pl.n, steps, st, d);
+}
+
+hsn_status run_chunk(hsn_ctx *ctx, Plan &pl, hipStream_t st, int kind, int steps, bool obj_last, bool chol_last,
+                     bool use_graph) {
+  if (!use_graph) {
+    queue_chunk(pl, pl.d, st, kind, steps, obj_last, chol_last);
+    HSN_LAUNCHED(ctx);
+    return HSN_OK;
+  }
+  for (auto &g : pl.graphs)
+    if (g.kind == kind && g.steps == steps && g.obj_last == obj_last && g.chol_last == chol_last) {
+      HSN_HIP(ctx, hipGraphLaunch(g.exec, st));
+      return HSN_OK;
+    }
+  Plan::G g;
+  g.kind = kind;
+  g.steps = steps;
+  g.obj_last = obj_last;
+  g.chol_last = chol_last;
+  // Captured on the context's own stream (the caller's may be the null
+  // stream, which cannot capture), launched on the caller's.
+  if (!ctx->cap_stream) HSN_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = ctx->cap_stream;
+  HSN_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  queue_chunk(pl, pl.d, cs, kind, steps, obj_last, chol_last);
+  const hipError_t le = hipGetLastError();
+  const hipError_t ce = hipStreamEndCapture(cs, &g.graph);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    return fail(ctx, HSN_ERR_DEVICE, "batched nmf: graph capture failed: %s",
+                hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  if (hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g.graph);
+    return fail(ctx, HSN_ERR_DEVICE, "batched nmf: graph instantiation failed");
+  }
+  pl.graphs.push_back(g);
+  HSN_HIP(ctx, hipGraphLaunch(g.exec, st));
+  return HSN_OK;
+}
+
+}  // namespace
+}  // namespace hsn
+
+extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nmf_problem *probs,
+                                               const hsn_nmf_opts *o, int flags, hsn_nmf_stats *stats, void *stream) {
+  using namespace hsn;
+  if (!ctx) return HSN_ERR_INVALID_ARG;
+  if (n < 1 || n > 4096 || !probs) return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: need 1 <= n <= 4096 problems");
+  if (!o) return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: opts is NULL");
+  if (o->algo != HSN_ALGO_MU || o->precision != HSN_PREC_FP32 || o->init != HSN_INIT_USER ||
+      (o->polish_rounds > 0 && o->polish_algo != HSN_ALGO_ANLS))
+    return fail(ctx, HSN_ERR_UNSUPPORTED, "batched nmf: float32 MU bulk + ANLS polish from a user start only");
+  if (o->max_iter < 0 || o->check_every < 1 || o->polish_rounds < 0)
+    return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: max_iter >= 0, check_every >= 1, polish_rounds >= 0 required");
+  if (flags & ~(HSN_BATCH_GRAPH | HSN_BATCH_AUTOTUNE)) return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: bad flags");
+  for (int i = 0; i < n; ++i) {
+    const hsn_nmf_problem &q = probs[i];
+    if (q.k < 1 || q.k > 8) return fail(ctx, HSN_ERR_SHAPE, "batched nmf: problem %d: k must be in 1..8", i);
+    if (q.n_p < 1 || q.n_k < 1 || q.n_k > 2048)
+      return fail(ctx, HSN_ERR_SHAPE, "batched nmf: problem %d: need n_p >= 1 and 1 <= n_k <= 2048", i);
+    if (!q.p || !q.V || !q.D) return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: problem %d: NULL pointer", i);
+    if (q.ldp < q.n_k || q.ldp % 4 != 0 || reinterpret_cast<uintptr_t>(q.p) % 16 != 0)
+      return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: problem %d: ldp >= n_k, ldp %% 4 == 0, 16-byte aligned p", i);
+    if (stats && stats[i].history_cap > 0 && !stats[i].history)
+      return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: stats[%d].history is NULL", i);
+  }
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool use_graph = flags & HSN_BATCH_GRAPH;
+  const bool tune = flags & HSN_BATCH_AUTOTUNE;
+  const int hist_cap = o->max_iter / o->check_every + 2 + o->polish_rounds;
+  const bool need_nv = o->polish_rounds > 0;
+
+  // Plan lookup: batch shape + schedule sizes + flags.
+  std::string sig = "n=" + std::to_string(n) + ";h=" + std::to_string(hist_cap) + ";nv=" + std::to_string(need_nv) +
+                    ";t=" + std::to_string(tune);
+  for (int i = 0; i < n; ++i)
+    sig += ";" + std::to_string(probs[i].n_p) + "," + std::to_string(probs[i].n_k) + "," +
+           std::to_string(probs[i].ldp) + "," + std::to_string(probs[i].k);
+  Plan *pl = nullptr;
+  for (Owned *ow : ctx->plans) {
+    Plan *c = dynamic_cast<Plan *>(ow);
+    if (c && c->sig == sig) pl = c;
+  }
+  const double tol = o->rel_obj_tol;
+  if (!pl) {
+    auto np = new Plan;
+    np->sig = sig;
+    np->n = n;
+    np->need_nv = need_nv;
+    np->hist_cap = hist_cap;
+    for (int i = 0; i < n; ++i) {
+      np->shapes.push_back({probs[i].n_p, probs[i].n_k, probs[i].ldp, probs[i].k});
+      np->max_k = std::max(np->max_k, probs[i].k);
+    }
+    const std::vector<int> cands[] = {partition(*np, 0, ctx->num_cu), partition(*np, 2, ctx->num_cu),
+                                      partition(*np, 4, ctx->num_cu), partition(*np, 8, ctx->num_cu),
+                                      partition(*np, 16, ctx->num_cu)};
+    np->wg_cap.assign(n, 1);
+    for (auto &c : cands)
+      for (int i = 0; i < n; ++i) np->wg_cap[i] = std::max(np->wg_cap[i], c[i]);
+    size_t total = 0;
+    const std::vector<InstMem> m = mem_layout(*np, total);
+    if (hipMalloc(&np->mem, total) != hipSuccess) {
+      (void)hipGetLastError();
+      delete np;
+      return fail(ctx, HSN_ERR_OOM, "batched nmf: cannot allocate %zu bytes of plan memory", total);
+    }
+    np->mem_bytes = total;
+    np->d = reinterpret_cast<BatchInst *>(np->mem);
+    np->d_tune = reinterpret_cast<BatchInst *>(np->mem + align256(sizeof(BatchInst) * n));
+    np->ctrl = reinterpret_cast<NmfCtrl *>(np->mem + align256(sizeof(BatchInst) * n) * 2);
+    NmfCtrl *tctrl = reinterpret_cast<NmfCtrl *>(np->mem + align256(sizeof(BatchInst) * n) * 2 +
+                                                 align256(sizeof(NmfCtrl) * n));
+    np->pass_lds = batched_pass_lds(np->max_k);
+    np->upd_lds = std::max(batched_update_lds(np->max_k, kModeNV), batched_update_lds(np->max_k, kModeMU));
+    if (batched_kernel_setup(np->pass_lds, np->upd_lds) != hipSuccess) {
+      (void)hipGetLastError();
+      delete np;
+      return fail(ctx, HSN_ERR_DEVICE, "batched nmf: kernel attribute setup failed");
+    }
+    np->wg = cands[0];
+    if (tune) {
+      // Time pass (N_D form) + D update per candidate on the tuning copy
+      // (scratch D, control and history; V and p only read).
+      float best = 1e30f;
+      int best_c = 0;
+      hipEvent_t e0, e1;
+      HSN_HIP(ctx, hipEventCreate(&e0));
+      HSN_HIP(ctx, hipEventCreate(&e1));
+      for (int c = 0; c < 5; ++c) {
+        std::vector<BatchInst> v;
+        int tw, tu, tr;
+        layout(*np, cands[c], probs, 0.0, v, tw, tu, tr, ctx->num_cu);
+        fill_pointers(*np, m, v, tctrl, true);
+        HSN_HIP(ctx, hipMemcpyAsync(np->d_tune, v.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice, st));
+        for (int i = 0; i < n; ++i)
+          HSN_HIP(ctx, hipMemcpyAsync(v[i].D, probs[i].D, sizeof(float) * probs[i].n_k * probs[i].k,
+                                      hipMemcpyDeviceToDevice, st));
+        launch_batched_init(n, 0, st, np->d_tune);
+        Plan tmp;
+        tmp.n = n;
+        tmp.total_wg = tw;
+        tmp.total_ub = tu;
+        tmp.total_rb = tr;
+        tmp.pass_lds = np->pass_lds;
+        tmp.upd_lds = np->upd_lds;
+        float ms_c = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+          HSN_HIP(ctx, hipEventRecord(e0, st));
+          launch_batched_pass(kModeND, true, tw, tmp.pass_lds, st, np->d_tune, n, 0);
+          launch_batched_update(kModeMU, tu, tmp.upd_lds, st, np->d_tune, n, 0, false, false);
+          HSN_HIP(ctx, hipEventRecord(e1, st));
+          HSN_HIP(ctx, hipEventSynchronize(e1));
+          float ms = 0.f;
+          HSN_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) ms_c += ms;
+        }
+        HSN_LAUNCHED(ctx);
+        if (ms_c < best) {
+          best = ms_c;
+          best_c = c;
+        }
+        np->tune_note += (c ? " " : "") + std::to_string(ms_c / 2);
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      np->wg = cands[best_c];
+      np->tune_note += " -> candidate " + std::to_string(best_c);
+    }
+    layout(*np, np->wg, nullptr, tol, np->h, np->total_wg, np->total_ub, np->total_rb, ctx->num_cu);
+    fill_pointers(*np, m, np->h, np->ctrl, false);
+    for (int i = 0; i < n; ++i) np->hist_off.push_back(m[i].hist);
+    ctx->plans.push_back(np);
+    pl = np;
+  }
+
+  // Per call: operands, stop references and tolerance into the descriptors.
+  for (int i = 0; i < n; ++i) {
+    pl->h[i].P = probs[i].p;
+    pl->h[i].V = probs[i].V;
+    pl->h[i].D = probs[i].D;
+    pl->h[i].f_ref = probs[i].f_ref > 0.0 ? probs[i].f_ref : 0.0;
+    pl->h[i].tol = tol;
+  }
+  const int n_steps = o->max_iter + o->polish_rounds;
+  const bool first_exact = o->max_iter == 0 && o->polish_rounds > 0;
+  if (stats) HSN_HIP(ctx, hipEventRecord(ctx->ev0, st));
+  HSN_HIP(ctx, hipMemcpyAsync(pl->d, pl->h.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice, st));
+  launch_batched_init(n, first_exact ? 1 : 0, st, pl->d);
+  // Steps beyond the schedule (the tail of the last polish chunk) return at once.
+  set_limit_kernel<<<(n + 63) / 64, 64, 0, st>>>(pl->d, n, n_steps);
+  HSN_LAUNCHED(ctx);
+
+  bool any_ref = false;
+  for (int i = 0; i < n; ++i) any_ref |= probs[i].f_ref > 0.0;
+  std::vector<NmfCtrl> hc(n);
+  auto all_stopped = [&](int done) -> int {  // -1 on error, 1 if every instance stopped before `done`
+    if (hipMemcpyAsync(hc.data(), pl->ctrl, sizeof(NmfCtrl) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return -1;
+    for (int i = 0; i < n; ++i)
+      if (hc[i].stop_at > done) return 0;
+    return 1;
+  };
+  hsn_status rc = HSN_OK;
+  int done = 0;
+  bool stopped = false;
+  const bool polish_follows = o->polish_rounds > 0;
+  while (done < o->max_iter && !stopped) {
+    const int c = std::min(o->check_every, o->max_iter - done);
+    const bool last_bulk = done + c == o->max_iter;
+    if ((rc = run_chunk(ctx, *pl, st, 0, c, true, polish_follows && last_bulk, use_graph)) != HSN_OK) return rc;
+    done += c;
+    if (any_ref && done < n_steps) {
+      const int a = all_stopped(done);
+      if (a < 0) return fail(ctx, HSN_ERR_DEVICE, "batched nmf: control read failed");
+      stopped = a == 1;
+    }
+  }
+  while (done < n_steps && !stopped) {
+    if ((rc = run_chunk(ctx, *pl, st, 1, kPolishChunk, true, true, use_graph)) != HSN_OK) return rc;
+    done += kPolishChunk;
+    if (any_ref && done < n_steps) {
+      const int a = all_stopped(done);
+      if (a < 0) return fail(ctx, HSN_ERR_DEVICE, "batched nmf: control read failed");
+      stopped = a == 1;
+    }
+  }
+  if (stats) {
+    HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
+    HSN_HIP(ctx, hipMemcpyAsync(hc.data(), pl->ctrl, sizeof(NmfCtrl) * n, hipMemcpyDeviceToHost, st));
+    HSN_HIP(ctx, hipStreamSynchronize(st));
+    float ms = 0.f;
+    HSN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    std::vector<double> h;
+    for (int i = 0; i < n; ++i) {
+      hsn_nmf_stats &s = stats[i];
+      const int fin = std::min(hc[i].stop_at, n_steps);
+      s.ms = ms;
+      s.iters = std::min(fin, o->max_iter);
+      s.polish_done = std::max(0, fin - o->max_iter);
+      s.history_len = 0;
+      s.objective = NAN;
+      const int len = std::min(hc[i].hist_len, pl->hist_cap);
+      if (len > 0) {
+        h.resize(len);
+        HSN_HIP(ctx, hipMemcpy(h.data(), pl->mem + pl->hist_off[i], sizeof(double) * len, hipMemcpyDeviceToHost));
+        s.objective = h.back();
+        const int nc = std::min(len, s.history_cap);
+        for (int j = 0; j < nc; ++j) s.history[j] = h[j];
+        s.history_len = nc;
+      }
+      s.rel_obj = probs[i].f_ref > 0.0 ? (s.objective - probs[i].f_ref) / probs[i].f_ref : NAN;
+    }
+  }
+  return HSN_OK;
+}

@@ -41,7 +41,7 @@ struct NmfCtrl {
   int stop_at;
   int upd_ticket;  // arrival counter of the D-update blocks (last block finishes G_D)
   int hist_len;    // objective values written so far
-  int pad;
+  int iter_base;   // batched runs: index of the first step of the replayed chunk
 };
 
 // Workspace of one decomposition (all device pointers).
@@ -58,6 +58,35 @@ struct NmfWork {
   uint16_t *img;     // bfloat16 operand images of D for the MFMA pass (or null)
   int n_wg;
 };
+
+// One decomposition of a batch (device copy read by the batched kernels):
+// its operands, its workspace and its ranges in the shared launch grids.
+struct BatchInst {
+  const float *P;
+  int64_t ldp, n_p;
+  int n_k, K, nq;
+  float *V, *D, *NV;
+  double *gd, *chol;
+  float *part_nd;
+  double *part_gv, *part_obj, *part_gd, *hist;
+  NmfCtrl *ctrl;
+  int wg0, n_wg;   // pass workgroups
+  int ub0, n_ub;   // D-update blocks
+  int rb0, n_rb;   // row-solve blocks
+  double f_ref, tol;
+};
+
+// Instance of a batch that owns grid block b: the last i with first(i) <= b
+// (first = the instances' ascending range starts).
+template <class F>
+__device__ __forceinline__ int batch_find(int n, int b, F first) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first(mid) <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 constexpr int kCholStride = 36;  // packed lower triangle of an 8x8 matrix
 

@@ -14,20 +14,35 @@ namespace hsn {
 constexpr int kPassThreads = 256;
 constexpr int kRows = 8;
 
+// LDS of one pass workgroup: red [4][kRows*K] f32 | vnew, vold [kRows][K] f32 |
+// gd_s [K*K] f64 | obj_s [4] f64.
+template <int K>
+struct PassLds {
+  static constexpr int red = 0;
+  static constexpr int vnew = red + (kPassThreads / 64) * kRows * K * 4;
+  static constexpr int vold = vnew + kRows * K * 4;
+  static constexpr int gd = (vold + kRows * K * 4 + 7) / 8 * 8;
+  static constexpr int obj = gd + K * K * 8;
+  static constexpr int bytes = obj + (kPassThreads / 64) * 8;
+};
+
+// One workgroup `wg` of `n_wg` of the pass (the kernels below supply the
+// index, the count and the LDS block).
 template <int K, int NQ, int MODE, bool OBJ>
-__global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
+__device__ __forceinline__ void pass_f32_body(
     const float *__restrict__ P, int64_t ldp, int64_t n_p, int n_k, float *__restrict__ V, float *__restrict__ NV,
     const float *__restrict__ D, const double *__restrict__ GD, const double *__restrict__ chol,
     float *__restrict__ part_nd, double *__restrict__ part_gv, double *__restrict__ part_obj,
-    const NmfCtrl *__restrict__ ctrl, int iter) {
+    const NmfCtrl *__restrict__ ctrl, int iter, int wg, int n_wg, char *__restrict__ lds) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  __shared__ float red[kPassThreads / 64][kRows * K];
-  __shared__ float vnew[kRows][K];
-  __shared__ float vold[kRows][K];
-  __shared__ double gd_s[K * K];
-  __shared__ double obj_s[kPassThreads / 64];
+  using L = PassLds<K>;
+  float(*red)[kRows * K] = reinterpret_cast<float(*)[kRows * K]>(lds + L::red);
+  float(*vnew)[K] = reinterpret_cast<float(*)[K]>(lds + L::vnew);
+  float(*vold)[K] = reinterpret_cast<float(*)[K]>(lds + L::vold);
+  double *gd_s = reinterpret_cast<double *>(lds + L::gd);
+  double *obj_s = reinterpret_cast<double *>(lds + L::obj);
 
   float d[NQ][4][K];
 #pragma unroll
@@ -51,7 +66,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
   __syncthreads();
 
   const int64_t n_tiles = (n_p + kRows - 1) / kRows;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  for (int64_t tile = wg; tile < n_tiles; tile += n_wg) {
     const int64_t row0 = tile * kRows;
     // The tile's V values (one per thread t < kRows*K) are loaded with the
     // tile, so the row rule does not wait on a global load.
@@ -187,7 +202,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
   }
 
   if (MODE != kModeNV) {
-    float *dst = part_nd + size_t(blockIdx.x) * n_k * K;
+    float *dst = part_nd + size_t(wg) * n_k * K;
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -198,7 +213,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
           for (int j = 0; j < K; ++j) dst[k * K + j] = nd[q][e][j];
         }
       }
-    if (t < K * K) part_gv[size_t(blockIdx.x) * K * K + t] = gv;
+    if (t < K * K) part_gv[size_t(wg) * K * K + t] = gv;
     if (OBJ) {
       obj = wave_sum_all(obj);
       if (lane == 0) obj_s[wave] = obj;
@@ -206,9 +221,77 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
       if (t == 0) {
         double s = 0.0;
         for (int w = 0; w < kPassThreads / 64; ++w) s += obj_s[w];
-        part_obj[blockIdx.x] = s;
+        part_obj[wg] = s;
       }
     }
+  }
+}
+
+template <int K, int NQ, int MODE, bool OBJ>
+__global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
+    const float *__restrict__ P, int64_t ldp, int64_t n_p, int n_k, float *__restrict__ V, float *__restrict__ NV,
+    const float *__restrict__ D, const double *__restrict__ GD, const double *__restrict__ chol,
+    float *__restrict__ part_nd, double *__restrict__ part_gv, double *__restrict__ part_obj,
+    const NmfCtrl *__restrict__ ctrl, int iter) {
+  __shared__ __attribute__((aligned(16))) char lds[PassLds<K>::bytes];
+  pass_f32_body<K, NQ, MODE, OBJ>(P, ldp, n_p, n_k, V, NV, D, GD, chol, part_nd, part_gv, part_obj, ctrl, iter,
+                                  int(blockIdx.x), int(gridDim.x), lds);
+}
+
+// ---------------------------------------------------------------------------
+// Batched pass: one launch over the workgroups of many decompositions.  Block
+// b belongs to the instance whose range [wg0, wg0 + n_wg) holds it; the
+// instance's K and bin count pick the body.  The iteration index is the
+// instance's iter_base (advanced on the device between graph replays) plus
+// the step's position inside the replayed chunk.
+// ---------------------------------------------------------------------------
+template <int MODE, bool OBJ>
+__global__ __launch_bounds__(kPassThreads) void batched_pass_kernel(const BatchInst *__restrict__ d, int n_inst,
+                                                                    int iter_local) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int i = batch_find(n_inst, int(blockIdx.x), [&](int j) { return d[j].wg0; });
+  const BatchInst &b = d[i];
+  const int wg = int(blockIdx.x) - b.wg0;
+  if (wg >= b.n_wg) return;
+  const int iter = b.ctrl->iter_base + iter_local;
+  switch (b.K * 4 + b.nq) {
+#define HSN_B(KK, NQ_)                                                                                          \
+  case KK * 4 + NQ_:                                                                                           \
+    pass_f32_body<KK, NQ_, MODE, OBJ>(b.P, b.ldp, b.n_p, b.n_k, b.V, b.NV, b.D, b.gd, b.chol, b.part_nd,        \
+                                      b.part_gv, b.part_obj, b.ctrl, iter, wg, b.n_wg, lds);                   \
+    break;
+    HSN_B(1, 1) HSN_B(2, 1) HSN_B(3, 1) HSN_B(4, 1) HSN_B(5, 1) HSN_B(6, 1) HSN_B(7, 1) HSN_B(8, 1)
+    HSN_B(1, 2) HSN_B(2, 2) HSN_B(3, 2) HSN_B(4, 2) HSN_B(5, 2) HSN_B(6, 2) HSN_B(7, 2) HSN_B(8, 2)
+#undef HSN_B
+    default: break;
+  }
+}
+
+size_t batched_pass_lds(int max_k) {
+  switch (max_k) {
+    case 1: return PassLds<1>::bytes;
+    case 2: return PassLds<2>::bytes;
+    case 3: return PassLds<3>::bytes;
+    case 4: return PassLds<4>::bytes;
+    case 5: return PassLds<5>::bytes;
+    case 6: return PassLds<6>::bytes;
+    case 7: return PassLds<7>::bytes;
+    default: return PassLds<8>::bytes;
+  }
+}
+
+// mode: kModeMU (obj or not), kModeNV, kModeND (objective always).
+void launch_batched_pass(int mode, bool obj, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
+                         int iter_local) {
+  if (mode == kModeMU) {
+    if (obj)
+      batched_pass_kernel<kModeMU, true><<<n_blocks, kPassThreads, lds, st>>>(d, n_inst, iter_local);
+    else
+      batched_pass_kernel<kModeMU, false><<<n_blocks, kPassThreads, lds, st>>>(d, n_inst, iter_local);
+  } else if (mode == kModeNV) {
+    batched_pass_kernel<kModeNV, false><<<n_blocks, kPassThreads, lds, st>>>(d, n_inst, iter_local);
+  } else {
+    batched_pass_kernel<kModeND, true><<<n_blocks, kPassThreads, lds, st>>>(d, n_inst, iter_local);
   }
 }
 

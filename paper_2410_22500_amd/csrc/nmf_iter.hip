@@ -63,10 +63,9 @@ __device__ inline void factor_all(const double *G, double *__restrict__ chol) {
 }
 
 template <int K>
-__global__ __launch_bounds__(kUpdThreads) void nmf_init_kernel(const float *__restrict__ D, int n_k, double *__restrict__ GD,
-                                                               double *__restrict__ chol, int want_chol,
-                                                               uint16_t *__restrict__ img, int64_t ldb,
-                                                               NmfCtrl *__restrict__ ctrl) {
+__device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n_k, double *__restrict__ GD,
+                                              double *__restrict__ chol, int want_chol, uint16_t *__restrict__ img,
+                                              int64_t ldb, NmfCtrl *__restrict__ ctrl) {
   const int t = threadIdx.x;
   __shared__ double red[kUpdThreads / 64][K * K];
   __shared__ double g_s[K * K];
@@ -106,35 +105,66 @@ __global__ __launch_bounds__(kUpdThreads) void nmf_init_kernel(const float *__re
     ctrl->stop_at = INT_MAX;
     ctrl->upd_ticket = 0;
     ctrl->hist_len = 0;
+    ctrl->iter_base = 0;
   }
   __syncthreads();
   if (want_chol) factor_all<K>(g_s, chol);
 }
 
+template <int K>
+__global__ __launch_bounds__(kUpdThreads) void nmf_init_kernel(const float *__restrict__ D, int n_k, double *__restrict__ GD,
+                                                               double *__restrict__ chol, int want_chol,
+                                                               uint16_t *__restrict__ img, int64_t ldb,
+                                                               NmfCtrl *__restrict__ ctrl) {
+  nmf_init_body<K>(D, n_k, GD, chol, want_chol, img, ldb, ctrl);
+}
+
 // RULE: kModeMU (Lee-Seung), kModeHALS (column sweep), kModeNV (exact NNLS rows)
+// LDS of one update block (all float64 unless noted).
 template <int K, int RULE>
-__global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
+struct UpdLds {
+  static constexpr int E1 = K * K + 1;         // G_V entries + the objective
+  static constexpr int G1 = kUpdThreads / E1;  // groups summing them
+  static constexpr int EB = kUpdRows * K;      // N_D entries of a block
+  static constexpr int G2 = kUpdThreads / EB;
+  static constexpr int G3 = kUpdThreads / (K * K);
+  static constexpr int NCH = (1 << K) * kCholStride / ((RULE == kModeNV) ? 1 : (1 << K));
+  static constexpr int red1 = 0;
+  static constexpr int red2 = red1 + G1 * E1 * 8;
+  static constexpr int gv = red2 + G2 * EB * 8;
+  static constexpr int gd = gv + K * K * 8;
+  static constexpr int nd = gd + K * K * 8;
+  static constexpr int obj = nd + EB * 8;
+  static constexpr int chol = obj + 8;
+  static constexpr int red3 = chol + NCH * 8;
+  static constexpr int dn = red3 + G3 * K * K * 8;   // float [kUpdRows][K]
+  static constexpr int last = dn + kUpdRows * K * 4;  // int
+  static constexpr int bytes = (last + 4 + 15) / 16 * 16;
+};
+
+// One block `blk` of `n_blk` of the D update.
+template <int K, int RULE>
+__device__ __forceinline__ void update_d_body(
     float *__restrict__ D, const float *__restrict__ part_nd, const double *__restrict__ part_gv,
     const double *__restrict__ part_obj, int n_wg, int n_k, NmfCtrl *__restrict__ ctrl, int iter, int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
-    int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb) {
+    int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int blk, int n_blk,
+    char *__restrict__ lds) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
-  constexpr int E1 = K * K + 1;                 // G_V entries + the objective
-  constexpr int G1 = kUpdThreads / E1;          // groups summing them
-  constexpr int EB = kUpdRows * K;              // N_D entries of this block
-  constexpr int G2 = kUpdThreads / EB;
-  __shared__ double red1[G1][E1];
-  __shared__ double red2[G2][EB];
-  __shared__ double gv_s[K * K];
-  __shared__ double gd_s[K * K];
-  __shared__ double nd_s[EB];
-  __shared__ float dn_s[kUpdRows][K];
-  __shared__ double obj_s;
-  __shared__ double chol_s[(1 << K) * kCholStride / ((RULE == kModeNV) ? 1 : (1 << K))];
-  __shared__ int last_s;
+  using L = UpdLds<K, RULE>;
+  constexpr int E1 = L::E1, G1 = L::G1, EB = L::EB, G2 = L::G2;
+  double(*red1)[E1] = reinterpret_cast<double(*)[E1]>(lds + L::red1);
+  double(*red2)[EB] = reinterpret_cast<double(*)[EB]>(lds + L::red2);
+  double *gv_s = reinterpret_cast<double *>(lds + L::gv);
+  double *gd_s = reinterpret_cast<double *>(lds + L::gd);
+  double *nd_s = reinterpret_cast<double *>(lds + L::nd);
+  float(*dn_s)[K] = reinterpret_cast<float(*)[K]>(lds + L::dn);
+  double &obj_s = *reinterpret_cast<double *>(lds + L::obj);
+  double *chol_s = reinterpret_cast<double *>(lds + L::chol);
+  int &last_s = *reinterpret_cast<int *>(lds + L::last);
 
-  const int k0 = blockIdx.x * kUpdRows;
+  const int k0 = blk * kUpdRows;
   // G_V and objective: each thread sums every G1-th workgroup partial (8 loads in flight).
   if (t < G1 * E1) {
     const int e = t % E1, g = t / E1;
@@ -172,7 +202,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
   }
   __syncthreads();
   if (RULE == kModeNV) factor_all<K>(gv_s, chol_s);
-  if (blockIdx.x == 0 && t == 0 && has_obj) {
+  if (blk == 0 && t == 0 && has_obj) {
     const int h = ctrl->hist_len;
     hist[h] = obj_s;
     ctrl->hist_len = h + 1;
@@ -226,20 +256,20 @@ __global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
     const int i = t / K, j = t % K;
     double s = 0.0;
     for (int r = 0; r < kUpdRows; ++r) s += double(dn_s[r][i]) * double(dn_s[r][j]);
-    part_gd[size_t(blockIdx.x) * K * K + t] = s;
+    part_gd[size_t(blk) * K * K + t] = s;
   }
   __threadfence();
   __syncthreads();
-  if (t == 0) last_s = (atomicAdd(&ctrl->upd_ticket, 1) == int(gridDim.x) - 1);
+  if (t == 0) last_s = (atomicAdd(&ctrl->upd_ticket, 1) == n_blk - 1);
   __syncthreads();
   if (!last_s) return;
   __threadfence();
   {
-    constexpr int G3 = kUpdThreads / (K * K);
-    __shared__ double red3[G3][K * K];
+    constexpr int G3 = L::G3;
+    double(*red3)[K * K] = reinterpret_cast<double(*)[K * K]>(lds + L::red3);
     if (t < G3 * K * K) {
       const int e = t % (K * K), g = t / (K * K);
-      red3[g][e] = strided_sum(g, G3, int(gridDim.x), [&](int b) { return part_gd[size_t(b) * K * K + e]; });
+      red3[g][e] = strided_sum(g, G3, n_blk, [&](int b) { return part_gd[size_t(b) * K * K + e]; });
     }
     __syncthreads();
     if (t < K * K) {
@@ -254,15 +284,26 @@ __global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
   }
 }
 
+template <int K, int RULE>
+__global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
+    float *__restrict__ D, const float *__restrict__ part_nd, const double *__restrict__ part_gv,
+    const double *__restrict__ part_obj, int n_wg, int n_k, NmfCtrl *__restrict__ ctrl, int iter, int has_obj,
+    double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
+    int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb) {
+  __shared__ __attribute__((aligned(16))) char lds[UpdLds<K, RULE>::bytes];
+  update_d_body<K, RULE>(D, part_nd, part_gv, part_obj, n_wg, n_k, ctrl, iter, has_obj, f_ref, tol, hist, GD, chol,
+                         next_chol, part_gd, img, ldb, int(blockIdx.x), int(gridDim.x), lds);
+}
+
 template <int K>
-__global__ __launch_bounds__(256) void nnls_rows_kernel(const float *__restrict__ NV, const double *__restrict__ GD,
-                                                        const double *__restrict__ chol, float *__restrict__ V,
-                                                        int64_t n_p, const NmfCtrl *__restrict__ ctrl, int iter) {
+__device__ __forceinline__ void nnls_rows_body(const float *__restrict__ NV, const double *__restrict__ GD,
+                                               const double *__restrict__ chol, float *__restrict__ V, int64_t n_p,
+                                               const NmfCtrl *__restrict__ ctrl, int iter, int blk, int n_blk) {
   if (iter >= ctrl->stop_at) return;
   __shared__ double g_s[K * K];
   if (threadIdx.x < K * K) g_s[threadIdx.x] = GD[threadIdx.x];
   __syncthreads();
-  for (int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x; row < n_p; row += int64_t(gridDim.x) * 256) {
+  for (int64_t row = int64_t(blk) * 256 + threadIdx.x; row < n_p; row += int64_t(n_blk) * 256) {
     double h[K], x[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) h[j] = NV[row * K + j];
@@ -270,6 +311,70 @@ __global__ __launch_bounds__(256) void nnls_rows_kernel(const float *__restrict_
 #pragma unroll
     for (int j = 0; j < K; ++j) V[row * K + j] = float(x[j]);
   }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void nnls_rows_kernel(const float *__restrict__ NV, const double *__restrict__ GD,
+                                                        const double *__restrict__ chol, float *__restrict__ V,
+                                                        int64_t n_p, const NmfCtrl *__restrict__ ctrl, int iter) {
+  nnls_rows_body<K>(NV, GD, chol, V, n_p, ctrl, iter, int(blockIdx.x), int(gridDim.x));
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: one launch covers the blocks of many decompositions (block
+// ranges per instance in BatchInst); iteration = the instance's iter_base +
+// the step's position in the replayed chunk.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kUpdThreads) void batched_init_kernel(const BatchInst *__restrict__ d, int want_chol) {
+  const BatchInst &b = d[blockIdx.x];
+  switch (b.K) {
+#define HSN_K(KK) \
+  case KK: nmf_init_body<KK>(b.D, b.n_k, b.gd, b.chol, want_chol, nullptr, 0, b.ctrl); break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+    default: break;
+  }
+}
+
+template <int RULE>
+__global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(const BatchInst *__restrict__ d, int n_inst,
+                                                                     int iter_local, int has_obj, int next_chol) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int i = batch_find(n_inst, int(blockIdx.x), [&](int j) { return d[j].ub0; });
+  const BatchInst &b = d[i];
+  const int blk = int(blockIdx.x) - b.ub0;
+  if (blk >= b.n_ub) return;
+  const int iter = b.ctrl->iter_base + iter_local;
+  switch (b.K) {
+#define HSN_K(KK)                                                                                                 \
+  case KK:                                                                                                        \
+    update_d_body<KK, RULE>(b.D, b.part_nd, b.part_gv, b.part_obj, b.n_wg, b.n_k, b.ctrl, iter, has_obj, b.f_ref, \
+                            b.tol, b.hist, b.gd, b.chol, next_chol, b.part_gd, nullptr, 0, blk, b.n_ub, lds);      \
+    break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+    default: break;
+  }
+}
+
+__global__ __launch_bounds__(256) void batched_rows_kernel(const BatchInst *__restrict__ d, int n_inst, int iter_local) {
+  const int i = batch_find(n_inst, int(blockIdx.x), [&](int j) { return d[j].rb0; });
+  const BatchInst &b = d[i];
+  const int blk = int(blockIdx.x) - b.rb0;
+  if (blk >= b.n_rb) return;
+  const int iter = b.ctrl->iter_base + iter_local;
+  switch (b.K) {
+#define HSN_K(KK) \
+  case KK: nnls_rows_body<KK>(b.NV, b.gd, b.chol, b.V, b.n_p, b.ctrl, iter, blk, b.n_rb); break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+    default: break;
+  }
+}
+
+__global__ void batched_advance_kernel(const BatchInst *__restrict__ d, int n_inst, int steps) {
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n_inst) d[i].ctrl->iter_base += steps;
 }
 
 // ---------------------------------------------------------------------------
@@ -318,6 +423,46 @@ void launch_nnls_rows(int K, hipStream_t st, const NmfWork &w, float *V, int64_t
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
   }
+}
+
+size_t batched_update_lds(int max_k, int rule) {
+  switch (max_k) {
+#define HSN_K(KK) \
+  case KK: return rule == kModeNV ? UpdLds<KK, kModeNV>::bytes : UpdLds<KK, kModeMU>::bytes;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7)
+#undef HSN_K
+    default: return rule == kModeNV ? UpdLds<8, kModeNV>::bytes : UpdLds<8, kModeMU>::bytes;
+  }
+}
+
+hipError_t batched_kernel_setup(size_t pass_lds, size_t upd_lds) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_update_kernel<kModeMU>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(upd_lds));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_update_kernel<kModeNV>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(upd_lds));
+  (void)pass_lds;
+  return e;
+}
+
+void launch_batched_init(int n_inst, int want_chol, hipStream_t st, const BatchInst *d) {
+  batched_init_kernel<<<n_inst, kUpdThreads, 0, st>>>(d, want_chol);
+}
+
+void launch_batched_update(int rule, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
+                           int iter_local, bool has_obj, bool next_chol) {
+  if (rule == kModeNV)
+    batched_update_kernel<kModeNV><<<n_blocks, kUpdThreads, lds, st>>>(d, n_inst, iter_local, has_obj, next_chol);
+  else
+    batched_update_kernel<kModeMU><<<n_blocks, kUpdThreads, lds, st>>>(d, n_inst, iter_local, has_obj, next_chol);
+}
+
+void launch_batched_rows(int n_blocks, hipStream_t st, const BatchInst *d, int n_inst, int iter_local) {
+  batched_rows_kernel<<<n_blocks, 256, 0, st>>>(d, n_inst, iter_local);
+}
+
+void launch_batched_advance(int n_inst, int steps, hipStream_t st, const BatchInst *d) {
+  batched_advance_kernel<<<(n_inst + 63) / 64, 64, 0, st>>>(d, n_inst, steps);
 }
 
 }  // namespace hsn

@@ -56,6 +56,14 @@ class NmfStats(C.Structure):
                 ("ms", C.c_float)]
 
 
+class NmfProblem(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("ldp", C.c_int64), ("n_p", C.c_int64), ("n_k", C.c_int64), ("k", C.c_int),
+                ("V", C.c_void_p), ("D", C.c_void_p), ("f_ref", C.c_double)]
+
+
+BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
+
+
 class Geom(C.Structure):
     _fields_ = [("n_views", C.c_int64), ("n_slices", C.c_int64), ("n_cols", C.c_int64), ("k", C.c_int),
                 ("angles", C.POINTER(C.c_double))]
@@ -75,6 +83,9 @@ _lib.hsn_normalize.restype = C.c_int
 _lib.hsn_subspace_nmf.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64, _P, _P,
                                   C.POINTER(NmfOpts), C.POINTER(NmfStats), _P]
 _lib.hsn_subspace_nmf.restype = C.c_int
+_lib.hsn_subspace_nmf_batched.argtypes = [_P, C.c_int, C.POINTER(NmfProblem), C.POINTER(NmfOpts), C.c_int,
+                                          C.POINTER(NmfStats), _P]
+_lib.hsn_subspace_nmf_batched.restype = C.c_int
 _lib.hsn_project.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_float, C.c_float, _P]
 _lib.hsn_project.restype = C.c_int
 _lib.hsn_backproject.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_float, C.c_float, _P]
@@ -217,6 +228,28 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
                                  C.byref(stats), _stream(dev)), ctx)
     return dict(iters=stats.iters, polish_done=stats.polish_done, objective=stats.objective, rel_obj=stats.rel_obj,
                 history=[hist[i] for i in range(stats.history_len)], ms=stats.ms)
+
+
+def hsn_subspace_nmf_batched(problems, max_iter: int = 100, check_every: int = 10, polish_rounds: int = 0,
+                             rel_obj_tol: float = 0.0, flags: int = BATCH_GRAPH, history_cap: int = 4096):
+    """problems: list of (p [N_p][ldp] f32, n_k, V [N_p][K], D [N_k][K], f_ref); V and D in place.
+    Float32 MU bulk then ANLS polish, one launch per phase over all instances."""
+    dev = _dev(problems[0][2])
+    ctx = context(dev)
+    n = len(problems)
+    arr = (NmfProblem * n)()
+    for i, (p, n_k, V, D, f_ref) in enumerate(problems):
+        arr[i] = NmfProblem(p.data_ptr(), p.stride(0), V.shape[0], n_k, V.shape[1], V.data_ptr(), D.data_ptr(),
+                            float(f_ref or 0.0))
+    opts = NmfOpts(1, ALGO_MU, PREC_FP32, INIT_USER, max_iter, check_every, polish_rounds, ALGO_ANLS, 0,
+                   rel_obj_tol, 0.0, None)
+    hists = [(C.c_double * max(history_cap, 1))() for _ in range(n)]
+    stats = (NmfStats * n)()
+    for i in range(n):
+        stats[i] = NmfStats(0, 0, 0.0, 0.0, C.cast(hists[i], C.POINTER(C.c_double)), history_cap, 0, 0.0)
+    _check(_lib.hsn_subspace_nmf_batched(ctx, n, arr, C.byref(opts), flags, stats, _stream(dev)), ctx)
+    return [dict(iters=s.iters, polish_done=s.polish_done, objective=s.objective, rel_obj=s.rel_obj,
+                 history=[hists[i][j] for j in range(s.history_len)], ms=s.ms) for i, s in enumerate(stats)]
 
 
 def hsn_project(x: torch.Tensor, n_views: int, angles: Optional[Sequence[float]] = None, alpha: float = 1.0,

@@ -1,0 +1,110 @@
+"""Batched decompositions (one launch per phase over uneven instances, graph
+replays, autotuned partition) against per-instance calls and the oracle.
+
+Without autotuning every instance is partitioned exactly as the
+single-instance call partitions it, and all sums run in a fixed order, so
+V, D and the objective history must be bitwise equal to those of
+hsn_subspace_nmf on each instance alone (which the oracle pins).  With the
+autotuned partition only the summation order of the N_D / G_V / objective
+partials changes: one step is held to 1e-5 relative against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import nmf as onmf
+from tests.gpu_util import rel_fro, show, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(777, 1000, 3), (3000, 512, 5), (500, 2048, 2), (2053, 1500, 6), (64, 100, 4), (4100, 256, 8)]
+
+
+def _instances(seed=0):
+    out = []
+    for i, (n_p, n_k, k) in enumerate(SHAPES):
+        g = np.random.Generator(np.random.PCG64(seed * 100 + i))
+        P = np.maximum(g.uniform(0, 1, (n_p, k)) @ g.uniform(0, 1, (k, n_k)) + 0.05 * g.standard_normal((n_p, n_k)), 0)
+        V0, D0 = synth.random_factors(n_p, n_k, k, seed * 100 + 50 + i)
+        ldp = (n_k + 3) // 4 * 4
+        pd = torch.zeros((n_p, ldp), dtype=torch.float32, device="cuda")
+        pd[:, :n_k] = torch.from_numpy(P.astype(np.float32)).cuda()
+        out.append(dict(P=P.astype(np.float32).astype(np.float64), p=pd, n_k=n_k,
+                        V0=V0.astype(np.float32), D0=D0.astype(np.float32)))
+    return out
+
+
+def _run_single(inst, **kw):
+    V = to_dev(inst["V0"])
+    D = to_dev(inst["D0"])
+    st = hsn_mod().hsn_subspace_nmf(inst["p"], None, inst["n_k"], V, D, polish_algo=hsn_mod().ALGO_ANLS, **kw)
+    return V.cpu().numpy(), D.cpu().numpy(), st
+
+
+def hsn_mod():
+    from paper_2410_22500_amd import hsn
+    return hsn
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_batched_is_bitwise_per_instance(hsn, flags):
+    insts = _instances()
+    kw = dict(max_iter=30, check_every=10, polish_rounds=6)
+    show("batched bitwise", flags=flags)
+    ref = [_run_single(x, **kw) for x in insts]
+    Vs = [to_dev(x["V0"]) for x in insts]
+    Ds = [to_dev(x["D0"]) for x in insts]
+    sts = hsn.hsn_subspace_nmf_batched([(x["p"], x["n_k"], V, D, 0.0) for x, V, D in zip(insts, Vs, Ds)],
+                                       flags=flags, **kw)
+    for i, (x, V, D, st, (Vr, Dr, sr)) in enumerate(zip(insts, Vs, Ds, sts, ref)):
+        assert np.array_equal(V.cpu().numpy(), Vr), i
+        assert np.array_equal(D.cpu().numpy(), Dr), i
+        assert st["history"] == sr["history"], i
+        assert st["iters"] == 30 and st["polish_done"] == 6
+
+
+def test_batched_stops_each_instance_like_alone(hsn):
+    insts = _instances(1)
+    long_kw = dict(max_iter=50, check_every=50, polish_rounds=150)
+    f_ref = [_run_single(x, **long_kw)[2]["history"][-1] * (1 - 1e-6) for x in insts]
+    kw = dict(max_iter=50, check_every=25, polish_rounds=150, rel_obj_tol=1e-4)
+    show("batched stop test")
+    ref = [_run_single(x, f_ref=f, **kw) for x, f in zip(insts, f_ref)]
+    Vs = [to_dev(x["V0"]) for x in insts]
+    Ds = [to_dev(x["D0"]) for x in insts]
+    sts = hsn.hsn_subspace_nmf_batched([(x["p"], x["n_k"], V, D, f) for x, V, D, f in zip(insts, Vs, Ds, f_ref)],
+                                       flags=hsn.BATCH_GRAPH, **kw)
+    for i, (st, (Vr, Dr, sr)) in enumerate(zip(sts, ref)):
+        show("  inst", i=i, iters=st["iters"], polish=st["polish_done"], rel=st["rel_obj"])
+        assert (st["iters"], st["polish_done"]) == (sr["iters"], sr["polish_done"])
+        assert st["rel_obj"] <= 1e-4
+        assert np.array_equal(Vs[i].cpu().numpy(), Vr) and np.array_equal(Ds[i].cpu().numpy(), Dr)
+
+
+def test_autotuned_batch_one_step_matches_oracle_and_plan_is_reused(hsn):
+    insts = _instances(2)
+    show("batched autotune")
+    for rep in range(2):  # the second call reuses the cached plan and graphs
+        Vs = [to_dev(x["V0"]) for x in insts]
+        Ds = [to_dev(x["D0"]) for x in insts]
+        sts = hsn.hsn_subspace_nmf_batched([(x["p"], x["n_k"], V, D, 0.0) for x, V, D in zip(insts, Vs, Ds)],
+                                           max_iter=1, check_every=1,
+                                           flags=hsn.BATCH_GRAPH | hsn.BATCH_AUTOTUNE)
+        for i, x in enumerate(insts):
+            V1, D1, fh, _ = onmf.mu_step(x["P"], x["V0"].astype(np.float64), x["D0"].astype(np.float64))
+            assert rel_fro(Vs[i].cpu().numpy(), V1) <= 1e-5, (rep, i)
+            assert rel_fro(Ds[i].cpu().numpy(), D1) <= 1e-5, (rep, i)
+            assert abs(sts[i]["history"][0] - fh) <= 1e-5 * fh
+
+
+def test_batched_rejects_bad_input(hsn):
+    insts = _instances()[:2]
+    V = to_dev(insts[0]["V0"])
+    D = to_dev(insts[0]["D0"])
+    with pytest.raises(hsn.HsnError):  # K = 9
+        bad = torch.zeros((V.shape[0], 9), device="cuda")
+        hsn.hsn_subspace_nmf_batched([(insts[0]["p"], insts[0]["n_k"], bad, torch.zeros((insts[0]["n_k"], 9),
+                                                                                        device="cuda"), 0.0)])
+    with pytest.raises(hsn.HsnError):  # misaligned pitch
+        p = torch.zeros((V.shape[0], insts[0]["n_k"] + 1), device="cuda")
+        hsn.hsn_subspace_nmf_batched([(p, insts[0]["n_k"], V, D, 0.0)])
