@@ -185,6 +185,9 @@ enum { HSN_BATCH_GRAPH = 1, HSN_BATCH_AUTOTUNE = 2 };
 hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nmf_problem *probs,
                                     const hsn_nmf_opts *opts, int flags, hsn_nmf_stats *stats,
                                     void *stream);
+/* Text description of the plan the last batched call on ctx used (groups,
+ * workgroups, tuning timings); valid until the next call. */
+const char *hsn_batched_plan_info(const hsn_ctx *ctx);
 
 /* ------------------------------------------------------------------ */
 /* Projector A (eq. 3 / eq. 5), K channels, all slices in one launch.   */

@@ -42,6 +42,7 @@ struct hsn_ctx {
   std::vector<hsn::Owned *> plans;
   // Stream used only to capture graphs (capture is not allowed on the null stream).
   hipStream_t cap_stream = nullptr;
+  std::string last_plan_note;  // description of the last batched plan used
 };
 
 namespace hsn {

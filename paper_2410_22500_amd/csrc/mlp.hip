@@ -31,7 +31,7 @@ namespace hsn {
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
                      int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                     float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter);
+                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter);
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
                      bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img);
 

@@ -24,10 +24,10 @@ namespace hsn {
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
                      int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                     float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter);
+                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter);
 bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
                       int64_t n_p, int n_k, float *V, const double *GD, const double *chol, const uint16_t *img,
-                      float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter);
+                      float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter);
 int pass_bf16_wgs(hsn_ctx *ctx, int64_t n_p);
 size_t bf16_image_elems(int64_t ldb);
 int64_t bf16_image_ldb(int64_t ldb);

@@ -13,6 +13,12 @@
 // workspace, graphs, tuned partition) is cached in the context per batch
 // shape.
 //
+// Kernels are compiled per K (and per bin class for the pass), since a
+// kernel that picked K at run time would carry the register footprint of the
+// largest K for every instance: instances are ordered by (K, bins > 1024) and
+// the pass and the row solves take one launch per such group; the D update
+// (modest registers) takes one launch for all.
+//
 // Partition: without autotuning each instance gets the workgroup count the
 // single-instance call would use, so results are bitwise those of
 // hsn_subspace_nmf.  The autotuner times candidate budgets of row tiles per
@@ -23,21 +29,21 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
 namespace hsn {
 
-size_t batched_pass_lds(int max_k);
 size_t batched_update_lds(int max_k, int rule);
 hipError_t batched_kernel_setup(size_t pass_lds, size_t upd_lds);
-void launch_batched_pass(int mode, bool obj, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
-                         int iter_local);
+void launch_batched_pass(int K, int nq, int mode, bool obj, int n_blocks, hipStream_t st, const BatchInst *d,
+                         int n_inst, int iter_local);
 void launch_batched_init(int n_inst, int want_chol, hipStream_t st, const BatchInst *d);
 void launch_batched_update(int rule, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
                            int iter_local, bool has_obj, bool next_chol);
-void launch_batched_rows(int n_blocks, hipStream_t st, const BatchInst *d, int n_inst, int iter_local);
+void launch_batched_rows(int K, int n_blocks, hipStream_t st, const BatchInst *d, int n_inst, int iter_local);
 void launch_batched_advance(int n_inst, int steps, hipStream_t st, const BatchInst *d);
 int update_d_blocks(int n_k);
 
@@ -56,9 +62,26 @@ struct Shape {
   int k;
 };
 
+struct Group {
+  int K, nq, i0, i1;  // instances [i0, i1) of the plan order
+  int n_wg, n_rb;     // blocks of the group's pass / row-solve launches
+};
+
+// The instances a chunk launches: all of them, or after some have stopped
+// the compacted list of the rest (so that no launch dispatches workgroups
+// that would only return).
+struct View {
+  std::string key;           // "all" or the active set
+  std::vector<Group> groups;
+  int n = 0, total_ub = 0;
+  BatchInst *d = nullptr;
+};
+
 struct Plan : Owned {
   std::string sig;
   int n = 0;
+  std::vector<int> order;   // plan position -> problem index
+  std::vector<Group> groups;
   int max_k = 1;
   bool need_nv = false;
   std::vector<Shape> shapes;
@@ -70,12 +93,13 @@ struct Plan : Owned {
   NmfCtrl *ctrl = nullptr;        // [n] contiguous (one read per chunk)
   char *mem = nullptr;            // per-instance workspace
   size_t mem_bytes = 0;
-  int total_wg = 0, total_ub = 0, total_rb = 0;
-  size_t pass_lds = 0, upd_lds = 0;
+  int total_ub = 0;
+  size_t upd_lds_mu = 0, upd_lds_nv = 0;
   int hist_cap = 0;
   std::vector<size_t> hist_off;
   // captured chunks: key = (kind, steps, flags)
   struct G {
+    std::string view;
     int kind, steps, obj_last, chol_last;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -93,33 +117,40 @@ struct Plan : Owned {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Lays out descriptors for the partition `wgs`; all pointers into p->mem.
+// Lays out descriptors (plan order) for the partition `wgs`; pass and
+// row-solve block ranges count from the first instance of the group, update
+// blocks from the first instance of the batch.  Fills groups' block totals.
 void layout(Plan &pl, const std::vector<int> &wgs, const hsn_nmf_problem *probs, double tol,
-            std::vector<BatchInst> &out, int &tot_wg, int &tot_ub, int &tot_rb, int num_cu) {
+            std::vector<BatchInst> &out, std::vector<Group> &groups, int &tot_ub, int num_cu) {
   out.assign(pl.n, BatchInst{});
-  tot_wg = tot_ub = tot_rb = 0;
-  for (int i = 0; i < pl.n; ++i) {
-    const Shape &s = pl.shapes[i];
-    BatchInst &b = out[i];
-    b.P = probs ? probs[i].p : nullptr;
-    b.ldp = s.ldp;
-    b.n_p = s.n_p;
-    b.n_k = int(s.n_k);
-    b.K = s.k;
-    b.nq = s.n_k > 1024 ? 2 : 1;
-    b.V = probs ? probs[i].V : nullptr;
-    b.D = probs ? probs[i].D : nullptr;
-    b.f_ref = (probs && probs[i].f_ref > 0.0) ? probs[i].f_ref : 0.0;
-    b.tol = tol;
-    b.wg0 = tot_wg;
-    b.n_wg = wgs[i];
-    tot_wg += wgs[i];
-    b.ub0 = tot_ub;
-    b.n_ub = update_d_blocks(int(s.n_k));
-    tot_ub += b.n_ub;
-    b.rb0 = tot_rb;
-    b.n_rb = int(std::min<int64_t>((s.n_p + 255) / 256, 8 * int64_t(num_cu)));
-    tot_rb += b.n_rb;
+  groups = pl.groups;
+  tot_ub = 0;
+  for (Group &g : groups) {
+    g.n_wg = g.n_rb = 0;
+    for (int i = g.i0; i < g.i1; ++i) {
+      const int q = pl.order[i];
+      const Shape &s = pl.shapes[i];
+      BatchInst &b = out[i];
+      b.P = probs ? probs[q].p : nullptr;
+      b.ldp = s.ldp;
+      b.n_p = s.n_p;
+      b.n_k = int(s.n_k);
+      b.K = s.k;
+      b.nq = s.n_k > 1024 ? 2 : 1;
+      b.V = probs ? probs[q].V : nullptr;
+      b.D = probs ? probs[q].D : nullptr;
+      b.f_ref = (probs && probs[q].f_ref > 0.0) ? probs[q].f_ref : 0.0;
+      b.tol = tol;
+      b.wg0 = g.n_wg;
+      b.n_wg = wgs[i];
+      g.n_wg += wgs[i];
+      b.ub0 = tot_ub;
+      b.n_ub = update_d_blocks(int(s.n_k));
+      tot_ub += b.n_ub;
+      b.rb0 = g.n_rb;
+      b.n_rb = int(std::min<int64_t>((s.n_p + 255) / 256, 8 * int64_t(num_cu)));
+      g.n_rb += b.n_rb;
+    }
   }
 }
 
@@ -155,15 +186,24 @@ std::vector<InstMem> mem_layout(const Plan &pl, size_t &total) {
   return m;
 }
 
-// Candidate partitions: the single-instance one, then budgets of T row tiles per workgroup.
-std::vector<int> partition(const Plan &pl, int tiles_per_wg, int num_cu) {
+// Candidate partitions.  budget <= 0: the single-instance partition
+// (min(tiles, 2 x CUs) workgroups each).  Otherwise `budget` workgroups in
+// all, shared in proportion to each instance's elements (at least 1, at most
+// its tile count and 2 x CUs): fewer workgroups per instance mean fewer N_D
+// partials for the D update to reduce.
+std::vector<int> partition(const Plan &pl, int budget, int num_cu) {
   std::vector<int> w(pl.n);
+  double tot = 0.0;
+  for (const Shape &s : pl.shapes) tot += double(s.n_p) * double(s.n_k);
   for (int i = 0; i < pl.n; ++i) {
     const int64_t tiles = (pl.shapes[i].n_p + kRowsPerTile - 1) / kRowsPerTile;
-    if (tiles_per_wg <= 0)
-      w[i] = int(std::min<int64_t>(tiles, 2 * int64_t(num_cu)));
-    else
-      w[i] = int(std::max<int64_t>(1, std::min<int64_t>((tiles + tiles_per_wg - 1) / tiles_per_wg, 2 * int64_t(num_cu))));
+    const int64_t cap = std::min<int64_t>(tiles, 2 * int64_t(num_cu));
+    if (budget <= 0) {
+      w[i] = int(cap);
+    } else {
+      const double share = double(budget) * double(pl.shapes[i].n_p) * double(pl.shapes[i].n_k) / tot;
+      w[i] = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(share + 0.5), cap)));
+    }
   }
   return w;
 }
@@ -187,39 +227,76 @@ void fill_pointers(Plan &pl, const std::vector<InstMem> &m, std::vector<BatchIns
   }
 }
 
-// Queues one chunk of `steps` steps of one kind.
+// One pass launch per (K, bin class) group.
+void pass_groups(const std::vector<Group> &gs, int mode, bool obj, hipStream_t st, const BatchInst *d, int s) {
+  for (const Group &g : gs) launch_batched_pass(g.K, g.nq, mode, obj, g.n_wg, st, d + g.i0, g.i1 - g.i0, s);
+}
+
+// One row-solve launch per group (its kernel is compiled for the group's K).
+void rows_groups(const std::vector<Group> &gs, hipStream_t st, const BatchInst *d, int s) {
+  for (const Group &g : gs) launch_batched_rows(g.K, g.n_rb, st, d + g.i0, g.i1 - g.i0, s);
+}
+
+// Queues one chunk of `steps` steps of one kind over the instances of v.
 //   kind 0: MU iterations (objective and G_D factors on the last if asked)
 //   kind 1: ANLS rounds
-void queue_chunk(const Plan &pl, const BatchInst *d, hipStream_t st, int kind, int steps, bool obj_last,
-                 bool chol_last) {
+void queue_chunk(const Plan &pl, const View &v, hipStream_t st, int kind, int steps, bool obj_last, bool chol_last) {
   for (int s = 0; s < steps; ++s) {
     const bool last = s + 1 == steps;
     if (kind == 0) {
-      launch_batched_pass(kModeMU, obj_last && last, pl.total_wg, pl.pass_lds, st, d, pl.n, s);
-      launch_batched_update(kModeMU, pl.total_ub, pl.upd_lds, st, d, pl.n, s, obj_last && last, chol_last && last);
+      pass_groups(v.groups, kModeMU, obj_last && last, st, v.d, s);
+      launch_batched_update(kModeMU, v.total_ub, pl.upd_lds_mu, st, v.d, v.n, s, obj_last && last,
+                            chol_last && last);
     } else {
-      launch_batched_pass(kModeNV, false, pl.total_wg, pl.pass_lds, st, d, pl.n, s);
-      launch_batched_rows(pl.total_rb, st, d, pl.n, s);
-      launch_batched_pass(kModeND, true, pl.total_wg, pl.pass_lds, st, d, pl.n, s);
-      launch_batched_update(kModeNV, pl.total_ub, pl.upd_lds, st, d, pl.n, s, true, true);
+      pass_groups(v.groups, kModeNV, false, st, v.d, s);
+      rows_groups(v.groups, st, v.d, s);
+      pass_groups(v.groups, kModeND, true, st, v.d, s);
+      launch_batched_update(kModeNV, v.total_ub, pl.upd_lds_nv, st, v.d, v.n, s, true, true);
     }
   }
-  launch_batched_advance(pl.n, steps, st, d);
+  launch_batched_advance(v.n, steps, st, v.d);
 }
 
-hsn_status run_chunk(hsn_ctx *ctx, Plan &pl, hipStream_t st, int kind, int steps, bool obj_last, bool chol_last,
-                     bool use_graph) {
+// The still-active instances (plan order) as a compacted view in dst.
+void compact(const Plan &pl, const std::vector<char> &act, BatchInst *dst, std::vector<BatchInst> &h, View &v) {
+  h.clear();
+  v.groups.clear();
+  v.key.assign(act.begin(), act.end());
+  v.total_ub = 0;
+  for (int j = 0; j < pl.n; ++j) {
+    if (!act[j]) continue;
+    BatchInst b = pl.h[j];
+    const int i = int(h.size());
+    if (v.groups.empty() || v.groups.back().K != b.K || v.groups.back().nq != b.nq)
+      v.groups.push_back({b.K, b.nq, i, i, 0, 0});
+    Group &g = v.groups.back();
+    g.i1 = i + 1;
+    b.wg0 = g.n_wg;
+    g.n_wg += b.n_wg;
+    b.rb0 = g.n_rb;
+    g.n_rb += b.n_rb;
+    b.ub0 = v.total_ub;
+    v.total_ub += b.n_ub;
+    h.push_back(b);
+  }
+  v.n = int(h.size());
+  v.d = dst;
+}
+
+hsn_status run_chunk(hsn_ctx *ctx, Plan &pl, const View &v, hipStream_t st, int kind, int steps, bool obj_last,
+                     bool chol_last, bool use_graph) {
   if (!use_graph) {
-    queue_chunk(pl, pl.d, st, kind, steps, obj_last, chol_last);
+    queue_chunk(pl, v, st, kind, steps, obj_last, chol_last);
     HSN_LAUNCHED(ctx);
     return HSN_OK;
   }
   for (auto &g : pl.graphs)
-    if (g.kind == kind && g.steps == steps && g.obj_last == obj_last && g.chol_last == chol_last) {
+    if (g.view == v.key && g.kind == kind && g.steps == steps && g.obj_last == obj_last && g.chol_last == chol_last) {
       HSN_HIP(ctx, hipGraphLaunch(g.exec, st));
       return HSN_OK;
     }
   Plan::G g;
+  g.view = v.key;
   g.kind = kind;
   g.steps = steps;
   g.obj_last = obj_last;
@@ -229,7 +306,7 @@ hsn_status run_chunk(hsn_ctx *ctx, Plan &pl, hipStream_t st, int kind, int steps
   if (!ctx->cap_stream) HSN_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   hipStream_t cs = ctx->cap_stream;
   HSN_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  queue_chunk(pl, pl.d, cs, kind, steps, obj_last, chol_last);
+  queue_chunk(pl, v, cs, kind, steps, obj_last, chol_last);
   const hipError_t le = hipGetLastError();
   const hipError_t ce = hipStreamEndCapture(cs, &g.graph);
   if (le != hipSuccess || ce != hipSuccess) {
@@ -298,13 +375,25 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
     np->n = n;
     np->need_nv = need_nv;
     np->hist_cap = hist_cap;
-    for (int i = 0; i < n; ++i) {
+    // plan order: by (K, bin class), stable
+    np->order.resize(n);
+    for (int i = 0; i < n; ++i) np->order[i] = i;
+    auto key = [&](int i) { return probs[i].k * 4 + (probs[i].n_k > 1024 ? 2 : 1); };
+    std::stable_sort(np->order.begin(), np->order.end(), [&](int a, int b) { return key(a) < key(b); });
+    for (int j = 0; j < n; ++j) {
+      const int i = np->order[j];
       np->shapes.push_back({probs[i].n_p, probs[i].n_k, probs[i].ldp, probs[i].k});
       np->max_k = std::max(np->max_k, probs[i].k);
+      if (np->groups.empty() || key(np->order[np->groups.back().i0]) != key(i))
+        np->groups.push_back({probs[i].k, probs[i].n_k > 1024 ? 2 : 1, j, j + 1, 0, 0});
+      else
+        np->groups.back().i1 = j + 1;
     }
-    const std::vector<int> cands[] = {partition(*np, 0, ctx->num_cu), partition(*np, 2, ctx->num_cu),
-                                      partition(*np, 4, ctx->num_cu), partition(*np, 8, ctx->num_cu),
-                                      partition(*np, 16, ctx->num_cu)};
+    const int nc = ctx->num_cu;
+    const int budgets[] = {0, 2 * nc, 4 * nc, 8 * nc, 16 * nc};
+    const std::vector<int> cands[] = {partition(*np, budgets[0], nc), partition(*np, budgets[1], nc),
+                                      partition(*np, budgets[2], nc), partition(*np, budgets[3], nc),
+                                      partition(*np, budgets[4], nc)};
     np->wg_cap.assign(n, 1);
     for (auto &c : cands)
       for (int i = 0; i < n; ++i) np->wg_cap[i] = std::max(np->wg_cap[i], c[i]);
@@ -321,9 +410,9 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
     np->ctrl = reinterpret_cast<NmfCtrl *>(np->mem + align256(sizeof(BatchInst) * n) * 2);
     NmfCtrl *tctrl = reinterpret_cast<NmfCtrl *>(np->mem + align256(sizeof(BatchInst) * n) * 2 +
                                                  align256(sizeof(NmfCtrl) * n));
-    np->pass_lds = batched_pass_lds(np->max_k);
-    np->upd_lds = std::max(batched_update_lds(np->max_k, kModeNV), batched_update_lds(np->max_k, kModeMU));
-    if (batched_kernel_setup(np->pass_lds, np->upd_lds) != hipSuccess) {
+    np->upd_lds_mu = batched_update_lds(np->max_k, kModeMU);
+    np->upd_lds_nv = batched_update_lds(np->max_k, kModeNV);
+    if (batched_kernel_setup(0, std::max(np->upd_lds_mu, np->upd_lds_nv)) != hipSuccess) {
       (void)hipGetLastError();
       delete np;
       return fail(ctx, HSN_ERR_DEVICE, "batched nmf: kernel attribute setup failed");
@@ -339,26 +428,22 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
       HSN_HIP(ctx, hipEventCreate(&e1));
       for (int c = 0; c < 5; ++c) {
         std::vector<BatchInst> v;
-        int tw, tu, tr;
-        layout(*np, cands[c], probs, 0.0, v, tw, tu, tr, ctx->num_cu);
+        std::vector<Group> tg;
+        int tu;
+        layout(*np, cands[c], probs, 0.0, v, tg, tu, ctx->num_cu);
         fill_pointers(*np, m, v, tctrl, true);
         HSN_HIP(ctx, hipMemcpyAsync(np->d_tune, v.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice, st));
-        for (int i = 0; i < n; ++i)
-          HSN_HIP(ctx, hipMemcpyAsync(v[i].D, probs[i].D, sizeof(float) * probs[i].n_k * probs[i].k,
+        for (int j = 0; j < n; ++j) {
+          const int i = np->order[j];
+          HSN_HIP(ctx, hipMemcpyAsync(v[j].D, probs[i].D, sizeof(float) * probs[i].n_k * probs[i].k,
                                       hipMemcpyDeviceToDevice, st));
+        }
         launch_batched_init(n, 0, st, np->d_tune);
-        Plan tmp;
-        tmp.n = n;
-        tmp.total_wg = tw;
-        tmp.total_ub = tu;
-        tmp.total_rb = tr;
-        tmp.pass_lds = np->pass_lds;
-        tmp.upd_lds = np->upd_lds;
         float ms_c = 0.f;
         for (int rep = 0; rep < 3; ++rep) {
           HSN_HIP(ctx, hipEventRecord(e0, st));
-          launch_batched_pass(kModeND, true, tw, tmp.pass_lds, st, np->d_tune, n, 0);
-          launch_batched_update(kModeMU, tu, tmp.upd_lds, st, np->d_tune, n, 0, false, false);
+          pass_groups(tg, kModeND, true, st, np->d_tune, 0);
+          launch_batched_update(kModeMU, tu, np->upd_lds_mu, st, np->d_tune, n, 0, false, false);
           HSN_HIP(ctx, hipEventRecord(e1, st));
           HSN_HIP(ctx, hipEventSynchronize(e1));
           float ms = 0.f;
@@ -370,27 +455,39 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
           best = ms_c;
           best_c = c;
         }
-        np->tune_note += (c ? " " : "") + std::to_string(ms_c / 2);
+        char buf[96];
+        std::snprintf(buf, sizeof(buf), "%sbudget %d: %.3f ms", c ? "; " : "", budgets[c], ms_c / 2);
+        np->tune_note += buf;
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       np->wg = cands[best_c];
-      np->tune_note += " -> candidate " + std::to_string(best_c);
+      np->tune_note += " -> budget " + std::to_string(budgets[best_c]);
     }
-    layout(*np, np->wg, nullptr, tol, np->h, np->total_wg, np->total_ub, np->total_rb, ctx->num_cu);
+    layout(*np, np->wg, nullptr, tol, np->h, np->groups, np->total_ub, ctx->num_cu);
     fill_pointers(*np, m, np->h, np->ctrl, false);
     for (int i = 0; i < n; ++i) np->hist_off.push_back(m[i].hist);
+    {
+      int tot = 0;
+      for (int w : np->wg) tot += w;
+      char buf[160];
+      std::snprintf(buf, sizeof(buf), "%d instances in %zu (K, bin class) groups; %d pass workgroups, %d update blocks%s",
+                    n, np->groups.size(), tot, np->total_ub, tune ? "; tuning: " : "");
+      np->tune_note = buf + np->tune_note;
+    }
     ctx->plans.push_back(np);
     pl = np;
   }
+  ctx->last_plan_note = pl->tune_note;
 
   // Per call: operands, stop references and tolerance into the descriptors.
-  for (int i = 0; i < n; ++i) {
-    pl->h[i].P = probs[i].p;
-    pl->h[i].V = probs[i].V;
-    pl->h[i].D = probs[i].D;
-    pl->h[i].f_ref = probs[i].f_ref > 0.0 ? probs[i].f_ref : 0.0;
-    pl->h[i].tol = tol;
+  for (int j = 0; j < n; ++j) {
+    const int i = pl->order[j];
+    pl->h[j].P = probs[i].p;
+    pl->h[j].V = probs[i].V;
+    pl->h[j].D = probs[i].D;
+    pl->h[j].f_ref = probs[i].f_ref > 0.0 ? probs[i].f_ref : 0.0;
+    pl->h[j].tol = tol;
   }
   const int n_steps = o->max_iter + o->polish_rounds;
   const bool first_exact = o->max_iter == 0 && o->polish_rounds > 0;
@@ -416,25 +513,47 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
   int done = 0;
   bool stopped = false;
   const bool polish_follows = o->polish_rounds > 0;
+  View full;
+  full.key = "all";
+  full.groups = pl->groups;
+  full.n = n;
+  full.total_ub = pl->total_ub;
+  full.d = pl->d;
+  View cur = full;
+  std::vector<BatchInst> h_act;
+  std::vector<char> act(n, 1);
+  // After a chunk: stop when every instance has stopped, else drop the
+  // stopped ones from the launches.
+  auto after_chunk = [&]() -> hsn_status {
+    if (!any_ref || done >= n_steps) return HSN_OK;
+    const int a = all_stopped(done);
+    if (a < 0) return fail(ctx, HSN_ERR_DEVICE, "batched nmf: control read failed");
+    stopped = a == 1;
+    if (stopped) return HSN_OK;
+    bool changed = false;
+    for (int j = 0; j < n; ++j) {
+      const char now = hc[j].stop_at > done ? 1 : 0;
+      changed |= now != act[j];
+      act[j] = now;
+    }
+    if (changed) {
+      compact(*pl, act, pl->d_tune, h_act, cur);
+      HSN_HIP(ctx, hipMemcpyAsync(pl->d_tune, h_act.data(), sizeof(BatchInst) * h_act.size(), hipMemcpyHostToDevice,
+                                  st));
+    }
+    return HSN_OK;
+  };
   while (done < o->max_iter && !stopped) {
     const int c = std::min(o->check_every, o->max_iter - done);
     const bool last_bulk = done + c == o->max_iter;
-    if ((rc = run_chunk(ctx, *pl, st, 0, c, true, polish_follows && last_bulk, use_graph)) != HSN_OK) return rc;
+    if ((rc = run_chunk(ctx, *pl, cur, st, 0, c, true, polish_follows && last_bulk, use_graph)) != HSN_OK) return rc;
     done += c;
-    if (any_ref && done < n_steps) {
-      const int a = all_stopped(done);
-      if (a < 0) return fail(ctx, HSN_ERR_DEVICE, "batched nmf: control read failed");
-      stopped = a == 1;
-    }
+    if ((rc = after_chunk()) != HSN_OK) return rc;
   }
   while (done < n_steps && !stopped) {
-    if ((rc = run_chunk(ctx, *pl, st, 1, kPolishChunk, true, true, use_graph)) != HSN_OK) return rc;
+    if ((rc = run_chunk(ctx, *pl, cur, st, 1, kPolishChunk, true, true, use_graph)) != HSN_OK) return rc;
     done += kPolishChunk;
-    if (any_ref && done < n_steps) {
-      const int a = all_stopped(done);
-      if (a < 0) return fail(ctx, HSN_ERR_DEVICE, "batched nmf: control read failed");
-      stopped = a == 1;
-    }
+    if ((rc = after_chunk()) != HSN_OK) return rc;
   }
   if (stats) {
     HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
@@ -443,18 +562,19 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
     float ms = 0.f;
     HSN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     std::vector<double> h;
-    for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      const int i = pl->order[j];
       hsn_nmf_stats &s = stats[i];
-      const int fin = std::min(hc[i].stop_at, n_steps);
+      const int fin = std::min(hc[j].stop_at, n_steps);
       s.ms = ms;
       s.iters = std::min(fin, o->max_iter);
       s.polish_done = std::max(0, fin - o->max_iter);
       s.history_len = 0;
       s.objective = NAN;
-      const int len = std::min(hc[i].hist_len, pl->hist_cap);
+      const int len = std::min(hc[j].hist_len, pl->hist_cap);
       if (len > 0) {
         h.resize(len);
-        HSN_HIP(ctx, hipMemcpy(h.data(), pl->mem + pl->hist_off[i], sizeof(double) * len, hipMemcpyDeviceToHost));
+        HSN_HIP(ctx, hipMemcpy(h.data(), pl->mem + pl->hist_off[j], sizeof(double) * len, hipMemcpyDeviceToHost));
         s.objective = h.back();
         const int nc = std::min(len, s.history_cap);
         for (int j = 0; j < nc; ++j) s.history[j] = h[j];
@@ -464,4 +584,8 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
     }
   }
   return HSN_OK;
+}
+
+extern "C" const char *hsn_batched_plan_info(const hsn_ctx *ctx) {
+  return ctx ? ctx->last_plan_note.c_str() : "";
 }

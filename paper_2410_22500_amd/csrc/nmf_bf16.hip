@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
                                                               float *__restrict__ part_nd,
                                                               double *__restrict__ part_gv,
                                                               double *__restrict__ part_obj,
-                                                              const NmfCtrl *__restrict__ ctrl, int iter) {
+                                                              NmfCtrl *__restrict__ ctrl, int iter) {
   if (iter >= ctrl->stop_at) return;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const Bf16Lds L = bf16_lds_layout(ldb, K);
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
 template <int K, int MODE, bool OBJ, int NW, int NBUF>
 static bool launch_bf16_inst(int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p, int n_k,
                              float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
-                             float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
+                             float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
   const int lds = bf16_lds_layout(ldb, K).total;
   static bool attr_set = false;
   if (!attr_set) {
@@ -335,7 +335,7 @@ static bool launch_bf16_inst(int n_wg, hipStream_t st, const uint16_t *Pb, int64
 template <int K, int NW, int NBUF>
 static bool launch_bf16_kw(int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p,
                            int n_k, float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
-                           float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
+                           float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
 #define HSN_INST(M_, O_) \
   launch_bf16_inst<K, M_, O_, NW, NBUF>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd, part_gv, part_obj, \
                                         ctrl, iter)
@@ -348,7 +348,7 @@ static bool launch_bf16_kw(int mode, bool obj, int n_wg, hipStream_t st, const u
 template <int K>
 static bool launch_bf16_k(int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p,
                           int n_k, float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
-                          float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
+                          float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
   const int64_t nw = bf16_ldb_pad(ldb) / 256;
 #define HSN_NW(NW_, NB_)                                                                                           \
   if (nw == NW_)                                                                                                   \
@@ -369,7 +369,7 @@ size_t bf16_image_elems(int64_t ldb) {
 
 bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
                       int64_t n_p, int n_k, float *V, const double *GD, const double *chol, const uint16_t *img,
-                      float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
+                      float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
   if (ldb > kMaxLdb || ldb % 32 != 0 || K < 1 || K > 8 ||
       (mode != kModeMU && mode != kModeHALS))
     return false;

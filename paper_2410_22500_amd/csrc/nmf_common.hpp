@@ -39,9 +39,11 @@ __device__ __forceinline__ void hals_row(const double *__restrict__ G, const dou
 // the tolerance (to i + 1), so no kernel of a running iteration is skipped.
 struct NmfCtrl {
   int stop_at;
-  int upd_ticket;  // arrival counter of the D-update blocks (last block finishes G_D)
-  int hist_len;    // objective values written so far
-  int iter_base;   // batched runs: index of the first step of the replayed chunk
+  int upd_ticket;   // arrival counter of the D-update blocks (last block finishes G_D)
+  int hist_len;     // objective values written so far
+  int iter_base;    // batched runs: index of the first step of the replayed chunk
+  int pad[4];
+  double gvo[65];   // G_V = V^T V (K*K) and the objective of the last pass, reduced
 };
 
 // Workspace of one decomposition (all device pointers).

@@ -33,7 +33,7 @@ __device__ __forceinline__ void pass_f32_body(
     const float *__restrict__ P, int64_t ldp, int64_t n_p, int n_k, float *__restrict__ V, float *__restrict__ NV,
     const float *__restrict__ D, const double *__restrict__ GD, const double *__restrict__ chol,
     float *__restrict__ part_nd, double *__restrict__ part_gv, double *__restrict__ part_obj,
-    const NmfCtrl *__restrict__ ctrl, int iter, int wg, int n_wg, char *__restrict__ lds) {
+    NmfCtrl *__restrict__ ctrl, int iter, int wg, int n_wg, char *__restrict__ lds) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
     const float *__restrict__ P, int64_t ldp, int64_t n_p, int n_k, float *__restrict__ V, float *__restrict__ NV,
     const float *__restrict__ D, const double *__restrict__ GD, const double *__restrict__ chol,
     float *__restrict__ part_nd, double *__restrict__ part_gv, double *__restrict__ part_obj,
-    const NmfCtrl *__restrict__ ctrl, int iter) {
+    NmfCtrl *__restrict__ ctrl, int iter) {
   __shared__ __attribute__((aligned(16))) char lds[PassLds<K>::bytes];
   pass_f32_body<K, NQ, MODE, OBJ>(P, ldp, n_p, n_k, V, NV, D, GD, chol, part_nd, part_gv, part_obj, ctrl, iter,
                                   int(blockIdx.x), int(gridDim.x), lds);
@@ -245,53 +245,46 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
 // instance's iter_base (advanced on the device between graph replays) plus
 // the step's position inside the replayed chunk.
 // ---------------------------------------------------------------------------
-template <int MODE, bool OBJ>
+template <int K, int NQ, int MODE, bool OBJ>
 __global__ __launch_bounds__(kPassThreads) void batched_pass_kernel(const BatchInst *__restrict__ d, int n_inst,
                                                                     int iter_local) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
+  __shared__ __attribute__((aligned(16))) char lds[PassLds<K>::bytes];
   const int i = batch_find(n_inst, int(blockIdx.x), [&](int j) { return d[j].wg0; });
   const BatchInst &b = d[i];
   const int wg = int(blockIdx.x) - b.wg0;
   if (wg >= b.n_wg) return;
   const int iter = b.ctrl->iter_base + iter_local;
-  switch (b.K * 4 + b.nq) {
-#define HSN_B(KK, NQ_)                                                                                          \
-  case KK * 4 + NQ_:                                                                                           \
-    pass_f32_body<KK, NQ_, MODE, OBJ>(b.P, b.ldp, b.n_p, b.n_k, b.V, b.NV, b.D, b.gd, b.chol, b.part_nd,        \
-                                      b.part_gv, b.part_obj, b.ctrl, iter, wg, b.n_wg, lds);                   \
-    break;
+  pass_f32_body<K, NQ, MODE, OBJ>(b.P, b.ldp, b.n_p, b.n_k, b.V, b.NV, b.D, b.gd, b.chol, b.part_nd, b.part_gv,
+                                  b.part_obj, b.ctrl, iter, wg, b.n_wg, lds);
+}
+
+// One launch over the instances d[0 .. n_inst) of one (K, bin class) group
+// (wg0 counted from the group's first instance).  mode: kModeMU (objective
+// or not), kModeNV, kModeND (objective always).
+template <int K, int NQ>
+void launch_batched_pass_kq(int mode, bool obj, int n_blocks, hipStream_t st, const BatchInst *d, int n_inst,
+                            int iter_local) {
+  if (mode == kModeMU) {
+    if (obj)
+      batched_pass_kernel<K, NQ, kModeMU, true><<<n_blocks, kPassThreads, 0, st>>>(d, n_inst, iter_local);
+    else
+      batched_pass_kernel<K, NQ, kModeMU, false><<<n_blocks, kPassThreads, 0, st>>>(d, n_inst, iter_local);
+  } else if (mode == kModeNV) {
+    batched_pass_kernel<K, NQ, kModeNV, false><<<n_blocks, kPassThreads, 0, st>>>(d, n_inst, iter_local);
+  } else {
+    batched_pass_kernel<K, NQ, kModeND, true><<<n_blocks, kPassThreads, 0, st>>>(d, n_inst, iter_local);
+  }
+}
+
+void launch_batched_pass(int K, int nq, int mode, bool obj, int n_blocks, hipStream_t st, const BatchInst *d,
+                         int n_inst, int iter_local) {
+  switch (K * 4 + nq) {
+#define HSN_B(KK, NQ_) \
+  case KK * 4 + NQ_: launch_batched_pass_kq<KK, NQ_>(mode, obj, n_blocks, st, d, n_inst, iter_local); break;
     HSN_B(1, 1) HSN_B(2, 1) HSN_B(3, 1) HSN_B(4, 1) HSN_B(5, 1) HSN_B(6, 1) HSN_B(7, 1) HSN_B(8, 1)
     HSN_B(1, 2) HSN_B(2, 2) HSN_B(3, 2) HSN_B(4, 2) HSN_B(5, 2) HSN_B(6, 2) HSN_B(7, 2) HSN_B(8, 2)
 #undef HSN_B
     default: break;
-  }
-}
-
-size_t batched_pass_lds(int max_k) {
-  switch (max_k) {
-    case 1: return PassLds<1>::bytes;
-    case 2: return PassLds<2>::bytes;
-    case 3: return PassLds<3>::bytes;
-    case 4: return PassLds<4>::bytes;
-    case 5: return PassLds<5>::bytes;
-    case 6: return PassLds<6>::bytes;
-    case 7: return PassLds<7>::bytes;
-    default: return PassLds<8>::bytes;
-  }
-}
-
-// mode: kModeMU (obj or not), kModeNV, kModeND (objective always).
-void launch_batched_pass(int mode, bool obj, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
-                         int iter_local) {
-  if (mode == kModeMU) {
-    if (obj)
-      batched_pass_kernel<kModeMU, true><<<n_blocks, kPassThreads, lds, st>>>(d, n_inst, iter_local);
-    else
-      batched_pass_kernel<kModeMU, false><<<n_blocks, kPassThreads, lds, st>>>(d, n_inst, iter_local);
-  } else if (mode == kModeNV) {
-    batched_pass_kernel<kModeNV, false><<<n_blocks, kPassThreads, lds, st>>>(d, n_inst, iter_local);
-  } else {
-    batched_pass_kernel<kModeND, true><<<n_blocks, kPassThreads, lds, st>>>(d, n_inst, iter_local);
   }
 }
 
@@ -301,7 +294,7 @@ void launch_batched_pass(int mode, bool obj, int n_blocks, size_t lds, hipStream
 template <int K>
 void launch_pass_f32_k(int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp, int64_t n_p,
                        int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                       float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
+                       float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
 #define HSN_PASS(NQ_, M_, O_)                                                                                   \
   pass_f32_kernel<K, NQ_, M_, O_><<<n_wg, kPassThreads, 0, st>>>(P, ldp, n_p, n_k, V, NV, D, GD, chol, part_nd,    \
                                                                  part_gv, part_obj, ctrl, iter)
@@ -331,7 +324,7 @@ void launch_pass_f32_k(int mode, bool obj, int nq, int n_wg, hipStream_t st, con
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
                      int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                     float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter) {
+                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
   switch (K) {
 #define HSN_K(KK)                                                                                                  \
   case KK:                                                                                                         \

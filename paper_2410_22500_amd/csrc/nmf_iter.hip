@@ -120,41 +120,71 @@ __global__ __launch_bounds__(kUpdThreads) void nmf_init_kernel(const float *__re
 }
 
 // RULE: kModeMU (Lee-Seung), kModeHALS (column sweep), kModeNV (exact NNLS rows)
+// G_V = sum of the workgroups' partials of V_new^T V_new, and the objective,
+// reduced once per pass (the D update reads them from ctrl->gvo): thread
+// group g sums every G-th partial (8 loads in flight), then the groups are
+// summed in order.  red: LDS of kUpdThreads doubles.
+template <int K>
+__device__ __forceinline__ void reduce_gv_body(const double *__restrict__ part_gv, const double *__restrict__ part_obj,
+                                               int n_wg, int has_obj, NmfCtrl *__restrict__ ctrl, int iter,
+                                               double *__restrict__ red) {
+  if (iter >= ctrl->stop_at) return;
+  constexpr int E = K * K + 1;
+  constexpr int G = kUpdThreads / E;
+  const int t = threadIdx.x;
+  if (t < G * E) {
+    const int e = t % E, g = t / E;
+    double acc = 0.0;
+    if (e < K * K)
+      acc = strided_sum(g, G, n_wg, [&](int w) { return part_gv[size_t(w) * K * K + e]; });
+    else if (has_obj)
+      acc = strided_sum(g, G, n_wg, [&](int w) { return part_obj[w]; });
+    red[g * E + e] = acc;
+  }
+  __syncthreads();
+  if (t < E) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += red[g * E + t];
+    ctrl->gvo[t] = s;
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kUpdThreads) void reduce_gv_kernel(const double *__restrict__ part_gv,
+                                                                const double *__restrict__ part_obj, int n_wg,
+                                                                int has_obj, NmfCtrl *__restrict__ ctrl, int iter) {
+  __shared__ double red[kUpdThreads];
+  reduce_gv_body<K>(part_gv, part_obj, n_wg, has_obj, ctrl, iter, red);
+}
+
 // LDS of one update block (all float64 unless noted).
 template <int K, int RULE>
 struct UpdLds {
-  static constexpr int E1 = K * K + 1;         // G_V entries + the objective
-  static constexpr int G1 = kUpdThreads / E1;  // groups summing them
   static constexpr int EB = kUpdRows * K;      // N_D entries of a block
   static constexpr int G2 = kUpdThreads / EB;
-  static constexpr int G3 = kUpdThreads / (K * K);
   static constexpr int NCH = (1 << K) * kCholStride / ((RULE == kModeNV) ? 1 : (1 << K));
-  static constexpr int red1 = 0;
-  static constexpr int red2 = red1 + G1 * E1 * 8;
+  static constexpr int red2 = 0;
   static constexpr int gv = red2 + G2 * EB * 8;
   static constexpr int gd = gv + K * K * 8;
   static constexpr int nd = gd + K * K * 8;
   static constexpr int obj = nd + EB * 8;
   static constexpr int chol = obj + 8;
-  static constexpr int red3 = chol + NCH * 8;
-  static constexpr int dn = red3 + G3 * K * K * 8;   // float [kUpdRows][K]
-  static constexpr int last = dn + kUpdRows * K * 4;  // int
-  static constexpr int bytes = (last + 4 + 15) / 16 * 16;
+  static constexpr int dn = chol + NCH * 8;           // float [kUpdRows][K]
+  static constexpr int bytes = (dn + kUpdRows * K * 4 + 15) / 16 * 16;
 };
 
 // One block `blk` of `n_blk` of the D update.
 template <int K, int RULE>
 __device__ __forceinline__ void update_d_body(
-    float *__restrict__ D, const float *__restrict__ part_nd, const double *__restrict__ part_gv,
-    const double *__restrict__ part_obj, int n_wg, int n_k, NmfCtrl *__restrict__ ctrl, int iter, int has_obj,
+    float *__restrict__ D, const float *__restrict__ part_nd, int n_wg, int n_k, NmfCtrl *__restrict__ ctrl, int iter,
+    int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
     int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int blk, int n_blk,
     char *__restrict__ lds) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   using L = UpdLds<K, RULE>;
-  constexpr int E1 = L::E1, G1 = L::G1, EB = L::EB, G2 = L::G2;
-  double(*red1)[E1] = reinterpret_cast<double(*)[E1]>(lds + L::red1);
+  constexpr int EB = L::EB, G2 = L::G2;
   double(*red2)[EB] = reinterpret_cast<double(*)[EB]>(lds + L::red2);
   double *gv_s = reinterpret_cast<double *>(lds + L::gv);
   double *gd_s = reinterpret_cast<double *>(lds + L::gd);
@@ -162,19 +192,11 @@ __device__ __forceinline__ void update_d_body(
   float(*dn_s)[K] = reinterpret_cast<float(*)[K]>(lds + L::dn);
   double &obj_s = *reinterpret_cast<double *>(lds + L::obj);
   double *chol_s = reinterpret_cast<double *>(lds + L::chol);
-  int &last_s = *reinterpret_cast<int *>(lds + L::last);
 
   const int k0 = blk * kUpdRows;
-  // G_V and objective: each thread sums every G1-th workgroup partial (8 loads in flight).
-  if (t < G1 * E1) {
-    const int e = t % E1, g = t / E1;
-    double acc = 0.0;
-    if (e < K * K)
-      acc = strided_sum(g, G1, n_wg, [&](int w) { return part_gv[size_t(w) * K * K + e]; });
-    else if (has_obj)
-      acc = strided_sum(g, G1, n_wg, [&](int w) { return part_obj[w]; });
-    red1[g][e] = acc;
-  }
+  // G_V and the objective were reduced by the pass's last workgroup.
+  if (t < K * K) gv_s[t] = ctrl->gvo[t];
+  else if (t == K * K) obj_s = has_obj ? ctrl->gvo[K * K] : 0.0;
   // N_D of this block's rows.
   if (t < G2 * EB) {
     const int e = t % EB, g = t / EB;
@@ -188,12 +210,6 @@ __device__ __forceinline__ void update_d_body(
     red2[g][e] = acc;
   }
   __syncthreads();
-  if (t < E1) {
-    double s = 0.0;
-    for (int g = 0; g < G1; ++g) s += red1[g][t];
-    if (t < K * K) gv_s[t] = s;
-    else obj_s = s;
-  }
   if (t >= 64 && t < 64 + EB) {
     const int e = t - 64;
     double s = 0.0;
@@ -251,48 +267,62 @@ __device__ __forceinline__ void update_d_body(
     for (int j = 0; j < K; ++j) dn_s[t][j] = dn[j];
   }
   __syncthreads();
-  // This block's share of G_D for the next pass; the last block to arrive sums them.
+  // This block's share of G_D for the next pass (summed by the finish kernel).
   if (t < K * K) {
     const int i = t / K, j = t % K;
     double s = 0.0;
     for (int r = 0; r < kUpdRows; ++r) s += double(dn_s[r][i]) * double(dn_s[r][j]);
     part_gd[size_t(blk) * K * K + t] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) last_s = (atomicAdd(&ctrl->upd_ticket, 1) == n_blk - 1);
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  {
-    constexpr int G3 = L::G3;
-    double(*red3)[K * K] = reinterpret_cast<double(*)[K * K]>(lds + L::red3);
-    if (t < G3 * K * K) {
-      const int e = t % (K * K), g = t / (K * K);
-      red3[g][e] = strided_sum(g, G3, n_blk, [&](int b) { return part_gd[size_t(b) * K * K + e]; });
-    }
-    __syncthreads();
-    if (t < K * K) {
-      double s = 0.0;
-      for (int g = 0; g < G3; ++g) s += red3[g][t];
-      gd_s[t] = s;
-      GD[t] = s;
-    }
-    if (t == 0) ctrl->upd_ticket = 0;
-    __syncthreads();
-    if (next_chol) factor_all<K>(gd_s, chol);
+}
+
+// After the D update: G_D = sum of the update blocks' partials (thread group
+// g sums every G-th block, then the groups in order) and, when the next step
+// solves rows exactly, the factors of its principal submatrices.  A kernel of
+// its own: the update's blocks would otherwise need device-scope fences to
+// hand their partials to a last block, which on this GPU flushes the L2.
+template <int K>
+__device__ __forceinline__ void finish_gd_body(const double *__restrict__ part_gd, int n_blk, double *__restrict__ GD,
+                                               double *__restrict__ chol, int next_chol,
+                                               const NmfCtrl *__restrict__ ctrl, int iter, double *__restrict__ red,
+                                               double *__restrict__ gd_s) {
+  if (iter >= ctrl->stop_at) return;
+  constexpr int G = kUpdThreads / (K * K);
+  const int t = threadIdx.x;
+  if (t < G * K * K) {
+    const int e = t % (K * K), g = t / (K * K);
+    red[g * K * K + e] = strided_sum(g, G, n_blk, [&](int b) { return part_gd[size_t(b) * K * K + e]; });
   }
+  __syncthreads();
+  if (t < K * K) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += red[g * K * K + t];
+    gd_s[t] = s;
+    GD[t] = s;
+  }
+  __syncthreads();
+  if (next_chol) factor_all<K>(gd_s, chol);
+}
+
+template <int K>
+__global__ __launch_bounds__(kUpdThreads) void finish_gd_kernel(const double *__restrict__ part_gd, int n_blk,
+                                                                double *__restrict__ GD, double *__restrict__ chol,
+                                                                int next_chol, const NmfCtrl *__restrict__ ctrl,
+                                                                int iter) {
+  __shared__ double red[kUpdThreads];
+  __shared__ double gd_s[K * K];
+  finish_gd_body<K>(part_gd, n_blk, GD, chol, next_chol, ctrl, iter, red, gd_s);
 }
 
 template <int K, int RULE>
 __global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
-    float *__restrict__ D, const float *__restrict__ part_nd, const double *__restrict__ part_gv,
-    const double *__restrict__ part_obj, int n_wg, int n_k, NmfCtrl *__restrict__ ctrl, int iter, int has_obj,
+    float *__restrict__ D, const float *__restrict__ part_nd, int n_wg, int n_k, NmfCtrl *__restrict__ ctrl, int iter,
+    int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
     int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb) {
   __shared__ __attribute__((aligned(16))) char lds[UpdLds<K, RULE>::bytes];
-  update_d_body<K, RULE>(D, part_nd, part_gv, part_obj, n_wg, n_k, ctrl, iter, has_obj, f_ref, tol, hist, GD, chol,
-                         next_chol, part_gd, img, ldb, int(blockIdx.x), int(gridDim.x), lds);
+  update_d_body<K, RULE>(D, part_nd, n_wg, n_k, ctrl, iter, has_obj, f_ref, tol, hist, GD, chol, next_chol, part_gd,
+                         img, ldb, int(blockIdx.x), int(gridDim.x), lds);
 }
 
 template <int K>
@@ -336,6 +366,37 @@ __global__ __launch_bounds__(kUpdThreads) void batched_init_kernel(const BatchIn
   }
 }
 
+// One block per instance.
+__global__ __launch_bounds__(kUpdThreads) void batched_reduce_gv_kernel(const BatchInst *__restrict__ d, int iter_local,
+                                                                        int has_obj) {
+  __shared__ double red[kUpdThreads];
+  const BatchInst &b = d[blockIdx.x];
+  const int iter = b.ctrl->iter_base + iter_local;
+  switch (b.K) {
+#define HSN_K(KK) \
+  case KK: reduce_gv_body<KK>(b.part_gv, b.part_obj, b.n_wg, has_obj, b.ctrl, iter, red); break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+    default: break;
+  }
+}
+
+// One block per instance.
+__global__ __launch_bounds__(kUpdThreads) void batched_finish_gd_kernel(const BatchInst *__restrict__ d, int iter_local,
+                                                                        int next_chol) {
+  __shared__ double red[kUpdThreads];
+  __shared__ double gd_s[64];
+  const BatchInst &b = d[blockIdx.x];
+  const int iter = b.ctrl->iter_base + iter_local;
+  switch (b.K) {
+#define HSN_K(KK) \
+  case KK: finish_gd_body<KK>(b.part_gd, b.n_ub, b.gd, b.chol, next_chol, b.ctrl, iter, red, gd_s); break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+    default: break;
+  }
+}
+
 template <int RULE>
 __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(const BatchInst *__restrict__ d, int n_inst,
                                                                      int iter_local, int has_obj, int next_chol) {
@@ -348,8 +409,8 @@ __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(const Batch
   switch (b.K) {
 #define HSN_K(KK)                                                                                                 \
   case KK:                                                                                                        \
-    update_d_body<KK, RULE>(b.D, b.part_nd, b.part_gv, b.part_obj, b.n_wg, b.n_k, b.ctrl, iter, has_obj, b.f_ref, \
-                            b.tol, b.hist, b.gd, b.chol, next_chol, b.part_gd, nullptr, 0, blk, b.n_ub, lds);      \
+    update_d_body<KK, RULE>(b.D, b.part_nd, b.n_wg, b.n_k, b.ctrl, iter, has_obj, b.f_ref, b.tol, b.hist, b.gd, \
+                            b.chol, next_chol, b.part_gd, nullptr, 0, blk, b.n_ub, lds);                        \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
@@ -357,19 +418,14 @@ __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(const Batch
   }
 }
 
+template <int K>
 __global__ __launch_bounds__(256) void batched_rows_kernel(const BatchInst *__restrict__ d, int n_inst, int iter_local) {
   const int i = batch_find(n_inst, int(blockIdx.x), [&](int j) { return d[j].rb0; });
   const BatchInst &b = d[i];
   const int blk = int(blockIdx.x) - b.rb0;
   if (blk >= b.n_rb) return;
   const int iter = b.ctrl->iter_base + iter_local;
-  switch (b.K) {
-#define HSN_K(KK) \
-  case KK: nnls_rows_body<KK>(b.NV, b.gd, b.chol, b.V, b.n_p, b.ctrl, iter, blk, b.n_rb); break;
-    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
-#undef HSN_K
-    default: break;
-  }
+  nnls_rows_body<K>(b.NV, b.gd, b.chol, b.V, b.n_p, b.ctrl, iter, blk, b.n_rb);
 }
 
 __global__ void batched_advance_kernel(const BatchInst *__restrict__ d, int n_inst, int steps) {
@@ -396,20 +452,34 @@ void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w
   const int nb = update_d_blocks(n_k);
   uint16_t *img = ldb_img > 0 ? w.img : nullptr;
   switch (K) {
+#define HSN_K(KK) \
+  case KK: reduce_gv_kernel<KK><<<1, kUpdThreads, 0, st>>>(w.part_gv, w.part_obj, n_wg, has_obj, w.ctrl, iter); break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+  }
+  switch (K) {
 #define HSN_K(KK)                                                                                                 \
   case KK:                                                                                                        \
     if (rule == kModeMU)                                                                                          \
-      update_d_kernel<KK, kModeMU><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, w.part_gv, w.part_obj, n_wg, n_k,    \
+      update_d_kernel<KK, kModeMU><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
                                                                w.chol, next_chol, w.part_gd, img, ldb_img);       \
     else if (rule == kModeHALS)                                                                                   \
-      update_d_kernel<KK, kModeHALS><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, w.part_gv, w.part_obj, n_wg, n_k,  \
+      update_d_kernel<KK, kModeHALS><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                          \
                                                                  w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd, \
                                                                  w.chol, next_chol, w.part_gd, img, ldb_img);     \
     else                                                                                                          \
-      update_d_kernel<KK, kModeNV><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, w.part_gv, w.part_obj, n_wg, n_k,    \
+      update_d_kernel<KK, kModeNV><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
                                                                w.chol, next_chol, w.part_gd, img, ldb_img);       \
+    break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+  }
+  switch (K) {
+#define HSN_K(KK)                                                                                                  \
+  case KK:                                                                                                         \
+    finish_gd_kernel<KK><<<1, kUpdThreads, 0, st>>>(w.part_gd, nb, w.gd, w.chol, next_chol, w.ctrl, iter);          \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
@@ -451,14 +521,22 @@ void launch_batched_init(int n_inst, int want_chol, hipStream_t st, const BatchI
 
 void launch_batched_update(int rule, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
                            int iter_local, bool has_obj, bool next_chol) {
+  batched_reduce_gv_kernel<<<n_inst, kUpdThreads, 0, st>>>(d, iter_local, has_obj);
   if (rule == kModeNV)
     batched_update_kernel<kModeNV><<<n_blocks, kUpdThreads, lds, st>>>(d, n_inst, iter_local, has_obj, next_chol);
   else
     batched_update_kernel<kModeMU><<<n_blocks, kUpdThreads, lds, st>>>(d, n_inst, iter_local, has_obj, next_chol);
+  batched_finish_gd_kernel<<<n_inst, kUpdThreads, 0, st>>>(d, iter_local, next_chol);
 }
 
-void launch_batched_rows(int n_blocks, hipStream_t st, const BatchInst *d, int n_inst, int iter_local) {
-  batched_rows_kernel<<<n_blocks, 256, 0, st>>>(d, n_inst, iter_local);
+// Over the instances d[0 .. n_inst) of one K group (rb0 counted from the group's first instance).
+void launch_batched_rows(int K, int n_blocks, hipStream_t st, const BatchInst *d, int n_inst, int iter_local) {
+  switch (K) {
+#define HSN_K(KK) \
+  case KK: batched_rows_kernel<KK><<<n_blocks, 256, 0, st>>>(d, n_inst, iter_local); break;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+  }
 }
 
 void launch_batched_advance(int n_inst, int steps, hipStream_t st, const BatchInst *d) {

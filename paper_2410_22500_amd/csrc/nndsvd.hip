@@ -406,7 +406,7 @@ __global__ void qinit_kernel(double *__restrict__ Q, int n_k, int L) {
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
                      int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                     float *part_nd, double *part_gv, double *part_obj, const NmfCtrl *ctrl, int iter);
+                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter);
 
 size_t nndsvd_ws_bytes(int64_t n_p, int n_k, int K, int n_split) {
   const int n_tb = (n_k + kGT - 1) / kGT;

@@ -86,6 +86,8 @@ _lib.hsn_subspace_nmf.restype = C.c_int
 _lib.hsn_subspace_nmf_batched.argtypes = [_P, C.c_int, C.POINTER(NmfProblem), C.POINTER(NmfOpts), C.c_int,
                                           C.POINTER(NmfStats), _P]
 _lib.hsn_subspace_nmf_batched.restype = C.c_int
+_lib.hsn_batched_plan_info.argtypes = [_P]
+_lib.hsn_batched_plan_info.restype = C.c_char_p
 _lib.hsn_project.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_float, C.c_float, _P]
 _lib.hsn_project.restype = C.c_int
 _lib.hsn_backproject.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_float, C.c_float, _P]
@@ -250,6 +252,10 @@ def hsn_subspace_nmf_batched(problems, max_iter: int = 100, check_every: int = 1
     _check(_lib.hsn_subspace_nmf_batched(ctx, n, arr, C.byref(opts), flags, stats, _stream(dev)), ctx)
     return [dict(iters=s.iters, polish_done=s.polish_done, objective=s.objective, rel_obj=s.rel_obj,
                  history=[hists[i][j] for j in range(s.history_len)], ms=s.ms) for i, s in enumerate(stats)]
+
+
+def hsn_batched_plan_info(device: int = 0) -> str:
+    return _lib.hsn_batched_plan_info(context(device)).decode()
 
 
 def hsn_project(x: torch.Tensor, n_views: int, angles: Optional[Sequence[float]] = None, alpha: float = 1.0,

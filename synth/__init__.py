@@ -262,6 +262,23 @@ def batched_instances(n: int = 32, seed: int = 3):
     return out
 
 
+def batched_scans(n: int = 32, seed: int = 3, counts: bool = True):
+    """The scans of batched_instances.  An instance whose objects cannot be
+    placed without overlap keeps its shape and draws its geometry again from
+    seed + 100000 * attempt (deterministic)."""
+    out = []
+    for d in batched_instances(n, seed):
+        for attempt in range(20):
+            try:
+                out.append(make_scan(counts=counts, **dict(d, seed=d["seed"] + 100000 * attempt)))
+                break
+            except RuntimeError:
+                continue
+        else:
+            raise RuntimeError("batched_scans: could not place objects")
+    return out
+
+
 def random_factors(n_p: int, n_k: int, k: int, seed: int, lo: float = 0.1, hi: float = 1.0):
     """Strictly positive seeded (V, D) pair, used as an explicit NMF start."""
     rng = np.random.Generator(np.random.PCG64(seed))
