@@ -240,6 +240,11 @@ def main():
         roof[name] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
                       "avg_launch_ms": ms / n, "launches": n, "queued": queued, "total_ms": ms,
                       "alg_per_launch": units / n}
+    # HBM bytes per launch from the committed counter runs, valid only while
+    # the kernel's source is the one the counters were taken on.
+    traffic = load_traffic() if args.workload == "mid" else {}
+    for name, r in roof.items():
+        r["traffic"] = traffic.get(name.split(" ")[0])
     dom = max(roof, key=lambda k: roof[k]["total_ms"])
     d = roof[dom]
     prj = roof.get(work[hsn.KERN_PROJECT][0])
@@ -274,7 +279,7 @@ def main():
                       "voxel_rays_per_s_AT": triples / (bpj["avg_launch_ms"] * 1e-3) if bpj else None,
                       "ms_A": prj["avg_launch_ms"] if prj else None, "ms_AT": bpj["avg_launch_ms"] if bpj else None},
         "roofline": {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
-                     "unit": d["unit"], "frac": d["frac"], "traffic": None,
+                     "unit": d["unit"], "frac": d["frac"], "traffic": d["traffic"],
                      "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
                      "alg_per_launch": d["alg_per_launch"], "all_kernels": roof},
     }
@@ -282,6 +287,24 @@ def main():
         out["cpu_baseline"] = cpu_baseline(sc, compare["plain_fp32"]["mu_iters"],
                                            compare["plain_fp32"]["anls_rounds"])
     print(json.dumps(out), flush=True)
+
+
+def load_traffic():
+    """kernel -> HBM bytes per launch (mid workload) from profiles/pmc_traffic_mid.json
+    (rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy probe), for kernels
+    whose source file still hashes to the value recorded with the counters."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_mid.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        rec = json.load(f)
+    out = {}
+    for name, k in rec.get("kernels", {}).items():
+        src = os.path.join(ROOT, k["source"])
+        if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == k["source_sha256"]:
+            out[name] = k["hbm_bytes_per_launch"]
+    return out
 
 
 def run_batched(args):
