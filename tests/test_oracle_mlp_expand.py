@@ -115,3 +115,33 @@ def test_fmd_tail_appendix_b_identity():
     np.testing.assert_allclose(expand.material_volumes(xs, T_est), xm, atol=1e-12)
     Dm = expand.material_spectra(Ds, T_est)
     np.testing.assert_allclose(xm @ Dm.T, xs @ Ds.T, rtol=1e-13)
+
+
+def test_canonical_form_pins():
+    """Canonical form of an NMF pair: a planted permutation and positive column
+    scaling of a known (V, D) is undone exactly, the product is unchanged, and
+    without a library the columns are ordered by the norm of the scaled V."""
+    import itertools
+    from oracle.metrics import canonical
+    g = np.random.Generator(np.random.PCG64(5))
+    k, n_p, n_k = 4, 50, 30
+    L = g.uniform(0.1, 1.0, (n_k, k))
+    Ln = L / np.linalg.norm(L, axis=0)
+    V = g.uniform(0.0, 2.0, (n_p, k))
+    perm = [2, 0, 3, 1]
+    scale = np.array([0.5, 3.0, 1.7, 0.2])
+    Dp = (Ln * scale)[:, perm]
+    Vp = (V / scale)[:, perm]
+    Vc, Dc = canonical(Vp, Dp, library=L)
+    assert np.allclose(Dc, Ln, rtol=1e-14, atol=0)
+    assert np.allclose(Vc, V, rtol=1e-13, atol=1e-15)
+    assert np.allclose(Vc @ Dc.T, Vp @ Dp.T, rtol=1e-13)
+    # the chosen permutation maximises the summed cosine (brute force)
+    cos = (Dp / np.linalg.norm(Dp, axis=0)).T @ Ln
+    best = max(itertools.permutations(range(k)), key=lambda p: sum(cos[p[m], m] for m in range(k)))
+    assert list(best) == [perm.index(m) for m in range(k)]
+    # without a library: descending norm of the scaled V columns
+    Vn, Dn = canonical(Vp, Dp)
+    norms = np.linalg.norm(Vn, axis=0)
+    assert np.all(np.diff(norms) <= 0)
+    assert np.allclose(np.linalg.norm(Dn, axis=0), 1.0, rtol=1e-14)
