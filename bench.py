@@ -50,8 +50,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=["mid", "tiny", "batched"],
-                    help="mid / tiny: the whole path on one scan; batched: 32 uneven decompositions")
+    ap.add_argument("--workload", default="mid", choices=["mid", "tiny", "full", "batched"],
+                    help="mid / tiny / full: the whole path on one scan; batched: 32 uneven decompositions")
     ap.add_argument("--mlp-scans", type=int, default=348)
     ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--compare-steps", type=int, default=2,
@@ -108,14 +108,20 @@ def main():
     dev = torch.device("cuda:0")
     t0 = time.time()
     cfg = synth.CONFIGS[args.workload]
-    sc = synth.config_scan(args.workload)
+    full = args.workload == "full"
+    # The full workload's 15.7 G counts are drawn on the GPU (seeded Philox).
+    sc = synth.config_scan(args.workload, counts=not full)
     K = sc.n_mat
     n_p, n_k = sc.n_p, sc.n_bins
     vpb = n_p * n_k
+    if full:
+        y, yo = synth.device_counts(sc, seed=cfg["seed"] * 7919 + 1, device=dev)
+    else:
+        y = torch.from_numpy(sc.y.view(np.int16)).to(dev)
+        yo = torch.from_numpy(sc.yo.view(np.int16)).to(dev)
+    torch.cuda.synchronize()
     log(f"workload {args.workload}: N_v={sc.n_views} N_r={sc.n_rows} N_c={sc.n_cols} N_k={n_k} K={K} "
         f"({vpb:.3e} vpb), generated in {time.time() - t0:.1f}s")
-    y = torch.from_numpy(sc.y.view(np.int16)).to(dev)
-    yo = torch.from_numpy(sc.yo.view(np.int16)).to(dev)
     V = torch.empty((n_p, K), dtype=torch.float32, device=dev)
     D = torch.empty((n_k, K), dtype=torch.float32, device=dev)
 
@@ -132,17 +138,22 @@ def main():
     # f*: lowest objective of long float32 reference runs (not timed).
     p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=True)
     refs = {}
+    # (the full workload's reference runs are shorter: an ANLS round streams 126 GB there)
+    r_anls, r_hals = (400, 600) if full else (2000, 3000)
     for name, kw in (("nndsvda+mu+anls", dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, polish_algo=hsn.ALGO_ANLS,
-                                              polish_rounds=2000)),
+                                              polish_rounds=r_anls, precision=hsn.PREC_BF16 if full else
+                                              hsn.PREC_FP32)),
                      ("nndsvda+mu+hals", dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, polish_algo=hsn.ALGO_HALS,
-                                              polish_rounds=3000)),
+                                              polish_rounds=r_hals, precision=hsn.PREC_BF16 if full else
+                                              hsn.PREC_FP32)),
                      ("learned+anls", dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0, polish_algo=hsn.ALGO_ANLS,
-                                           polish_rounds=2000))):
+                                           polish_rounds=r_anls))):
         st = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, **kw)
         h = np.array(st["history"])
         refs[name] = float(h.min())
         log(f"reference {name}: min f {h.min():.9e}, last rel change {abs(h[-2] - h[-1]) / h[-1]:.2e}")
     f_star = min(refs.values())
+    del p, pb
 
     paths = {
         "learned": dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0),
@@ -190,9 +201,11 @@ def main():
         f"rel obj {recs[-1]['rel_obj']:.3e}")
 
     compare = {}
+    compare_prof = {}
     for path in ("plain_fp32", "cold_bf16"):
         step(path)
-        ms_p, rp, _ = timed(path, args.compare_steps, False)
+        ms_p, rp, pp = timed(path, args.compare_steps, True)
+        compare_prof[path] = (pp, rp)
         nm = float(np.mean([r["ms"] for r in rp]))
         compare[path] = {"ms_per_step": ms_p, "nmf_ms": nm, "nmf_vpb_per_s": vpb / (nm * 1e-3),
                          "mu_iters": rp[-1]["iters"], "anls_rounds": rp[-1]["polish_done"],
@@ -245,6 +258,32 @@ def main():
     traffic = load_traffic() if args.workload == "mid" else {}
     for name, r in roof.items():
         r["traffic"] = traffic.get(name.split(" ")[0])
+    # The comparison paths' streaming passes (their bulk is the largest HBM
+    # stream of the method): MU pass = p once + V read and written; each ANLS
+    # round = two passes of p once + V (or N_V) once.
+    for path, (pp, rp) in compare_prof.items():
+        it_ = sum(r["iters"] for r in rp)
+        rd_ = sum(r["polish_done"] for r in rp)
+        bf = path == "cold_bf16"
+        kinds = [(hsn.KERN_NMF_PASS_BF16, it_ * (2.0 * elems + 2 * vb), it_)] if bf else []
+        kinds.append((hsn.KERN_NMF_PASS, (0 if bf else it_ * (4.0 * elems + 2 * vb)) + rd_ * 2 * (4.0 * elems + vb),
+                      (0 if bf else it_) + 2 * rd_))
+        ent = {}
+        for kk, by, nl in kinds:
+            ms, nq = pp.get(kk, (0.0, 0))
+            if nl and ms > 0:
+                ach = by / (ms * 1e-3) / 1e9
+                ent["bf16 MU pass" if kk == hsn.KERN_NMF_PASS_BF16 else "f32 passes"] = {
+                    "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                    "avg_launch_ms": ms / nl, "launches": nl, "queued": nq}
+        gms, gn = pp.get(hsn.KERN_NNDSVD_GRAM, (0.0, 0))
+        if gn:
+            fl = 2.0 * n_p * n_k * n_k
+            ent["NNDSVD Gram (MFMA)"] = {"bound": "mfma", "achieved": fl / (gms / gn * 1e-3) / 1e12,
+                                         "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                         "frac": fl / (gms / gn * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,
+                                         "avg_launch_ms": gms / gn, "launches": gn}
+        compare[path]["roofline"] = ent
     dom = max(roof, key=lambda k: roof[k]["total_ms"])
     d = roof[dom]
     prj = roof.get(work[hsn.KERN_PROJECT][0])
@@ -283,7 +322,7 @@ def main():
                      "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
                      "alg_per_launch": d["alg_per_launch"], "all_kernels": roof},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not full:
         out["cpu_baseline"] = cpu_baseline(sc, compare["plain_fp32"]["mu_iters"],
                                            compare["plain_fp32"]["anls_rounds"])
     print(json.dumps(out), flush=True)
