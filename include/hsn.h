@@ -242,6 +242,24 @@ hsn_status hsn_rehydrate(hsn_ctx *ctx, const float *xs, const float *D, int64_t 
                          int64_t bin_end, float *xh, int64_t ldh, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Fast material decomposition tail (Alg. 2, eq. 7-9), semi-supervised.  */
+/* ------------------------------------------------------------------ */
+
+/*
+ * From the reconstructed subspace volume x^s [n_x][k] (hsn_cgls output), the
+ * subspace spectra D^s [n_k][k] (hsn_subspace_nmf's D) and one region label
+ * per voxel (labels[n] in 0..n_m-1, or -1 for a voxel in no region; the
+ * paper's masks M_i):
+ *   T  [n_m][k]   T[i][j] = mean of x^s[n][j] over the voxels of region i   eq. (7)
+ *                 (a region without voxels gives a zero row)
+ *   xm [n_x][n_m] xm[n] = argmin_{x >= 0} ||x^s[n] - x T||^2, per voxel       eq. (8)
+ *   Dm [n_k][n_m] Dm = D^s T^T, the material spectra                         eq. (9)
+ * All outputs float32 (device); sums and solves in float64.  k, n_m in 1..8.
+ */
+hsn_status hsn_fmd(hsn_ctx *ctx, const float *xs, int64_t n_x, int k, const int32_t *labels, int n_m,
+                   const float *Ds, int64_t n_k, float *T, float *xm, float *Dm, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Learned warm start of eq. (4): spectrum -> K coefficients.            */
 /* ------------------------------------------------------------------ */
 

@@ -127,6 +127,8 @@ _lib.hsn_mlp_load.argtypes = [_P, C.POINTER(_P), C.c_char_p]
 _lib.hsn_mlp_load.restype = C.c_int
 _lib.hsn_canonicalize.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, C.c_int, _P, _P]
 _lib.hsn_canonicalize.restype = C.c_int
+_lib.hsn_fmd.argtypes = [_P, _P, C.c_int64, C.c_int, _P, C.c_int, _P, C.c_int64, _P, _P, _P, _P]
+_lib.hsn_fmd.restype = C.c_int
 _lib.hsn_profile_enable.argtypes = [_P, C.c_int]
 _lib.hsn_profile_enable.restype = C.c_int
 _lib.hsn_profile_read.argtypes = [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
@@ -457,3 +459,19 @@ def hsn_canonicalize(V: torch.Tensor, D: torch.Tensor, library: Optional[torch.T
     ctx = context(dev)
     n_p, k = V.shape
     _check(_lib.hsn_canonicalize(ctx, _ptr(V), n_p, _ptr(D), D.shape[0], k, _ptr(library), _stream(dev)), ctx)
+
+
+def hsn_fmd(xs: torch.Tensor, labels: torch.Tensor, n_m: int, Ds: torch.Tensor):
+    """Alg. 2 tail: (T [n_m][K], x^m [n_x][n_m], D^m [n_k][n_m]) from x^s [n_x][K],
+    int32 labels [n_x] (-1 = no region) and D^s [n_k][K]."""
+    dev = _dev(xs)
+    ctx = context(dev)
+    n_x, k = xs.shape
+    n_k = Ds.shape[0]
+    assert labels.dtype == torch.int32 and xs.is_contiguous() and Ds.is_contiguous()
+    T = torch.empty((n_m, k), dtype=torch.float32, device=xs.device)
+    xm = torch.empty((n_x, n_m), dtype=torch.float32, device=xs.device)
+    Dm = torch.empty((n_k, n_m), dtype=torch.float32, device=xs.device)
+    _check(_lib.hsn_fmd(ctx, _ptr(xs), n_x, k, _ptr(labels), n_m, _ptr(Ds), n_k, _ptr(T), _ptr(xm), _ptr(Dm),
+                        _stream(dev)), ctx)
+    return T, xm, Dm
