@@ -1,6 +1,8 @@
 // Context lifetime, error reporting and workspace management.
 #include "common.hpp"
 
+#include <algorithm>
+
 namespace hsn {
 
 hsn_status fail(hsn_ctx *ctx, hsn_status st, const char *fmt, ...) {
@@ -31,6 +33,22 @@ hsn_status ensure_ws(hsn_ctx *ctx, size_t bytes) {
     return fail(ctx, HSN_ERR_OOM, "workspace allocation of %zu bytes failed", want);
   }
   ctx->ws_bytes = want;
+  return HSN_OK;
+}
+
+hsn_status ensure_host_stage(hsn_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->host_stage_bytes) return HSN_OK;
+  HSN_HIP(ctx, hipDeviceSynchronize());
+  if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+  ctx->host_stage = nullptr;
+  ctx->host_stage_bytes = 0;
+  const size_t n = std::max<size_t>(bytes, 1 << 16);
+  if (hipHostMalloc(&ctx->host_stage, n, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->host_stage = nullptr;
+    return fail(ctx, HSN_ERR_OOM, "cannot allocate %zu bytes of pinned host memory", n);
+  }
+  ctx->host_stage_bytes = n;
   return HSN_OK;
 }
 
@@ -112,6 +130,7 @@ void hsn_destroy(hsn_ctx *ctx) {
   hsn::DeviceGuard g(ctx->device);
   (void)hipDeviceSynchronize();
   for (hsn::Owned *o : ctx->plans) delete o;
+  if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->geom) (void)hipFree(ctx->geom);

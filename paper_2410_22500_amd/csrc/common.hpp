@@ -43,12 +43,18 @@ struct hsn_ctx {
   // Stream used only to capture graphs (capture is not allowed on the null stream).
   hipStream_t cap_stream = nullptr;
   std::string last_plan_note;  // description of the last batched plan used
+  // Pinned host staging for small device-to-host reads (control block, history).
+  void *host_stage = nullptr;
+  size_t host_stage_bytes = 0;
 };
 
 namespace hsn {
 
 hsn_status fail(hsn_ctx *ctx, hsn_status st, const char *fmt, ...);
 hsn_status ensure_ws(hsn_ctx *ctx, size_t bytes);
+// Pinned host staging buffer of at least `bytes` (grown on demand; the
+// stream is synchronised before it is replaced).
+hsn_status ensure_host_stage(hsn_ctx *ctx, size_t bytes);
 // Bracket one kernel launch with timing events when profiling is on.
 void prof_begin(hsn_ctx *ctx, int kind, hipStream_t st);
 void prof_end(hsn_ctx *ctx, int kind, hipStream_t st);

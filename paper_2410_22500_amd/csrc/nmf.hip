@@ -254,10 +254,15 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     }
   }
   if (stats) {
+    // One round trip: control block and the whole history into pinned memory.
     HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
-    HSN_HIP(ctx, hipMemcpyAsync(&hc, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
-    HSN_HIP(ctx, hipEventSynchronize(ctx->ev1));
+    if ((rc = ensure_host_stage(ctx, sizeof(NmfCtrl) + sizeof(double) * hist_cap)) != HSN_OK) return rc;
+    NmfCtrl *hcp = static_cast<NmfCtrl *>(ctx->host_stage);
+    double *hh = reinterpret_cast<double *>(static_cast<char *>(ctx->host_stage) + sizeof(NmfCtrl));
+    HSN_HIP(ctx, hipMemcpyAsync(hcp, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
+    HSN_HIP(ctx, hipMemcpyAsync(hh, R.w.hist, sizeof(double) * hist_cap, hipMemcpyDeviceToHost, st));
     HSN_HIP(ctx, hipStreamSynchronize(st));
+    hc = *hcp;
     float ms = 0.f;
     HSN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     const int done = std::min(hc.stop_at, issued);
@@ -266,17 +271,16 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     stats->polish_done = std::max(0, done - o->max_iter);
     stats->history_len = 0;
     double last = NAN;
-    if (hc.hist_len > 0) {
-      std::vector<double> h(hc.hist_len);
-      HSN_HIP(ctx, hipMemcpy(h.data(), R.w.hist, sizeof(double) * hc.hist_len, hipMemcpyDeviceToHost));
-      last = h.back();
-      const int n_copy = std::min(hc.hist_len, stats->history_cap);
-      for (int i = 0; i < n_copy; ++i) stats->history[i] = h[i];
+    const int len = std::min(hc.hist_len, hist_cap);
+    if (len > 0) {
+      last = hh[len - 1];
+      const int n_copy = std::min(len, stats->history_cap);
+      for (int i = 0; i < n_copy; ++i) stats->history[i] = hh[i];
       stats->history_len = n_copy;
     }
     stats->objective = last;
     stats->rel_obj = stop_test ? (last - o->f_ref) / o->f_ref : NAN;
-    if (hc.hist_len > 0 && std::isnan(last)) return fail(ctx, HSN_ERR_NUMERIC, "nmf: objective is NaN");
+    if (len > 0 && std::isnan(last)) return fail(ctx, HSN_ERR_NUMERIC, "nmf: objective is NaN");
   }
   return HSN_OK;
 }
