@@ -218,6 +218,31 @@ hsn_status hsn_backproject(hsn_ctx *ctx, const hsn_geom *g, const float *s, floa
                            float alpha, float beta, void *stream);
 
 /*
+ * Launch shape of hsn_project, hsn_backproject and hsn_cgls: a tuning knob
+ * for the operators of eq. (3)/(5); every shape computes the same entries.
+ *   views   A stages the slice image through LDS for `views` views of one
+ *           orientation per workgroup: 1, 2 or 4.
+ *   split   A runs `split` copies of those rays per workgroup, each over
+ *           every split-th image row, summed in copy order: 1, 2, 4, 8, 16
+ *           (reduced until the workgroup fits 1024 threads).
+ *   voxels  A^T stages the slice's sinogram rows through LDS for `voxels`
+ *           voxels per thread: 1, 2 or 4.
+ *   threads A^T workgroup size: 64, 128, 256, 512 or 1024.
+ * 0 = chosen from the geometry and the CU count (the default); views or
+ * voxels -1 = the gather kernel for that operator, which reads every tap
+ * from the caches.  Other values: HSN_ERR_INVALID_ARG.  With split 1 (and
+ * for A^T always) the staged and gather kernels give the same float32
+ * values bit for bit; split > 1 changes the order of the sums per ray.
+ * Geometries whose staged row does not fit 61 KB of LDS ((n_cols + 4) k
+ * floats, 8 pad pixels for odd k), or n_cols > 1024 for A, use the gather
+ * kernels whatever is set.
+ */
+hsn_status hsn_projector_set_launch(hsn_ctx *ctx, int views, int split, int voxels, int threads);
+/* The shape the next call would use for g: shape[0..3] = views, split,
+ * voxels, threads as above, 0 where that operator runs the gather kernel. */
+hsn_status hsn_projector_launch_info(hsn_ctx *ctx, const hsn_geom *g, int *shape);
+
+/*
  * eq. (5) with h = 0: x_j = argmin ||V_j - A x_j||^2 for every channel j by
  * CGLS from x = 0, n_iter iterations (one A and one A^T each), all channels
  * at once with per-channel scalars kept on the device (no host sync).

@@ -33,6 +33,9 @@ struct hsn_ctx {
   double *geom = nullptr;
   size_t geom_cap = 0;
   std::vector<double> geom_host;
+  // Projector launch shape (hsn_projector_set_launch; 0 = chosen from the
+  // geometry, -1 = the gather kernels).
+  int proj_views = 0, proj_split = 0, proj_voxels = 0, proj_threads = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // Optional kernel timing: event pairs per kernel kind.
   bool prof = false;

@@ -12,10 +12,13 @@
 // Adjoint = voxel gather: one thread per voxel loops over the views and
 // reads the two detector bins that straddle the voxel centre.  Both
 // evaluate the same entries, so A^T is the exact adjoint up to float32
-// rounding.  Crossing positions are evaluated in float64 (|x| reaches
-// ~N/sqrt(2) pixels, where a float32 position would carry ~1e-5 px error);
-// weights and channel sums are float32.  All K channels of a pixel or bin
-// are contiguous, so each tap is one vector load.
+// rounding.  Positions carry far more than float32 precision (|x| reaches
+// ~N/sqrt(2) pixels, where a float32 position would carry ~1e-5 px error):
+// the adjoint evaluates them in float64; the forward ray starts in float64
+// and steps in 32.32 fixed point, integer steps that are exact, so a
+// position is off by less than (m + 1) 2^-33 px after m steps.  Weights
+// and channel sums are float32.  All K channels of a pixel or bin are
+// contiguous, so each tap is one vector load.
 #include "common.hpp"
 
 #include <algorithm>
@@ -52,6 +55,7 @@ __device__ __forceinline__ void load_k(const float *__restrict__ p, float (&out)
 }
 
 constexpr int kRayThreads = 128;
+constexpr int kViewGroup = 4;  // views per orientation group of the LDS projector
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, each with its own L2; workgroups go round-robin over them
 
 // XCD-aware block order: with >= 8 slices, block id b runs on XCD b % 8 and
@@ -99,16 +103,50 @@ __device__ __forceinline__ void block_sumsq(const float (&v)[K], bool valid, dou
   }
 }
 
+// One ray (view g, detector column c): it steps along the image axis
+// closer to its direction (rows for flat views, |cos| >= |sin|; columns for
+// steep ones) and crosses the other axis at u(m) = u0 + m du, held as
+// U = u 2^32 in 32.32 fixed point.  [m_lo, m_hi] is a conservative range of
+// the steps at which a tap can fall inside the image.
+struct Ray {
+  int64_t U0, dU;
+  int m_lo, m_hi;
+  float inv_w, s1;  // 1/w and 2^-32 / w
+};
+__device__ __forceinline__ Ray ray_setup(const ViewGeom &g, int c, int n) {
+  Ray ry;
+  const double h = 0.5 * double(n - 1);
+  const double sc = double(c) - h;
+  const bool steep = fabs(g.sn) > fabs(g.cs);
+  const double a = steep ? g.sn : g.cs, b = steep ? g.cs : g.sn;
+  const double u0 = (sc + h * b) / a + h;
+  const double du = -b / a;
+  ry.U0 = __double2ll_rn(u0 * 4294967296.0);
+  ry.dU = __double2ll_rn(du * 4294967296.0);
+  ry.m_lo = 0;
+  ry.m_hi = n - 1;
+  if (du != 0.0) {
+    const double ma = (-1.0 - u0) / du, mb = (double(n) - u0) / du;
+    // clamped in float64 before the conversion (|du| may be ~1e-16)
+    ry.m_lo = int(fmax(0.0, floor(fmin(ma, mb)) - 1.0));
+    ry.m_hi = int(fmin(double(n - 1), ceil(fmax(ma, mb)) + 1.0));
+  } else if (u0 < -1.0 || u0 >= double(n)) {
+    ry.m_hi = -1;
+  }
+  ry.inv_w = float(g.inv_w);
+  ry.s1 = ry.inv_w * 2.3283064365386963e-10f;  // exact: a power of two
+  return ry;
+}
+
 // s[v][r][c][:] = alpha * sum_taps a * x[r][j][i][:] + beta * s[v][r][c][:]
 //
-// The ray steps along the image axis closer to its direction: rows j for
-// flat views (|cos| >= |sin|), columns i for steep ones.  Steep views read
-// the transposed image xT[r][i][j][:] (= x[r][j][i][:]), so for every view
-// the taps of neighbouring detector columns are neighbouring pixels of one
-// image row and a wave's loads are contiguous.  Steps where the ray is
-// outside the image are skipped by a conservative step range; at the image
-// edge a tap index is clamped and its weight set to 0, which keeps the loop
-// free of branches.  Optional: per-block sums of squares of the outputs.
+// One thread per ray.  Steep views read the transposed image
+// xT[r][i][j][:] (= x[r][j][i][:]), so for every view the taps of
+// neighbouring detector columns are neighbouring pixels of one image row
+// and a wave's loads are contiguous.  Tap t0 = floor(u) has weight
+// (1 - f)/w and tap t0 + 1 weight f/w (f = u - t0); at the image edge a tap
+// index is clamped and its weight set to 0, which keeps the loop free of
+// branches.  Optional: per-block sums of squares of the outputs.
 template <int K>
 __global__ __launch_bounds__(kRayThreads) void project_kernel(const float *__restrict__ x,
                                                               const float *__restrict__ xT, float *__restrict__ s,
@@ -122,36 +160,19 @@ __global__ __launch_bounds__(kRayThreads) void project_kernel(const float *__res
   const int r = bs.slice;
   const int c = cx * kRayThreads + threadIdx.x;
   const ViewGeom g = geom[v];
-  const double h = 0.5 * double(n - 1);
-  const double sc = double(c) - h;
-  const float inv_w = float(g.inv_w);
-  const bool steep = fabs(g.sn) > fabs(g.cs);
-  const double a = steep ? g.sn : g.cs, b = steep ? g.cs : g.sn;
-  // crossing position along the other axis at step m: u(m) = u0 + m du
-  const double u0 = (sc + h * b) / a + h;
-  const double du = -b / a;
-  int m_lo = 0, m_hi = n - 1;
-  if (du != 0.0) {
-    const double ma = (-1.0 - u0) / du, mb = (double(n) - u0) / du;
-    // clamped in float64 before the conversion (|du| may be ~1e-16)
-    m_lo = int(fmax(0.0, floor(fmin(ma, mb)) - 1.0));
-    m_hi = int(fmin(double(n - 1), ceil(fmax(ma, mb)) + 1.0));
-  } else if (u0 < -1.0 || u0 >= double(n)) {
-    m_hi = -1;
-  }
+  const Ray ry = ray_setup(g, c, n);
   float acc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0.0f;
-  const float *img = (steep ? xT : x) + size_t(r) * n * n * K;
+  const float *img = ((fabs(g.sn) > fabs(g.cs)) ? xT : x) + size_t(r) * n * n * K;
   if (c < n) {
+    int64_t U = ry.U0 + int64_t(ry.m_lo) * ry.dU;
 #pragma unroll 4
-    for (int m = m_lo; m <= m_hi; ++m) {
-      const double u = fma(double(m), du, u0);
-      const double fl = floor(u);
-      const int t0 = int(fl);
-      const float f = float(u - fl);
-      const float w0 = (t0 >= 0 && t0 < n) ? (1.0f - f) * inv_w : 0.0f;
-      const float w1 = (t0 + 1 >= 0 && t0 + 1 < n) ? f * inv_w : 0.0f;
+    for (int m = ry.m_lo; m <= ry.m_hi; ++m, U += ry.dU) {
+      const int t0 = int(U >> 32);
+      const float w1f = float(uint32_t(U)) * ry.s1;
+      const float w0 = (t0 >= 0 && t0 < n) ? ry.inv_w - w1f : 0.0f;
+      const float w1 = (t0 + 1 >= 0 && t0 + 1 < n) ? w1f : 0.0f;
       const int i0 = min(max(t0, 0), n - 1), i1 = min(max(t0 + 1, 0), n - 1);
       const float *row = img + size_t(m) * n * K;
       float p0[K], p1[K];
@@ -226,6 +247,348 @@ __global__ __launch_bounds__(kVoxThreads) void backproject_kernel(const float *_
     }
   }
   if (sumsq) block_sumsq<K, kVoxThreads>(res, ok, sumsq, (size_t(r) * n + j) * nx + cx);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged projector.  The kernels above take every tap from L1/L2 with
+// a dependent gather per step.  Here a block copies the rows it shares (the
+// slice image for A, the slice's sinogram rows for A^T) into LDS in bands
+// and takes the taps from there, while the next band's global loads are in
+// flight.  Staged rows are channel-planar (channel q of pixel t of staged
+// row i at q * plane + i * ldp + pad + t), so the two taps of a lane are
+// neighbouring words and neighbouring lanes read neighbouring words; the
+// plane stride is a compile-time constant, so each tap is one LDS read with
+// an immediate offset.  Rows carry zero pixels (bins) on both sides and a
+// tap index is clamped into them: no bounds tests or weight masks in the
+// inner loops.  A clamped tap reads 0 where the gather kernels apply weight
+// 0, so with one thread per ray (split 1) both paths give the same values
+// bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kLdsMaxThreads = 1024;
+constexpr int kStageFloats = 15360;  // 60 KB of channel planes
+constexpr int kStagePad = 2;         // zero pixels (bins) on each side of a staged row
+constexpr int kCopyFloats = 8;       // floats each thread copies per band
+
+// Plane stride of the staged rows (floats).
+template <int K>
+__host__ __device__ constexpr int lds_plane() { return (kStageFloats / K) / 4 * 4; }
+
+template <int K>
+__device__ __forceinline__ int planar_offset(int row, int col, int ldp) {
+  const int pix = col / K, q = col - pix * K;
+  return q * lds_plane<K>() + row * ldp + kStagePad + pix;
+}
+
+// One thread's part of a band copy: up to kCopyFloats floats of `rows`
+// rows of `width` interleaved floats each (row i at src + i * src_ld), at
+// band-local flat positions t + u * nt (scalar) or 4 (t + u * nt) + j
+// (float4, VEC), written channel-planar.  load() issues the global loads
+// into registers; store() writes them to LDS, so a band's loads can be in
+// flight while the previous band is used.
+template <int K, bool VEC>
+struct BandCopy {
+  int width, ldp;
+  int row4[2], col4[2];
+  float buf[kCopyFloats];
+
+  __device__ __forceinline__ void init(int w, int ld) {
+    width = w;
+    ldp = ld;
+    if constexpr (VEC) {
+      const int w4 = w / 4;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int f = int(threadIdx.x) + u * int(blockDim.x);
+        row4[u] = f / w4;
+        col4[u] = 4 * (f - row4[u] * w4);
+      }
+    }
+  }
+  __device__ __forceinline__ void load(const float *__restrict__ src, size_t src_ld, int rows) {
+    if constexpr (VEC) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (row4[u] < rows) {
+          const float4 v = *reinterpret_cast<const float4 *>(src + size_t(row4[u]) * src_ld + col4[u]);
+          buf[4 * u] = v.x;
+          buf[4 * u + 1] = v.y;
+          buf[4 * u + 2] = v.z;
+          buf[4 * u + 3] = v.w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kCopyFloats; ++u) {
+        const int e = int(threadIdx.x) + u * int(blockDim.x);
+        const int r = e / width, c = e - r * width;
+        if (r < rows) buf[u] = src[size_t(r) * src_ld + c];
+      }
+    }
+  }
+  __device__ __forceinline__ void store(float *__restrict__ planes, int rows) const {
+    if constexpr (VEC) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (row4[u] < rows) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) planes[planar_offset<K>(row4[u], col4[u] + j, ldp)] = buf[4 * u + j];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kCopyFloats; ++u) {
+        const int e = int(threadIdx.x) + u * int(blockDim.x);
+        const int r = e / width, c = e - r * width;
+        if (r < rows) planes[planar_offset<K>(r, c, ldp)] = buf[u];
+      }
+    }
+  }
+};
+
+// Both taps of every channel at staged pixel p: a[q] = p[q plane],
+// b[q] = p[q plane + 1].
+template <int K>
+__device__ __forceinline__ void planar_taps(const float *p, float (&a)[K], float (&b)[K]) {
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    a[q] = p[q * lds_plane<K>()];
+    b[q] = p[q * lds_plane<K>() + 1];
+  }
+}
+
+// Zeroes the pad pixels of `rows` staged rows in every channel plane.
+template <int K>
+__device__ __forceinline__ void zero_pads(float *__restrict__ planes, int ldp, int n, int rows) {
+  constexpr int PP = 2 * kStagePad;
+  for (int e = threadIdx.x; e < K * rows * PP; e += blockDim.x) {
+    const int q = e / (rows * PP), rest = e - q * (rows * PP);
+    const int row = rest / PP, k = rest - row * PP;
+    planes[q * lds_plane<K>() + row * ldp + (k < kStagePad ? k : n + k)] = 0.0f;
+  }
+}
+
+// Block sum of squares of up to S values per thread (rows of v), any block
+// size up to kLdsMaxThreads: partial[block][q].
+template <int K, int S>
+__device__ __forceinline__ void block_sumsq_n(const float (&v)[S][K], const bool (&valid)[S],
+                                              double *__restrict__ partial, size_t block) {
+  __shared__ double red[kLdsMaxThreads / 64][K];
+  const int nw = int(blockDim.x) >> 6;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    double a = 0.0;
+#pragma unroll
+    for (int e = 0; e < S; ++e) a += valid[e] ? double(v[e][q]) * double(v[e][q]) : 0.0;
+    const double t = hsn::wave_sum_all(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w][threadIdx.x];
+    partial[block * K + threadIdx.x] = t;
+  }
+}
+
+// A: one block = one slice and vb views of one orientation (a view group,
+// or a half or quarter of one).  The slice image (x for flat views, xT for
+// steep ones) passes through LDS in bands of band_rows rows.  Ray slot
+// (view vi, column c) = vi * n + c; `split` copies of the ray set share the
+// block (thread = copy * t1 + slot, t1 = blockDim.x / split), copy sp takes
+// the band rows m with (m - m0) % split == sp, and the copies' sums are
+// added in copy order at the end.
+template <int K, bool VEC>
+__global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
+    const float *__restrict__ x, const float *__restrict__ xT, float *__restrict__ s,
+    const ViewGeom *__restrict__ geom, const double *__restrict__ groups, int n_groups, int vb, int split,
+    int n_slices, int n, int band_rows, float alpha, float beta, double *__restrict__ sumsq) {
+  extern __shared__ __align__(16) float stage[];  // K planes of band_rows staged rows; then the copies' sums
+  constexpr int LP = lds_plane<K>();
+  const int per_group = kViewGroup / vb;
+  const BlockSlot bs = block_slot(blockIdx.x, n_slices, n_groups * per_group);
+  if (bs.slice >= n_slices) return;
+  const int r = bs.slice;
+  const int gi = bs.rest / per_group, sub = bs.rest % per_group;
+  const size_t part = size_t(r) * (n_groups * per_group) + bs.rest;
+  // Views of a group share their orientation; padding (-1) sits at the end
+  // of a group, so a sub-group whose first entry is padding is empty.
+  const int v_first = int(groups[gi * kViewGroup + sub * vb]);
+  if (v_first < 0) {
+    if (sumsq && int(threadIdx.x) < K) sumsq[part * K + threadIdx.x] = 0.0;
+    return;
+  }
+  const bool steep = fabs(geom[v_first].sn) > fabs(geom[v_first].cs);
+  const int ldp = n + 2 * kStagePad;
+  const int t1 = int(blockDim.x) / split;
+  const int sp = int(threadIdx.x) / t1, slot = int(threadIdx.x) - sp * t1;
+  const int vi = slot / n, c = slot - vi * n;
+  int view = -1;
+  Ray ry{0, 0, 0, -1, 0.0f, 0.0f};
+  if (vi < vb) {
+    view = int(groups[gi * kViewGroup + sub * vb + vi]);
+    if (view >= 0) ry = ray_setup(geom[view], c, n);
+  }
+  zero_pads<K>(stage, ldp, n, band_rows);
+  const float *img = (steep ? xT : x) + size_t(r) * n * n * K;
+  BandCopy<K, VEC> cp;
+  cp.init(n * K, ldp);
+  int rows = min(band_rows, n);
+  cp.load(img, size_t(n) * K, rows);
+  float acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0.0f;
+  const int64_t dUs = ry.dU * split;
+  const int bstep = ldp * split;
+  for (int m0 = 0; m0 < n; m0 += band_rows) {
+    __syncthreads();  // the previous band is no longer read
+    cp.store(stage, rows);
+    __syncthreads();
+    const int rows_next = min(band_rows, n - m0 - band_rows);
+    if (rows_next > 0) cp.load(img + size_t(m0 + band_rows) * n * K, size_t(n) * K, rows_next);
+    const int mb = max(ry.m_lo, m0), me = min(ry.m_hi, m0 + rows - 1);
+    int m = m0 + sp + ((max(mb - m0 - sp, 0) + split - 1) / split) * split;  // first own row >= mb
+    int64_t U = ry.U0 + int64_t(m) * ry.dU;
+    int base = (m - m0) * ldp + kStagePad;
+    for (; m <= me; m += split, U += dUs, base += bstep) {
+      const int t0 = min(max(int(U >> 32), -kStagePad), n + kStagePad - 2);
+      float a0[K], a1[K];
+      planar_taps<K>(stage + (base + t0), a0, a1);
+      const float w1 = float(uint32_t(U)) * ry.s1;
+      const float w0 = ry.inv_w - w1;
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc[q] = fmaf(w1, a1[q], fmaf(w0, a0[q], acc[q]));
+    }
+    rows = rows_next;
+  }
+  if (split > 1) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) stage[int(threadIdx.x) * K + q] = acc[q];
+    __syncthreads();
+    if (sp == 0) {
+      for (int c2 = 1; c2 < split; ++c2)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += stage[(c2 * t1 + slot) * K + q];
+    }
+  }
+  float res[1][K];
+  bool ok[1] = {sp == 0 && view >= 0};
+#pragma unroll
+  for (int q = 0; q < K; ++q) res[0][q] = 0.0f;
+  if (ok[0]) {
+    float *out = s + ((size_t(view) * n_slices + r) * n + c) * K;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      res[0][q] = (beta == 0.0f) ? alpha * acc[q] : fmaf(alpha, acc[q], beta * out[q]);
+      out[q] = res[0][q];
+    }
+  }
+  if (sumsq) block_sumsq_n<K, 1>(res, ok, sumsq, part);
+}
+
+// Bytes of per-view geometry staged by backproject_lds_kernel ahead of the
+// channel planes (cos, sin as float64, 1/w as float32), 16-byte aligned.
+__host__ __device__ inline int geom_stage_bytes(int views) { return (views * 20 + 15) / 16 * 16; }
+constexpr int kMaxViewChunk = 96;
+
+// A^T: one block = one slice and VPT * blockDim.x consecutive voxels of it
+// (row-major j, i); voxel w of the block is taken by thread w % blockDim.x.
+// The slice's sinogram rows pass through LDS in chunks of view_chunk views,
+// with the chunk's geometry.
+template <int K, int VPT, bool VEC>
+__global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
+    const float *__restrict__ s, float *__restrict__ x, const ViewGeom *__restrict__ geom, int n_views,
+    int n_slices, int n, int view_chunk, float alpha, float beta, double *__restrict__ sumsq) {
+  extern __shared__ __align__(16) float stage[];
+  constexpr int LP = lds_plane<K>();
+  const int nt = blockDim.x;
+  const int per_block = VPT * nt;
+  const int n_blk = (n * n + per_block - 1) / per_block;
+  const BlockSlot bs = block_slot(blockIdx.x, n_slices, n_blk);
+  if (bs.slice >= n_slices) return;
+  const int r = bs.slice;
+  double *g_cs = reinterpret_cast<double *>(stage);
+  double *g_sn = g_cs + view_chunk;
+  float *g_iw = reinterpret_cast<float *>(g_sn + view_chunk);
+  float *planes = stage + geom_stage_bytes(view_chunk) / 4;
+  const int ldp = n + 2 * kStagePad;
+  const double h = 0.5 * double(n - 1);
+  int vox[VPT];
+  double xi[VPT], yj[VPT];
+#pragma unroll
+  for (int e = 0; e < VPT; ++e) {
+    const int w = bs.rest * per_block + e * nt + int(threadIdx.x);
+    vox[e] = w < n * n ? w : -1;
+    const int j = w < n * n ? w / n : 0;
+    const int i = w < n * n ? w - j * n : 0;
+    xi[e] = double(i) - h;
+    yj[e] = double(j) - h;
+  }
+  zero_pads<K>(planes, ldp, n, view_chunk);
+  float acc[VPT][K];
+#pragma unroll
+  for (int e = 0; e < VPT; ++e)
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[e][q] = 0.0f;
+  const size_t view_stride = size_t(n_slices) * n * K;
+  const float *sr = s + size_t(r) * n * K;
+  BandCopy<K, VEC> cp;
+  cp.init(n * K, ldp);
+  int nv = min(view_chunk, n_views);
+  cp.load(sr, view_stride, nv);
+  ViewGeom gn{};
+  if (int(threadIdx.x) < nv) gn = geom[threadIdx.x];
+  for (int v0 = 0; v0 < n_views; v0 += view_chunk) {
+    __syncthreads();  // the previous chunk is no longer read
+    cp.store(planes, nv);
+    if (int(threadIdx.x) < nv) {
+      g_cs[threadIdx.x] = gn.cs;
+      g_sn[threadIdx.x] = gn.sn;
+      g_iw[threadIdx.x] = float(gn.inv_w);
+    }
+    __syncthreads();
+    const int nv_next = min(view_chunk, n_views - v0 - view_chunk);
+    if (nv_next > 0) {
+      cp.load(sr + size_t(v0 + view_chunk) * view_stride, view_stride, nv_next);
+      if (int(threadIdx.x) < nv_next) gn = geom[v0 + view_chunk + threadIdx.x];
+    }
+    int base = kStagePad;
+    for (int vl = 0; vl < nv; ++vl, base += ldp) {
+      const double cs = g_cs[vl], sn = g_sn[vl];
+      const float inv_w = g_iw[vl];
+#pragma unroll
+      for (int e = 0; e < VPT; ++e) {
+        const double u = fma(xi[e], cs, fma(yj[e], sn, h));  // detector position of the voxel centre
+        const double fl = floor(u);
+        const int c0 = min(max(int(fl), -kStagePad), n + kStagePad - 2);
+        float a0[K], a1[K];
+        planar_taps<K>(planes + (base + c0), a0, a1);
+        const float f = float(u - fl);                      // |d| of tap c0; tap c0+1 has |d| = 1 - f
+        const float w0 = fmaxf(0.0f, 1.0f - f * inv_w) * inv_w;
+        const float w1 = fmaxf(0.0f, 1.0f - (1.0f - f) * inv_w) * inv_w;
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[e][q] = fmaf(w1, a1[q], fmaf(w0, a0[q], acc[e][q]));
+      }
+    }
+    nv = nv_next;
+  }
+  float res[VPT][K];
+  bool ok[VPT];
+#pragma unroll
+  for (int e = 0; e < VPT; ++e) {
+    ok[e] = vox[e] >= 0;
+#pragma unroll
+    for (int q = 0; q < K; ++q) res[e][q] = 0.0f;
+    if (ok[e]) {
+      float *out = x + (size_t(r) * n * n + size_t(vox[e])) * K;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        res[e][q] = (beta == 0.0f) ? alpha * acc[e][q] : fmaf(alpha, acc[e][q], beta * out[q]);
+        out[q] = res[e][q];
+      }
+    }
+  }
+  if (sumsq) block_sumsq_n<K, VPT>(res, ok, sumsq, size_t(r) * n_blk + bs.rest);
 }
 
 constexpr int kTile = 32;
@@ -391,9 +754,20 @@ hsn_status check_geom(hsn_ctx *ctx, const hsn_geom *g) {
 }
 
 // Per-view constants in float64 on the host; uploaded only when they change.
-hsn_status upload_geom(hsn_ctx *ctx, const hsn_geom *g, hipStream_t st, const ViewGeom **out) {
+// Views of one orientation in groups of kViewGroup for the LDS projector:
+// flat views (|cos| >= |sin|) in order, then steep ones; -1 pads a group.
+struct GeomTab {
+  const ViewGeom *views;
+  const double *groups;  // [n_groups][kViewGroup] view index (as double), -1 = none
+  int n_groups;
+};
+
+// Per-view constants in float64 on the host, and the view groups; uploaded
+// only when they change.
+hsn_status upload_geom(hsn_ctx *ctx, const hsn_geom *g, hipStream_t st, GeomTab *out) {
   const int nv = int(g->n_views);
   std::vector<double> tab(size_t(nv) * 4);
+  std::vector<int> flat, steep;
   for (int v = 0; v < nv; ++v) {
     const double t = g->angles ? g->angles[v] : double(v) * M_PI / double(nv);
     const double cs = std::cos(t), sn = std::sin(t);
@@ -402,7 +776,15 @@ hsn_status upload_geom(hsn_ctx *ctx, const hsn_geom *g, hipStream_t st, const Vi
     tab[4 * v + 1] = sn;
     tab[4 * v + 2] = w;
     tab[4 * v + 3] = 1.0 / w;
+    (std::fabs(sn) > std::fabs(cs) ? steep : flat).push_back(v);
   }
+  int n_groups = 0;
+  for (const auto *list : {&flat, &steep})
+    for (size_t a = 0; a < list->size(); a += kViewGroup) {
+      for (int e = 0; e < kViewGroup; ++e)
+        tab.push_back(a + e < list->size() ? double((*list)[a + e]) : -1.0);
+      ++n_groups;
+    }
   if (tab != ctx->geom_host) {
     if (ctx->geom_cap < tab.size()) {
       if (ctx->geom) {
@@ -423,7 +805,9 @@ hsn_status upload_geom(hsn_ctx *ctx, const hsn_geom *g, hipStream_t st, const Vi
     HSN_HIP(ctx, hipMemcpy(ctx->geom, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
     ctx->geom_host = tab;
   }
-  *out = reinterpret_cast<const ViewGeom *>(ctx->geom);
+  out->views = reinterpret_cast<const ViewGeom *>(ctx->geom);
+  out->groups = ctx->geom + size_t(nv) * 4;
+  out->n_groups = n_groups;
   return HSN_OK;
 }
 
@@ -435,26 +819,164 @@ unsigned project_grid(const hsn_geom *g) {
 unsigned backproject_grid(const hsn_geom *g) {
   return slot_grid(g->n_slices, g->n_cols * ((g->n_cols + kVoxThreads - 1) / kVoxThreads));
 }
-size_t project_partials(const hsn_geom *g) {
-  return size_t(g->n_slices) * g->n_views * ((g->n_cols + kRayThreads - 1) / kRayThreads);
+
+// Launch shape of one projector application: the LDS-staged kernel or,
+// where a staged row does not fit or the caller asked for it, the gather
+// kernel.
+struct ProjLaunch {
+  bool lds = false;
+  int vb = 0, split = 0;    // A: views per block, copies of the ray set per block
+  int vpt = 0;              // A^T: voxels per thread
+  int threads = 0;
+  int rows = 0;             // A: image rows per band; A^T: views per chunk
+  unsigned grid = 0;
+  size_t partials = 0;      // sum-of-squares partials (one per real block)
+  size_t lds_bytes = 0;
+};
+
+int round64(int64_t v) { return int((v + 63) / 64 * 64); }
+int64_t staged_ldp(const hsn_geom *g) { return g->n_cols + 2 * kStagePad; }
+int64_t plane_of(int k) {
+  switch (k) {
+    case 1: return lds_plane<1>();
+    case 2: return lds_plane<2>();
+    case 3: return lds_plane<3>();
+    case 4: return lds_plane<4>();
+    case 5: return lds_plane<5>();
+    case 6: return lds_plane<6>();
+    case 7: return lds_plane<7>();
+    default: return lds_plane<8>();
+  }
 }
-size_t backproject_partials(const hsn_geom *g) {
-  return size_t(g->n_slices) * g->n_cols * ((g->n_cols + kVoxThreads - 1) / kVoxThreads);
+
+ProjLaunch plan_project(const hsn_ctx *ctx, const hsn_geom *g, int n_groups) {
+  ProjLaunch L;
+  const int64_t n = g->n_cols, K = g->k, ldp = staged_ldp(g), LP = plane_of(g->k);
+  if (ctx->proj_views < 0 || ldp > LP || n > kLdsMaxThreads) {
+    L.threads = kRayThreads;
+    L.grid = project_grid(g);
+    L.partials = size_t(g->n_slices) * g->n_views * ((n + kRayThreads - 1) / kRayThreads);
+    return L;
+  }
+  auto blocks = [&](int vb) { return int64_t(g->n_slices) * n_groups * (kViewGroup / vb); };
+  int vb = ctx->proj_views;
+  if (vb > 0) {
+    while (vb > 1 && int64_t(vb) * n > kLdsMaxThreads) vb /= 2;
+  } else {
+    // Most views per block (least staging) that still gives every CU a block.
+    vb = 1;
+    for (int c : {4, 2}) {
+      if (int64_t(c) * n <= kLdsMaxThreads && blocks(c) >= int64_t(ctx->num_cu)) {
+        vb = c;
+        break;
+      }
+    }
+  }
+  const int t1 = round64(int64_t(vb) * n);
+  int split = ctx->proj_split;
+  if (split <= 0) {
+    // Copies of the ray set up to 1024 threads per block.
+    split = 1;
+    while (2 * split * t1 <= kLdsMaxThreads) split *= 2;
+  }
+  while (split > 1 && split * t1 > kLdsMaxThreads) split /= 2;
+  const int nt = split * t1;
+  const int64_t band = std::max<int64_t>(1, std::min<int64_t>({n, LP / ldp, int64_t(kCopyFloats) * nt / (n * K)}));
+  L.lds = true;
+  L.vb = vb;
+  L.split = split;
+  L.threads = nt;
+  L.rows = int(band);
+  L.grid = slot_grid(g->n_slices, int64_t(n_groups) * (kViewGroup / vb));
+  L.partials = size_t(blocks(vb));
+  L.lds_bytes = sizeof(float) * size_t(std::max<int64_t>((K - 1) * LP + band * ldp, split > 1 ? int64_t(nt) * K : 0));
+  return L;
+}
+
+ProjLaunch plan_backproject(const hsn_ctx *ctx, const hsn_geom *g) {
+  ProjLaunch L;
+  const int64_t n = g->n_cols, K = g->k, ldp = staged_ldp(g), LP = plane_of(g->k);
+  if (ctx->proj_voxels < 0 || ldp > LP || n * K > int64_t(kCopyFloats) * kLdsMaxThreads) {
+    L.threads = kVoxThreads;
+    L.grid = backproject_grid(g);
+    L.partials = size_t(g->n_slices) * n * ((n + kVoxThreads - 1) / kVoxThreads);
+    return L;
+  }
+  int nt = ctx->proj_threads > 0 ? ctx->proj_threads : kLdsMaxThreads;
+  nt = std::max<int>({64, round64((n * K + kCopyFloats - 1) / kCopyFloats), std::min<int>(nt, round64(n * n))});
+  nt = std::min(nt, kLdsMaxThreads);
+  auto per_slice = [&](int vpt) { return (n * n + int64_t(vpt) * nt - 1) / (int64_t(vpt) * nt); };
+  int vpt = ctx->proj_voxels;
+  if (vpt <= 0) {
+    // Most voxels per thread (fewest sinogram stagings) that still give
+    // every CU a block.
+    vpt = 1;
+    for (int c : {4, 2}) {
+      if (int64_t(g->n_slices) * per_slice(c) >= int64_t(ctx->num_cu)) {
+        vpt = c;
+        break;
+      }
+    }
+  }
+  const int64_t vc = std::max<int64_t>(
+      1, std::min<int64_t>({int64_t(g->n_views), LP / ldp, int64_t(kMaxViewChunk), int64_t(nt),
+                            int64_t(kCopyFloats) * nt / (n * K)}));
+  L.lds = true;
+  L.vpt = vpt;
+  L.threads = nt;
+  L.rows = int(vc);
+  L.grid = slot_grid(g->n_slices, per_slice(vpt));
+  L.partials = size_t(g->n_slices) * per_slice(vpt);
+  L.lds_bytes = size_t(geom_stage_bytes(int(vc))) + sizeof(float) * size_t((K - 1) * LP + vc * ldp);
+  return L;
+}
+
+bool aligned16(const void *p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
+
+template <int K>
+void launch_project(const ProjLaunch &L, const float *x, const float *xT, float *s, const GeomTab &gt,
+                    const hsn_geom *g, float alpha, float beta, double *sumsq, hipStream_t st) {
+  const int n = int(g->n_cols);
+  if (!L.lds) {
+    project_kernel<K><<<L.grid, kRayThreads, 0, st>>>(x, xT, s, gt.views, int(g->n_slices), int(g->n_views), n,
+                                                      alpha, beta, sumsq);
+    return;
+  }
+  const bool vec4 = (n * K) % 4 == 0 && aligned16(x) && (!xT || aligned16(xT));
+  if (vec4)
+    project_lds_kernel<K, true><<<L.grid, L.threads, L.lds_bytes, st>>>(
+        x, xT, s, gt.views, gt.groups, gt.n_groups, L.vb, L.split, int(g->n_slices), n, L.rows, alpha, beta, sumsq);
+  else
+    project_lds_kernel<K, false><<<L.grid, L.threads, L.lds_bytes, st>>>(
+        x, xT, s, gt.views, gt.groups, gt.n_groups, L.vb, L.split, int(g->n_slices), n, L.rows, alpha, beta, sumsq);
+}
+
+template <int K, int VPT>
+void launch_backproject_lds(const ProjLaunch &L, const float *s, float *x, const GeomTab &gt, const hsn_geom *g,
+                            float alpha, float beta, double *sumsq, hipStream_t st) {
+  const int n = int(g->n_cols);
+  const bool vec4 = (n * K) % 4 == 0 && aligned16(s);
+  if (vec4)
+    backproject_lds_kernel<K, VPT, true><<<L.grid, L.threads, L.lds_bytes, st>>>(
+        s, x, gt.views, int(g->n_views), int(g->n_slices), n, L.rows, alpha, beta, sumsq);
+  else
+    backproject_lds_kernel<K, VPT, false><<<L.grid, L.threads, L.lds_bytes, st>>>(
+        s, x, gt.views, int(g->n_views), int(g->n_slices), n, L.rows, alpha, beta, sumsq);
 }
 
 template <int K>
-void launch_project(const float *x, const float *xT, float *s, const ViewGeom *geom, const hsn_geom *g, float alpha,
-                    float beta, double *sumsq, hipStream_t st) {
-  project_kernel<K><<<project_grid(g), kRayThreads, 0, st>>>(x, xT, s, geom, int(g->n_slices), int(g->n_views),
-                                                             int(g->n_cols), alpha, beta, sumsq);
-}
-
-template <int K>
-void launch_backproject(const float *s, float *x, const ViewGeom *geom, const hsn_geom *g, float alpha, float beta,
-                        double *sumsq, hipStream_t st) {
-  backproject_kernel<K><<<backproject_grid(g), kVoxThreads, 0, st>>>(s, x, geom, int(g->n_views),
-                                                                     int(g->n_slices), int(g->n_cols), alpha, beta,
-                                                                     sumsq);
+void launch_backproject(const ProjLaunch &L, const float *s, float *x, const GeomTab &gt, const hsn_geom *g,
+                        float alpha, float beta, double *sumsq, hipStream_t st) {
+  if (!L.lds) {
+    backproject_kernel<K><<<L.grid, kVoxThreads, 0, st>>>(s, x, gt.views, int(g->n_views), int(g->n_slices),
+                                                          int(g->n_cols), alpha, beta, sumsq);
+    return;
+  }
+  switch (L.vpt) {
+    case 1: launch_backproject_lds<K, 1>(L, s, x, gt, g, alpha, beta, sumsq, st); break;
+    case 2: launch_backproject_lds<K, 2>(L, s, x, gt, g, alpha, beta, sumsq, st); break;
+    default: launch_backproject_lds<K, 4>(L, s, x, gt, g, alpha, beta, sumsq, st); break;
+  }
 }
 
 // mode 0: pT = p^T; mode 1: p = sv + coef p, pT = p^T; mode 2: p = sv, pT = p^T.
@@ -463,6 +985,17 @@ void launch_xpby_t(float *p, float *pT, const float *sv, const double *coef, con
                    hipStream_t st) {
   const unsigned t = unsigned((g->n_cols + kTile - 1) / kTile);
   xpby_transpose_kernel<K><<<dim3(t, t, unsigned(g->n_slices)), 256, 0, st>>>(p, pT, sv, coef, int(g->n_cols), mode);
+}
+
+// Number of view groups upload_geom forms for g.
+int count_groups(const hsn_geom *g) {
+  const int nv = int(g->n_views);
+  int steep = 0;
+  for (int v = 0; v < nv; ++v) {
+    const double t = g->angles ? g->angles[v] : double(v) * M_PI / double(nv);
+    steep += std::fabs(std::sin(t)) > std::fabs(std::cos(t));
+  }
+  return (nv - steep + kViewGroup - 1) / kViewGroup + (steep + kViewGroup - 1) / kViewGroup;
 }
 
 bool has_steep_view(const hsn_geom *g) {
@@ -509,7 +1042,7 @@ extern "C" hsn_status hsn_project(hsn_ctx *ctx, const hsn_geom *g, const float *
   if ((rc = check_align(ctx, x, g->k, "x")) != HSN_OK || (rc = check_align(ctx, s, g->k, "s")) != HSN_OK) return rc;
   hsn::DeviceGuard dg(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const ViewGeom *geom = nullptr;
+  GeomTab gt{};
   // Steep views read a transposed copy of x (workspace).
   float *xT = nullptr;
   if (has_steep_view(g)) {
@@ -517,10 +1050,11 @@ extern "C" hsn_status hsn_project(hsn_ctx *ctx, const hsn_geom *g, const float *
     if ((rc = hsn::ensure_ws(ctx, sizeof(float) * nxk)) != HSN_OK) return rc;
     xT = static_cast<float *>(ctx->ws);
   }
-  if ((rc = upload_geom(ctx, g, st, &geom)) != HSN_OK) return rc;
+  if ((rc = upload_geom(ctx, g, st, &gt)) != HSN_OK) return rc;
+  const ProjLaunch L = plan_project(ctx, g, gt.n_groups);
   if (xT) HSN_DISPATCH_K(g->k, launch_xpby_t, const_cast<float *>(x), xT, nullptr, nullptr, g, 0, st);
   hsn::prof_begin(ctx, HSN_KERN_PROJECT, st);
-  HSN_DISPATCH_K(g->k, launch_project, x, xT, s, geom, g, alpha, beta, nullptr, st);
+  HSN_DISPATCH_K(g->k, launch_project, L, x, xT, s, gt, g, alpha, beta, nullptr, st);
   hsn::prof_end(ctx, HSN_KERN_PROJECT, st);
   HSN_LAUNCHED(ctx);
   return HSN_OK;
@@ -535,10 +1069,11 @@ extern "C" hsn_status hsn_backproject(hsn_ctx *ctx, const hsn_geom *g, const flo
   if ((rc = check_align(ctx, x, g->k, "x")) != HSN_OK || (rc = check_align(ctx, s, g->k, "s")) != HSN_OK) return rc;
   hsn::DeviceGuard dg(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const ViewGeom *geom = nullptr;
-  if ((rc = upload_geom(ctx, g, st, &geom)) != HSN_OK) return rc;
+  GeomTab gt{};
+  if ((rc = upload_geom(ctx, g, st, &gt)) != HSN_OK) return rc;
+  const ProjLaunch L = plan_backproject(ctx, g);
   hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
-  HSN_DISPATCH_K(g->k, launch_backproject, s, x, geom, g, alpha, beta, nullptr, st);
+  HSN_DISPATCH_K(g->k, launch_backproject, L, s, x, gt, g, alpha, beta, nullptr, st);
   hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
   HSN_LAUNCHED(ctx);
   return HSN_OK;
@@ -562,14 +1097,17 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
   // The sums of squares of A p and A^T r come from the projector epilogues
   // (one partial per block); ||r|| for the optional residual history from
   // the dot kernel.
-  const size_t nb_proj = project_partials(g), nb_back = backproject_partials(g);
+  GeomTab gt{};
+  if ((rc = upload_geom(ctx, g, st, &gt)) != HSN_OK) return rc;
+  const ProjLaunch LA = plan_project(ctx, g, gt.n_groups), LB = plan_backproject(ctx, g);
+  const size_t nb_proj = LA.partials, nb_back = LB.partials;
+  if (nb_proj >= size_t(INT32_MAX) || nb_back >= size_t(INT32_MAX))
+    return hsn::fail(ctx, HSN_ERR_SHAPE, "cgls: geometry too large for one launch");
   const size_t n_part = std::max<size_t>({nb_proj, nb_back, size_t(kDotBlocks)});
   const size_t need = hsn::Carver::need({sizeof(float) * ns * K, sizeof(float) * ns * K, sizeof(float) * nx * K,
                                          sizeof(float) * nx * K, sizeof(float) * nx * K,
                                          sizeof(double) * n_part * K, sizeof(double) * 24});
   if ((rc = hsn::ensure_ws(ctx, need)) != HSN_OK) return rc;
-  const ViewGeom *geom = nullptr;
-  if ((rc = upload_geom(ctx, g, st, &geom)) != HSN_OK) return rc;
   hsn::Carver cv(ctx->ws);
   float *r = cv.take<float>(ns * K), *q = cv.take<float>(ns * K);
   float *sv = cv.take<float>(nx * K), *p = cv.take<float>(nx * K), *pT = cv.take<float>(nx * K);
@@ -580,7 +1118,7 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
   fill_zero_kernel<<<blocks(nx * K), eb, 0, st>>>(x, nx * K);
   HSN_HIP(ctx, hipMemcpyAsync(r, sino, sizeof(float) * ns * K, hipMemcpyDeviceToDevice, st));
   hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
-  HSN_DISPATCH_K(K, launch_backproject, r, sv, geom, g, 1.0f, 0.0f, partial, st);
+  HSN_DISPATCH_K(K, launch_backproject, LB, r, sv, gt, g, 1.0f, 0.0f, partial, st);
   hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
   cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_back), K, kSetGamma, scal, nullptr);
   HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, nullptr, g, 2, st);
@@ -590,12 +1128,12 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
   }
   for (int it = 0; it < n_iter; ++it) {
     hsn::prof_begin(ctx, HSN_KERN_PROJECT, st);
-    HSN_DISPATCH_K(K, launch_project, p, pT, q, geom, g, 1.0f, 0.0f, partial, st);
+    HSN_DISPATCH_K(K, launch_project, LA, p, pT, q, gt, g, 1.0f, 0.0f, partial, st);
     hsn::prof_end(ctx, HSN_KERN_PROJECT, st);
     cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_proj), K, kAlpha, scal, nullptr);
     chan_axpy2_kernel<<<blocks(nx * K + ns * K), eb, 0, st>>>(x, p, nx * K, r, q, ns * K, scal + 8, K);
     hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
-    HSN_DISPATCH_K(K, launch_backproject, r, sv, geom, g, 1.0f, 0.0f, partial, st);
+    HSN_DISPATCH_K(K, launch_backproject, LB, r, sv, gt, g, 1.0f, 0.0f, partial, st);
     hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
     cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_back), K, kBeta, scal, nullptr);
     HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, scal + 16, g, 1, st);
@@ -605,5 +1143,36 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
     }
   }
   HSN_LAUNCHED(ctx);
+  return HSN_OK;
+}
+
+extern "C" hsn_status hsn_projector_set_launch(hsn_ctx *ctx, int views, int split, int voxels, int threads) {
+  if (!ctx) return HSN_ERR_INVALID_ARG;
+  if (!(views == -1 || views == 0 || views == 1 || views == 2 || views == 4))
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "projector launch: views must be -1, 0, 1, 2 or 4 (got %d)", views);
+  if (!(split == 0 || split == 1 || split == 2 || split == 4 || split == 8 || split == 16))
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "projector launch: split must be 0, 1, 2, 4, 8 or 16 (got %d)", split);
+  if (!(voxels == -1 || voxels == 0 || voxels == 1 || voxels == 2 || voxels == 4))
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "projector launch: voxels must be -1, 0, 1, 2 or 4 (got %d)", voxels);
+  if (!(threads == 0 || threads == 64 || threads == 128 || threads == 256 || threads == 512 || threads == 1024))
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "projector launch: threads must be 0 or 64..1024, a power of 2 (got %d)",
+                     threads);
+  ctx->proj_views = views;
+  ctx->proj_split = split;
+  ctx->proj_voxels = voxels;
+  ctx->proj_threads = threads;
+  return HSN_OK;
+}
+
+extern "C" hsn_status hsn_projector_launch_info(hsn_ctx *ctx, const hsn_geom *g, int *shape) {
+  if (!ctx) return HSN_ERR_INVALID_ARG;
+  hsn_status rc = check_geom(ctx, g);
+  if (rc != HSN_OK) return rc;
+  if (!shape) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "projector launch info: shape is NULL");
+  const ProjLaunch LA = plan_project(ctx, g, count_groups(g)), LB = plan_backproject(ctx, g);
+  shape[0] = LA.lds ? LA.vb : 0;
+  shape[1] = LA.lds ? LA.split : 0;
+  shape[2] = LB.lds ? LB.vpt : 0;
+  shape[3] = LB.lds ? LB.threads : 0;
   return HSN_OK;
 }

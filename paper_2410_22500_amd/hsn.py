@@ -94,6 +94,10 @@ _lib.hsn_backproject.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_float, C.c_flo
 _lib.hsn_backproject.restype = C.c_int
 _lib.hsn_cgls.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_int, _P, _P]
 _lib.hsn_cgls.restype = C.c_int
+_lib.hsn_projector_set_launch.argtypes = [_P, C.c_int, C.c_int, C.c_int, C.c_int]
+_lib.hsn_projector_set_launch.restype = C.c_int
+_lib.hsn_projector_launch_info.argtypes = [_P, C.POINTER(Geom), C.POINTER(C.c_int)]
+_lib.hsn_projector_launch_info.restype = C.c_int
 _lib.hsn_rehydrate.argtypes = [_P, _P, _P, C.c_int64, C.c_int64, C.c_int, C.c_int64, C.c_int64, C.c_int64,
                                C.c_int64, _P, C.c_int64, _P]
 _lib.hsn_rehydrate.restype = C.c_int
@@ -284,6 +288,24 @@ def hsn_backproject(s: torch.Tensor, angles: Optional[Sequence[float]] = None, a
         out = torch.empty((n_r, n, n, k), dtype=torch.float32, device=s.device)
     _check(_lib.hsn_backproject(ctx, C.byref(g), _ptr(s), _ptr(out), alpha, beta, _stream(dev)), ctx)
     return out
+
+
+def hsn_projector_set_launch(views: int = 0, split: int = 0, voxels: int = 0, threads: int = 0,
+                             device: int = 0) -> None:
+    """Projector launch shape (A: views per block, ray-set copies per block; A^T: voxels per
+    thread, threads per block); 0 = automatic, views / voxels -1 = gather kernels."""
+    ctx = context(device)
+    _check(_lib.hsn_projector_set_launch(ctx, int(views), int(split), int(voxels), int(threads)), ctx)
+
+
+def hsn_projector_launch_info(n_views: int, n_slices: int, n: int, k: int,
+                              angles: Optional[Sequence[float]] = None, device: int = 0):
+    """(views, split, voxels, threads) the projector would use; 0 = gather kernel."""
+    ctx = context(device)
+    g, keep = _geom(n_views, n_slices, n, k, angles)
+    out = (C.c_int * 4)()
+    _check(_lib.hsn_projector_launch_info(ctx, C.byref(g), out), ctx)
+    return tuple(out)
 
 
 def hsn_cgls(sino: torch.Tensor, n_iter: int, angles: Optional[Sequence[float]] = None, resid: bool = False):

@@ -121,6 +121,102 @@ def test_projector_mid_config_shape(hsn):
     assert rel_fro(xb, oprj.backproject(y, 128)) <= 1e-5
 
 
+# Geometries for the launch-shape checks: n * k not a multiple of 4 (scalar
+# staging), n not a multiple of 64, view groups padded at both
+# orientations, custom angles mixing flat and steep views, one slice.
+_SHAPES = [(37, 11, 3, 3, None), (64, 60, 4, 9, None), (50, 13, 5, 2, None),
+           (24, 6, 8, 1, [0.0, 0.3, 1.2, 1.9, 2.6, 3.0]), (128, 9, 1, 8, None), (19, 5, 7, 2, None)]
+
+
+@pytest.mark.parametrize("n,n_views,k,n_r,angles", _SHAPES)
+def test_projector_launch_shapes_bitwise(hsn, n, n_views, k, n_r, angles):
+    # The LDS-staged kernels evaluate every ray and voxel with the arithmetic
+    # of the gather kernels; a tap outside the image reads a staged zero
+    # where the gather kernel applies weight 0.  With one copy of the ray set
+    # per block (split 1) every launch shape must give the same float32
+    # values bit for bit; more copies only reorder the sum along each ray.
+    import torch
+    g = np.random.Generator(np.random.PCG64(n * 31 + k))
+    th = None if angles is None else np.array(angles)
+    x = to_dev(g.standard_normal((n_r, n, n, k)), torch.float32)
+    y = to_dev(g.standard_normal((n_views, n_r, n, k)), torch.float32)
+    try:
+        hsn.hsn_projector_set_launch(-1, 0, -1, 0)
+        assert hsn.hsn_projector_launch_info(n_views, n_r, n, k, angles=th) == (0, 0, 0, 0)
+        s_ref = hsn.hsn_project(x, n_views, angles=th).cpu().numpy()
+        x_ref = hsn.hsn_backproject(y, angles=th).cpu().numpy()
+        assert rel_fro(s_ref, oprj.project(x.cpu().numpy().astype(np.float64), n_views, thetas=th)) <= 1e-5
+        assert rel_fro(x_ref, oprj.backproject(y.cpu().numpy().astype(np.float64), n, thetas=th)) <= 1e-5
+        for vb in (1, 2, 4):
+            for split in (1, 2, 4, 16):
+                hsn.hsn_projector_set_launch(vb, split, -1, 0)
+                info = hsn.hsn_projector_launch_info(n_views, n_r, n, k, angles=th)
+                show("project lds", n=n, n_views=n_views, k=k, n_r=n_r, shape=info)
+                assert info[0] == vb and info[1] <= split
+                s = hsn.hsn_project(x, n_views, angles=th).cpu().numpy()
+                if info[1] == 1:
+                    np.testing.assert_array_equal(s, s_ref)
+                else:
+                    assert rel_fro(s, s_ref) <= 1e-6
+        for vpt in (1, 2, 4):
+            for nt in (64, 256, 1024):
+                hsn.hsn_projector_set_launch(-1, 0, vpt, nt)
+                info = hsn.hsn_projector_launch_info(n_views, n_r, n, k, angles=th)
+                show("backproject lds", n=n, n_views=n_views, k=k, n_r=n_r, shape=info)
+                assert info[2] == vpt
+                xb = hsn.hsn_backproject(y, angles=th).cpu().numpy()
+                np.testing.assert_array_equal(xb, x_ref)
+    finally:
+        hsn.hsn_projector_set_launch(0, 0, 0, 0)
+
+
+def test_projector_launch_knob_errors_and_auto(hsn):
+    for bad in ((3, 0, 0, 0), (0, 3, 0, 0), (0, 0, 3, 0), (0, 0, 0, 100), (-2, 0, 0, 0)):
+        with pytest.raises(hsn.HsnError):
+            hsn.hsn_projector_set_launch(*bad)
+    # defaults: LDS-staged kernels at the benchmark shapes
+    for geo in ((60, 16, 128, 4), (120, 256, 256, 5)):
+        va, sp, vx, nt = hsn.hsn_projector_launch_info(*geo)
+        show("auto launch", geo=geo, shape=(va, sp, vx, nt))
+        assert va in (1, 2, 4) and sp >= 1 and vx in (1, 2, 4) and 64 <= nt <= 1024
+    # a staged row beyond the LDS budget: gather kernels
+    assert hsn.hsn_projector_launch_info(4, 1, 2048, 8) == (0, 0, 0, 0)
+
+
+def test_projector_full_config_slices(hsn):
+    # Two slices of the full reconstruction shape (256 x 256, 120 views,
+    # K = 5) through the default (LDS-staged) launch against the oracle.
+    import torch
+    g = np.random.Generator(np.random.PCG64(14))
+    x = g.uniform(0, 1, (2, 256, 256, 5))
+    show("projector full slices", shape=hsn.hsn_projector_launch_info(120, 2, 256, 5))
+    s = hsn.hsn_project(to_dev(x, torch.float32), 120).cpu().numpy()
+    assert rel_fro(s, oprj.project(x, 120)) <= 1e-5
+    y = g.standard_normal((120, 2, 256, 5))
+    xb = hsn.hsn_backproject(to_dev(y, torch.float32)).cpu().numpy()
+    assert rel_fro(xb, oprj.backproject(y, 256)) <= 1e-5
+
+
+def test_cgls_launch_shapes_agree(hsn):
+    # The fused sums of squares come from one partial per block, so launch
+    # shapes differ in summation order only: the iterates agree to float32
+    # rounding.
+    import torch
+    g = np.random.Generator(np.random.PCG64(15))
+    n, nv, k = 40, 24, 5
+    b = to_dev(g.standard_normal((nv, 3, n, k)), torch.float32)
+    try:
+        hsn.hsn_projector_set_launch(-1, 0, -1, 0)
+        x0 = hsn.hsn_cgls(b, 4).cpu().numpy()
+        for shape in ((1, 1, 1, 64), (2, 4, 2, 256), (4, 16, 4, 1024), (0, 0, 0, 0)):
+            hsn.hsn_projector_set_launch(*shape)
+            show("cgls launch", shape=shape)
+            x = hsn.hsn_cgls(b, 4).cpu().numpy()
+            assert rel_fro(x, x0) <= 1e-5
+    finally:
+        hsn.hsn_projector_set_launch(0, 0, 0, 0)
+
+
 def test_cgls_parity(hsn):
     # The operator applications are pinned to 1e-5 above.  The CGLS
     # recursion itself amplifies rounding: on this instance a 1e-10 relative
