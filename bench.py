@@ -263,8 +263,8 @@ def main():
                             args.steps * (2.0 * elems + 512.0 * n_p), "hbm"),
         hsn.KERN_MLP_ROWS: ("mlp_rows_kernel (network inference, bf16 MFMA)",
                             args.steps * mlp_flops_row * n_p, "mfma"),
-        hsn.KERN_PROJECT: ("project_kernel (A, Joseph footprint, K channels)", None, "alu"),
-        hsn.KERN_BACKPROJECT: ("backproject_kernel (A^T)", None, "alu"),
+        hsn.KERN_PROJECT: ("project_lds_kernel (A, Joseph footprint, K channels, LDS-staged)", None, "alu"),
+        hsn.KERN_BACKPROJECT: ("backproject_lds_kernel (A^T, LDS-staged)", None, "alu"),
     }
     # Float32 passes that did work: one N_D pass for D0 per step and two passes
     # per ANLS round; passes queued after the stop test fired return at once,

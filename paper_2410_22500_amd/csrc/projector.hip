@@ -194,6 +194,33 @@ __global__ __launch_bounds__(kRayThreads) void project_kernel(const float *__res
   if (sumsq) block_sumsq<K, kRayThreads>(res, c < n, sumsq, (size_t(v) * n_slices + r) * nx + cx);
 }
 
+// Detector position of voxel (i, j) in view g: u = x_i cos + y_j sin + h,
+// held as U = u 2^32 = a_i C + b_j S + (n - 1) 2^31 with the odd integers
+// a_i = 2i - n + 1, b_j = 2j - n + 1 (x_i = a_i / 2, y_j = b_j / 2) and
+// C = cos 2^31, S = sin 2^31 rounded to int32: integer arithmetic, exact
+// given C and S, whose rounding moves u by at most n 2^-33 px.  Tap
+// c0 = floor(u) = U >> 32 at |d| = f = (U mod 2^32) 2^-32, tap c0 + 1 at
+// 1 - f; footprint weights max(0, 1 - |d|/w)/w with 1/w = iw:
+//   w0 = max(0, iw - f iw^2),  w1 = max(0, iw - iw^2 + f iw^2).
+struct VoxView {
+  int C, S;
+  float iw2, c1, iw;  // iw^2 2^-32, iw - iw^2, iw
+};
+__device__ __forceinline__ VoxView vox_view(const ViewGeom &g) {
+  VoxView vv;
+  vv.C = __double2int_rn(fmin(fmax(g.cs * 2147483648.0, -2147483647.0), 2147483647.0));
+  vv.S = __double2int_rn(fmin(fmax(g.sn * 2147483648.0, -2147483647.0), 2147483647.0));
+  vv.iw = float(g.inv_w);
+  vv.iw2 = (vv.iw * vv.iw) * 2.3283064365386963e-10f;  // exact scaling by 2^-32
+  vv.c1 = vv.iw - vv.iw * vv.iw;
+  return vv;
+}
+__device__ __forceinline__ void vox_weights(uint32_t lo, float iw, float iw2, float c1, float &w0, float &w1) {
+  const float lf = float(lo);
+  w0 = fmaxf(0.0f, fmaf(-lf, iw2, iw));
+  w1 = fmaxf(0.0f, fmaf(lf, iw2, c1));
+}
+
 constexpr int kVoxThreads = 128;
 
 // x[r][j][i][:] = alpha * sum_v sum_taps a * s[v][r][c][:] + beta * x[r][j][i][:]
@@ -212,8 +239,8 @@ __global__ __launch_bounds__(kVoxThreads) void backproject_kernel(const float *_
   const int r = bs.slice;
   const int i = cx * kVoxThreads + threadIdx.x;
   const bool ok = i < n;
-  const double h = 0.5 * double(n - 1);
-  const double xi = double(ok ? i : 0) - h, yj = double(j) - h;
+  const int a = 2 * (ok ? i : 0) - n + 1, b = 2 * j - n + 1;
+  const int64_t H = int64_t(n - 1) << 31;
   float acc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0.0f;
@@ -221,14 +248,13 @@ __global__ __launch_bounds__(kVoxThreads) void backproject_kernel(const float *_
   const float *sr = s + size_t(r) * n * K;
 #pragma unroll 4
   for (int v = 0; v < n_views; ++v) {
-    const ViewGeom g = geom[v];
-    const double u = fma(xi, g.cs, fma(yj, g.sn, h));   // detector position of the voxel centre
-    const double fl = floor(u);
-    const int c0 = int(fl);
-    const float f = float(u - fl);                      // |d| of tap c0; tap c0+1 has |d| = 1 - f
-    const float inv_w = float(g.inv_w);
-    const float w0 = (c0 >= 0 && c0 < n) ? fmaxf(0.0f, 1.0f - f * inv_w) * inv_w : 0.0f;
-    const float w1 = (c0 + 1 >= 0 && c0 + 1 < n) ? fmaxf(0.0f, 1.0f - (1.0f - f) * inv_w) * inv_w : 0.0f;
+    const VoxView vv = vox_view(geom[v]);
+    const int64_t U = int64_t(a) * vv.C + (int64_t(b) * vv.S + H);
+    const int c0 = int(U >> 32);
+    float w0, w1;
+    vox_weights(uint32_t(U), vv.iw, vv.iw2, vv.c1, w0, w1);
+    w0 = (c0 >= 0 && c0 < n) ? w0 : 0.0f;
+    w1 = (c0 + 1 >= 0 && c0 + 1 < n) ? w1 : 0.0f;
     const int k0 = min(max(c0, 0), n - 1), k1 = min(max(c0 + 1, 0), n - 1);
     const float *sv = sr + size_t(v) * view_stride;
     float p0[K], p1[K];
@@ -486,43 +512,47 @@ __global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
   if (sumsq) block_sumsq_n<K, 1>(res, ok, sumsq, part);
 }
 
-// Bytes of per-view geometry staged by backproject_lds_kernel ahead of the
-// channel planes (cos, sin as float64, 1/w as float32), 16-byte aligned.
-__host__ __device__ inline int geom_stage_bytes(int views) { return (views * 20 + 15) / 16 * 16; }
-constexpr int kMaxViewChunk = 96;
+// Per-view geometry staged by backproject_lds_kernel ahead of the channel
+// planes: C, S (int32), the step D = (b_{j + dj} - b_j) S between a
+// thread's voxels (int64), iw^2 2^-32, iw - iw^2 and iw (float32).
+struct StagedView {
+  int64_t D;
+  int C, S;
+  float iw2, c1, iw, pad;
+};
+__host__ __device__ inline int geom_stage_bytes(int views) { return views * int(sizeof(StagedView)); }
+constexpr int kMaxViewChunk = 64;
 
 // A^T: one block = one slice and VPT * blockDim.x consecutive voxels of it
 // (row-major j, i); voxel w of the block is taken by thread w % blockDim.x.
-// The slice's sinogram rows pass through LDS in chunks of view_chunk views,
-// with the chunk's geometry.
+// With VPT > 1, blockDim.x is a multiple of n, so a thread's voxels share
+// the column i and lie blockDim.x / n rows apart: their positions differ by
+// the integer step D.  The slice's sinogram rows pass through LDS in chunks
+// of view_chunk views, with the chunk's geometry.
 template <int K, int VPT, bool VEC>
 __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
     const float *__restrict__ s, float *__restrict__ x, const ViewGeom *__restrict__ geom, int n_views,
     int n_slices, int n, int view_chunk, float alpha, float beta, double *__restrict__ sumsq) {
   extern __shared__ __align__(16) float stage[];
-  constexpr int LP = lds_plane<K>();
   const int nt = blockDim.x;
   const int per_block = VPT * nt;
   const int n_blk = (n * n + per_block - 1) / per_block;
   const BlockSlot bs = block_slot(blockIdx.x, n_slices, n_blk);
   if (bs.slice >= n_slices) return;
   const int r = bs.slice;
-  double *g_cs = reinterpret_cast<double *>(stage);
-  double *g_sn = g_cs + view_chunk;
-  float *g_iw = reinterpret_cast<float *>(g_sn + view_chunk);
+  StagedView *gv = reinterpret_cast<StagedView *>(stage);
   float *planes = stage + geom_stage_bytes(view_chunk) / 4;
   const int ldp = n + 2 * kStagePad;
-  const double h = 0.5 * double(n - 1);
+  const int64_t H = int64_t(n - 1) << 31;
+  const int db = 2 * (nt / n);  // b_j step between a thread's voxels (VPT > 1)
   int vox[VPT];
-  double xi[VPT], yj[VPT];
+  const int w0i = bs.rest * per_block + int(threadIdx.x);
+  const int j0 = w0i / n, i0 = w0i - j0 * n;
+  const int a = 2 * i0 - n + 1, b0 = 2 * j0 - n + 1;
 #pragma unroll
   for (int e = 0; e < VPT; ++e) {
-    const int w = bs.rest * per_block + e * nt + int(threadIdx.x);
+    const int w = w0i + e * nt;
     vox[e] = w < n * n ? w : -1;
-    const int j = w < n * n ? w / n : 0;
-    const int i = w < n * n ? w - j * n : 0;
-    xi[e] = double(i) - h;
-    yj[e] = double(j) - h;
   }
   zero_pads<K>(planes, ldp, n, view_chunk);
   float acc[VPT][K];
@@ -542,9 +572,16 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
     __syncthreads();  // the previous chunk is no longer read
     cp.store(planes, nv);
     if (int(threadIdx.x) < nv) {
-      g_cs[threadIdx.x] = gn.cs;
-      g_sn[threadIdx.x] = gn.sn;
-      g_iw[threadIdx.x] = float(gn.inv_w);
+      const VoxView vv = vox_view(gn);
+      StagedView sv;
+      sv.C = vv.C;
+      sv.S = vv.S;
+      sv.D = int64_t(db) * vv.S;
+      sv.iw2 = vv.iw2;
+      sv.c1 = vv.c1;
+      sv.iw = vv.iw;
+      sv.pad = 0.0f;
+      gv[threadIdx.x] = sv;
     }
     __syncthreads();
     const int nv_next = min(view_chunk, n_views - v0 - view_chunk);
@@ -554,18 +591,15 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
     }
     int base = kStagePad;
     for (int vl = 0; vl < nv; ++vl, base += ldp) {
-      const double cs = g_cs[vl], sn = g_sn[vl];
-      const float inv_w = g_iw[vl];
+      const StagedView sv = gv[vl];
+      int64_t U = int64_t(a) * sv.C + (int64_t(b0) * sv.S + H);
 #pragma unroll
-      for (int e = 0; e < VPT; ++e) {
-        const double u = fma(xi[e], cs, fma(yj[e], sn, h));  // detector position of the voxel centre
-        const double fl = floor(u);
-        const int c0 = min(max(int(fl), -kStagePad), n + kStagePad - 2);
+      for (int e = 0; e < VPT; ++e, U += sv.D) {
+        const int c0 = min(max(int(U >> 32), -kStagePad), n + kStagePad - 2);
         float a0[K], a1[K];
         planar_taps<K>(planes + (base + c0), a0, a1);
-        const float f = float(u - fl);                      // |d| of tap c0; tap c0+1 has |d| = 1 - f
-        const float w0 = fmaxf(0.0f, 1.0f - f * inv_w) * inv_w;
-        const float w1 = fmaxf(0.0f, 1.0f - (1.0f - f) * inv_w) * inv_w;
+        float w0, w1;
+        vox_weights(uint32_t(U), sv.iw, sv.iw2, sv.c1, w0, w1);
 #pragma unroll
         for (int q = 0; q < K; ++q) acc[e][q] = fmaf(w1, a1[q], fmaf(w0, a0[q], acc[e][q]));
       }
@@ -593,20 +627,76 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
 
 constexpr int kTile = 32;
 
+// tot[q] = sum over b < nblk of partial[b][q], q < K, by a block of 256
+// threads in a fixed order, so that every block that calls it gets the same
+// bits.  tot is visible to the whole block on return.
+__device__ __forceinline__ void sum_partials(const double *__restrict__ partial, int nblk, int K,
+                                             double *__restrict__ tot) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  const int G = 256 / K;
+  if (t < G * K) {
+    const int q = t % K, g = t / K;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = g;
+    for (; b + 3 * G < nblk; b += 4 * G) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = partial[size_t(b + u * G) * K + q];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] += v[u];
+    }
+    for (int u = 0; b < nblk; b += G, ++u) a[u & 3] += partial[size_t(b) * K + q];
+    red[t] = (a[0] + a[1]) + (a[2] + a[3]);
+  }
+  __syncthreads();
+  if (t < K) {
+    double sum = 0.0;
+    for (int g = 0; g < G; ++g) sum += red[g * K + t];
+    tot[t] = sum;
+  }
+  __syncthreads();
+}
+
+// CGLS scalars on the device: gamma[2][8] (double-buffered ||A^T r||^2),
+// alpha[8], beta[8].
+constexpr int kScal = 32;
+enum { kGamma = 0, kAlphaOff = 16, kBetaOff = 24 };
+
 // Per slice: xT[r][i][j][:] = x[r][j][i][:] through a 32 x 32 LDS tile.
-// With coef (CGLS direction update), first p = sv + coef[q] * p is formed
-// and written back (coef == NULL: p = sv), then transposed into pT.
+// mode 0: pT = p^T.  mode 2: p = sv, pT = p^T.  mode 1: p = sv + coef[q] p,
+// pT = p^T.  mode 3 (CGLS step, one launch): beta = ||A^T r||^2 / gamma
+// from the A^T partial sums (gamma = st[gsel], the new value goes to
+// st[1 - gsel]), x += alpha p with the old p, then p = sv + beta p, pT = p^T.
 template <int K>
 __global__ __launch_bounds__(256) void xpby_transpose_kernel(float *__restrict__ p, float *__restrict__ pT,
                                                              const float *__restrict__ sv,
-                                                             const double *__restrict__ coef, int n, int mode) {
+                                                             const double *__restrict__ coef, int n, int mode,
+                                                             float *__restrict__ x, const double *__restrict__ partial,
+                                                             int nblk, double *__restrict__ st, int gsel) {
   __shared__ float tile[kTile][kTile + 1][K];
+  __shared__ double tot[8];
   const int r = blockIdx.z;
   const int j0 = blockIdx.y * kTile, i0 = blockIdx.x * kTile;
   const size_t base = size_t(r) * n * n * K;
-  float cf[K];
+  float cf[K], al[K];
+  if (mode == 3) {
+    sum_partials(partial, nblk, K, tot);
+    const double *gamma = st + kGamma + 8 * gsel;
 #pragma unroll
-  for (int q = 0; q < K; ++q) cf[q] = (mode == 1) ? float(coef[q]) : 0.0f;
+    for (int q = 0; q < K; ++q) {
+      cf[q] = float(gamma[q] > 0.0 ? tot[q] / gamma[q] : 0.0);
+      al[q] = float(st[kAlphaOff + q]);
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && int(threadIdx.x) < K)
+      st[kGamma + 8 * (1 - gsel) + threadIdx.x] = tot[threadIdx.x];
+  } else {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      cf[q] = (mode == 1) ? float(coef[q]) : 0.0f;
+      al[q] = 0.0f;
+    }
+  }
   for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
     const int jj = e / kTile, ii = e % kTile;
     const int j = j0 + jj, i = i0 + ii;
@@ -615,13 +705,19 @@ __global__ __launch_bounds__(256) void xpby_transpose_kernel(float *__restrict__
       float val[K];
       if (mode == 0) {  // plain transpose of p
         load_k<K>(p + o, val);
-      } else {          // p = sv + coef * p (mode 1), p = sv (mode 2)
+      } else {          // p = sv + coef * p (modes 1, 3), p = sv (mode 2)
         float a[K], b[K];
         load_k<K>(sv + o, a);
-        if (mode == 1) load_k<K>(p + o, b);
+        if (mode != 2) load_k<K>(p + o, b);
+        if (mode == 3) {
+          float xv[K];
+          load_k<K>(x + o, xv);
+#pragma unroll
+          for (int q = 0; q < K; ++q) x[o + q] = fmaf(al[q], b[q], xv[q]);
+        }
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-          val[q] = (mode == 1) ? fmaf(cf[q], b[q], a[q]) : a[q];
+          val[q] = (mode == 2) ? a[q] : fmaf(cf[q], b[q], a[q]);
           p[o + q] = val[q];
         }
       }
@@ -673,48 +769,28 @@ __global__ __launch_bounds__(kDotThreads) void chan_dot_kernel(const float *__re
   }
 }
 
-// st layout: gamma[8], alpha[8], beta[8]
+// One block of 256 threads, from partial sums tot[q] (see sum_partials):
+//   kSetGamma: gamma[gsel] = tot          kAlpha: alpha = gamma[gsel] / tot
+//   kBeta: beta = tot / gamma[gsel], gamma[1 - gsel] = tot
+//   kResid: out = sqrt(tot)
+// A zero denominator gives 0 (the iteration has converged).
 enum { kSetGamma = 0, kAlpha = 1, kBeta = 2, kResid = 3 };
 __global__ __launch_bounds__(256) void cgls_scalar_kernel(const double *__restrict__ partial, int nblk, int K,
-                                                          int mode, double *__restrict__ st,
+                                                          int mode, double *__restrict__ st, int gsel,
                                                           double *__restrict__ out) {
-  // 256 threads = K channels x groups; each group sums every G-th block partial.
-  __shared__ double red[256];
   __shared__ double tot[8];
-  const int t = threadIdx.x;
-  const int G = 256 / K;
-  if (t < G * K) {
-    const int q = t % K, g = t / K;
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    int b = g;
-    for (; b + 3 * G < nblk; b += 4 * G) {
-      double v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = partial[size_t(b + u * G) * K + q];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] += v[u];
-    }
-    for (int u = 0; b < nblk; b += G, ++u) a[u & 3] += partial[size_t(b) * K + q];
-    red[t] = (a[0] + a[1]) + (a[2] + a[3]);
-  }
-  __syncthreads();
-  if (t < K) {
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) s += red[g * K + t];
-    tot[t] = s;
-  }
-  __syncthreads();
-  const int q = t;
+  sum_partials(partial, nblk, K, tot);
+  const int q = threadIdx.x;
   if (q >= K) return;
   const double tq = tot[q];
-  double *gamma = st, *alpha = st + 8, *beta = st + 16;
+  double *gamma = st + kGamma + 8 * gsel, *gamma_next = st + kGamma + 8 * (1 - gsel);
   if (mode == kSetGamma) {
     gamma[q] = tq;
   } else if (mode == kAlpha) {
-    alpha[q] = (tq > 0.0) ? gamma[q] / tq : 0.0;
+    st[kAlphaOff + q] = (tq > 0.0) ? gamma[q] / tq : 0.0;
   } else if (mode == kBeta) {
-    beta[q] = (gamma[q] > 0.0) ? tq / gamma[q] : 0.0;
-    gamma[q] = tq;
+    st[kBetaOff + q] = (gamma[q] > 0.0) ? tq / gamma[q] : 0.0;
+    gamma_next[q] = tq;
   } else if (out) {
     out[q] = sqrt(tq);
   }
@@ -736,6 +812,29 @@ __global__ void chan_axpy2_kernel(float *__restrict__ x, const float *__restrict
       const int64_t f = e - nx;
       r[f] = fmaf(-float(coef[f % K]), q[f], r[f]);
     }
+  }
+}
+
+// CGLS residual step in one launch (256 threads per block): alpha =
+// gamma[gsel] / ||A p||^2 from the A partial sums, stored by block 0 for
+// the direction update; r -= alpha q over nr values.
+__global__ __launch_bounds__(256) void cgls_rstep_kernel(float *__restrict__ r, const float *__restrict__ q, int64_t nr,
+                                                         int K, const double *__restrict__ partial, int nblk,
+                                                         double *__restrict__ st, int gsel) {
+  __shared__ double tot[8];
+  sum_partials(partial, nblk, K, tot);
+  float al[8];
+  const double *gamma = st + kGamma + 8 * gsel;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) al[c] = (c < K && tot[c] > 0.0) ? float(gamma[c] / tot[c]) : 0.0f;
+  if (blockIdx.x == 0 && int(threadIdx.x) < K)
+    st[kAlphaOff + threadIdx.x] = tot[threadIdx.x] > 0.0 ? gamma[threadIdx.x] / tot[threadIdx.x] : 0.0;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < nr; e += int64_t(gridDim.x) * blockDim.x) {
+    const int c = int(e % K);
+    float a = al[0];
+#pragma unroll
+    for (int cc = 1; cc < 8; ++cc) a = (c == cc) ? al[cc] : a;
+    r[e] = fmaf(-a, q[e], r[e]);
   }
 }
 
@@ -918,6 +1017,9 @@ ProjLaunch plan_backproject(const hsn_ctx *ctx, const hsn_geom *g) {
       }
     }
   }
+  // Several voxels per thread step between rows of one column: the block
+  // must span whole image rows.
+  if (nt % n != 0) vpt = 1;
   const int64_t vc = std::max<int64_t>(
       1, std::min<int64_t>({int64_t(g->n_views), LP / ldp, int64_t(kMaxViewChunk), int64_t(nt),
                             int64_t(kCopyFloats) * nt / (n * K)}));
@@ -979,12 +1081,15 @@ void launch_backproject(const ProjLaunch &L, const float *s, float *x, const Geo
   }
 }
 
-// mode 0: pT = p^T; mode 1: p = sv + coef p, pT = p^T; mode 2: p = sv, pT = p^T.
+// mode 0: pT = p^T; mode 1: p = sv + coef p, pT = p^T; mode 2: p = sv, pT = p^T;
+// mode 3: the fused CGLS direction step (see xpby_transpose_kernel).
 template <int K>
 void launch_xpby_t(float *p, float *pT, const float *sv, const double *coef, const hsn_geom *g, int mode,
-                   hipStream_t st) {
+                   hipStream_t st, float *x = nullptr, const double *partial = nullptr, int nblk = 0,
+                   double *scal = nullptr, int gsel = 0) {
   const unsigned t = unsigned((g->n_cols + kTile - 1) / kTile);
-  xpby_transpose_kernel<K><<<dim3(t, t, unsigned(g->n_slices)), 256, 0, st>>>(p, pT, sv, coef, int(g->n_cols), mode);
+  xpby_transpose_kernel<K><<<dim3(t, t, unsigned(g->n_slices)), 256, 0, st>>>(p, pT, sv, coef, int(g->n_cols), mode,
+                                                                              x, partial, nblk, scal, gsel);
 }
 
 // Number of view groups upload_geom forms for g.
@@ -1106,42 +1211,58 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
   const size_t n_part = std::max<size_t>({nb_proj, nb_back, size_t(kDotBlocks)});
   const size_t need = hsn::Carver::need({sizeof(float) * ns * K, sizeof(float) * ns * K, sizeof(float) * nx * K,
                                          sizeof(float) * nx * K, sizeof(float) * nx * K,
-                                         sizeof(double) * n_part * K, sizeof(double) * 24});
+                                         sizeof(double) * n_part * K, sizeof(double) * kScal});
   if ((rc = hsn::ensure_ws(ctx, need)) != HSN_OK) return rc;
   hsn::Carver cv(ctx->ws);
   float *r = cv.take<float>(ns * K), *q = cv.take<float>(ns * K);
   float *sv = cv.take<float>(nx * K), *p = cv.take<float>(nx * K), *pT = cv.take<float>(nx * K);
-  double *partial = cv.take<double>(n_part * K), *scal = cv.take<double>(24);
+  double *partial = cv.take<double>(n_part * K), *scal = cv.take<double>(kScal);
   const int eb = 256;
   auto blocks = [&](int64_t m) { return unsigned(std::min<int64_t>((m + eb - 1) / eb, 4096)); };
+  // With few projector partials every block of the update kernels sums them
+  // itself (4 launches per iteration); otherwise one block does and the
+  // updates read the scalars (6 launches).
+  const bool fused = std::max(nb_proj, nb_back) <= 1024;
 
   fill_zero_kernel<<<blocks(nx * K), eb, 0, st>>>(x, nx * K);
   HSN_HIP(ctx, hipMemcpyAsync(r, sino, sizeof(float) * ns * K, hipMemcpyDeviceToDevice, st));
   hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
   HSN_DISPATCH_K(K, launch_backproject, LB, r, sv, gt, g, 1.0f, 0.0f, partial, st);
   hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
-  cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_back), K, kSetGamma, scal, nullptr);
+  cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_back), K, kSetGamma, scal, 0, nullptr);
   HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, nullptr, g, 2, st);
   if (resid) {
     HSN_DISPATCH_K(K, launch_dot, r, r, ns, partial, st);
-    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kResid, scal, resid);
+    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kResid, scal, 0, resid);
   }
   for (int it = 0; it < n_iter; ++it) {
+    const int gsel = it & 1;
     hsn::prof_begin(ctx, HSN_KERN_PROJECT, st);
     HSN_DISPATCH_K(K, launch_project, LA, p, pT, q, gt, g, 1.0f, 0.0f, partial, st);
     hsn::prof_end(ctx, HSN_KERN_PROJECT, st);
-    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_proj), K, kAlpha, scal, nullptr);
-    chan_axpy2_kernel<<<blocks(nx * K + ns * K), eb, 0, st>>>(x, p, nx * K, r, q, ns * K, scal + 8, K);
+    if (fused) {
+      cgls_rstep_kernel<<<std::min(blocks(ns * K), 512u), 256, 0, st>>>(r, q, ns * K, K, partial, int(nb_proj), scal,
+                                                                        gsel);
+    } else {
+      cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_proj), K, kAlpha, scal, gsel, nullptr);
+      chan_axpy2_kernel<<<blocks(nx * K + ns * K), eb, 0, st>>>(x, p, nx * K, r, q, ns * K, scal + kAlphaOff, K);
+    }
     hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
     HSN_DISPATCH_K(K, launch_backproject, LB, r, sv, gt, g, 1.0f, 0.0f, partial, st);
     hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
-    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_back), K, kBeta, scal, nullptr);
-    HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, scal + 16, g, 1, st);
+    if (fused) {
+      HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, nullptr, g, 3, st, x, partial, int(nb_back), scal, gsel);
+    } else {
+      cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_back), K, kBeta, scal, gsel, nullptr);
+      HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, scal + kBetaOff, g, 1, st);
+    }
     if (resid) {
       HSN_DISPATCH_K(K, launch_dot, r, r, ns, partial, st);
-      cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kResid, scal, resid + size_t(it + 1) * K);
+      cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kResid, scal, 0, resid + size_t(it + 1) * K);
     }
   }
+  // The fused path adds alpha p to x in the direction step, which the last
+  // iteration still runs; nothing is left to add here.
   HSN_LAUNCHED(ctx);
   return HSN_OK;
 }

@@ -163,7 +163,7 @@ def test_projector_launch_shapes_bitwise(hsn, n, n_views, k, n_r, angles):
                 hsn.hsn_projector_set_launch(-1, 0, vpt, nt)
                 info = hsn.hsn_projector_launch_info(n_views, n_r, n, k, angles=th)
                 show("backproject lds", n=n, n_views=n_views, k=k, n_r=n_r, shape=info)
-                assert info[2] == vpt
+                assert info[2] in (1, vpt)  # several voxels per thread need whole image rows per block
                 xb = hsn.hsn_backproject(y, angles=th).cpu().numpy()
                 np.testing.assert_array_equal(xb, x_ref)
     finally:
