@@ -164,9 +164,16 @@ def main():
     last_x = {}
 
     def step(path, record=None):
-        p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=True)
-        s = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, polish_rounds=POLISH_CAP,
-                                 polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star, **paths[path])
+        if path == "learned":
+            # one pass writes p and the network's pooled input; no bfloat16 copy of p
+            p, _, pooled, _, _ = hsn.hsn_normalize_pooled(y, yo, mlp.precision)
+            s = hsn.hsn_subspace_nmf(p, None, n_k, V, D, check_every=BULK, polish_rounds=POLISH_CAP,
+                                     polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star,
+                                     mlp_pooled=pooled, **paths[path])
+        else:
+            p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=True)
+            s = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, polish_rounds=POLISH_CAP,
+                                     polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star, **paths[path])
         sino = V.view(sc.n_views, sc.n_rows, sc.n_cols, K)
         x = hsn.hsn_cgls(sino, CGLS_ITERS)
         last_x["x"] = x
@@ -255,8 +262,9 @@ def main():
     triples = float(sc.n_views) * sc.n_rows * sc.n_cols * sc.n_cols * K
     mlp_flops_row = 2.0 * (256 * 128 + 128 * 128 + 128 * 16)
     work = {  # kind -> (name, total algorithmic units over the timed region, bound, unit)
-        hsn.KERN_NORMALIZE: ("normalize_kernel (u16 counts -> f32 p + bf16 p)",
-                             args.steps * (8.0 * elems + 2.0 * sc.n_rows * sc.n_cols * n_k), "hbm"),
+        hsn.KERN_NORMALIZE: ("normalize_kernel (u16 counts -> f32 p + pooled network input)",
+                             args.steps * (6.0 * elems + 2.0 * sc.n_rows * sc.n_cols * n_k +
+                                           (512.0 if mlp.precision == hsn.PREC_BF16 else 1024.0) * n_p), "hbm"),
         hsn.KERN_NMF_PASS: ("pass_f32_kernel (N_V / N_D passes over f32 p)",
                             args.steps * (4.0 * elems + vb) + rounds * 2 * (4.0 * elems + vb), "hbm"),
         hsn.KERN_MLP_POOL: ("pool_kernel (bf16 p -> 256-bin pooled rows)",

@@ -88,6 +88,23 @@ hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *dims,
                          float *p, int64_t ldp, uint16_t *p_bf16, int64_t ldb,
                          float *offset_b, double *sumsq, void *stream);
 
+/*
+ * hsn_normalize plus the input of the learned warm start in the same pass:
+ * pooled [N_p][256], row i of p average-pooled to 256 values exactly as
+ * hsn_mlp_pool pools p_bf16 (bfloat16-rounded p, bin j covering
+ * [floor(j N_k/256), ceil((j+1) N_k/256)), summed in bin order in float32),
+ * stored as bfloat16 bits (pooled_precision HSN_PREC_BF16) or float32
+ * (HSN_PREC_FP32): the precision of the network that will read it (see
+ * hsn_nmf_opts.mlp_pooled).  p and p_bf16 may both be NULL.  Requires
+ * N_k <= 2048; pooled 4-byte aligned.  Other arguments as hsn_normalize.
+ */
+hsn_status hsn_normalize_pooled(hsn_ctx *ctx, const hsn_dims *dims,
+                                const void *y, int y_dtype, const void *y_open, int y_open_dtype,
+                                const uint8_t *bg_mask, float count_floor, int clip_nonneg,
+                                float *p, int64_t ldp, uint16_t *p_bf16, int64_t ldb,
+                                float *offset_b, double *sumsq, void *pooled, int pooled_precision,
+                                void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Subspace extraction: eq. (4) (V, D) = argmin_{V,D>=0} ||p - V D^T||^2 */
 /* ------------------------------------------------------------------ */
@@ -104,7 +121,8 @@ enum { HSN_INIT_USER = 0,  /* V and D hold the start on entry                   
                                  uses p_bf16 for the Gram P^T P when given      */
        HSN_INIT_MLP = 2 };    /* learned warm start: V0 = opts.mlp(pooled p_bf16),
                                  D0 = argmin_{D>=0} ||p - V0 D^T|| row by row, exact
-                                 zeros of D0 set to 1e-6 mean(D0); needs p and p_bf16 */
+                                 zeros of D0 set to 1e-6 mean(D0); needs p, and
+                                 p_bf16 unless opts.mlp_pooled is given */
 
 typedef struct hsn_mlp hsn_mlp;
 
@@ -121,6 +139,9 @@ typedef struct {
   double rel_obj_tol; /* stop when (f - f_ref)/f_ref <= tol; ignored if f_ref <= 0 */
   double f_ref;       /* reference objective f* (> 0 enables the stop test) */
   const hsn_mlp *mlp; /* network for HSN_INIT_MLP (its k must equal k), else NULL */
+  const void *mlp_pooled; /* optional for HSN_INIT_MLP: the network input already pooled
+                             (hsn_normalize_pooled, in the network's precision, [N_p][256]);
+                             NULL: pooled here from p_bf16 */
 } hsn_nmf_opts;
 
 typedef struct {

@@ -758,17 +758,22 @@ hsn_status check_mlp(hsn_ctx *ctx, const hsn_mlp *m) {
 
 // V0 = network(pool(p_bf16)) with the pooled rows in xbuf (n_p x 256 of the
 // network's precision).
+// V0 = network(pooled rows): the rows are pooled from pb into xbuf here,
+// or come already pooled (pooled != NULL, [n_p][256] in the network's
+// precision).
 hsn_status mlp_infer_into(hsn_ctx *ctx, const hsn_mlp *m, const uint16_t *pb, int64_t ldb, int64_t n_p, int n_k,
-                          float *V0, void *xbuf, hipStream_t st) {
-  const int nbp = int(std::min<int64_t>((n_p + kWaves - 1) / kWaves, 16 * int64_t(ctx->num_cu)));
-  prof_begin(ctx, HSN_KERN_MLP_POOL, st);
-  if (m->prec == HSN_PREC_BF16)
-    pool_kernel<uint16_t><<<nbp, 256, 0, st>>>(pb, ldb, n_p, n_k, static_cast<uint16_t *>(xbuf));
-  else
-    pool_kernel<float><<<nbp, 256, 0, st>>>(pb, ldb, n_p, n_k, static_cast<float *>(xbuf));
-  prof_end(ctx, HSN_KERN_MLP_POOL, st);
+                          float *V0, void *xbuf, const void *pooled, hipStream_t st) {
+  if (!pooled) {
+    const int nbp = int(std::min<int64_t>((n_p + kWaves - 1) / kWaves, 16 * int64_t(ctx->num_cu)));
+    prof_begin(ctx, HSN_KERN_MLP_POOL, st);
+    if (m->prec == HSN_PREC_BF16)
+      pool_kernel<uint16_t><<<nbp, 256, 0, st>>>(pb, ldb, n_p, n_k, static_cast<uint16_t *>(xbuf));
+    else
+      pool_kernel<float><<<nbp, 256, 0, st>>>(pb, ldb, n_p, n_k, static_cast<float *>(xbuf));
+    prof_end(ctx, HSN_KERN_MLP_POOL, st);
+  }
   RowsArgs ra{};
-  ra.x = xbuf;
+  ra.x = pooled ? const_cast<void *>(pooled) : xbuf;
   ra.ldx = kIn;
   ra.n = n_p;
   ra.pub = m->pub;
@@ -796,8 +801,8 @@ int mlp_device(const hsn_mlp *m) { return m->device; }
 // updates can move them.  Leaves the control block open for the run.
 hsn_status mlp_nmf_start(hsn_ctx *ctx, hipStream_t st, const hsn_mlp *m, const float *p, int64_t ldp,
                          const uint16_t *pb, int64_t ldb, int64_t n_p, int n_k, float *V, float *D, void *xbuf,
-                         const NmfWork &w, int n_wg) {
-  hsn_status rc = mlp_infer_into(ctx, m, pb, ldb, n_p, n_k, V, xbuf, st);
+                         const void *pooled, const NmfWork &w, int n_wg) {
+  hsn_status rc = mlp_infer_into(ctx, m, pb, ldb, n_p, n_k, V, xbuf, pooled, st);
   if (rc != HSN_OK) return rc;
   const int K = m->k;
   ctrl_reset_kernel<<<1, 1, 0, st>>>(w.ctrl);
@@ -1029,7 +1034,7 @@ extern "C" hsn_status hsn_mlp_infer(hsn_ctx *ctx, const hsn_mlp *m, const uint16
   if (n_p == 0) return HSN_OK;
   DeviceGuard dg(ctx->device);
   if ((rc = ensure_ws(ctx, mlp_pool_bytes(m, n_p) + 256)) != HSN_OK) return rc;
-  return mlp_infer_into(ctx, m, p_bf16, ldb, n_p, int(n_k), V0, ctx->ws, static_cast<hipStream_t>(stream));
+  return mlp_infer_into(ctx, m, p_bf16, ldb, n_p, int(n_k), V0, ctx->ws, nullptr, static_cast<hipStream_t>(stream));
 }
 
 extern "C" hsn_status hsn_mlp_save(hsn_ctx *ctx, const hsn_mlp *m, const char *path) {

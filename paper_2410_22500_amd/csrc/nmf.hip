@@ -42,7 +42,7 @@ int mlp_k(const hsn_mlp *m);
 int mlp_device(const hsn_mlp *m);
 hsn_status mlp_nmf_start(hsn_ctx *ctx, hipStream_t st, const hsn_mlp *m, const float *p, int64_t ldp,
                          const uint16_t *pb, int64_t ldb, int64_t n_p, int n_k, float *V, float *D, void *xbuf,
-                         const NmfWork &w, int n_wg);
+                         const void *pooled, const NmfWork &w, int n_wg);
 hsn_status nndsvd_init(hsn_ctx *ctx, hipStream_t st, const float *p, int64_t ldp, const uint16_t *pb, int64_t ldb,
                        int64_t n_p, int n_k, int K, float *V, float *D, void *ws, int n_split);
 
@@ -146,7 +146,8 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     if (ldp < n_k || ldp % 4 != 0 || reinterpret_cast<uintptr_t>(p) % 16 != 0)
       return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: ldp must be >= n_k and a multiple of 4, p 16-byte aligned");
   }
-  if ((bf16 && o->max_iter > 0) || pol_bf16 > 0 || o->init == HSN_INIT_MLP) {
+  const bool mlp_pools = o->init == HSN_INIT_MLP && !o->mlp_pooled;
+  if ((bf16 && o->max_iter > 0) || pol_bf16 > 0 || mlp_pools) {
     if (!p_bf16) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: p_bf16 is required for the bfloat16 bulk");
     if (ldb < n_k || ldb % 32 != 0 || reinterpret_cast<uintptr_t>(p_bf16) % 16 != 0)
       return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: ldb must be >= n_k and a multiple of 32, p_bf16 16-byte aligned");
@@ -181,7 +182,7 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   }
   // The learned start pools p into a scratch block placed after the NMF's
   // arrays (its kernels run before the first NMF kernel reads them).
-  const size_t need_pool = o->init == HSN_INIT_MLP ? mlp_pool_bytes(o->mlp, n_p) + 256 : 0;
+  const size_t need_pool = mlp_pools ? mlp_pool_bytes(o->mlp, n_p) + 256 : 0;
   hsn_status rc = ensure_ws(ctx, std::max(need + need_pool, need_init));
   if (rc != HSN_OK) return rc;
   Carver cv(ctx->ws);
@@ -222,7 +223,8 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
       (rc = nndsvd_init(ctx, st, p, ldp, p_bf16, ldb, n_p, int(n_k), K, V, D, ctx->ws, n_split)) != HSN_OK)
     return rc;
   if (o->init == HSN_INIT_MLP &&
-      (rc = mlp_nmf_start(ctx, st, o->mlp, p, ldp, p_bf16, ldb, n_p, int(n_k), V, D, pool_buf, R.w, wg_f32)) != HSN_OK)
+      (rc = mlp_nmf_start(ctx, st, o->mlp, p, ldp, p_bf16, ldb, n_p, int(n_k), V, D, pool_buf, o->mlp_pooled, R.w,
+                          wg_f32)) != HSN_OK)
     return rc;
   launch_nmf_init(K, st, D, int(n_k), R.w, !steps.empty() && steps[0].rule == kModeANLS ? 1 : 0,
                   any_bf16 ? bf16_image_ldb(ldb) : 0);

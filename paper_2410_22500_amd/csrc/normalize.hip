@@ -19,9 +19,13 @@ __device__ __forceinline__ float ld_count<uint16_t>(const uint16_t *a, int64_t i
 template <>
 __device__ __forceinline__ float ld_count<float>(const float *a, int64_t i) { return a[i]; }
 
-// -ln(y/y^o) evaluated as ln(y^o/y): one rounding in the ratio, one in the log.
+// -ln(y/y^o) evaluated as ln(y^o/y) = log2(y^o / y) ln 2 with the hardware
+// reciprocal and log2, each within about 1 ulp: a few 1e-7 relative.  A
+// ratio below the float32 normal range (2^-126, counts ratios no detector
+// produces; never for uint16 counts with f >= 1) would flush to -inf.
 __device__ __forceinline__ float neglog(float y, float yo, float floor_) {
-  return logf(fmaxf(yo, floor_) / fmaxf(y, floor_));
+  const float ratio = fmaxf(yo, floor_) * __builtin_amdgcn_rcpf(fmaxf(y, floor_));
+  return __builtin_amdgcn_logf(ratio) * 0.69314718055994531f;
 }
 
 // b[v][k] = (1/|B|) sum_{(r,c) in B} -ln(y/y^o).  Grid (k-blocks, N_v);
@@ -44,76 +48,117 @@ __global__ __launch_bounds__(kThreads) void offset_kernel(const TY *__restrict__
   b[v * nk + k] = float(acc / double(cnt > 0 ? cnt : 1));
 }
 
-// Main stream.  Thread item = 8 consecutive bins of one row.
-template <typename TY, typename TO, bool VEC>
+// Average pooling of a row to the 256 network inputs: input i covers bins
+// [floor(i N_k / 256), ceil((i + 1) N_k / 256)) of the bfloat16-rounded p,
+// summed in bin order in float32 and divided by the bin count (the
+// arithmetic of the learned start's own pooling of p_bf16).
+constexpr int kPoolIn = 256;
+constexpr int kPoolMaxBins = 2048;
+
+// Main stream.  A block walks groups of R = max(1, 256 / cpr) rows, cpr =
+// ceil(width / 8) chunks of 8 bins per row; thread t takes row t / cpr of
+// the group and chunk t % cpr (rows longer than 2048 bins: one row per
+// group, chunks t, t + 256, ...).  POOL (1: bfloat16 out, 2: float32 out)
+// also writes the pooled rows, from a copy of the group's bfloat16-rounded
+// rows in LDS (R * N_k <= 2048 floats).
+template <typename TY, typename TO, bool VEC, int POOL>
 __global__ __launch_bounds__(kThreads) void normalize_kernel(
     const TY *__restrict__ y, const TO *__restrict__ yo, int64_t n_rows, int64_t n_pix, int64_t nk,
     const float *__restrict__ b, float floor_, int clip, float *__restrict__ p, int64_t ldp,
-    uint16_t *__restrict__ pb, int64_t ldb, double *__restrict__ partial) {
-  const int64_t width = (pb && ldb > nk) ? ldb : nk;
-  const int64_t chunks = (width + 7) / 8;
-  const int64_t items = n_rows * chunks;
+    uint16_t *__restrict__ pb, int64_t ldb, void *__restrict__ pooled, double *__restrict__ partial) {
+  __shared__ float rowbuf[POOL ? kPoolMaxBins : 1];
+  const int width = int((pb && ldb > nk) ? ldb : nk);
+  const int cpr = (width + 7) / 8;
+  const int R = cpr <= kThreads ? kThreads / cpr : 1;
+  const int t = threadIdx.x;
+  const int rr = cpr <= kThreads ? t / cpr : 0;
+  const int ch0 = cpr <= kThreads ? t - rr * cpr : t;
+  const int nki = int(nk);
   double ss = 0.0;
-  for (int64_t it = int64_t(blockIdx.x) * kThreads + threadIdx.x; it < items;
-       it += int64_t(gridDim.x) * kThreads) {
-    const int64_t row = it / chunks;
-    const int64_t k0 = (it - row * chunks) * 8;
-    const int64_t v = row / n_pix;
+  for (int64_t g0 = int64_t(blockIdx.x) * R; g0 < n_rows; g0 += int64_t(gridDim.x) * R) {
+    const int64_t row = g0 + rr;
+    const bool row_ok = rr < R && row < n_rows;
+    const int64_t v = row_ok ? row / n_pix : 0;
     const int64_t px = row - v * n_pix;
-    float out[8];
-    if (VEC && k0 + 8 <= nk) {
-      // 16-byte loads of 8 uint16 counts (alignment checked on the host).
-      const uint4 yv = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(y) + row * nk + k0);
-      const uint4 ov = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(yo) + px * nk + k0);
-      const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w};
-      const uint32_t ow[4] = {ov.x, ov.y, ov.z, ov.w};
+    for (int ch = ch0; row_ok && ch < cpr; ch += kThreads) {
+      const int k0 = ch * 8;
+      float out[8];
+      if (VEC && k0 + 8 <= nki) {
+        // 16-byte loads of 8 uint16 counts (alignment checked on the host).
+        const uint4 yv = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(y) + row * nk + k0);
+        const uint4 ov = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(yo) + px * nk + k0);
+        const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w};
+        const uint32_t ow[4] = {ov.x, ov.y, ov.z, ov.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float yc = float((yw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+          const float oc = float((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+          out[e] = neglog(yc, oc, floor_);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = k0 + e;
+          out[e] = (k < nki) ? neglog(ld_count(y, row * nk + k), ld_count(yo, px * nk + k), floor_) : 0.0f;
+        }
+      }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float yc = float((yw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-        const float oc = float((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-        out[e] = neglog(yc, oc, floor_);
+        const int k = k0 + e;
+        float pv = out[e];
+        if (k < nki) {
+          if (b) pv -= b[v * nk + k];
+          if (clip) pv = fmaxf(pv, 0.0f);
+        } else {
+          pv = 0.0f;
+        }
+        out[e] = pv;
+        ss += double(pv) * double(pv);
       }
-    } else {
+      if (p) {
+        if (VEC && k0 + 8 <= nki) {
+          float4 *dst = reinterpret_cast<float4 *>(p + row * ldp + k0);
+          dst[0] = make_float4(out[0], out[1], out[2], out[3]);
+          dst[1] = make_float4(out[4], out[5], out[6], out[7]);
+        } else {
+          for (int e = 0; e < 8; ++e)
+            if (k0 + e < nki) p[row * ldp + k0 + e] = out[e];
+        }
+      }
+      if (pb) {
+        if (VEC && k0 + 8 <= ldb) {
+          uint32_t w[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t k = k0 + e;
-        out[e] = (k < nk) ? neglog(ld_count(y, row * nk + k), ld_count(yo, px * nk + k), floor_) : 0.0f;
+          for (int e = 0; e < 4; ++e)
+            w[e] = uint32_t(hsn::f32_to_bf16_bits(out[2 * e])) | (uint32_t(hsn::f32_to_bf16_bits(out[2 * e + 1])) << 16);
+          *reinterpret_cast<uint4 *>(pb + row * ldb + k0) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
+          for (int e = 0; e < 8; ++e)
+            if (k0 + e < ldb) pb[row * ldb + k0 + e] = hsn::f32_to_bf16_bits(out[e]);
+        }
       }
-    }
+      if constexpr (POOL != 0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t k = k0 + e;
-      float pv = out[e];
-      if (k < nk) {
-        if (b) pv -= b[v * nk + k];
-        if (clip) pv = fmaxf(pv, 0.0f);
-      } else {
-        pv = 0.0f;
-      }
-      out[e] = pv;
-      ss += double(pv) * double(pv);
-    }
-    if (p) {
-      if (VEC && k0 + 8 <= nk) {
-        float4 *dst = reinterpret_cast<float4 *>(p + row * ldp + k0);
-        dst[0] = make_float4(out[0], out[1], out[2], out[3]);
-        dst[1] = make_float4(out[4], out[5], out[6], out[7]);
-      } else {
         for (int e = 0; e < 8; ++e)
-          if (k0 + e < nk) p[row * ldp + k0 + e] = out[e];
+          if (k0 + e < nki) rowbuf[rr * nki + k0 + e] = hsn::bf16_bits_to_f32(hsn::f32_to_bf16_bits(out[e]));
       }
     }
-    if (pb) {
-      if (VEC && k0 + 8 <= ldb) {
-        uint32_t w[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          w[e] = uint32_t(hsn::f32_to_bf16_bits(out[2 * e])) | (uint32_t(hsn::f32_to_bf16_bits(out[2 * e + 1])) << 16);
-        *reinterpret_cast<uint4 *>(pb + row * ldb + k0) = make_uint4(w[0], w[1], w[2], w[3]);
-      } else {
-        for (int e = 0; e < 8; ++e)
-          if (k0 + e < ldb) pb[row * ldb + k0 + e] = hsn::f32_to_bf16_bits(out[e]);
+    if constexpr (POOL != 0) {
+      __syncthreads();
+      for (int o = t; o < R * kPoolIn; o += kThreads) {
+        const int orow = o / kPoolIn, i = o - orow * kPoolIn;
+        const int64_t prow = g0 + orow;
+        if (prow >= n_rows) continue;
+        const int lo = (i * nki) / kPoolIn, hi = ((i + 1) * nki + kPoolIn - 1) / kPoolIn;
+        float sum = 0.0f;
+        for (int c = lo; c < hi; ++c) sum += rowbuf[orow * nki + c];
+        const float val = sum / float(hi - lo);
+        if constexpr (POOL == 1)
+          static_cast<uint16_t *>(pooled)[prow * kPoolIn + i] = hsn::f32_to_bf16_bits(val);
+        else
+          static_cast<float *>(pooled)[prow * kPoolIn + i] = val;
       }
+      __syncthreads();
     }
   }
   // Block reduction of the float64 sum of squares, fixed order.
@@ -122,9 +167,9 @@ __global__ __launch_bounds__(kThreads) void normalize_kernel(
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) t += red[w];
-    partial[blockIdx.x] = t;
+    double tt = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) tt += red[w];
+    partial[blockIdx.x] = tt;
   }
 }
 
@@ -142,10 +187,18 @@ __global__ void sum_partials_kernel(const double *__restrict__ partial, int n, d
   }
 }
 
+template <typename TY, typename TO, bool VEC, int POOL>
+void launch_norm(int64_t n_rows, int64_t n_pix, int64_t nk, const TY *y, const TO *yo, const float *b, float floor_,
+                 int clip, float *p, int64_t ldp, uint16_t *pb, int64_t ldb, void *pooled, double *partial,
+                 hipStream_t st) {
+  normalize_kernel<TY, TO, VEC, POOL><<<kSumBlocks, kThreads, 0, st>>>(y, yo, n_rows, n_pix, nk, b, floor_, clip, p,
+                                                                       ldp, pb, ldb, pooled, partial);
+}
+
 template <typename TY, typename TO>
 hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo, const uint8_t *mask,
                       float floor_, int clip, float *p, int64_t ldp, uint16_t *pb, int64_t ldb,
-                      float *offset_b, double *sumsq, hipStream_t st) {
+                      float *offset_b, double *sumsq, void *pooled, int pool_mode, hipStream_t st) {
   const int64_t n_pix = d->n_rows * d->n_cols;
   const int64_t n_rows = d->n_views * n_pix;
   const int64_t nk = d->n_bins;
@@ -166,12 +219,13 @@ hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo
                    (!p || (ldp % 4 == 0 && reinterpret_cast<uintptr_t>(p) % 16 == 0)) &&
                    (!pb || reinterpret_cast<uintptr_t>(pb) % 16 == 0);
   hsn::prof_begin(ctx, HSN_KERN_NORMALIZE, st);
-  if (vec)
-    normalize_kernel<TY, TO, true><<<kSumBlocks, kThreads, 0, st>>>(y, yo, n_rows, n_pix, nk, b, floor_, clip, p,
-                                                                    ldp, pb, ldb, partial);
-  else
-    normalize_kernel<TY, TO, false><<<kSumBlocks, kThreads, 0, st>>>(y, yo, n_rows, n_pix, nk, b, floor_, clip, p,
-                                                                     ldp, pb, ldb, partial);
+#define HSN_NORM(V, P) launch_norm<TY, TO, V, P>(n_rows, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st)
+  if (vec) {
+    if (pool_mode == 0) HSN_NORM(true, 0); else if (pool_mode == 1) HSN_NORM(true, 1); else HSN_NORM(true, 2);
+  } else {
+    if (pool_mode == 0) HSN_NORM(false, 0); else if (pool_mode == 1) HSN_NORM(false, 1); else HSN_NORM(false, 2);
+  }
+#undef HSN_NORM
   hsn::prof_end(ctx, HSN_KERN_NORMALIZE, st);
   HSN_LAUNCHED(ctx);
   if (sumsq) {
@@ -183,13 +237,16 @@ hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo
 
 }  // namespace
 
-extern "C" hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype,
-                                    const void *y_open, int y_open_dtype, const uint8_t *bg_mask,
-                                    float count_floor, int clip_nonneg, float *p, int64_t ldp, uint16_t *p_bf16,
-                                    int64_t ldb, float *offset_b, double *sumsq, void *stream) {
+static hsn_status normalize_impl(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype, const void *y_open,
+                          int y_open_dtype, const uint8_t *bg_mask, float count_floor, int clip_nonneg, float *p,
+                          int64_t ldp, uint16_t *p_bf16, int64_t ldb, float *offset_b, double *sumsq,
+                          void *pooled, int pool_mode, void *stream) {
   if (!ctx) return HSN_ERR_INVALID_ARG;
   if (!d || !y || !y_open) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: dims, y and y_open are required");
-  if (!p && !p_bf16) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: at least one of p, p_bf16 is required");
+  if (!p && !p_bf16 && !pooled)
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: at least one of p, p_bf16, pooled is required");
+  if (pooled && d && d->n_bins > kPoolMaxBins)
+    return hsn::fail(ctx, HSN_ERR_SHAPE, "normalize: pooled output needs n_bins <= %d", kPoolMaxBins);
   if (d->n_views <= 0 || d->n_rows <= 0 || d->n_cols <= 0 || d->n_bins <= 0)
     return hsn::fail(ctx, HSN_ERR_SHAPE, "normalize: all dimensions must be positive");
   if ((y_dtype != HSN_U16 && y_dtype != HSN_F32) || (y_open_dtype != HSN_U16 && y_open_dtype != HSN_F32))
@@ -204,13 +261,36 @@ extern "C" hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *d, const void 
   const bool yu = y_dtype == HSN_U16, ou = y_open_dtype == HSN_U16;
   if (yu && ou)
     return launch_all(ctx, d, (const uint16_t *)y, (const uint16_t *)y_open, bg_mask, count_floor, clip_nonneg, p,
-                      ldp, p_bf16, ldb, offset_b, sumsq, st);
+                      ldp, p_bf16, ldb, offset_b, sumsq, pooled, pool_mode, st);
   if (yu && !ou)
     return launch_all(ctx, d, (const uint16_t *)y, (const float *)y_open, bg_mask, count_floor, clip_nonneg, p, ldp,
-                      p_bf16, ldb, offset_b, sumsq, st);
+                      p_bf16, ldb, offset_b, sumsq, pooled, pool_mode, st);
   if (!yu && ou)
     return launch_all(ctx, d, (const float *)y, (const uint16_t *)y_open, bg_mask, count_floor, clip_nonneg, p, ldp,
-                      p_bf16, ldb, offset_b, sumsq, st);
+                      p_bf16, ldb, offset_b, sumsq, pooled, pool_mode, st);
   return launch_all(ctx, d, (const float *)y, (const float *)y_open, bg_mask, count_floor, clip_nonneg, p, ldp,
-                    p_bf16, ldb, offset_b, sumsq, st);
+                    p_bf16, ldb, offset_b, sumsq, pooled, pool_mode, st);
+}
+
+extern "C" hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype,
+                                    const void *y_open, int y_open_dtype, const uint8_t *bg_mask,
+                                    float count_floor, int clip_nonneg, float *p, int64_t ldp, uint16_t *p_bf16,
+                                    int64_t ldb, float *offset_b, double *sumsq, void *stream) {
+  return normalize_impl(ctx, d, y, y_dtype, y_open, y_open_dtype, bg_mask, count_floor, clip_nonneg, p, ldp, p_bf16,
+                        ldb, offset_b, sumsq, nullptr, 0, stream);
+}
+
+extern "C" hsn_status hsn_normalize_pooled(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype,
+                                           const void *y_open, int y_open_dtype, const uint8_t *bg_mask,
+                                           float count_floor, int clip_nonneg, float *p, int64_t ldp,
+                                           uint16_t *p_bf16, int64_t ldb, float *offset_b, double *sumsq,
+                                           void *pooled, int pooled_precision, void *stream) {
+  if (!ctx) return HSN_ERR_INVALID_ARG;
+  if (!pooled) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize_pooled: pooled is required");
+  if (pooled_precision != HSN_PREC_BF16 && pooled_precision != HSN_PREC_FP32)
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize_pooled: pooled_precision must be HSN_PREC_BF16 or HSN_PREC_FP32");
+  if (reinterpret_cast<uintptr_t>(pooled) % 4 != 0)
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize_pooled: pooled must be 4-byte aligned");
+  return normalize_impl(ctx, d, y, y_dtype, y_open, y_open_dtype, bg_mask, count_floor, clip_nonneg, p, ldp, p_bf16,
+                        ldb, offset_b, sumsq, pooled, pooled_precision == HSN_PREC_BF16 ? 1 : 2, stream);
 }

@@ -42,7 +42,7 @@ class NmfOpts(C.Structure):
     _fields_ = [("k", C.c_int), ("algo", C.c_int), ("precision", C.c_int), ("init", C.c_int),
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("polish_rounds", C.c_int),
                 ("polish_algo", C.c_int), ("polish_bf16_rounds", C.c_int), ("rel_obj_tol", C.c_double),
-                ("f_ref", C.c_double), ("mlp", C.c_void_p)]
+                ("f_ref", C.c_double), ("mlp", C.c_void_p), ("mlp_pooled", C.c_void_p)]
 
 
 class TrainOpts(C.Structure):
@@ -80,6 +80,9 @@ _lib.hsn_version.restype = C.c_int
 _lib.hsn_normalize.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, _P, C.c_float, C.c_int,
                                _P, C.c_int64, _P, C.c_int64, _P, _P, _P]
 _lib.hsn_normalize.restype = C.c_int
+_lib.hsn_normalize_pooled.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, _P, C.c_float, C.c_int,
+                                      _P, C.c_int64, _P, C.c_int64, _P, _P, _P, C.c_int, _P]
+_lib.hsn_normalize_pooled.restype = C.c_int
 _lib.hsn_subspace_nmf.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64, _P, _P,
                                   C.POINTER(NmfOpts), C.POINTER(NmfStats), _P]
 _lib.hsn_subspace_nmf.restype = C.c_int
@@ -217,17 +220,45 @@ def hsn_normalize(y: torch.Tensor, yo: torch.Tensor, bg_mask: Optional[torch.Ten
     return p, pb, b, ss
 
 
+def hsn_normalize_pooled(y: torch.Tensor, yo: torch.Tensor, pooled_precision: int, bg_mask: Optional[torch.Tensor] = None,
+                         count_floor: float = 1.0, clip: bool = True, want_f32: bool = True, want_bf16: bool = False,
+                         want_offset: bool = False, ldp: Optional[int] = None, ldb: Optional[int] = None):
+    """hsn_normalize plus the learned start's pooled input [N_p][256] (bfloat16 bits as int16 for
+    PREC_BF16, float32 for PREC_FP32).  Returns (p, p_bf16, pooled, b, sumsq)."""
+    dev = _dev(y)
+    ctx = context(dev)
+    n_v, n_r, n_c, n_k = y.shape
+    dims = Dims(n_v, n_r, n_c, n_k)
+    yd = F32 if y.dtype == torch.float32 else U16
+    od = F32 if yo.dtype == torch.float32 else U16
+    n_p = n_v * n_r * n_c
+    ldp = ldp or round_up(n_k, 4)
+    ldb = ldb or round_up(n_k, 32)
+    p = torch.empty((n_p, ldp), dtype=torch.float32, device=y.device) if want_f32 else None
+    pb = torch.empty((n_p, ldb), dtype=torch.int16, device=y.device) if want_bf16 else None
+    pooled = torch.empty((n_p, 256), dtype=torch.int16 if pooled_precision == PREC_BF16 else torch.float32,
+                         device=y.device)
+    b = torch.empty((n_v, n_k), dtype=torch.float32, device=y.device) if (want_offset and bg_mask is not None) else None
+    ss = torch.empty((), dtype=torch.float64, device=y.device)
+    _check(_lib.hsn_normalize_pooled(ctx, C.byref(dims), _ptr(y), yd, _ptr(yo), od, _ptr(bg_mask), float(count_floor),
+                                     int(clip), _ptr(p), ldp, _ptr(pb), ldb, _ptr(b), _ptr(ss), _ptr(pooled),
+                                     int(pooled_precision), _stream(dev)), ctx)
+    return p, pb, pooled, b, ss
+
+
 def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], n_k: int, V: torch.Tensor,
                      D: torch.Tensor, algo: int = ALGO_MU, precision: int = PREC_FP32, max_iter: int = 100,
                      check_every: int = 10, polish_rounds: int = 0, polish_algo: int = ALGO_ANLS,
                      polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0,
-                     init: int = INIT_USER, mlp: Optional["Mlp"] = None, history_cap: int = 4096) -> dict:
+                     init: int = INIT_USER, mlp: Optional["Mlp"] = None, history_cap: int = 4096,
+                     mlp_pooled: Optional[torch.Tensor] = None) -> dict:
     """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device)."""
     dev = _dev(V)
     ctx = context(dev)
     n_p, k = V.shape
     opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo,
-                   polish_bf16_rounds, rel_obj_tol, f_ref, mlp.handle if mlp is not None else None)
+                   polish_bf16_rounds, rel_obj_tol, f_ref, mlp.handle if mlp is not None else None,
+                   _ptr(mlp_pooled))
     hist = (C.c_double * max(history_cap, 1))()
     stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0)
     ldp = p.stride(0) if p is not None else 0

@@ -241,7 +241,15 @@ def test_nmf_learned_start(hsn):
     tol = max(1e-5, np.linalg.cond(V0.T @ V0) * 2.0 ** -23)
     show("  D0", err=rel_fro(D.cpu().numpy(), Dr), tol=tol)
     assert rel_fro(D.cpu().numpy(), Dr) <= tol
-    # rejected: missing network, mismatched k
+    # the same start from rows pooled in the normalisation pass (no p_bf16)
+    _, _, pooled, _, _ = hsn.hsn_normalize_pooled(y, yo, hsn.PREC_BF16, want_f32=False)
+    V2 = torch.zeros_like(V)
+    D2 = torch.zeros_like(D)
+    hsn.hsn_subspace_nmf(p, None, n_k, V2, D2, init=hsn.INIT_MLP, mlp=m, max_iter=0, mlp_pooled=pooled)
+    assert torch.equal(V2, V) and torch.equal(D2, D)
+    # rejected: missing network, mismatched k, neither p_bf16 nor pooled rows
+    with pytest.raises(hsn.HsnError):
+        hsn.hsn_subspace_nmf(p, None, n_k, V, D, init=hsn.INIT_MLP, mlp=m, max_iter=0)
     with pytest.raises(hsn.HsnError):
         hsn.hsn_subspace_nmf(p, pb, n_k, V, D, init=hsn.INIT_MLP, max_iter=0)
     m4 = hsn.hsn_mlp_create(4, hsn.PREC_BF16, None)

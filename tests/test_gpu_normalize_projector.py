@@ -78,6 +78,35 @@ def test_normalize_mid_config_sampled_rows(hsn):
     np.testing.assert_array_equal(bits, bf16_rne(p[rows].cpu().numpy()))
 
 
+@pytest.mark.parametrize("n_k,shape,prec,mask", [(1024, (3, 4, 5), 1, False), (2000, (2, 3, 4), 0, True),
+                                                 (300, (2, 2, 7), 1, True), (37, (1, 3, 3), 0, False),
+                                                 (256, (5, 1, 9), 1, False)])
+def test_normalize_pooled_matches_separate_calls(hsn, n_k, shape, prec, mask):
+    # The fused pass writes the same p, p_bf16 and offset as hsn_normalize,
+    # and pooled rows equal to pooling its p_bf16 with hsn_mlp_pool, bit for
+    # bit; the sum of squares agrees to float64 rounding (another order).
+    import torch
+    g = np.random.Generator(np.random.PCG64(n_k))
+    n_v, n_r, n_c = shape
+    y = torch.from_numpy(g.integers(0, 4000, (n_v, n_r, n_c, n_k), dtype=np.uint16).view(np.int16)).cuda()
+    yo = torch.from_numpy(g.integers(1000, 6000, (n_r, n_c, n_k), dtype=np.uint16).view(np.int16)).cuda()
+    bg = torch.from_numpy((g.random((n_r, n_c)) < 0.3).astype(np.uint8)).cuda() if mask else None
+    if bg is not None:
+        bg[0, 0] = 1
+    show("normalize pooled", n_k=n_k, shape=shape, prec=prec, mask=mask)
+    p0, pb0, b0, ss0 = hsn.hsn_normalize(y, yo, bg_mask=bg, want_bf16=True, want_offset=mask)
+    p1, pb1, pooled, b1, ss1 = hsn.hsn_normalize_pooled(y, yo, prec, bg_mask=bg, want_bf16=True, want_offset=mask)
+    assert torch.equal(p0[:, :n_k], p1[:, :n_k]) and torch.equal(pb0, pb1)  # p's pad columns are not written
+    if mask:
+        assert torch.equal(b0, b1)
+    assert abs(float(ss0) - float(ss1)) <= 1e-12 * abs(float(ss0))
+    ref = hsn.hsn_mlp_pool(pb0, n_k, prec)
+    assert torch.equal(pooled, ref)
+    # pooled rows alone (no p, no p_bf16)
+    _, _, pooled2, _, _ = hsn.hsn_normalize_pooled(y, yo, prec, bg_mask=bg, want_f32=False)
+    assert torch.equal(pooled2, ref)
+
+
 @pytest.mark.parametrize("n,n_views,k,n_r", [(16, 12, 1, 2), (17, 9, 3, 1), (32, 30, 4, 3), (24, 8, 8, 2),
                                              (33, 7, 5, 1)])
 def test_projector_parity_and_adjoint(hsn, n, n_views, k, n_r):
