@@ -625,7 +625,7 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
   if (sumsq) block_sumsq_n<K, VPT>(res, ok, sumsq, size_t(r) * n_blk + bs.rest);
 }
 
-constexpr int kTile = 32;
+constexpr int kTile = 16;  // 16 x 16 pixels: one per thread of a 256-thread block
 
 // tot[q] = sum over b < nblk of partial[b][q], q < K, by a block of 256
 // threads in a fixed order, so that every block that calls it gets the same
@@ -663,7 +663,7 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ partial,
 constexpr int kScal = 32;
 enum { kGamma = 0, kAlphaOff = 16, kBetaOff = 24 };
 
-// Per slice: xT[r][i][j][:] = x[r][j][i][:] through a 32 x 32 LDS tile.
+// Per slice: xT[r][i][j][:] = x[r][j][i][:] through a 16 x 16 LDS tile.
 // mode 0: pT = p^T.  mode 2: p = sv, pT = p^T.  mode 1: p = sv + coef[q] p,
 // pT = p^T.  mode 3 (CGLS step, one launch): beta = ||A^T r||^2 / gamma
 // from the A^T partial sums (gamma = st[gsel], the new value goes to
