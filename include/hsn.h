@@ -273,6 +273,23 @@ hsn_status hsn_projector_launch_info(hsn_ctx *ctx, const hsn_geom *g, int *shape
 hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sino, float *x,
                     int n_iter, double *resid, void *stream);
 
+/*
+ * Filtered backprojection, the per-channel reconstruction the paper uses
+ * for its DHR baseline (one FBP per wavelength bin) and for "FHR with FBP"
+ * (FBP of the K subspace sinograms); Section V, Tables II and IV.  The
+ * filter is the band-limited ramp sampled at the detector pitch (Ram-Lak:
+ * h[0] = 1/4, h[d] = -1/(pi^2 d^2) for odd d, 0 for even d != 0), applied
+ * to every detector row as a zero-padded linear convolution over the N_c
+ * columns; then x = (pi / N_v) A^T q with the adjoint of hsn_backproject.
+ *   sino [N_v][N_r][N_c] rays of k floats each, ray i at sino + i * ld
+ *        (ld >= k floats; ld = k: contiguous [N_v][N_r][N_c][k]; ld > k
+ *        reads k consecutive bins of a wider row, e.g. 8 bins of p),
+ *        4-byte aligned;
+ *   x    [N_r][N_c][N_c][k] out (alignment as hsn_backproject).
+ * Requires N_c * k <= 8192.  Workspace: N_v N_r N_c k floats.
+ */
+hsn_status hsn_fbp(hsn_ctx *ctx, const hsn_geom *g, const float *sino, int64_t ld, float *x, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Subspace expansion: eq. (6) x^h = x^s D^T over a voxel x bin range.   */
 /* ------------------------------------------------------------------ */
@@ -400,7 +417,8 @@ enum {
   HSN_KERN_MLP_WGRAD = 6,   /* warm-start network: weight-gradient contraction over the batch */
   HSN_KERN_NNDSVD_GRAM = 7, /* NNDSVD start: the Gram P^T P on MFMA */
   HSN_KERN_MLP_POOL = 8,    /* warm-start network: pooling of p_bf16 rows to 256 bins */
-  HSN_KERN_COUNT = 9
+  HSN_KERN_FBP_FILTER = 9,  /* FBP: the ramp filter of the detector rows */
+  HSN_KERN_COUNT = 10
 };
 
 /* When on != 0, every launch of the kernels above is bracketed by a pair of

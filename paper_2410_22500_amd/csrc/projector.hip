@@ -838,6 +838,59 @@ __global__ __launch_bounds__(256) void cgls_rstep_kernel(float *__restrict__ r, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// FBP ramp filter (band-limited ramp sampled at the detector pitch:
+// h[0] = 1/4, h[d] = -1/(pi^2 d^2) for odd d, 0 for even d != 0):
+//   q[row][c][:] = sum_{c'} h[c - c'] s[row][c'][:]   (zero-padded, not circular)
+// One workgroup per detector row (view, slice), the row staged in LDS; each
+// output sums the centre tap, then the odd taps d = 1, 3, ... (left before
+// right), in float32.
+// ---------------------------------------------------------------------------
+constexpr int kFbpMaxFloats = 8192;
+
+template <int K>
+__global__ __launch_bounds__(256) void ramp_filter_kernel(const float *__restrict__ s, int64_t ld, int n,
+                                                          float *__restrict__ q) {
+  __shared__ float row[kFbpMaxFloats];
+  __shared__ float hodd[kFbpMaxFloats / 2 + 1];  // h[2m + 1]
+  const int64_t rr = blockIdx.x;
+  const float *src = s + rr * n * ld;
+  for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
+    const int c = e / K, k = e - (e / K) * K;
+    row[e] = src[int64_t(c) * ld + k];
+  }
+  for (int m = threadIdx.x; 2 * m + 1 < n; m += blockDim.x) {
+    const double d = double(2 * m + 1);
+    hodd[m] = float(-1.0 / (M_PI * M_PI * d * d));
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    float acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.25f * row[c * K + k];
+    for (int m = 0; 2 * m + 1 < n; ++m) {
+      const int d = 2 * m + 1;
+      const float h = hodd[m];
+      if (c - d >= 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] = fmaf(h, row[(c - d) * K + k], acc[k]);
+      }
+      if (c + d < n) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] = fmaf(h, row[(c + d) * K + k], acc[k]);
+      }
+    }
+    float *dst = q + (rr * n + c) * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) dst[k] = acc[k];
+  }
+}
+
+template <int K>
+void launch_ramp(const float *s, int64_t ld, const hsn_geom *g, float *q, hipStream_t st) {
+  ramp_filter_kernel<K><<<unsigned(g->n_views * g->n_slices), 256, 0, st>>>(s, ld, int(g->n_cols), q);
+}
+
 hsn_status check_geom(hsn_ctx *ctx, const hsn_geom *g) {
   if (!g) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "geometry is NULL");
   if (g->n_views <= 0 || g->n_slices <= 0 || g->n_cols <= 0)
@@ -1295,5 +1348,34 @@ extern "C" hsn_status hsn_projector_launch_info(hsn_ctx *ctx, const hsn_geom *g,
   shape[1] = LA.lds ? LA.split : 0;
   shape[2] = LB.lds ? LB.vpt : 0;
   shape[3] = LB.lds ? LB.threads : 0;
+  return HSN_OK;
+}
+
+extern "C" hsn_status hsn_fbp(hsn_ctx *ctx, const hsn_geom *g, const float *sino, int64_t ld, float *x, void *stream) {
+  if (!ctx) return HSN_ERR_INVALID_ARG;
+  hsn_status rc = check_geom(ctx, g);
+  if (rc != HSN_OK) return rc;
+  if (!sino || !x) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "fbp: sino and x are required");
+  if (ld < g->k) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "fbp: ld must be >= k");
+  if (g->n_cols * g->k > kFbpMaxFloats)
+    return hsn::fail(ctx, HSN_ERR_SHAPE, "fbp: n_cols * k must be <= %d", kFbpMaxFloats);
+  if (reinterpret_cast<uintptr_t>(sino) % 4 != 0) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "fbp: sino not 4-byte aligned");
+  if ((rc = check_align(ctx, x, g->k, "x")) != HSN_OK) return rc;
+  hsn::DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t ns = g->n_views * g->n_slices * g->n_cols;
+  if ((rc = hsn::ensure_ws(ctx, sizeof(float) * size_t(ns) * g->k)) != HSN_OK) return rc;
+  float *q = static_cast<float *>(ctx->ws);
+  GeomTab gt{};
+  if ((rc = upload_geom(ctx, g, st, &gt)) != HSN_OK) return rc;
+  const ProjLaunch LB = plan_backproject(ctx, g);
+  hsn::prof_begin(ctx, HSN_KERN_FBP_FILTER, st);
+  HSN_DISPATCH_K(g->k, launch_ramp, sino, ld, g, q, st);
+  hsn::prof_end(ctx, HSN_KERN_FBP_FILTER, st);
+  const float scale = float(M_PI / double(g->n_views));
+  hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
+  HSN_DISPATCH_K(g->k, launch_backproject, LB, q, x, gt, g, scale, 0.0f, nullptr, st);
+  hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
+  HSN_LAUNCHED(ctx);
   return HSN_OK;
 }

@@ -30,8 +30,8 @@ INIT_USER, INIT_NNDSVDA, INIT_MLP = 0, 1, 2
 MLP_IN, MLP_HIDDEN = 256, 128
 
 (KERN_NMF_PASS, KERN_PROJECT, KERN_BACKPROJECT, KERN_NORMALIZE, KERN_NMF_PASS_BF16, KERN_MLP_ROWS,
- KERN_MLP_WGRAD, KERN_NNDSVD_GRAM, KERN_MLP_POOL) = range(9)
-KERN_COUNT = 9
+ KERN_MLP_WGRAD, KERN_NNDSVD_GRAM, KERN_MLP_POOL, KERN_FBP_FILTER) = range(10)
+KERN_COUNT = 10
 
 
 class Dims(C.Structure):
@@ -97,6 +97,8 @@ _lib.hsn_backproject.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_float, C.c_flo
 _lib.hsn_backproject.restype = C.c_int
 _lib.hsn_cgls.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_int, _P, _P]
 _lib.hsn_cgls.restype = C.c_int
+_lib.hsn_fbp.argtypes = [_P, C.POINTER(Geom), _P, C.c_int64, _P, _P]
+_lib.hsn_fbp.restype = C.c_int
 _lib.hsn_projector_set_launch.argtypes = [_P, C.c_int, C.c_int, C.c_int, C.c_int]
 _lib.hsn_projector_set_launch.restype = C.c_int
 _lib.hsn_projector_launch_info.argtypes = [_P, C.POINTER(Geom), C.POINTER(C.c_int)]
@@ -349,6 +351,20 @@ def hsn_cgls(sino: torch.Tensor, n_iter: int, angles: Optional[Sequence[float]] 
     rh = torch.empty((n_iter + 1, k), dtype=torch.float64, device=sino.device) if resid else None
     _check(_lib.hsn_cgls(ctx, C.byref(g), _ptr(sino), _ptr(x), n_iter, _ptr(rh), _stream(dev)), ctx)
     return (x, rh) if resid else x
+
+
+def hsn_fbp(sino: torch.Tensor, n_views: int, n_slices: int, n: int, k: int,
+            angles: Optional[Sequence[float]] = None, ld: Optional[int] = None,
+            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Filtered backprojection of k-channel rays (ray i at sino.data_ptr() + i * ld floats;
+    ld = k: sino is [N_v][N_r][N][k]) -> x [N_r][N][N][k]."""
+    dev = _dev(sino)
+    ctx = context(dev)
+    g, keep = _geom(n_views, n_slices, n, k, angles)
+    if out is None:
+        out = torch.empty((n_slices, n, n, k), dtype=torch.float32, device=sino.device)
+    _check(_lib.hsn_fbp(ctx, C.byref(g), _ptr(sino), int(ld or k), _ptr(out), _stream(dev)), ctx)
+    return out
 
 
 def hsn_rehydrate(xs: torch.Tensor, D: torch.Tensor, vox=None, bins=None) -> torch.Tensor:
