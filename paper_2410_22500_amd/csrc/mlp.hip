@@ -25,6 +25,7 @@
 #include <cstring>
 #include <numeric>
 #include <random>
+#include <type_traits>
 #include <vector>
 
 namespace hsn {
@@ -307,6 +308,116 @@ __global__ __launch_bounds__(256) void mlp_rows_kernel(RowsArgs a) {
     a.part_b[size_t(blockIdx.x) * kBiasCols + c] = s;
   }
   if (threadIdx.x == 0) a.part_loss[blockIdx.x] = redl[0] + redl[1] + redl[2] + redl[3];
+}
+
+// Inference of the bfloat16 network with two 16-row tiles per wave: every
+// weight fragment read from L2 feeds two MFMAs (half the weight traffic of
+// mlp_rows_kernel, which reads all weights for every 16 rows).  Per row the
+// arithmetic and the MFMA order are those of mlp_rows_kernel<uint16_t, K,
+// false>, so both give the same outputs.  A wave's h1 and then h2 share one
+// LDS tile pair (a wave's LDS accesses are performed in order).
+constexpr int kTilesW = 2;
+constexpr int kRowsB2 = kWaves * kTilesW * kRowsW;
+
+template <int K>
+__global__ __launch_bounds__(256) void mlp_infer2_kernel(RowsArgs a) {
+  using T = uint16_t;
+  using M = Mma<T>;
+  constexpr int E = M::E, KS = M::KS;
+  constexpr int LP = kHid + 16 / int(sizeof(T));
+  __shared__ __attribute__((aligned(16))) T buf[kWaves][kTilesW][kRowsW][LP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t wbase = int64_t(blockIdx.x) * kRowsB2 + w * (kTilesW * kRowsW);
+  const T *pub = static_cast<const T *>(a.pub);
+  const T *w1t = pub + kPubW1t, *w2t = pub + kPubW2t, *w3t = pub + kPubW3t;
+  const Layout L = layout(K);
+  const float *b1 = a.theta + L.b1, *b2 = a.theta + L.b2, *b3 = a.theta + L.b3;
+
+  f32x4 acc[kTilesW][8];
+  // ---- layer 1: z1 = x W1 + b1
+  {
+    const T *xr[kTilesW];
+    bool ok[kTilesW];
+#pragma unroll
+    for (int t = 0; t < kTilesW; ++t) {
+      const int64_t row = wbase + 16 * t + lr;
+      ok[t] = row < a.n;
+      const int64_t smp = ok[t] ? (a.idx ? int64_t(a.idx[a.row0 + row]) : a.row0 + row) : 0;
+      xr[t] = static_cast<const T *>(a.x) + smp * a.ldx + E * lg;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll 2
+    for (int s = 0; s < kIn / KS; ++s) {
+      typename M::frag fa[kTilesW];
+#pragma unroll
+      for (int t = 0; t < kTilesW; ++t) fa[t] = ok[t] ? M::load(xr[t] + s * KS) : M::zero();
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const typename M::frag fb = M::load(w1t + (16 * j + lr) * kIn + s * KS + E * lg);
+#pragma unroll
+        for (int t = 0; t < kTilesW; ++t) acc[t][j] = M::mma(fa[t], fb, acc[t][j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float bb = b1[16 * j + lr];
+#pragma unroll
+      for (int t = 0; t < kTilesW; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) buf[w][t][4 * lg + i][16 * j + lr] = M::cvt(gelu(acc[t][j][i] + bb));
+    }
+  }
+  __syncthreads();
+  // ---- layer 2: z2 = h1 W2 + b2
+  {
+#pragma unroll
+    for (int t = 0; t < kTilesW; ++t)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int s = 0; s < kHid / KS; ++s) {
+      typename M::frag fa[kTilesW];
+#pragma unroll
+      for (int t = 0; t < kTilesW; ++t) fa[t] = M::load(&buf[w][t][lr][s * KS + E * lg]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const typename M::frag fb = M::load(w2t + (16 * j + lr) * kHid + s * KS + E * lg);
+#pragma unroll
+        for (int t = 0; t < kTilesW; ++t) acc[t][j] = M::mma(fa[t], fb, acc[t][j]);
+      }
+    }
+    __syncthreads();  // every h1 read is done before h2 overwrites the tiles
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float bb = b2[16 * j + lr];
+#pragma unroll
+      for (int t = 0; t < kTilesW; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) buf[w][t][4 * lg + i][16 * j + lr] = M::cvt(gelu(acc[t][j][i] + bb));
+    }
+  }
+  __syncthreads();
+  // ---- layer 3: z3 = h2 W3 + b3, y = softplus(z3)
+  f32x4 c3[kTilesW];
+#pragma unroll
+  for (int t = 0; t < kTilesW; ++t) c3[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int s = 0; s < kHid / KS; ++s) {
+    const typename M::frag fb = M::load(w3t + lr * kHid + s * KS + E * lg);
+#pragma unroll
+    for (int t = 0; t < kTilesW; ++t) c3[t] = M::mma(M::load(&buf[w][t][lr][s * KS + E * lg]), fb, c3[t]);
+  }
+  const int col = lr;
+  const float bb3 = col < K ? b3[col] : 0.0f;
+#pragma unroll
+  for (int t = 0; t < kTilesW; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = wbase + 16 * t + 4 * lg + i;
+      if (col < K && row < a.n) a.y[(a.row0 + row) * a.ldy + col] = softplus(c3[t][i] + bb3);
+    }
 }
 
 struct WgradArgs {
@@ -616,6 +727,11 @@ template <class T>
 void launch_rows(int K, bool train, int n_blk, hipStream_t st, const RowsArgs &a) {
   if (train) {
 #define B(KK) mlp_rows_kernel<T, KK, true><<<n_blk, 256, 0, st>>>(a)
+    HSN_MLP_DISPATCH(K, B)
+#undef B
+  } else if (std::is_same<T, uint16_t>::value) {
+    const unsigned nb2 = unsigned((a.n + kRowsB2 - 1) / kRowsB2);
+#define B(KK) mlp_infer2_kernel<KK><<<nb2, 256, 0, st>>>(a)
     HSN_MLP_DISPATCH(K, B)
 #undef B
   } else {
