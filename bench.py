@@ -277,7 +277,7 @@ def main():
     triples = float(sc.n_views) * sc.n_rows * sc.n_cols * sc.n_cols * K
     mlp_flops_row = 2.0 * (256 * 128 + 128 * 128 + 128 * 16)
     work = {  # kind -> (name, total algorithmic units over the timed region, bound, unit)
-        hsn.KERN_NORMALIZE: ("normalize_kernel (u16 counts -> f32 p + pooled network input)",
+        hsn.KERN_NORMALIZE: ("normalize_u16_kernel (u16 counts -> f32 p + pooled network input)",
                              args.steps * (6.0 * elems + 2.0 * sc.n_rows * sc.n_cols * n_k +
                                            (512.0 if mlp.precision == hsn.PREC_BF16 else 1024.0) * n_p), "hbm"),
         hsn.KERN_NMF_PASS: ("pass_f32_kernel (N_V / N_D passes over f32 p)",

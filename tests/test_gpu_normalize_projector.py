@@ -42,10 +42,13 @@ def test_normalize_tiny_config(hsn, flt):
     assert abs(ss.item() - ss_ref) <= 1e-6 * ss_ref
 
 
-def test_normalize_ragged_floor_offset_noclip(hsn):
-    # 37 bins (not a multiple of 8), zero counts, a background mask and no clip.
+@pytest.mark.parametrize("n_k", [37, 64])
+def test_normalize_ragged_floor_offset_noclip(hsn, n_k):
+    # Zero counts, a background mask and no clip; 37 bins (not a multiple of
+    # 8: the general kernel) and 64 bins (whole 8-bin chunks: the uint16 fast
+    # kernel with the offset and the bfloat16 copy).
     g = np.random.Generator(np.random.PCG64(5))
-    n_v, n_r, n_c, n_k = 7, 3, 10, 37
+    n_v, n_r, n_c = 7, 3, 10
     yo = g.poisson(500, (n_r, n_c, n_k)).astype(np.uint16)
     y = g.poisson(300, (n_v, n_r, n_c, n_k)).astype(np.uint16)
     y[0, 0, 0, :5] = 0
@@ -59,6 +62,33 @@ def test_normalize_ragged_floor_offset_noclip(hsn):
     _check_p(p[:, :n_k].cpu().numpy(), p_ref)
     assert rel_fro(b.cpu().numpy(), b_ref) <= 1e-6
     assert abs(ss.item() - ss_ref) <= 1e-6 * ss_ref
+
+
+@pytest.mark.parametrize("n_k,mask", [(1024, False), (64, True), (2000, True)])
+def test_normalize_fast_kernel_matches_general(hsn, n_k, mask):
+    # 16-byte aligned uint16 counts in whole 8-bin chunks take the fast
+    # kernel; the same open beam at an odd address takes the general one
+    # (scalar loads).  Same rows per block and summation order: the same p,
+    # offset, pooled rows and sum of squares, bit for bit.
+    import torch
+    g = np.random.Generator(np.random.PCG64(n_k + 3))
+    n_v, n_r, n_c = 3, 4, 5
+    y = torch.from_numpy(g.integers(0, 4000, (n_v, n_r, n_c, n_k), dtype=np.uint16).view(np.int16)).cuda()
+    yo_h = torch.from_numpy(g.integers(1000, 6000, (n_r, n_c, n_k), dtype=np.uint16).view(np.int16))
+    yo = yo_h.cuda()
+    yo_odd = torch.zeros(n_r * n_c * n_k + 1, dtype=torch.int16, device="cuda")[1:].view(n_r, n_c, n_k)
+    yo_odd.copy_(yo)
+    assert yo_odd.data_ptr() % 16 != 0
+    bg = torch.from_numpy((g.random((n_r, n_c)) < 0.3).astype(np.uint8)).cuda() if mask else None
+    if bg is not None:
+        bg[0, 0] = 1
+    show("normalize fast vs general", n_k=n_k, mask=mask)
+    p0, _, pooled0, b0, ss0 = hsn.hsn_normalize_pooled(y, yo, hsn.PREC_BF16, bg_mask=bg, want_offset=mask)
+    p1, _, pooled1, b1, ss1 = hsn.hsn_normalize_pooled(y, yo_odd, hsn.PREC_BF16, bg_mask=bg, want_offset=mask)
+    assert torch.equal(p0[:, :n_k], p1[:, :n_k]) and torch.equal(pooled0, pooled1)
+    assert float(ss0) == float(ss1)
+    if mask:
+        assert torch.equal(b0, b1)
 
 
 def test_normalize_mid_config_sampled_rows(hsn):
@@ -80,7 +110,8 @@ def test_normalize_mid_config_sampled_rows(hsn):
 
 @pytest.mark.parametrize("n_k,shape,prec,mask", [(1024, (3, 4, 5), 1, False), (2000, (2, 3, 4), 0, True),
                                                  (300, (2, 2, 7), 1, True), (37, (1, 3, 3), 0, False),
-                                                 (256, (5, 1, 9), 1, False)])
+                                                 (256, (5, 1, 9), 1, False),
+                                                 (1024, (2, 3, 4), 0, True)])
 def test_normalize_pooled_matches_separate_calls(hsn, n_k, shape, prec, mask):
     # The fused pass writes the same p, p_bf16 and offset as hsn_normalize,
     # and pooled rows equal to pooling its p_bf16 with hsn_mlp_pool, bit for
