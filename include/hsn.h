@@ -274,6 +274,33 @@ hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sino, float *x
                     int n_iter, double *resid, void *stream);
 
 /*
+ * eq. (5) with the qGGMRF prior h (the paper's MBIR), every channel j:
+ *   x_j = argmin 1/(2 sigma_v[j]^2) ||V_j - A x_j||^2 + h(x_j),
+ *   h(x) = sum over 8-neighbour pairs {s, r} inside a slice of
+ *          b_sr rho(x_s - x_r),  b = w1 (nearest), w1/sqrt(2) (diagonal),
+ *          w1 = 1/(4 + 2 sqrt(2)), pixels outside the image omitted;
+ *   rho(d) = |d|^p / (p sx^p) u / (1 + u),  u = |d / (T sx)|^(2-p),  sx = sigma_x[j]
+ * (q = 2; the paper gives no prior parameters: these are the standard
+ * qGGMRF form and a stated reading).  Majorisation-minimisation: each of
+ * n_outer iterations takes the symmetric-bound quadratic surrogate of h at
+ * the current x and runs n_inner conjugate-gradient iterations on
+ * (A^T A + sigma_v^2 L) x = A^T V from the current x (the cost never
+ * increases in exact arithmetic).  Per inner iteration: one A, one A^T, one
+ * prior stencil and three small kernels; per outer iteration one more A,
+ * A^T and stencil.  No positivity constraint.
+ *   sino [N_v][N_r][N_c][K] float32 in (device);
+ *   x [N_r][N_c][N_c][K] float32 in/out (device): the start on entry
+ *     (zeros for a cold start), the estimate on return;
+ *   sigma_v, sigma_x: host arrays of K doubles, each finite and > 0;
+ *   1 <= p <= 2, T > 0.
+ * Errors (nothing launched): HSN_ERR_INVALID_ARG for NULL pointers, bad
+ * parameters, misaligned x or sino; HSN_ERR_SHAPE for bad geometry;
+ * HSN_ERR_OOM if the workspace (6 volumes + 1 sinogram) cannot be allocated.
+ */
+hsn_status hsn_mbir(hsn_ctx *ctx, const hsn_geom *g, const float *sino, float *x, const double *sigma_v,
+                    const double *sigma_x, double p, double T, int n_outer, int n_inner, void *stream);
+
+/*
  * Filtered backprojection, the per-channel reconstruction the paper uses
  * for its DHR baseline (one FBP per wavelength bin) and for "FHR with FBP"
  * (FBP of the K subspace sinograms); Section V, Tables II and IV.  The

@@ -839,6 +839,129 @@ __global__ __launch_bounds__(256) void cgls_rstep_kernel(float *__restrict__ r, 
 }
 
 // ---------------------------------------------------------------------------
+// qGGMRF prior of eq. (5) (q = 2): h(x) = sum over 8-neighbour pairs {s, r}
+// inside a slice of b_sr rho(x_s - x_r), b = w1 (nearest), w1 / sqrt(2)
+// (diagonal), w1 = 1 / (4 + 2 sqrt(2));
+//   rho(d) = |d|^p / (p sx^p) u / (1 + u),  u = |d / (T sx)|^(2 - p).
+// The majorisation-minimisation solver uses its symmetric-bound quadratic
+// surrogate with a(d) = rho'(|d|) / (2 |d|) = c0 / (1 + u) (1 + ((2 - p) / p) / (1 + u)),
+// c0 = 1 / (2 sx^2 T^(2-p)), and the surrogate Hessian
+//   (L v)_s = 2 sum_r b_sr a(x'_s - x'_r) (v_s - v_r)   (x' the anchor).
+// ---------------------------------------------------------------------------
+struct PriorArgs {
+  float c0[8];       // 1 / (2 sigma_x^2 T^(2-p)) per channel
+  float inv_tsx[8];  // 1 / (T sigma_x)
+  float s2[8];       // sigma_v^2
+  float e;           // 2 - p
+  float rq;          // (2 - p) / p
+};
+
+constexpr float kPriorW1 = 0.14644660940672624f;   // 1 / (4 + 2 sqrt(2))
+constexpr float kPriorW2 = 0.10355339059327377f;   // w1 / sqrt(2)
+constexpr int kPriorBlocks = 1024;
+
+__device__ __forceinline__ float prior_coef(float d, float c0, float inv_tsx, float e, float rq) {
+  const float u = (e == 0.0f) ? 1.0f : powf(fabsf(d) * inv_tsx, e);
+  const float iu = 1.0f / (1.0f + u);
+  return c0 * iu * fmaf(rq, iu, 1.0f);
+}
+
+// w_s += sign sigma_v^2 (L v)_s for every voxel, L with the weights of the
+// anchor xa; per-block float64 partials of <v, w_new> (dot_self = 0) or
+// <w_new, w_new> (dot_self = 1) per channel.  Fixed grid (grid-stride over
+// voxels), so the sums have a fixed order.
+template <int K>
+__global__ __launch_bounds__(256) void prior_apply_kernel(const float *__restrict__ xa, const float *__restrict__ v,
+                                                          float *__restrict__ w, int n, int64_t n_vox, PriorArgs pa,
+                                                          float sign, int dot_self, double *__restrict__ partial) {
+  double dot[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) dot[q] = 0.0;
+  const int64_t nn = int64_t(n) * n;
+  for (int64_t vox = int64_t(blockIdx.x) * 256 + threadIdx.x; vox < n_vox; vox += int64_t(gridDim.x) * 256) {
+    const int64_t r = vox / nn;
+    const int rem = int(vox - r * nn);
+    const int j = rem / n, i = rem - (rem / n) * n;
+    float as[K], vs[K], acc[K];
+    load_k<K>(xa + vox * K, as);
+    load_k<K>(v + vox * K, vs);
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.0f;
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) {
+      const int dj = (nb < 3) ? -1 : (nb < 5 ? 0 : 1);               // rows above, same row, below
+      const int di = (nb < 3) ? nb - 1 : (nb < 5 ? 2 * nb - 7 : nb - 6);  // -1 0 1 | -1 1 | -1 0 1
+      const int jj = j + dj, ii = i + di;
+      if (jj < 0 || jj >= n || ii < 0 || ii >= n) continue;
+      const float b = (dj == 0 || di == 0) ? kPriorW1 : kPriorW2;
+      const int64_t o = (r * nn + int64_t(jj) * n + ii) * K;
+      float ar[K], vr[K];
+      load_k<K>(xa + o, ar);
+      load_k<K>(v + o, vr);
+#pragma unroll
+      for (int q = 0; q < K; ++q)
+        acc[q] = fmaf(b * prior_coef(as[q] - ar[q], pa.c0[q], pa.inv_tsx[q], pa.e, pa.rq), vs[q] - vr[q], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const float res = fmaf(sign * pa.s2[q], 2.0f * acc[q], w[vox * K + q]);
+      w[vox * K + q] = res;
+      dot[q] += double(dot_self ? res : vs[q]) * double(res);
+    }
+  }
+  __shared__ double red[4][K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const double t = hsn::wave_sum_all(dot[q]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = t;
+  }
+  __syncthreads();
+  if (int(threadIdx.x) < K) {
+    const int q = threadIdx.x;
+    partial[size_t(blockIdx.x) * K + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+  }
+}
+
+// CG step of the surrogate solve: x += alpha d, r -= alpha w (alpha per
+// channel from st), per-block partials of <r, r>.  Fixed grid.
+template <int K>
+__global__ __launch_bounds__(kDotThreads) void mbir_step_kernel(float *__restrict__ x, const float *__restrict__ d,
+                                                                float *__restrict__ r, const float *__restrict__ w,
+                                                                int64_t n_vox, const double *__restrict__ st,
+                                                                double *__restrict__ partial) {
+  float al[K];
+  double dot[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    al[q] = float(st[kAlphaOff + q]);
+    dot[q] = 0.0;
+  }
+  for (int64_t vox = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; vox < n_vox;
+       vox += int64_t(gridDim.x) * kDotThreads) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int64_t e = vox * K + q;
+      x[e] = fmaf(al[q], d[e], x[e]);
+      const float rn = fmaf(-al[q], w[e], r[e]);
+      r[e] = rn;
+      dot[q] += double(rn) * double(rn);
+    }
+  }
+  __shared__ double red[kDotThreads / 64][K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const double t = hsn::wave_sum_all(dot[q]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = t;
+  }
+  __syncthreads();
+  if (int(threadIdx.x) < K) {
+    double t = 0.0;
+    for (int wv = 0; wv < kDotThreads / 64; ++wv) t += red[wv][threadIdx.x];
+    partial[size_t(blockIdx.x) * K + threadIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FBP ramp filter (band-limited ramp sampled at the detector pitch:
 // h[0] = 1/4, h[d] = -1/(pi^2 d^2) for odd d, 0 for even d != 0):
 //   q[row][c][:] = sum_{c'} h[c - c'] s[row][c'][:]   (zero-padded, not circular)
@@ -1182,6 +1305,20 @@ void launch_dot(const float *a, const float *b, int64_t n_items, double *partial
   chan_dot_kernel<K><<<kDotBlocks, kDotThreads, 0, st>>>(a, b, n_items, partial);
 }
 
+template <int K>
+void launch_prior_apply(const float *xa, const float *v, float *w, const hsn_geom *g, const PriorArgs &pa, float sign,
+                        int dot_self, double *partial, hipStream_t st) {
+  const int64_t n_vox = int64_t(g->n_slices) * g->n_cols * g->n_cols;
+  prior_apply_kernel<K><<<kPriorBlocks, 256, 0, st>>>(xa, v, w, int(g->n_cols), n_vox, pa, sign, dot_self, partial);
+}
+
+template <int K>
+void launch_mbir_step(float *x, const float *d, float *r, const float *w, const hsn_geom *g, const double *scal,
+                      double *partial, hipStream_t st) {
+  const int64_t n_vox = int64_t(g->n_slices) * g->n_cols * g->n_cols;
+  mbir_step_kernel<K><<<kDotBlocks, kDotThreads, 0, st>>>(x, d, r, w, n_vox, scal, partial);
+}
+
 hsn_status check_align(hsn_ctx *ctx, const void *p, int k, const char *what) {
   const uintptr_t a = reinterpret_cast<uintptr_t>(p);
   const uintptr_t need = (k == 4 || k == 8) ? 16 : (k == 2 ? 8 : 4);
@@ -1316,6 +1453,82 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
   }
   // The fused path adds alpha p to x in the direction step, which the last
   // iteration still runs; nothing is left to add here.
+  HSN_LAUNCHED(ctx);
+  return HSN_OK;
+}
+
+extern "C" hsn_status hsn_mbir(hsn_ctx *ctx, const hsn_geom *g, const float *sino, float *x, const double *sigma_v,
+                               const double *sigma_x, double p, double T, int n_outer, int n_inner, void *stream) {
+  if (!ctx) return HSN_ERR_INVALID_ARG;
+  hsn_status rc = check_geom(ctx, g);
+  if (rc != HSN_OK) return rc;
+  if (!sino || !x || !sigma_v || !sigma_x)
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "mbir: sino, x, sigma_v and sigma_x are required");
+  if (n_outer < 0 || n_inner < 0) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "mbir: iteration counts must be >= 0");
+  if (!(p >= 1.0 && p <= 2.0)) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "mbir: p must be in [1, 2] (got %g)", p);
+  if (!(T > 0.0) || !std::isfinite(T)) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "mbir: T must be > 0");
+  const int K = g->k;
+  PriorArgs pa{};
+  for (int q = 0; q < K; ++q) {
+    if (!(sigma_v[q] > 0.0) || !(sigma_x[q] > 0.0) || !std::isfinite(sigma_v[q]) || !std::isfinite(sigma_x[q]))
+      return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "mbir: sigma_v[%d] and sigma_x[%d] must be finite and > 0", q, q);
+    pa.c0[q] = float(1.0 / (2.0 * sigma_x[q] * sigma_x[q] * std::pow(T, 2.0 - p)));
+    pa.inv_tsx[q] = float(1.0 / (T * sigma_x[q]));
+    pa.s2[q] = float(sigma_v[q] * sigma_v[q]);
+  }
+  pa.e = float(2.0 - p);
+  pa.rq = float((2.0 - p) / p);
+  if ((rc = check_align(ctx, x, K, "x")) != HSN_OK || (rc = check_align(ctx, sino, K, "sino")) != HSN_OK) return rc;
+  hsn::DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t n = g->n_cols;
+  const int64_t nx = g->n_slices * n * n;           // voxels
+  const int64_t ns = g->n_views * g->n_slices * n;  // rays
+  GeomTab gt{};
+  if ((rc = upload_geom(ctx, g, st, &gt)) != HSN_OK) return rc;
+  const ProjLaunch LA = plan_project(ctx, g, gt.n_groups), LB = plan_backproject(ctx, g);
+  const size_t n_part = std::max<size_t>(kPriorBlocks, kDotBlocks);
+  const size_t need = hsn::Carver::need({sizeof(float) * ns * K, sizeof(float) * nx * K, sizeof(float) * nx * K,
+                                         sizeof(float) * nx * K, sizeof(float) * nx * K, sizeof(float) * nx * K,
+                                         sizeof(float) * nx * K, sizeof(double) * n_part * K, sizeof(double) * kScal});
+  if ((rc = hsn::ensure_ws(ctx, need)) != HSN_OK) return rc;
+  hsn::Carver cv(ctx->ws);
+  float *s = cv.take<float>(ns * K);
+  float *xa = cv.take<float>(nx * K), *xT = cv.take<float>(nx * K), *r = cv.take<float>(nx * K);
+  float *d = cv.take<float>(nx * K), *dT = cv.take<float>(nx * K), *w = cv.take<float>(nx * K);
+  double *partial = cv.take<double>(n_part * K), *scal = cv.take<double>(kScal);
+
+  for (int outer = 0; outer < n_outer; ++outer) {
+    // Anchor x' = x; r = A^T (V - A x) - sigma_v^2 L x; d = r; gamma = <r, r>.
+    HSN_HIP(ctx, hipMemcpyAsync(xa, x, sizeof(float) * nx * K, hipMemcpyDeviceToDevice, st));
+    HSN_HIP(ctx, hipMemcpyAsync(s, sino, sizeof(float) * ns * K, hipMemcpyDeviceToDevice, st));
+    HSN_DISPATCH_K(K, launch_xpby_t, x, xT, nullptr, nullptr, g, 0, st);
+    hsn::prof_begin(ctx, HSN_KERN_PROJECT, st);
+    HSN_DISPATCH_K(K, launch_project, LA, x, xT, s, gt, g, -1.0f, 1.0f, nullptr, st);
+    hsn::prof_end(ctx, HSN_KERN_PROJECT, st);
+    hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
+    HSN_DISPATCH_K(K, launch_backproject, LB, s, r, gt, g, 1.0f, 0.0f, nullptr, st);
+    hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
+    HSN_DISPATCH_K(K, launch_prior_apply, xa, x, r, g, pa, -1.0f, 1, partial, st);
+    cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kPriorBlocks, K, kSetGamma, scal, 0, nullptr);
+    HSN_DISPATCH_K(K, launch_xpby_t, d, dT, r, nullptr, g, 2, st);
+    for (int it = 0; it < n_inner; ++it) {
+      const int gsel = it & 1;
+      // w = (A^T A + sigma_v^2 L) d; alpha = gamma / <d, w>
+      hsn::prof_begin(ctx, HSN_KERN_PROJECT, st);
+      HSN_DISPATCH_K(K, launch_project, LA, d, dT, s, gt, g, 1.0f, 0.0f, nullptr, st);
+      hsn::prof_end(ctx, HSN_KERN_PROJECT, st);
+      hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
+      HSN_DISPATCH_K(K, launch_backproject, LB, s, w, gt, g, 1.0f, 0.0f, nullptr, st);
+      hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
+      HSN_DISPATCH_K(K, launch_prior_apply, xa, d, w, g, pa, 1.0f, 0, partial, st);
+      cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kPriorBlocks, K, kAlpha, scal, gsel, nullptr);
+      // x += alpha d; r -= alpha w; beta = <r, r> / gamma; d = r + beta d
+      HSN_DISPATCH_K(K, launch_mbir_step, x, d, r, w, g, scal, partial, st);
+      cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kBeta, scal, gsel, nullptr);
+      HSN_DISPATCH_K(K, launch_xpby_t, d, dT, r, scal + kBetaOff, g, 1, st);
+    }
+  }
   HSN_LAUNCHED(ctx);
   return HSN_OK;
 }

@@ -99,6 +99,9 @@ _lib.hsn_cgls.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_int, _P, _P]
 _lib.hsn_cgls.restype = C.c_int
 _lib.hsn_fbp.argtypes = [_P, C.POINTER(Geom), _P, C.c_int64, _P, _P]
 _lib.hsn_fbp.restype = C.c_int
+_lib.hsn_mbir.argtypes = [_P, C.POINTER(Geom), _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                         C.c_double, C.c_int, C.c_int, _P]
+_lib.hsn_mbir.restype = C.c_int
 _lib.hsn_projector_set_launch.argtypes = [_P, C.c_int, C.c_int, C.c_int, C.c_int]
 _lib.hsn_projector_set_launch.restype = C.c_int
 _lib.hsn_projector_launch_info.argtypes = [_P, C.POINTER(Geom), C.POINTER(C.c_int)]
@@ -351,6 +354,30 @@ def hsn_cgls(sino: torch.Tensor, n_iter: int, angles: Optional[Sequence[float]] 
     rh = torch.empty((n_iter + 1, k), dtype=torch.float64, device=sino.device) if resid else None
     _check(_lib.hsn_cgls(ctx, C.byref(g), _ptr(sino), _ptr(x), n_iter, _ptr(rh), _stream(dev)), ctx)
     return (x, rh) if resid else x
+
+
+def hsn_mbir(sino: torch.Tensor, sigma_v, sigma_x, p: float = 1.2, T: float = 1.0, n_outer: int = 10,
+             n_inner: int = 5, x0: Optional[torch.Tensor] = None, angles: Optional[Sequence[float]] = None):
+    """qGGMRF-MBIR per channel: sino [N_v][N_r][N][K] -> x [N_r][N][N][K].  sigma_v, sigma_x: a
+    scalar or K values; x0: the start (default zeros), copied."""
+    dev = _dev(sino)
+    ctx = context(dev)
+    n_v, n_r, n, k = sino.shape
+    g, keep = _geom(n_v, n_r, n, k, angles)
+    def per_channel(v):
+        vals = [float(t) for t in v] if hasattr(v, "__len__") else [float(v)] * k
+        if len(vals) != k:
+            raise ValueError(f"expected {k} per-channel values, got {len(vals)}")
+        return (C.c_double * k)(*vals)
+
+    sv, sx = per_channel(sigma_v), per_channel(sigma_x)
+    if x0 is None:
+        x = torch.zeros((n_r, n, n, k), dtype=torch.float32, device=sino.device)
+    else:
+        x = x0.to(device=sino.device, dtype=torch.float32).contiguous().clone()
+    _check(_lib.hsn_mbir(ctx, C.byref(g), _ptr(sino), _ptr(x), sv, sx, float(p), float(T), int(n_outer),
+                         int(n_inner), _stream(dev)), ctx)
+    return x
 
 
 def hsn_fbp(sino: torch.Tensor, n_views: int, n_slices: int, n: int, k: int,
