@@ -860,9 +860,13 @@ constexpr float kPriorW1 = 0.14644660940672624f;   // 1 / (4 + 2 sqrt(2))
 constexpr float kPriorW2 = 0.10355339059327377f;   // w1 / sqrt(2)
 constexpr int kPriorBlocks = 1024;
 
+// u = 2^(e log2 t) and 1 / (1 + u) on the hardware exp2, log2 and reciprocal
+// (about 1 ulp each); t = 0 gives log2 = -inf and u = 0.  Both ends of an
+// edge evaluate the same |d| with the same instructions, so L stays
+// symmetric bit for bit.
 __device__ __forceinline__ float prior_coef(float d, float c0, float inv_tsx, float e, float rq) {
-  const float u = (e == 0.0f) ? 1.0f : powf(fabsf(d) * inv_tsx, e);
-  const float iu = 1.0f / (1.0f + u);
+  const float u = (e == 0.0f) ? 1.0f : __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(fabsf(d) * inv_tsx));
+  const float iu = __builtin_amdgcn_rcpf(1.0f + u);
   return c0 * iu * fmaf(rq, iu, 1.0f);
 }
 
