@@ -284,7 +284,7 @@ def main():
                             args.steps * (4.0 * elems + vb) + rounds * 2 * (4.0 * elems + vb), "hbm"),
         hsn.KERN_MLP_POOL: ("pool_kernel (bf16 p -> 256-bin pooled rows)",
                             args.steps * (2.0 * elems + 512.0 * n_p), "hbm"),
-        hsn.KERN_MLP_ROWS: ("mlp_rows_kernel (network inference, bf16 MFMA)",
+        hsn.KERN_MLP_ROWS: ("mlp_infer2_kernel (network inference, bf16 MFMA)",
                             args.steps * mlp_flops_row * n_p, "mfma"),
         hsn.KERN_PROJECT: ("project_lds_kernel (A, Joseph footprint, K channels, LDS-staged)", None, "alu"),
         hsn.KERN_BACKPROJECT: ("backproject_lds_kernel (A^T, LDS-staged)", None, "alu"),

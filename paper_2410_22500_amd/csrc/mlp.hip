@@ -319,8 +319,11 @@ __global__ __launch_bounds__(256) void mlp_rows_kernel(RowsArgs a) {
 constexpr int kTilesW = 2;
 constexpr int kRowsB2 = kWaves * kTilesW * kRowsW;
 
+// Four waves per SIMD (at most 128 registers, no spills): a CU holds four
+// workgroups, 1024 on the chip, so the mid workload's 960 row blocks run in
+// one round instead of 768 plus a quarter-full second round at three.
 template <int K>
-__global__ __launch_bounds__(256) void mlp_infer2_kernel(RowsArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mlp_infer2_kernel(RowsArgs a) {
   using T = uint16_t;
   using M = Mma<T>;
   constexpr int E = M::E, KS = M::KS;

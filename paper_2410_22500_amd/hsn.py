@@ -446,7 +446,8 @@ class Mlp:
         self.n_params = hsn_mlp_n_params(self.k)
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.hsn_mlp_destroy(self.handle)
             self.handle = None
 
