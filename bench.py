@@ -59,7 +59,66 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy of 1 GiB (reference for HBM counters) and exit")
+    ap.add_argument("--traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="turn two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, WRITE_SIZE; csv) into "
+                         "HBM bytes per launch of the mid-shape kernels, scaled by the copy probe, and exit")
     return ap.parse_args()
+
+
+# Kernels whose every launch in the mid benchmark has the mid shape (the CGLS
+# and MBIR loops of the measured steps), their template instance and source.
+TRAFFIC_KERNELS = {
+    "project_lds_kernel": ("project_lds_kernel<4, true>", "paper_2410_22500_amd/csrc/projector.hip"),
+    "backproject_lds_kernel": ("backproject_lds_kernel<4, 1, true>", "paper_2410_22500_amd/csrc/projector.hip"),
+    "xpby_transpose_kernel": ("xpby_transpose_kernel<4>", "paper_2410_22500_amd/csrc/projector.hip"),
+    "cgls_rstep_kernel": ("cgls_rstep_kernel(", "paper_2410_22500_amd/csrc/projector.hip"),
+    "prior_apply_kernel": ("prior_apply_kernel<4>", "paper_2410_22500_amd/csrc/projector.hip"),
+    "mbir_step_kernel": ("mbir_step_kernel<4>", "paper_2410_22500_amd/csrc/projector.hip"),
+}
+
+
+def traffic_from_counters(fetch_dir, write_dir, out_json):
+    """Average FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel from the
+    rocprofv3 csv output, times the copy probe's bytes-per-KiB factors (kept in
+    the existing record), with the SHA-256 of each kernel's source file."""
+    import csv
+    import glob
+    import hashlib
+
+    def per_kernel(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        acc = {}
+        for fn in files:
+            for row in csv.DictReader(open(fn)):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name = row.get("Kernel_Name", "")
+                for key, (inst, _) in TRAFFIC_KERNELS.items():
+                    if inst in name and not (key == "project_lds_kernel" and "backproject" in name):
+                        acc.setdefault(key, []).append(float(row["Counter_Value"]))
+        return acc
+
+    old = json.load(open(out_json)) if os.path.exists(out_json) else {}
+    probe = old.get("copy_probe")
+    if not probe:
+        sys.exit("--traffic: the copy probe factors are missing from " + out_json)
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    kernels = {}
+    for key, (inst, src) in TRAFFIC_KERNELS.items():
+        if key not in fetch or key not in write:
+            continue
+        fk = sum(fetch[key]) / len(fetch[key])
+        wk = sum(write[key]) / len(write[key])
+        fb, wb = fk * 1024 * probe["fetch_factor"], wk * 1024 * probe["write_factor"]
+        kernels[key] = {"instance": inst.rstrip("("), "workload": "mid (60 views, 16 slices, 128 columns, K=4)",
+                        "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+                        "dispatches": [len(fetch[key]), len(write[key])], "fetch_bytes": fb, "write_bytes": wb,
+                        "hbm_bytes_per_launch": fb + wb, "source": src,
+                        "source_sha256": hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()}
+    rec = {"note": old.get("note", ""), "copy_probe": probe, "kernels": kernels}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps({k: round(v["hbm_bytes_per_launch"] / 1e6, 3) for k, v in kernels.items()}), flush=True)
 
 
 def copy_probe():
@@ -93,9 +152,12 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
+    if args.traffic:
+        traffic_from_counters(*args.traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "how the path would shard is described in DESIGN.md but not built.", file=sys.stderr)
+              "sharding across GPUs is designed but not built.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
         run_batched(args)

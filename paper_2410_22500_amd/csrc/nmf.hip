@@ -79,7 +79,11 @@ hsn_status queue_step(Run &R, const Step &s, int iter, bool next_exact, const fl
   const bool obj = s.obj || s.rule == kModeANLS;
   if (s.rule == kModeANLS) {
     prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
-    launch_pass_f32(R.K, kModeNV, false, nq, n_wg, R.st, p, ldp, R.n_p, R.n_k, V, R.w.nv, D, R.w.gd, R.w.chol,
+    // The N_V pass writes no per-workgroup partials, so it takes up to 8
+    // workgroups per CU for latency hiding (same rows per workgroup rule,
+    // same results): 98 -> 86 us at mid.
+    const int wg_nv = int(std::min<int64_t>((R.n_p + 7) / 8, 8 * int64_t(R.ctx->num_cu)));
+    launch_pass_f32(R.K, kModeNV, false, nq, wg_nv, R.st, p, ldp, R.n_p, R.n_k, V, R.w.nv, D, R.w.gd, R.w.chol,
                     R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter);
     prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
     const int nb = int(std::min<int64_t>((R.n_p + 255) / 256, 8 * int64_t(R.ctx->num_cu)));
