@@ -235,12 +235,23 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   HSN_LAUNCHED(ctx);
   // Queue in chunks; between chunks read stop_at once (only when a stop test
   // is on).  The stop can only fire at a step that evaluates the objective, so
-  // a chunk ends after a number of such steps that starts at 2 and doubles up
-  // to 32: a run that converges early (a learned start) queues few launches
+  // a chunk ends after a number of such steps that starts at 1 and doubles up
+  // to 32: a run that converges at once (a learned start) queues no launches
   // past its stop, a long run pays few host round trips.
-  int issued = 0, chunk_obj = 2;
+  int issued = 0, chunk_obj = 1;
   NmfCtrl hc{};
   hc.stop_at = INT32_MAX;
+  // With stats requested, each stop-test read-back also brings the history
+  // (one round trip); when the loop ends on such a read-back, the stats need
+  // no second one.
+  NmfCtrl *hcp = nullptr;
+  double *hh = nullptr;
+  if (stats) {
+    if ((rc = ensure_host_stage(ctx, sizeof(NmfCtrl) + sizeof(double) * hist_cap)) != HSN_OK) return rc;
+    hcp = static_cast<NmfCtrl *>(ctx->host_stage);
+    hh = reinterpret_cast<double *>(static_cast<char *>(ctx->host_stage) + sizeof(NmfCtrl));
+  }
+  bool staged = false;
   while (issued < int(steps.size())) {
     int end = issued, n_obj = 0;
     while (end < int(steps.size()) && n_obj < chunk_obj) {
@@ -253,21 +264,31 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
       if ((rc = queue_step(R, steps[i], i, next_exact, p, ldp, p_bf16, ldb, V, D)) != HSN_OK) return rc;
     }
     issued = end;
+    staged = false;
     if (stop_test && issued < int(steps.size())) {
-      HSN_HIP(ctx, hipMemcpyAsync(&hc, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
-      HSN_HIP(ctx, hipStreamSynchronize(st));
+      if (stats) {
+        HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
+        HSN_HIP(ctx, hipMemcpyAsync(hcp, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
+        HSN_HIP(ctx, hipMemcpyAsync(hh, R.w.hist, sizeof(double) * hist_cap, hipMemcpyDeviceToHost, st));
+        HSN_HIP(ctx, hipStreamSynchronize(st));
+        hc = *hcp;
+        staged = true;
+      } else {
+        HSN_HIP(ctx, hipMemcpyAsync(&hc, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
+        HSN_HIP(ctx, hipStreamSynchronize(st));
+      }
       if (hc.stop_at <= issued) break;
     }
   }
   if (stats) {
-    // One round trip: control block and the whole history into pinned memory.
-    HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
-    if ((rc = ensure_host_stage(ctx, sizeof(NmfCtrl) + sizeof(double) * hist_cap)) != HSN_OK) return rc;
-    NmfCtrl *hcp = static_cast<NmfCtrl *>(ctx->host_stage);
-    double *hh = reinterpret_cast<double *>(static_cast<char *>(ctx->host_stage) + sizeof(NmfCtrl));
-    HSN_HIP(ctx, hipMemcpyAsync(hcp, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
-    HSN_HIP(ctx, hipMemcpyAsync(hh, R.w.hist, sizeof(double) * hist_cap, hipMemcpyDeviceToHost, st));
-    HSN_HIP(ctx, hipStreamSynchronize(st));
+    // One round trip (control block and the whole history into pinned
+    // memory), unless the last stop test already brought them.
+    if (!staged) {
+      HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
+      HSN_HIP(ctx, hipMemcpyAsync(hcp, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
+      HSN_HIP(ctx, hipMemcpyAsync(hh, R.w.hist, sizeof(double) * hist_cap, hipMemcpyDeviceToHost, st));
+      HSN_HIP(ctx, hipStreamSynchronize(st));
+    }
     hc = *hcp;
     float ms = 0.f;
     HSN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));

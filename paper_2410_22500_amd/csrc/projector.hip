@@ -796,9 +796,28 @@ __global__ __launch_bounds__(256) void cgls_scalar_kernel(const double *__restri
   }
 }
 
-__global__ void fill_zero_kernel(float *__restrict__ y, int64_t n) {
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
-    y[e] = 0.0f;
+// CGLS start in one launch: x = 0 over nx values, r = b over nr values (a
+// kernel rather than a runtime copy, which leaves a gap before the next
+// kernel on the stream).
+__global__ void cgls_start_kernel(float *__restrict__ x, int64_t nx, float *__restrict__ r,
+                                  const float *__restrict__ b, int64_t nr) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < nx + nr; e += int64_t(gridDim.x) * blockDim.x) {
+    if (e < nx)
+      x[e] = 0.0f;
+    else
+      r[e - nx] = b[e - nx];
+  }
+}
+
+// Two device copies in one launch (a = a_src over na values, b = b_src over nb).
+__global__ void copy2_kernel(float *__restrict__ a, const float *__restrict__ a_src, int64_t na,
+                             float *__restrict__ b, const float *__restrict__ b_src, int64_t nb) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < na + nb; e += int64_t(gridDim.x) * blockDim.x) {
+    if (e < na)
+      a[e] = a_src[e];
+    else
+      b[e - na] = b_src[e - na];
+  }
 }
 
 // x += coef[ch] * p over nx values, then r -= coef[ch] * q over nr values (one launch).
@@ -1418,8 +1437,7 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
   // updates read the scalars (6 launches).
   const bool fused = std::max(nb_proj, nb_back) <= 1024;
 
-  fill_zero_kernel<<<blocks(nx * K), eb, 0, st>>>(x, nx * K);
-  HSN_HIP(ctx, hipMemcpyAsync(r, sino, sizeof(float) * ns * K, hipMemcpyDeviceToDevice, st));
+  cgls_start_kernel<<<blocks(nx * K + ns * K), eb, 0, st>>>(x, nx * K, r, sino, ns * K);
   hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
   HSN_DISPATCH_K(K, launch_backproject, LB, r, sv, gt, g, 1.0f, 0.0f, partial, st);
   hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
@@ -1504,8 +1522,8 @@ extern "C" hsn_status hsn_mbir(hsn_ctx *ctx, const hsn_geom *g, const float *sin
 
   for (int outer = 0; outer < n_outer; ++outer) {
     // Anchor x' = x; r = A^T (V - A x) - sigma_v^2 L x; d = r; gamma = <r, r>.
-    HSN_HIP(ctx, hipMemcpyAsync(xa, x, sizeof(float) * nx * K, hipMemcpyDeviceToDevice, st));
-    HSN_HIP(ctx, hipMemcpyAsync(s, sino, sizeof(float) * ns * K, hipMemcpyDeviceToDevice, st));
+    copy2_kernel<<<unsigned(std::min<int64_t>((nx * K + ns * K + 255) / 256, 4096)), 256, 0, st>>>(
+        xa, x, nx * K, s, sino, ns * K);
     HSN_DISPATCH_K(K, launch_xpby_t, x, xT, nullptr, nullptr, g, 0, st);
     hsn::prof_begin(ctx, HSN_KERN_PROJECT, st);
     HSN_DISPATCH_K(K, launch_project, LA, x, xT, s, gt, g, -1.0f, 1.0f, nullptr, st);

@@ -66,6 +66,22 @@ def test_mbir_mid_geometry_slices(hsn):
     assert rel_fro(x, ref) <= 1e-5
 
 
+def test_mbir_bench_shape_all_slices(hsn):
+    # The benchmark's MBIR launch: all 16 slices of the mid reconstruction
+    # (the CG scalars couple the slices, so the whole volume is compared),
+    # per-channel parameters, started from a non-zero image.
+    import torch
+    b = _sino(128, 60, 16, 4, 11)
+    g = np.random.Generator(np.random.PCG64(12))
+    x0 = (0.1 * g.standard_normal((16, 128, 128, 4))).astype(np.float32)
+    sv, sx = np.array([0.05, 0.1, 0.2, 0.4]), np.array([0.3, 0.5, 0.7, 0.9])
+    show("mbir bench shape", shape=hsn.hsn_projector_launch_info(60, 16, 128, 4))
+    x = hsn.hsn_mbir(to_dev(b, torch.float32), sv, sx, p=1.2, T=1.0, n_outer=1, n_inner=2,
+                     x0=to_dev(x0)).cpu().numpy()
+    ref = om.mbir(b, 128, sv, sx, 1.2, 1.0, 1, 2, x0=x0.astype(np.float64))
+    assert rel_fro(x, ref) <= 1e-5
+
+
 def test_mbir_warm_start_and_zero_iterations(hsn):
     import torch
     n, n_views, n_r, k = 16, 12, 1, 2
