@@ -225,13 +225,20 @@ def main():
 
     last_x = {}
 
+    learned_bufs = {}
+
     def step(path, record=None):
         if path == "learned":
-            # one pass writes p and the network's pooled input; no bfloat16 copy of p
-            p, _, pooled, _, _ = hsn.hsn_normalize_pooled(y, yo, mlp.precision)
-            s = hsn.hsn_subspace_nmf(p, None, n_k, V, D, check_every=BULK, polish_rounds=POLISH_CAP,
-                                     polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star,
-                                     mlp_pooled=pooled, **paths[path])
+            # The whole path in one C call (hsn_fhr_step): one normalisation pass writes p
+            # and the network's pooled input (no bfloat16 copy of p), the learned start and
+            # ANLS rounds to rel obj 1e-4, CGLS, and x^h of one slice; buffers are reused.
+            x, _, s = hsn.hsn_fhr_step(y, yo, V, D, CGLS_ITERS, vox=(0, sc.n_cols * sc.n_cols), bins=(0, n_k),
+                                       bufs=learned_bufs, check_every=BULK, polish_rounds=POLISH_CAP,
+                                       polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star, **paths[path])
+            last_x["x"] = x
+            if record is not None:
+                record.append(s)
+            return s
         else:
             p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=True)
             s = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, polish_rounds=POLISH_CAP,

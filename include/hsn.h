@@ -317,6 +317,31 @@ hsn_status hsn_mbir(hsn_ctx *ctx, const hsn_geom *g, const float *sino, float *x
  */
 hsn_status hsn_fbp(hsn_ctx *ctx, const hsn_geom *g, const float *sino, int64_t ld, float *x, void *stream);
 
+/*
+ * The FHR hot path of one scan in one call, in the order of Alg. 1 with the
+ * h = 0 reconstruction: eq. (2) (hsn_normalize, or hsn_normalize_pooled for
+ * a learned start, floor count_floor, clipped at 0, no offset), eq. (4)
+ * (hsn_subspace_nmf with *opts; for HSN_INIT_MLP its mlp_pooled is set to
+ * `pooled`), eq. (5) (hsn_cgls, cgls_iters iterations, on V read as the
+ * sinogram [N_v][N_r][N_c][K], angles as hsn_geom.angles), and eq. (6)
+ * (hsn_rehydrate of [vox_begin, vox_end) x [bin_begin, bin_end) into xh,
+ * skipped when xh is NULL).  Same kernels, same results as those calls in
+ * sequence; the host's turn-around after the NMF's convergence read-back
+ * stays in C.
+ *   p [N_p][ldp] float32 and pooled [N_p][256] (learned start only, in the
+ *   network's precision): caller-owned intermediates (device);
+ *   V [N_p][K], D [N_k][K]: in/out as for hsn_subspace_nmf;
+ *   x [N_r][N_c][N_c][K] float32 out; stats as for hsn_subspace_nmf.
+ * Errors: those of the composed calls (the first failing one returns; the
+ * earlier ones have been queued); HSN_ERR_INVALID_ARG for NULL required
+ * pointers or a learned start without opts.mlp or pooled.
+ */
+hsn_status hsn_fhr_step(hsn_ctx *ctx, const hsn_dims *dims, const void *y, int y_dtype, const void *y_open,
+                        int y_open_dtype, float count_floor, float *p, int64_t ldp, void *pooled, float *V,
+                        float *D, const hsn_nmf_opts *opts, hsn_nmf_stats *stats, const double *angles,
+                        int cgls_iters, float *x, int64_t vox_begin, int64_t vox_end, int64_t bin_begin,
+                        int64_t bin_end, float *xh, int64_t ldh, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Subspace expansion: eq. (6) x^h = x^s D^T over a voxel x bin range.   */
 /* ------------------------------------------------------------------ */

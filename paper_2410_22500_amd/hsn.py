@@ -99,6 +99,10 @@ _lib.hsn_cgls.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_int, _P, _P]
 _lib.hsn_cgls.restype = C.c_int
 _lib.hsn_fbp.argtypes = [_P, C.POINTER(Geom), _P, C.c_int64, _P, _P]
 _lib.hsn_fbp.restype = C.c_int
+_lib.hsn_fhr_step.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, C.c_float, _P, C.c_int64, _P, _P, _P,
+                             C.POINTER(NmfOpts), C.POINTER(NmfStats), _P, C.c_int, _P, C.c_int64, C.c_int64, C.c_int64,
+                             C.c_int64, _P, C.c_int64, _P]
+_lib.hsn_fhr_step.restype = C.c_int
 _lib.hsn_mbir.argtypes = [_P, C.POINTER(Geom), _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
                          C.c_double, C.c_int, C.c_int, _P]
 _lib.hsn_mbir.restype = C.c_int
@@ -354,6 +358,50 @@ def hsn_cgls(sino: torch.Tensor, n_iter: int, angles: Optional[Sequence[float]] 
     rh = torch.empty((n_iter + 1, k), dtype=torch.float64, device=sino.device) if resid else None
     _check(_lib.hsn_cgls(ctx, C.byref(g), _ptr(sino), _ptr(x), n_iter, _ptr(rh), _stream(dev)), ctx)
     return (x, rh) if resid else x
+
+
+def hsn_fhr_step(y: torch.Tensor, yo: torch.Tensor, V: torch.Tensor, D: torch.Tensor, cgls_iters: int,
+                 vox=None, bins=None, angles: Optional[Sequence[float]] = None, count_floor: float = 1.0,
+                 bufs: Optional[dict] = None, algo: int = ALGO_MU, precision: int = PREC_FP32, max_iter: int = 100,
+                 check_every: int = 10, polish_rounds: int = 0, polish_algo: int = ALGO_ANLS,
+                 polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0, init: int = INIT_USER,
+                 mlp: Optional["Mlp"] = None, history_cap: int = 4096):
+    """The whole FHR path of one scan in one C call: counts y [N_v][N_r][N_c][N_k] and y^o (uint16 bits
+    as int16) -> V, D in place, x [N_r][N_c][N_c][K], and x^h over vox x bins (None if vox is None).
+    bufs: optional dict that keeps the intermediates (p, pooled) and outputs (x, xh) between calls."""
+    dev = _dev(y)
+    ctx = context(dev)
+    n_v, n_r, n_c, n_k = y.shape
+    n_p, k = V.shape
+    dims = Dims(n_v, n_r, n_c, n_k)
+    bufs = {} if bufs is None else bufs
+    ldp = round_up(n_k, 4)
+    if "p" not in bufs:
+        bufs["p"] = torch.empty((n_p, ldp), dtype=torch.float32, device=y.device)
+    learned = init == INIT_MLP
+    if learned and mlp is not None and "pooled" not in bufs:
+        bufs["pooled"] = torch.empty((n_p, MLP_IN), dtype=mlp.x_dtype, device=y.device)
+    if "x" not in bufs:
+        bufs["x"] = torch.empty((n_r, n_c, n_c, k), dtype=torch.float32, device=y.device)
+    vb, ve = vox if vox is not None else (0, 0)
+    bb, be = bins if bins is not None else (0, n_k)
+    if vox is not None and "xh" not in bufs:
+        bufs["xh"] = torch.empty((ve - vb, be - bb), dtype=torch.float32, device=y.device)
+    xh = bufs.get("xh") if vox is not None else None
+    opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo, polish_bf16_rounds,
+                   rel_obj_tol, f_ref, mlp.handle if mlp is not None else None, None)
+    hist = (C.c_double * max(history_cap, 1))()
+    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0)
+    keep = (C.c_double * n_v)(*[float(a) for a in angles]) if angles is not None else None
+    yd = F32 if y.dtype == torch.float32 else U16
+    od = F32 if yo.dtype == torch.float32 else U16
+    _check(_lib.hsn_fhr_step(ctx, C.byref(dims), _ptr(y), yd, _ptr(yo), od, float(count_floor), _ptr(bufs["p"]), ldp,
+                             _ptr(bufs.get("pooled") if learned else None), _ptr(V), _ptr(D), C.byref(opts),
+                             C.byref(stats), keep, int(cgls_iters), _ptr(bufs["x"]), vb, ve, bb, be, _ptr(xh),
+                             be - bb, _stream(dev)), ctx)
+    st = dict(iters=stats.iters, polish_done=stats.polish_done, objective=stats.objective, rel_obj=stats.rel_obj,
+              history=[hist[i] for i in range(stats.history_len)], ms=stats.ms)
+    return bufs["x"], xh, st
 
 
 def hsn_mbir(sino: torch.Tensor, sigma_v, sigma_x, p: float = 1.2, T: float = 1.0, n_outer: int = 10,

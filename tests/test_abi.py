@@ -43,6 +43,9 @@ def test_null_context_is_invalid_arg(lib):
     assert lib.hsn_backproject(None, v(), v(), v(), C.c_float(1), C.c_float(0), v()) == 1
     assert lib.hsn_cgls(None, v(), v(), v(), 1, v(), v()) == 1
     assert lib.hsn_mbir(None, v(), v(), v(), v(), v(), C.c_double(1.2), C.c_double(1.0), 1, 1, v()) == 1
+    assert lib.hsn_fhr_step(None, v(), v(), 0, v(), 0, C.c_float(1), v(), C.c_int64(0), v(), v(), v(), v(), v(),
+                            v(), 0, v(), C.c_int64(0), C.c_int64(0), C.c_int64(0), C.c_int64(0), v(),
+                            C.c_int64(0), v()) == 1
     assert lib.hsn_rehydrate(None, v(), v(), C.c_int64(1), C.c_int64(1), 1, C.c_int64(0), C.c_int64(1),
                              C.c_int64(0), C.c_int64(1), v(), C.c_int64(1), v()) == 1
     assert lib.hsn_last_error(None) == b"null context"
