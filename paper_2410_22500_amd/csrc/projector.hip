@@ -891,52 +891,85 @@ __device__ __forceinline__ float prior_coef(float d, float c0, float inv_tsx, fl
 
 // w_s += sign sigma_v^2 (L v)_s for every voxel, L with the weights of the
 // anchor xa; per-block float64 partials of <v, w_new> (dot_self = 0) or
-// <w_new, w_new> (dot_self = 1) per channel.  Fixed grid (grid-stride over
-// voxels), so the sums have a fixed order.
+// <w_new, w_new> (dot_self = 1) per channel.  A block takes 16 x 16 tiles of
+// a slice in turn (fixed grid, so the sums have a fixed order) and stages
+// the tile of xa and v with a one-pixel halo in LDS, so every operand is
+// read from HBM about once.
+constexpr int kPriorTile = 16, kPriorHalo = kPriorTile + 2;
+
 template <int K>
 __global__ __launch_bounds__(256) void prior_apply_kernel(const float *__restrict__ xa, const float *__restrict__ v,
-                                                          float *__restrict__ w, int n, int64_t n_vox, PriorArgs pa,
+                                                          float *__restrict__ w, int n, int n_slices, PriorArgs pa,
                                                           float sign, int dot_self, double *__restrict__ partial) {
+  __shared__ float sa[kPriorHalo * kPriorHalo * K], sv[kPriorHalo * kPriorHalo * K];
   double dot[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) dot[q] = 0.0;
+  const int t = threadIdx.x, tx = t % kPriorTile, ty = t / kPriorTile;
+  const int tn = (n + kPriorTile - 1) / kPriorTile;
+  const int64_t n_tiles = int64_t(n_slices) * tn * tn;
   const int64_t nn = int64_t(n) * n;
-  for (int64_t vox = int64_t(blockIdx.x) * 256 + threadIdx.x; vox < n_vox; vox += int64_t(gridDim.x) * 256) {
-    const int64_t r = vox / nn;
-    const int rem = int(vox - r * nn);
-    const int j = rem / n, i = rem - (rem / n) * n;
-    float as[K], vs[K], acc[K];
-    load_k<K>(xa + vox * K, as);
-    load_k<K>(v + vox * K, vs);
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t r = tile / (int64_t(tn) * tn);
+    const int rem = int(tile - r * tn * tn);
+    const int j0 = (rem / tn) * kPriorTile, i0 = (rem % tn) * kPriorTile;
+    __syncthreads();  // the previous tile's LDS reads are done
+    for (int e = t; e < kPriorHalo * kPriorHalo; e += 256) {
+      const int hy = e / kPriorHalo, hx = e - hy * kPriorHalo;
+      const int jj = j0 + hy - 1, ii = i0 + hx - 1;
+      float a[K], b[K];
+      if (jj >= 0 && jj < n && ii >= 0 && ii < n) {
+        const int64_t o = (r * nn + int64_t(jj) * n + ii) * K;
+        load_k<K>(xa + o, a);
+        load_k<K>(v + o, b);
+      } else {
 #pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] = 0.0f;
+        for (int q = 0; q < K; ++q) a[q] = b[q] = 0.0f;
+      }
 #pragma unroll
-    for (int nb = 0; nb < 8; ++nb) {
-      const int dj = (nb < 3) ? -1 : (nb < 5 ? 0 : 1);               // rows above, same row, below
-      const int di = (nb < 3) ? nb - 1 : (nb < 5 ? 2 * nb - 7 : nb - 6);  // -1 0 1 | -1 1 | -1 0 1
-      const int jj = j + dj, ii = i + di;
-      if (jj < 0 || jj >= n || ii < 0 || ii >= n) continue;
-      const float b = (dj == 0 || di == 0) ? kPriorW1 : kPriorW2;
-      const int64_t o = (r * nn + int64_t(jj) * n + ii) * K;
-      float ar[K], vr[K];
-      load_k<K>(xa + o, ar);
-      load_k<K>(v + o, vr);
-#pragma unroll
-      for (int q = 0; q < K; ++q)
-        acc[q] = fmaf(b * prior_coef(as[q] - ar[q], pa.c0[q], pa.inv_tsx[q], pa.e, pa.rq), vs[q] - vr[q], acc[q]);
+      for (int q = 0; q < K; ++q) {
+        sa[e * K + q] = a[q];
+        sv[e * K + q] = b[q];
+      }
     }
+    __syncthreads();
+    const int j = j0 + ty, i = i0 + tx;
+    if (j < n && i < n) {
+      const int c = (ty + 1) * kPriorHalo + tx + 1;
+      float as[K], vs[K], acc[K];
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-      const float res = fmaf(sign * pa.s2[q], 2.0f * acc[q], w[vox * K + q]);
-      w[vox * K + q] = res;
-      dot[q] += double(dot_self ? res : vs[q]) * double(res);
+      for (int q = 0; q < K; ++q) {
+        as[q] = sa[c * K + q];
+        vs[q] = sv[c * K + q];
+        acc[q] = 0.0f;
+      }
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) {
+        const int dj = (nb < 3) ? -1 : (nb < 5 ? 0 : 1);                 // rows above, same row, below
+        const int di = (nb < 3) ? nb - 1 : (nb < 5 ? 2 * nb - 7 : nb - 6);  // -1 0 1 | -1 1 | -1 0 1
+        const int jj = j + dj, ii = i + di;
+        if (jj < 0 || jj >= n || ii < 0 || ii >= n) continue;
+        const float b = (dj == 0 || di == 0) ? kPriorW1 : kPriorW2;
+        const int cn = c + dj * kPriorHalo + di;
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+          acc[q] = fmaf(b * prior_coef(as[q] - sa[cn * K + q], pa.c0[q], pa.inv_tsx[q], pa.e, pa.rq),
+                        vs[q] - sv[cn * K + q], acc[q]);
+      }
+      const int64_t vox = r * nn + int64_t(j) * n + i;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const float res = fmaf(sign * pa.s2[q], 2.0f * acc[q], w[vox * K + q]);
+        w[vox * K + q] = res;
+        dot[q] += double(dot_self ? res : vs[q]) * double(res);
+      }
     }
   }
   __shared__ double red[4][K];
 #pragma unroll
   for (int q = 0; q < K; ++q) {
-    const double t = hsn::wave_sum_all(dot[q]);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = t;
+    const double tt = hsn::wave_sum_all(dot[q]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = tt;
   }
   __syncthreads();
   if (int(threadIdx.x) < K) {
@@ -1331,8 +1364,8 @@ void launch_dot(const float *a, const float *b, int64_t n_items, double *partial
 template <int K>
 void launch_prior_apply(const float *xa, const float *v, float *w, const hsn_geom *g, const PriorArgs &pa, float sign,
                         int dot_self, double *partial, hipStream_t st) {
-  const int64_t n_vox = int64_t(g->n_slices) * g->n_cols * g->n_cols;
-  prior_apply_kernel<K><<<kPriorBlocks, 256, 0, st>>>(xa, v, w, int(g->n_cols), n_vox, pa, sign, dot_self, partial);
+  prior_apply_kernel<K><<<kPriorBlocks, 256, 0, st>>>(xa, v, w, int(g->n_cols), int(g->n_slices), pa, sign, dot_self,
+                                                       partial);
 }
 
 template <int K>
