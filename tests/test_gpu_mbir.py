@@ -96,6 +96,49 @@ def test_mbir_warm_start_and_zero_iterations(hsn):
     assert rel_fro(x, ref) <= 1e-5
 
 
+def test_mbir_custom_angles_tiny_image(hsn):
+    # An image smaller than one 16 x 16 stencil tile (n = 5), one channel,
+    # uneven view angles.
+    import torch
+    th = np.array([0.0, 0.3, 0.9, 1.4, 1.6, 2.2, 2.9])
+    g = np.random.Generator(np.random.PCG64(31))
+    x = g.uniform(0, 1, (2, 5, 5, 1))
+    b = (oprj.project(x, 7, thetas=th) + 0.02 * g.standard_normal((7, 2, 5, 1))).astype(np.float32)
+    show("mbir tiny angles")
+    # one outer x 3 CG iterations: the element-wise bar of the other step tests (float32 CG
+    # amplifies rounding with more steps; longer runs are checked at the minimiser)
+    xg = hsn.hsn_mbir(to_dev(b), 0.1, 0.4, p=1.1, T=0.7, n_outer=1, n_inner=3, angles=th).cpu().numpy()
+    ref = om.mbir(b.astype(np.float64), 5, 0.1, 0.4, 1.1, 0.7, 1, 3, thetas=th)
+    assert rel_fro(xg, ref) <= 1e-5
+
+
+def test_mbir_quadratic_prior_solves_the_linear_system(hsn):
+    # p = 2: the surrogate is exact, so enough CG steps give the solution of
+    # (A^T A + sigma_v^2 L) x = A^T b with the constant-weight Laplacian,
+    # formed densely here (float32 CG: 1e-4).
+    import torch
+    n, nv = 10, 14
+    b = _sino(n, nv, 1, 1, 5)
+    sv, sx = 0.3, 0.5
+    show("mbir quadratic")
+    x = hsn.hsn_mbir(to_dev(b, torch.float32), sv, sx, p=2.0, T=1.0, n_outer=1, n_inner=100).cpu().numpy()
+    A = oprj.dense_matrix(n, nv)
+    L = np.zeros((n * n, n * n))
+    for dj, di, w in om.PAIRS:
+        for j in range(n):
+            for i in range(n):
+                jj, ii = j + dj, i + di
+                if 0 <= jj < n and 0 <= ii < n:
+                    s_, r_ = j * n + i, jj * n + ii
+                    c = 2 * w / (4 * sx * sx)
+                    L[s_, s_] += c
+                    L[r_, r_] += c
+                    L[s_, r_] -= c
+                    L[r_, s_] -= c
+    ref = np.linalg.solve(A.T @ A + sv * sv * L, A.T @ b[:, 0, :, 0].ravel())
+    assert rel_fro(x[0, :, :, 0].ravel(), ref) <= 1e-4
+
+
 def test_mbir_rejects_bad_arguments(hsn):
     import torch
     s = torch.zeros((4, 1, 16, 2), device="cuda")
