@@ -286,7 +286,7 @@ hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sino, float *x
  * the current x and runs n_inner conjugate-gradient iterations on
  * (A^T A + sigma_v^2 L) x = A^T V from the current x (the cost never
  * increases in exact arithmetic).  Per inner iteration: one A, one A^T, one
- * prior stencil and three small kernels; per outer iteration one more A,
+ * prior stencil and two small kernels; per outer iteration one more A,
  * A^T and stencil.  No positivity constraint.
  *   sino [N_v][N_r][N_c][K] float32 in (device);
  *   x [N_r][N_c][N_c][K] float32 in/out (device): the start on entry

@@ -668,6 +668,8 @@ enum { kGamma = 0, kAlphaOff = 16, kBetaOff = 24 };
 // pT = p^T.  mode 3 (CGLS step, one launch): beta = ||A^T r||^2 / gamma
 // from the A^T partial sums (gamma = st[gsel], the new value goes to
 // st[1 - gsel]), x += alpha p with the old p, then p = sv + beta p, pT = p^T.
+// mode 4: mode 3 without the x update (the MBIR direction step, whose
+// partials are <r, r> of the CG step kernel).
 template <int K>
 __global__ __launch_bounds__(256) void xpby_transpose_kernel(float *__restrict__ p, float *__restrict__ pT,
                                                              const float *__restrict__ sv,
@@ -680,7 +682,7 @@ __global__ __launch_bounds__(256) void xpby_transpose_kernel(float *__restrict__
   const int j0 = blockIdx.y * kTile, i0 = blockIdx.x * kTile;
   const size_t base = size_t(r) * n * n * K;
   float cf[K], al[K];
-  if (mode == 3) {
+  if (mode == 3 || mode == 4) {
     sum_partials(partial, nblk, K, tot);
     const double *gamma = st + kGamma + 8 * gsel;
 #pragma unroll
@@ -978,18 +980,26 @@ __global__ __launch_bounds__(256) void prior_apply_kernel(const float *__restric
   }
 }
 
-// CG step of the surrogate solve: x += alpha d, r -= alpha w (alpha per
-// channel from st), per-block partials of <r, r>.  Fixed grid.
+// CG step of the surrogate solve: alpha = gamma[gsel] / <d, w> per channel,
+// every block summing the prior kernel's partials of <d, w> itself in one
+// fixed order (the scalars of cgls_scalar_kernel, without its launch); then
+// x += alpha d, r -= alpha w, and per-block partials of <r, r> into
+// partial_out (a buffer of its own: other blocks still read the inputs).
+// Fixed grid.
 template <int K>
 __global__ __launch_bounds__(kDotThreads) void mbir_step_kernel(float *__restrict__ x, const float *__restrict__ d,
                                                                 float *__restrict__ r, const float *__restrict__ w,
-                                                                int64_t n_vox, const double *__restrict__ st,
-                                                                double *__restrict__ partial) {
+                                                                int64_t n_vox, const double *__restrict__ st, int gsel,
+                                                                const double *__restrict__ partial_dw, int nblk_dw,
+                                                                double *__restrict__ partial_out) {
+  __shared__ double tot[8];
+  sum_partials(partial_dw, nblk_dw, K, tot);
+  const double *gamma = st + kGamma + 8 * gsel;
   float al[K];
   double dot[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) {
-    al[q] = float(st[kAlphaOff + q]);
+    al[q] = float(tot[q] > 0.0 ? gamma[q] / tot[q] : 0.0);
     dot[q] = 0.0;
   }
   for (int64_t vox = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; vox < n_vox;
@@ -1013,7 +1023,7 @@ __global__ __launch_bounds__(kDotThreads) void mbir_step_kernel(float *__restric
   if (int(threadIdx.x) < K) {
     double t = 0.0;
     for (int wv = 0; wv < kDotThreads / 64; ++wv) t += red[wv][threadIdx.x];
-    partial[size_t(blockIdx.x) * K + threadIdx.x] = t;
+    partial_out[size_t(blockIdx.x) * K + threadIdx.x] = t;
   }
 }
 
@@ -1314,7 +1324,7 @@ void launch_backproject(const ProjLaunch &L, const float *s, float *x, const Geo
 }
 
 // mode 0: pT = p^T; mode 1: p = sv + coef p, pT = p^T; mode 2: p = sv, pT = p^T;
-// mode 3: the fused CGLS direction step (see xpby_transpose_kernel).
+// mode 3: the fused CGLS direction step, mode 4: the MBIR one (see xpby_transpose_kernel).
 template <int K>
 void launch_xpby_t(float *p, float *pT, const float *sv, const double *coef, const hsn_geom *g, int mode,
                    hipStream_t st, float *x = nullptr, const double *partial = nullptr, int nblk = 0,
@@ -1370,9 +1380,10 @@ void launch_prior_apply(const float *xa, const float *v, float *w, const hsn_geo
 
 template <int K>
 void launch_mbir_step(float *x, const float *d, float *r, const float *w, const hsn_geom *g, const double *scal,
-                      double *partial, hipStream_t st) {
+                      int gsel, const double *partial_dw, double *partial_out, hipStream_t st) {
   const int64_t n_vox = int64_t(g->n_slices) * g->n_cols * g->n_cols;
-  mbir_step_kernel<K><<<kDotBlocks, kDotThreads, 0, st>>>(x, d, r, w, n_vox, scal, partial);
+  mbir_step_kernel<K><<<kDotBlocks, kDotThreads, 0, st>>>(x, d, r, w, n_vox, scal, gsel, partial_dw, kPriorBlocks,
+                                                          partial_out);
 }
 
 hsn_status check_align(hsn_ctx *ctx, const void *p, int k, const char *what) {
@@ -1545,13 +1556,15 @@ extern "C" hsn_status hsn_mbir(hsn_ctx *ctx, const hsn_geom *g, const float *sin
   const size_t n_part = std::max<size_t>(kPriorBlocks, kDotBlocks);
   const size_t need = hsn::Carver::need({sizeof(float) * ns * K, sizeof(float) * nx * K, sizeof(float) * nx * K,
                                          sizeof(float) * nx * K, sizeof(float) * nx * K, sizeof(float) * nx * K,
-                                         sizeof(float) * nx * K, sizeof(double) * n_part * K, sizeof(double) * kScal});
+                                         sizeof(float) * nx * K, sizeof(double) * n_part * K,
+                                         sizeof(double) * kDotBlocks * K, sizeof(double) * kScal});
   if ((rc = hsn::ensure_ws(ctx, need)) != HSN_OK) return rc;
   hsn::Carver cv(ctx->ws);
   float *s = cv.take<float>(ns * K);
   float *xa = cv.take<float>(nx * K), *xT = cv.take<float>(nx * K), *r = cv.take<float>(nx * K);
   float *d = cv.take<float>(nx * K), *dT = cv.take<float>(nx * K), *w = cv.take<float>(nx * K);
-  double *partial = cv.take<double>(n_part * K), *scal = cv.take<double>(kScal);
+  double *partial = cv.take<double>(n_part * K), *partial_rr = cv.take<double>(kDotBlocks * K);
+  double *scal = cv.take<double>(kScal);
 
   for (int outer = 0; outer < n_outer; ++outer) {
     // Anchor x' = x; r = A^T (V - A x) - sigma_v^2 L x; d = r; gamma = <r, r>.
@@ -1577,11 +1590,10 @@ extern "C" hsn_status hsn_mbir(hsn_ctx *ctx, const hsn_geom *g, const float *sin
       HSN_DISPATCH_K(K, launch_backproject, LB, s, w, gt, g, 1.0f, 0.0f, nullptr, st);
       hsn::prof_end(ctx, HSN_KERN_BACKPROJECT, st);
       HSN_DISPATCH_K(K, launch_prior_apply, xa, d, w, g, pa, 1.0f, 0, partial, st);
-      cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kPriorBlocks, K, kAlpha, scal, gsel, nullptr);
-      // x += alpha d; r -= alpha w; beta = <r, r> / gamma; d = r + beta d
-      HSN_DISPATCH_K(K, launch_mbir_step, x, d, r, w, g, scal, partial, st);
-      cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kBeta, scal, gsel, nullptr);
-      HSN_DISPATCH_K(K, launch_xpby_t, d, dT, r, scal + kBetaOff, g, 1, st);
+      // x += alpha d; r -= alpha w (alpha from the <d, w> partials); then
+      // beta = <r, r> / gamma and d = r + beta d (from the <r, r> partials)
+      HSN_DISPATCH_K(K, launch_mbir_step, x, d, r, w, g, scal, gsel, partial, partial_rr, st);
+      HSN_DISPATCH_K(K, launch_xpby_t, d, dT, r, nullptr, g, 4, st, nullptr, partial_rr, kDotBlocks, scal, gsel);
     }
   }
   HSN_LAUNCHED(ctx);
