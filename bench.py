@@ -156,7 +156,7 @@ def main():
         traffic_from_counters(*args.traffic)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: measures one GPU only (got --gpus {args.gpus}); "
               "sharding across GPUs is designed but not built.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":

@@ -36,7 +36,7 @@ typedef enum {
   HSN_OK = 0,
   HSN_ERR_INVALID_ARG = 1,  /* NULL where required, bad enum, bad pitch/alignment */
   HSN_ERR_SHAPE = 2,        /* sizes out of the supported range */
-  HSN_ERR_UNSUPPORTED = 3,  /* valid request this build does not implement */
+  HSN_ERR_UNSUPPORTED = 3,  /* valid request the library does not implement */
   HSN_ERR_OOM = 4,          /* workspace allocation failed */
   HSN_ERR_DEVICE = 5,       /* a HIP runtime call failed */
   HSN_ERR_NUMERIC = 6       /* NaN/Inf detected in a result */
