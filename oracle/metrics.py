@@ -1,24 +1,17 @@
 """Measures used to judge a decomposition.
 
-  rel_obj      (f - f*) / f*, f* = the lowest objective reached for the
-               instance (the absolute f/||p||^2 cannot reach 1e-4 on
-               Poisson data: the noise floor sits far above it)
   canonical    NMF is unique only up to column permutation and positive
                scaling; D columns are scaled to unit l2 (V inversely) and
                ordered by matching a reference library (or by descending
                column norm of V when there is none)
-  snr_db       eq. (11): 10 log10 of the mean over bins and materials of
-               (mu_signal / sigma_noise)^2 over homogeneous regions
+  snr_fhr      eq. (11): SNR of a hyperspectral reconstruction
+  snr_fmd      eq. (12): SNR of material reconstructions
 """
 from __future__ import annotations
 
 import itertools
 
 import numpy as np
-
-
-def rel_obj(f, f_star):
-    return (np.asarray(f, np.float64) - f_star) / f_star
 
 
 def canonical(V, D, library=None):
@@ -44,14 +37,25 @@ def canonical(V, D, library=None):
     return Vn[:, order], Dn[:, order]
 
 
-def snr_db(recon, truth_regions):
-    """recon [N_x][N_k]; truth_regions: list of index arrays, one per
-    homogeneous region.  Mean over bins and regions of (mean/std)^2."""
+def snr_fhr(recon, material_regions, background):
+    """eq. (11), Section V-B: 10 log10 of the mean over bins k and materials
+    m of (mu_{m,k} / sigma_k)^2, where mu_{m,k} is the mean of bin k over the
+    voxels of material m's region and sigma_k the standard deviation of bin
+    k over the background region (outside the sample).
+      recon [N_x][N_k]; material_regions: one index array per material;
+      background: index array.
+    Reading: sigma is the population deviation (divisor n); log base 10 (dB)."""
     recon = np.asarray(recon, np.float64)
-    vals = []
-    for reg in truth_regions:
-        sel = recon[reg]
-        mu = sel.mean(axis=0)
-        sd = sel.std(axis=0)
-        vals.append((mu / np.where(sd > 0, sd, np.inf)) ** 2)
-    return float(10 * np.log10(np.mean(vals)))
+    sd = recon[background].std(axis=0, ddof=0)
+    ratios = [(recon[reg].mean(axis=0) / sd) ** 2 for reg in material_regions]
+    return float(10.0 * np.log10(np.mean(ratios)))
+
+
+def snr_fmd(xm, material_regions, background):
+    """eq. (12), Section V-B: 10 log10 of the mean over materials m of
+    (mu_m / sigma_m)^2, where mu_m is the mean of material image m over its
+    region and sigma_m the standard deviation of material image m over the
+    background region.  xm [N_x][N_m]; regions as snr_fhr."""
+    xm = np.asarray(xm, np.float64)
+    ratios = [(xm[reg, m].mean() / xm[background, m].std(ddof=0)) ** 2 for m, reg in enumerate(material_regions)]
+    return float(10.0 * np.log10(np.mean(ratios)))

@@ -189,6 +189,43 @@ def _dev(t: torch.Tensor) -> int:
     return t.device.index or 0
 
 
+_U16 = (torch.int16, torch.uint16)
+
+
+def _need(t, name: str, dtype, shape=None, layout: str = "contiguous", device=None, extent=None):
+    """Reject, before any library call, a tensor the kernels would misread:
+    wrong dtype, a shape that disagrees with the other arguments (None in
+    `shape` matches any size), a layout the kernels do not index (layout
+    "contiguous"; "rows": 2-D with unit column stride and a row pitch of at
+    least its width, e.g. p[:, :n_k]; "inner": unit last-dimension stride),
+    storage shorter than `extent` elements from the tensor's first element,
+    or memory on another device than `device`.  Checked in that order; the
+    wrappers then check (_dev) that the memory is on a GPU."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"hsn: {name} must be a torch.Tensor, got {type(t).__name__}")
+    dts = dtype if isinstance(dtype, tuple) else (dtype,)
+    if t.dtype not in dts:
+        raise ValueError(f"hsn: {name} must have dtype {' or '.join(str(d) for d in dts)}, got {t.dtype}")
+    if shape is not None and (t.dim() != len(shape) or any(s is not None and a != s for a, s in zip(t.shape, shape))):
+        raise ValueError(f"hsn: {name} must have shape {tuple('*' if s is None else s for s in shape)}, "
+                         f"got {tuple(t.shape)}")
+    if layout == "contiguous" and not t.is_contiguous():
+        raise ValueError(f"hsn: {name} must be contiguous (got strides {t.stride()})")
+    if layout == "rows" and (t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1) or t.stride(0) < t.shape[1]):
+        raise ValueError(f"hsn: {name} must be a 2-D array of rows with unit column stride (got strides {t.stride()})")
+    if layout == "inner" and t.dim() > 0 and t.shape[-1] > 1 and t.stride(-1) != 1:
+        raise ValueError(f"hsn: {name} needs a unit stride in its last dimension (got strides {t.stride()})")
+    if extent is not None and t.untyped_storage().nbytes() // t.element_size() - t.storage_offset() < extent:
+        raise ValueError(f"hsn: {name} holds fewer than the {extent} elements the call reads")
+    if device is not None and t.device != device:
+        raise ValueError(f"hsn: {name} is on {t.device}, the call's other tensors on {device}")
+    return t
+
+
+def _opt(t, *a, **kw):
+    return None if t is None else _need(t, *a, **kw)
+
+
 def _geom(n_views, n_slices, n_cols, k, angles):
     g = Geom(n_views, n_slices, n_cols, k, None)
     keep = None
@@ -206,11 +243,19 @@ def round_up(x: int, m: int) -> int:
 # Entry points (same names as the C ABI)
 # ---------------------------------------------------------------------------
 
+def _check_counts(y, yo, bg_mask=None):
+    _need(y, "y", _U16 + (torch.float32,), shape=(None, None, None, None))
+    n_v, n_r, n_c, n_k = y.shape
+    _need(yo, "y_open", _U16 + (torch.float32,), shape=(n_r, n_c, n_k), device=y.device)
+    _opt(bg_mask, "bg_mask", torch.uint8, shape=(n_r, n_c), device=y.device)
+
+
 def hsn_normalize(y: torch.Tensor, yo: torch.Tensor, bg_mask: Optional[torch.Tensor] = None,
                   count_floor: float = 1.0, clip: bool = True, want_f32: bool = True, want_bf16: bool = False,
                   want_offset: bool = False, ldp: Optional[int] = None, ldb: Optional[int] = None):
     """y [N_v][N_r][N_c][N_k] (uint16 as int16/uint16 bits or float32), yo [N_r][N_c][N_k].
     Returns (p [N_p][ldp] f32 or None, p_bf16 [N_p][ldb] int16 bits or None, b or None, sumsq f64 scalar)."""
+    _check_counts(y, yo, bg_mask)
     dev = _dev(y)
     ctx = context(dev)
     n_v, n_r, n_c, n_k = y.shape
@@ -234,6 +279,7 @@ def hsn_normalize_pooled(y: torch.Tensor, yo: torch.Tensor, pooled_precision: in
                          want_offset: bool = False, ldp: Optional[int] = None, ldb: Optional[int] = None):
     """hsn_normalize plus the learned start's pooled input [N_p][256] (bfloat16 bits as int16 for
     PREC_BF16, float32 for PREC_FP32).  Returns (p, p_bf16, pooled, b, sumsq)."""
+    _check_counts(y, yo, bg_mask)
     dev = _dev(y)
     ctx = context(dev)
     n_v, n_r, n_c, n_k = y.shape
@@ -262,9 +308,18 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
                      init: int = INIT_USER, mlp: Optional["Mlp"] = None, history_cap: int = 4096,
                      mlp_pooled: Optional[torch.Tensor] = None) -> dict:
     """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device)."""
+    _need(V, "V", torch.float32, shape=(None, None))
+    n_p, k = V.shape
+    _need(D, "D", torch.float32, shape=(n_k, k), device=V.device)
+    _opt(p, "p", torch.float32, shape=(n_p, None), layout="rows", device=V.device)
+    _opt(p_bf16, "p_bf16", _U16, shape=(n_p, None), layout="rows", device=V.device)
+    if mlp_pooled is not None:
+        _need(mlp_pooled, "mlp_pooled", mlp.x_dtype if mlp is not None else (torch.int16, torch.float32),
+              shape=(n_p, MLP_IN), device=V.device)
+    if p is not None and p.shape[1] < n_k or p_bf16 is not None and p_bf16.shape[1] < n_k:
+        raise ValueError(f"hsn: p and p_bf16 rows must hold n_k = {n_k} bins")
     dev = _dev(V)
     ctx = context(dev)
-    n_p, k = V.shape
     opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo,
                    polish_bf16_rounds, rel_obj_tol, f_ref, mlp.handle if mlp is not None else None,
                    _ptr(mlp_pooled))
@@ -282,6 +337,15 @@ def hsn_subspace_nmf_batched(problems, max_iter: int = 100, check_every: int = 1
                              rel_obj_tol: float = 0.0, flags: int = BATCH_GRAPH, history_cap: int = 4096):
     """problems: list of (p [N_p][ldp] f32, n_k, V [N_p][K], D [N_k][K], f_ref); V and D in place.
     Float32 MU bulk then ANLS polish, one launch per phase over all instances."""
+    if not problems:
+        raise ValueError("hsn: no problems")
+    dev0 = problems[0][2].device if isinstance(problems[0][2], torch.Tensor) else None
+    for i, (p, n_k, V, D, _) in enumerate(problems):
+        _need(V, f"problems[{i}].V", torch.float32, shape=(None, None), device=dev0)
+        _need(D, f"problems[{i}].D", torch.float32, shape=(n_k, V.shape[1]), device=dev0)
+        _need(p, f"problems[{i}].p", torch.float32, shape=(V.shape[0], None), layout="rows", device=dev0)
+        if p.shape[1] < n_k:
+            raise ValueError(f"hsn: problems[{i}].p rows must hold n_k = {n_k} bins")
     dev = _dev(problems[0][2])
     ctx = context(dev)
     n = len(problems)
@@ -307,9 +371,12 @@ def hsn_batched_plan_info(device: int = 0) -> str:
 def hsn_project(x: torch.Tensor, n_views: int, angles: Optional[Sequence[float]] = None, alpha: float = 1.0,
                 beta: float = 0.0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """x [N_r][N][N][K] -> s [N_v][N_r][N][K]."""
+    _need(x, "x", torch.float32, shape=(None, None, None, None))
+    n_r, n, _, k = x.shape
+    _need(x, "x", torch.float32, shape=(n_r, n, n, k))
+    _opt(out, "out", torch.float32, shape=(n_views, n_r, n, k), device=x.device)
     dev = _dev(x)
     ctx = context(dev)
-    n_r, n, _, k = x.shape
     g, keep = _geom(n_views, n_r, n, k, angles)
     if out is None:
         out = torch.empty((n_views, n_r, n, k), dtype=torch.float32, device=x.device)
@@ -320,9 +387,11 @@ def hsn_project(x: torch.Tensor, n_views: int, angles: Optional[Sequence[float]]
 def hsn_backproject(s: torch.Tensor, angles: Optional[Sequence[float]] = None, alpha: float = 1.0, beta: float = 0.0,
                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """s [N_v][N_r][N][K] -> x [N_r][N][N][K]."""
+    _need(s, "s", torch.float32, shape=(None, None, None, None))
+    n_v, n_r, n, k = s.shape
+    _opt(out, "out", torch.float32, shape=(n_r, n, n, k), device=s.device)
     dev = _dev(s)
     ctx = context(dev)
-    n_v, n_r, n, k = s.shape
     g, keep = _geom(n_v, n_r, n, k, angles)
     if out is None:
         out = torch.empty((n_r, n, n, k), dtype=torch.float32, device=s.device)
@@ -350,6 +419,7 @@ def hsn_projector_launch_info(n_views: int, n_slices: int, n: int, k: int,
 
 def hsn_cgls(sino: torch.Tensor, n_iter: int, angles: Optional[Sequence[float]] = None, resid: bool = False):
     """Per-channel CGLS from x = 0: sino [N_v][N_r][N][K] -> x [N_r][N][N][K] (and residual norms)."""
+    _need(sino, "sino", torch.float32, shape=(None, None, None, None))
     dev = _dev(sino)
     ctx = context(dev)
     n_v, n_r, n, k = sino.shape
@@ -369,9 +439,12 @@ def hsn_fhr_step(y: torch.Tensor, yo: torch.Tensor, V: torch.Tensor, D: torch.Te
     """The whole FHR path of one scan in one C call: counts y [N_v][N_r][N_c][N_k] and y^o (uint16 bits
     as int16) -> V, D in place, x [N_r][N_c][N_c][K], and x^h over vox x bins (None if vox is None).
     bufs: optional dict that keeps the intermediates (p, pooled) and outputs (x, xh) between calls."""
+    _check_counts(y, yo)
+    n_v, n_r, n_c, n_k = y.shape
+    _need(V, "V", torch.float32, shape=(n_v * n_r * n_c, None), device=y.device)
+    _need(D, "D", torch.float32, shape=(n_k, V.shape[1]), device=y.device)
     dev = _dev(y)
     ctx = context(dev)
-    n_v, n_r, n_c, n_k = y.shape
     n_p, k = V.shape
     dims = Dims(n_v, n_r, n_c, n_k)
     bufs = {} if bufs is None else bufs
@@ -408,10 +481,13 @@ def hsn_mbir(sino: torch.Tensor, sigma_v, sigma_x, p: float = 1.2, T: float = 1.
              n_inner: int = 5, x0: Optional[torch.Tensor] = None, angles: Optional[Sequence[float]] = None):
     """qGGMRF-MBIR per channel: sino [N_v][N_r][N][K] -> x [N_r][N][N][K].  sigma_v, sigma_x: a
     scalar or K values; x0: the start (default zeros), copied."""
+    _need(sino, "sino", torch.float32, shape=(None, None, None, None))
+    n_v, n_r, n, k = sino.shape
+    _opt(x0, "x0", (torch.float32, torch.float64), shape=(n_r, n, n, k), layout=None, device=sino.device)
     dev = _dev(sino)
     ctx = context(dev)
-    n_v, n_r, n, k = sino.shape
     g, keep = _geom(n_v, n_r, n, k, angles)
+
     def per_channel(v):
         vals = [float(t) for t in v] if hasattr(v, "__len__") else [float(v)] * k
         if len(vals) != k:
@@ -433,6 +509,9 @@ def hsn_fbp(sino: torch.Tensor, n_views: int, n_slices: int, n: int, k: int,
             out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Filtered backprojection of k-channel rays (ray i at sino.data_ptr() + i * ld floats;
     ld = k: sino is [N_v][N_r][N][k]) -> x [N_r][N][N][k]."""
+    ld_ = int(ld or k)
+    _need(sino, "sino", torch.float32, layout="inner", extent=(n_views * n_slices * n - 1) * ld_ + k)
+    _opt(out, "out", torch.float32, shape=(n_slices, n, n, k), device=sino.device)
     dev = _dev(sino)
     ctx = context(dev)
     g, keep = _geom(n_views, n_slices, n, k, angles)
@@ -444,6 +523,8 @@ def hsn_fbp(sino: torch.Tensor, n_views: int, n_slices: int, n: int, k: int,
 
 def hsn_rehydrate(xs: torch.Tensor, D: torch.Tensor, vox=None, bins=None) -> torch.Tensor:
     """x^h = x^s D^T over [vox[0], vox[1]) x [bins[0], bins[1])."""
+    _need(xs, "xs", torch.float32, shape=(None, None))
+    _need(D, "D", torch.float32, shape=(None, xs.shape[1]), device=xs.device)
     dev = _dev(xs)
     ctx = context(dev)
     n_x, k = xs.shape
@@ -532,6 +613,9 @@ def hsn_mlp_create(k: int, precision: int = PREC_BF16, params=None, device: int 
 
 def hsn_mlp_pool(p_bf16: torch.Tensor, n_k: int, x_dtype: int = PREC_BF16) -> torch.Tensor:
     """[N_p][ldb] bfloat16 bits -> [N_p][256] pooled (int16 bits or float32)."""
+    _need(p_bf16, "p_bf16", _U16, shape=(None, None), layout="rows")
+    if p_bf16.shape[1] < n_k:
+        raise ValueError(f"hsn: p_bf16 rows must hold n_k = {n_k} bins")
     dev = _dev(p_bf16)
     ctx = context(dev)
     n_p = p_bf16.shape[0]
@@ -542,9 +626,9 @@ def hsn_mlp_pool(p_bf16: torch.Tensor, n_k: int, x_dtype: int = PREC_BF16) -> to
 
 
 def hsn_mlp_forward(mlp: Mlp, x: torch.Tensor) -> torch.Tensor:
+    _need(x, "x", mlp.x_dtype, shape=(None, MLP_IN))
     dev = _dev(x)
     ctx = context(dev)
-    assert x.dtype == mlp.x_dtype and x.shape[1] == MLP_IN and x.is_contiguous()
     y = torch.empty((x.shape[0], mlp.k), dtype=torch.float32, device=x.device)
     _check(_lib.hsn_mlp_forward(ctx, mlp.handle, _ptr(x), x.shape[0], _ptr(y), _stream(dev)), ctx)
     return y
@@ -552,9 +636,10 @@ def hsn_mlp_forward(mlp: Mlp, x: torch.Tensor) -> torch.Tensor:
 
 def hsn_mlp_loss_grad(mlp: Mlp, x: torch.Tensor, target: torch.Tensor):
     """(mean squared error, flat gradient [n_params]) over all rows as one batch."""
+    _need(x, "x", mlp.x_dtype, shape=(None, MLP_IN))
+    _need(target, "target", torch.float32, shape=(x.shape[0], mlp.k), device=x.device)
     dev = _dev(x)
     ctx = context(dev)
-    assert x.dtype == mlp.x_dtype and x.is_contiguous() and target.is_contiguous()
     g = torch.empty(mlp.n_params, dtype=torch.float32, device=x.device)
     loss = torch.empty((), dtype=torch.float64, device=x.device)
     _check(_lib.hsn_mlp_loss_grad(ctx, mlp.handle, _ptr(x), _ptr(target), x.shape[0], _ptr(g), _ptr(loss),
@@ -565,9 +650,10 @@ def hsn_mlp_loss_grad(mlp: Mlp, x: torch.Tensor, target: torch.Tensor):
 def hsn_mlp_train(mlp: Mlp, x: torch.Tensor, target: torch.Tensor, epochs: int, batch: int = 4096,
                   lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, seed: int = 0):
     """Adam over shuffled mini-batches; returns the per-epoch mean batch loss."""
+    _need(x, "x", mlp.x_dtype, shape=(None, MLP_IN))
+    _need(target, "target", torch.float32, shape=(x.shape[0], mlp.k), device=x.device)
     dev = _dev(x)
     ctx = context(dev)
-    assert x.dtype == mlp.x_dtype and x.is_contiguous() and target.is_contiguous()
     o = TrainOpts(epochs, batch, lr, beta1, beta2, eps, seed)
     hist = (C.c_double * max(epochs, 1))()
     _check(_lib.hsn_mlp_train(ctx, mlp.handle, _ptr(x), _ptr(target), x.shape[0], C.byref(o),
@@ -576,6 +662,10 @@ def hsn_mlp_train(mlp: Mlp, x: torch.Tensor, target: torch.Tensor, epochs: int, 
 
 
 def hsn_mlp_infer(mlp: Mlp, p_bf16: torch.Tensor, n_k: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _need(p_bf16, "p_bf16", _U16, shape=(None, None), layout="rows")
+    if p_bf16.shape[1] < n_k:
+        raise ValueError(f"hsn: p_bf16 rows must hold n_k = {n_k} bins")
+    _opt(out, "out", torch.float32, shape=(p_bf16.shape[0], mlp.k), device=p_bf16.device)
     dev = _dev(p_bf16)
     ctx = context(dev)
     n_p = p_bf16.shape[0]
@@ -600,6 +690,9 @@ def hsn_mlp_load(path: str, device: int = 0) -> Mlp:
 
 def hsn_canonicalize(V: torch.Tensor, D: torch.Tensor, library: Optional[torch.Tensor] = None) -> None:
     """In place: unit-norm D columns, V scaled inversely, columns matched to library (or by |V|)."""
+    _need(V, "V", torch.float32, shape=(None, None))
+    _need(D, "D", torch.float32, shape=(None, V.shape[1]), device=V.device)
+    _opt(library, "library", torch.float32, shape=tuple(D.shape), device=V.device)
     dev = _dev(V)
     ctx = context(dev)
     n_p, k = V.shape
@@ -609,11 +702,13 @@ def hsn_canonicalize(V: torch.Tensor, D: torch.Tensor, library: Optional[torch.T
 def hsn_fmd(xs: torch.Tensor, labels: torch.Tensor, n_m: int, Ds: torch.Tensor):
     """Alg. 2 tail: (T [n_m][K], x^m [n_x][n_m], D^m [n_k][n_m]) from x^s [n_x][K],
     int32 labels [n_x] (-1 = no region) and D^s [n_k][K]."""
+    _need(xs, "xs", torch.float32, shape=(None, None))
+    _need(labels, "labels", torch.int32, shape=(xs.shape[0],), device=xs.device)
+    _need(Ds, "Ds", torch.float32, shape=(None, xs.shape[1]), device=xs.device)
     dev = _dev(xs)
     ctx = context(dev)
     n_x, k = xs.shape
     n_k = Ds.shape[0]
-    assert labels.dtype == torch.int32 and xs.is_contiguous() and Ds.is_contiguous()
     T = torch.empty((n_m, k), dtype=torch.float32, device=xs.device)
     xm = torch.empty((n_x, n_m), dtype=torch.float32, device=xs.device)
     Dm = torch.empty((n_k, n_m), dtype=torch.float32, device=xs.device)

@@ -196,3 +196,64 @@ def test_stationary_reference_is_lower_than_mu():
     _, _, _, ff = nmf.mu_run(P, V, D, 200)
     fs, _, _ = nmf.stationary_reference(P, V, D)
     assert fs <= ff[-1] * (1 + 1e-12)
+
+
+def test_kkt_residual_hand_cases():
+    # 1 x 1 problem p = 1, D = 1: g_V = 2 (v - 1).
+    P, D = np.array([[1.0]]), np.array([[1.0]])
+    # v = 0 with a negative gradient (-2) violates g >= 0: residual |g| / |2 p d| = 1
+    assert nmf.kkt_residual(P, np.array([[0.0]]), D)[0] == pytest.approx(1.0, rel=1e-15)
+    # v = 2 > 0 with g = 2 violates x g = 0: residual min(2, 2) / 2 = 1
+    assert nmf.kkt_residual(P, np.array([[2.0]]), D)[0] == pytest.approx(1.0, rel=1e-15)
+    # v = 1: g = 0, stationary
+    assert nmf.kkt_residual(P, np.array([[1.0]]), D)[0] == 0.0
+    # p = -1: v = 0 is the constrained minimiser (g = 2 >= 0 at x = 0)
+    assert nmf.kkt_residual(-P, np.array([[0.0]]), D)[0] == 0.0
+    # an exact positive factorisation is stationary in both blocks
+    g = _rng(70)
+    V = g.uniform(0.2, 1, (40, 3))
+    D = g.uniform(0.2, 1, (25, 3))
+    rv, rd = nmf.kkt_residual(V @ D.T, V, D)
+    assert rv <= 1e-14 and rd <= 1e-14
+
+
+def test_kkt_residual_gradient_is_the_objective_gradient():
+    # the interior residual is the gradient itself: check it against central
+    # differences of f = ||P - V D^T||^2 at a strictly positive point
+    P = _noisy_lowrank(71, n_p=12, n_k=9, k=2)
+    g = _rng(72)
+    V = g.uniform(0.5, 1, (12, 2))
+    D = g.uniform(0.5, 1, (9, 2))
+    gV = 2.0 * (V @ (D.T @ D) - P @ D)
+    h = 1e-6
+    for (i, j) in [(0, 0), (5, 1), (11, 0)]:
+        Vp, Vm = V.copy(), V.copy()
+        Vp[i, j] += h
+        Vm[i, j] -= h
+        fd = (nmf.objective(P, Vp, D) - nmf.objective(P, Vm, D)) / (2 * h)
+        assert fd == pytest.approx(gV[i, j], rel=1e-7)
+    # where every gradient entry is below its x, the residual is ||g|| / ||2 P D||
+    if np.all(np.abs(gV) < V):
+        assert nmf.kkt_residual(P, V, D)[0] == pytest.approx(np.linalg.norm(gV) / np.linalg.norm(2 * P @ D))
+
+
+def test_stationary_reference_is_a_kkt_point():
+    # A small noisy scan, where plain ANLS is still 2e-4 above the minimum
+    # after 300 rounds: the reference must end at a first-order stationary
+    # point (both KKT residuals <= 1e-9 relative) and below every ANLS iterate.
+    sc = synth.make_scan(n_views=12, n_rows=1, n_cols=24, n_bins=48, n_mat=3, flux=1e4, seed=5)
+    from oracle.normalize import normalize
+    P, _, _ = normalize(sc.y, sc.yo)
+    V0, D0 = synth.random_factors(P.shape[0], P.shape[1], 3, 7)
+    fs, Vs, Ds = nmf.stationary_reference(P, V0, D0, max_rounds=50)
+    rv, rd = nmf.kkt_residual(P, Vs, Ds)
+    assert rv <= 1e-9 and rd <= 1e-9, (rv, rd)
+    assert np.all(Vs >= 0) and np.all(Ds >= 0)
+    assert fs == pytest.approx(nmf.objective(P, Vs, Ds), rel=1e-15)
+    f_anls, Va, Da = nmf.stationary_reference(P, V0, D0, max_rounds=50, refine=False)
+    assert fs <= f_anls
+    # the pin bites: an early-stopped reference (one ANLS round, or the
+    # 50 rounds alone) is far from stationary
+    assert max(nmf.kkt_residual(P, Va, Da)) > 1e-6
+    _, V1, D1 = nmf.stationary_reference(P, V0, D0, max_rounds=1, refine=False)
+    assert max(nmf.kkt_residual(P, V1, D1)) > 1e-4
