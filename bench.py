@@ -50,9 +50,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=["mid", "tiny", "full", "batched"],
-                    help="mid / tiny / full: the whole path on one scan; batched: 32 uneven decompositions")
-    ap.add_argument("--mlp-scans", type=int, default=348)
+    ap.add_argument("--workload", default="full", choices=["full", "mid", "tiny", "batched"],
+                    help="full / mid / tiny: the whole path on one scan; batched: 32 uneven decompositions")
+    ap.add_argument("--mlp-scans", type=int, default=None, help="training scans (default 348; 40 with --quick)")
+    ap.add_argument("--quick", action="store_true",
+                    help="short set-up and no comparison paths or CPU baseline (for profiler runs)")
     ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--compare-steps", type=int, default=2,
                     help="steps of each comparison path (plain FP32, cold BF16)")
@@ -60,27 +62,40 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy of 1 GiB (reference for HBM counters) and exit")
     ap.add_argument("--traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
-                    help="turn two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, WRITE_SIZE; csv) into "
-                         "HBM bytes per launch of the mid-shape kernels, scaled by the copy probe, and exit")
+                    help="turn two rocprofv3 --pmc runs of this benchmark on --workload (FETCH_SIZE, WRITE_SIZE; "
+                         "csv) into HBM bytes per launch of its kernels, scaled by the copy probe, and exit")
     return ap.parse_args()
 
 
-# Kernels whose every launch in the mid benchmark has the mid shape (the CGLS
-# and MBIR loops of the measured steps), their template instance and source.
+# Kernels whose every launch in a workload's benchmark has that workload's
+# shape: name -> (template instance prefix as rocprofv3 prints it, source).
+_PRJ = "paper_2410_22500_amd/csrc/projector.hip"
 TRAFFIC_KERNELS = {
-    "project_lds_kernel": ("project_lds_kernel<4, true>", "paper_2410_22500_amd/csrc/projector.hip"),
-    "backproject_lds_kernel": ("backproject_lds_kernel<4, 1, true>", "paper_2410_22500_amd/csrc/projector.hip"),
-    "xpby_transpose_kernel": ("xpby_transpose_kernel<4>", "paper_2410_22500_amd/csrc/projector.hip"),
-    "cgls_rstep_kernel": ("cgls_rstep_kernel(", "paper_2410_22500_amd/csrc/projector.hip"),
-    "prior_apply_kernel": ("prior_apply_kernel<4>", "paper_2410_22500_amd/csrc/projector.hip"),
-    "mbir_step_kernel": ("mbir_step_kernel<4>", "paper_2410_22500_amd/csrc/projector.hip"),
+    "mid": {
+        "project_lds_kernel": ("project_lds_kernel<4, true>", _PRJ),
+        "backproject_lds_kernel": ("backproject_lds_kernel<4, 1, true>", _PRJ),
+        "xpby_transpose_kernel": ("xpby_transpose_kernel<4>", _PRJ),
+        "cgls_rstep_kernel": ("cgls_rstep_kernel(", _PRJ),
+        "prior_apply_kernel": ("prior_apply_kernel<4>", _PRJ),
+        "mbir_step_kernel": ("mbir_step_kernel<4>", _PRJ),
+    },
+    "full": {
+        "pass_bf16_kernel": ("pass_bf16_kernel<5, 4, true, 8, 1>", "paper_2410_22500_amd/csrc/nmf_bf16.hip"),
+        "pass_f32_kernel": ("pass_f32_kernel<5, 2, 4, true>", "paper_2410_22500_amd/csrc/nmf_f32.hip"),
+        "normalize": ("normalize_", "paper_2410_22500_amd/csrc/normalize.hip"),
+        "project_lds_kernel": ("project_lds_kernel<5,", _PRJ),
+        "backproject_lds_kernel": ("backproject_lds_kernel<5,", _PRJ),
+    },
 }
+WORKLOAD_TEXT = {"mid": "mid (60 views, 16 slices, 128 columns, 1024 bins, K=4)",
+                 "full": "full (120 views, 256 slices, 256 columns, 2000 bins, K=5)"}
 
 
-def traffic_from_counters(fetch_dir, write_dir, out_json):
+def traffic_from_counters(fetch_dir, write_dir, out_json, workload="mid"):
     """Average FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel from the
     rocprofv3 csv output, times the copy probe's bytes-per-KiB factors (kept in
-    the existing record), with the SHA-256 of each kernel's source file."""
+    the existing record or in profiles/pmc_traffic_mid.json), with the SHA-256
+    of each kernel's source file."""
     import csv
     import glob
     import hashlib
@@ -93,7 +108,7 @@ def traffic_from_counters(fetch_dir, write_dir, out_json):
                 if row.get("Counter_Name") != counter:
                     continue
                 name = row.get("Kernel_Name", "")
-                for key, (inst, _) in TRAFFIC_KERNELS.items():
+                for key, (inst, _) in TRAFFIC_KERNELS[workload].items():
                     if inst in name and not (key == "project_lds_kernel" and "backproject" in name):
                         acc.setdefault(key, []).append(float(row["Counter_Value"]))
         return acc
@@ -101,16 +116,19 @@ def traffic_from_counters(fetch_dir, write_dir, out_json):
     old = json.load(open(out_json)) if os.path.exists(out_json) else {}
     probe = old.get("copy_probe")
     if not probe:
+        mid_rec = os.path.join(ROOT, "profiles", "pmc_traffic_mid.json")
+        probe = json.load(open(mid_rec)).get("copy_probe") if os.path.exists(mid_rec) else None
+    if not probe:
         sys.exit("--traffic: the copy probe factors are missing from " + out_json)
     fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
     kernels = {}
-    for key, (inst, src) in TRAFFIC_KERNELS.items():
+    for key, (inst, src) in TRAFFIC_KERNELS[workload].items():
         if key not in fetch or key not in write:
             continue
         fk = sum(fetch[key]) / len(fetch[key])
         wk = sum(write[key]) / len(write[key])
         fb, wb = fk * 1024 * probe["fetch_factor"], wk * 1024 * probe["write_factor"]
-        kernels[key] = {"instance": inst.rstrip("("), "workload": "mid (60 views, 16 slices, 128 columns, K=4)",
+        kernels[key] = {"instance": inst.rstrip("("), "workload": WORKLOAD_TEXT[workload],
                         "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
                         "dispatches": [len(fetch[key]), len(write[key])], "fetch_bytes": fb, "write_bytes": wb,
                         "hbm_bytes_per_launch": fb + wb, "source": src,
@@ -153,7 +171,7 @@ def main():
         copy_probe()
         return
     if args.traffic:
-        traffic_from_counters(*args.traffic)
+        traffic_from_counters(*args.traffic, workload=args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (got --gpus {args.gpus}); "
@@ -187,66 +205,72 @@ def main():
     V = torch.empty((n_p, K), dtype=torch.float32, device=dev)
     D = torch.empty((n_k, K), dtype=torch.float32, device=dev)
 
-    # Warm-start network: trained on the workload's material library (not timed).
+    # Warm-start network (not timed): trained on decompositions of tiny-geometry
+    # scans made of the workload's materials, at the workload's bin count and flux.
     t0 = time.time()
-    X, T, tt = warmstart.make_training_set(args.mlp_scans, k=K, library_seed=cfg["seed"],
+    n_scans = args.mlp_scans if args.mlp_scans is not None else (40 if args.quick else 348)
+    geo = warmstart.workload_geometry(n_k, sc.flux)
+    X, T, tt = warmstart.make_training_set(n_scans, k=K, library_seed=cfg["seed"], geometry=geo,
                                            log=lambda s: log(s))
     mlp, loss_hist, t_train = warmstart.train(X, T, k=K, epochs=args.mlp_epochs)
     n_train = int(X.shape[0])
     del X, T
-    log(f"network: {n_train} spectra, training {t_train:.2f}s, loss {loss_hist[0]:.3g} -> {loss_hist[-1]:.3g} "
-        f"(set-up {time.time() - t0:.1f}s)")
+    torch.cuda.empty_cache()
+    log(f"network: {n_train} spectra ({n_scans} scans, {geo['n_bins']} bins, flux {geo['flux']:g}), training "
+        f"{t_train:.2f}s, loss {loss_hist[0]:.3g} -> {loss_hist[-1]:.3g} (set-up {time.time() - t0:.1f}s)")
 
-    # f*: lowest objective of long float32 reference runs (not timed).
-    p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=True)
+    # f*: the lowest objective of long float32 ANLS reference runs from two
+    # starts (not timed); the last 100 rounds' relative decrease says how close
+    # to stationary each run ended.
+    p, pb, _, _, bias = hsn.hsn_normalize(y, yo, want_bf16=True, want_bias=True)
     refs = {}
-    # (the full workload's reference runs are shorter: an ANLS round streams 126 GB there)
-    r_anls, r_hals = (400, 600) if full else (2000, 3000)
-    for name, kw in (("nndsvda+mu+anls", dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, polish_algo=hsn.ALGO_ANLS,
-                                              polish_rounds=r_anls, precision=hsn.PREC_BF16 if full else
-                                              hsn.PREC_FP32)),
-                     ("nndsvda+mu+hals", dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, polish_algo=hsn.ALGO_HALS,
-                                              polish_rounds=r_hals, precision=hsn.PREC_BF16 if full else
-                                              hsn.PREC_FP32)),
-                     ("learned+anls", dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0, polish_algo=hsn.ALGO_ANLS,
-                                           polish_rounds=r_anls))):
-        st = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, **kw)
+    r_rounds = 100 if args.quick else (600 if full else 2000)
+    for name, kw in (("nndsvda+mu+anls", dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, polish_rounds=r_rounds,
+                                              precision=hsn.PREC_BF16 if full else hsn.PREC_FP32)),
+                     ("learned+anls", dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0, polish_rounds=r_rounds))):
+        t1 = time.time()
+        st = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, polish_algo=hsn.ALGO_ANLS, **kw)
         h = np.array(st["history"])
-        refs[name] = float(h.min())
-        log(f"reference {name}: min f {h.min():.9e}, last rel change {abs(h[-2] - h[-1]) / h[-1]:.2e}")
-    f_star = min(refs.values())
-    del p, pb
+        tail = float((h[-101] - h[-1]) / h[-1]) if len(h) > 101 else None
+        refs[name] = {"f": float(h.min()), "rounds": st["polish_done"], "last_100_rounds_rel_decrease": tail}
+        log(f"reference {name}: min f {h.min():.9e}, last-100-round rel decrease {tail}, {time.time() - t1:.1f}s")
+    f_star = min(r["f"] for r in refs.values())
+    del p, pb, bias
+    torch.cuda.empty_cache()
 
+    bf16_rounds = POLISH_CAP - 100
     paths = {
-        "learned": dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0),
+        # learned start, ANLS rounds on the bfloat16 p until the bias-corrected
+        # objective meets the tolerance, then float32 ANLS rounds decide the stop
+        "learned": dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0, polish_bf16_rounds=bf16_rounds),
+        "learned_fp32": dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0),
         "plain_fp32": dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, precision=hsn.PREC_FP32),
-        "cold_bf16": dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, precision=hsn.PREC_BF16),
+        "cold_bf16": dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, precision=hsn.PREC_BF16,
+                          polish_bf16_rounds=bf16_rounds),
     }
-
     last_x = {}
-
     learned_bufs = {}
 
     def step(path, record=None):
         if path == "learned":
-            # The whole path in one C call (hsn_fhr_step): one normalisation pass writes p
-            # and the network's pooled input (no bfloat16 copy of p), the learned start and
-            # ANLS rounds to rel obj 1e-4, CGLS, and x^h of one slice; buffers are reused.
+            # The whole path in one C call (hsn_fhr_step): one normalisation pass writes p,
+            # its bfloat16 copy (with -||p - p_bf16||^2) and the network's pooled input,
+            # the learned start, ANLS rounds to rel obj 1e-4, CGLS, and x^h of one slice.
             x, _, s = hsn.hsn_fhr_step(y, yo, V, D, CGLS_ITERS, vox=(0, sc.n_cols * sc.n_cols), bins=(0, n_k),
                                        bufs=learned_bufs, check_every=BULK, polish_rounds=POLISH_CAP,
                                        polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star, **paths[path])
             last_x["x"] = x
-            if record is not None:
-                record.append(s)
-            return s
         else:
-            p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=True)
+            want_b = paths[path].get("polish_bf16_rounds", 0) > 0 or paths[path].get("precision") == hsn.PREC_BF16
+            p, pb, _, _, bias = hsn.hsn_normalize(y, yo, want_bf16=True, want_bias=True)
             s = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, polish_rounds=POLISH_CAP,
-                                     polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star, **paths[path])
-        sino = V.view(sc.n_views, sc.n_rows, sc.n_cols, K)
-        x = hsn.hsn_cgls(sino, CGLS_ITERS)
-        last_x["x"] = x
-        hsn.hsn_rehydrate(x.view(-1, K), D, vox=(0, sc.n_cols * sc.n_cols), bins=(0, n_k))
+                                     polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star,
+                                     bf16_bias=bias if want_b else None, **paths[path])
+            del p, pb
+            sino = V.view(sc.n_views, sc.n_rows, sc.n_cols, K)
+            x = hsn.hsn_cgls(sino, CGLS_ITERS)
+            last_x["x"] = x
+            hsn.hsn_rehydrate(x.view(-1, K), D, vox=(0, sc.n_cols * sc.n_cols), bins=(0, n_k))
         if record is not None:
             record.append(s)
         return s
@@ -281,14 +305,15 @@ def main():
     ms_step_prof, recs_prof, prof = timed("learned", args.steps, True)
     nmf_ms = float(np.mean([r["ms"] for r in recs]))
     reached = all(r["rel_obj"] <= REL_OBJ for r in recs)
-    log(f"learned path: {ms_step:.3f} ms/step, NMF {nmf_ms:.3f} ms, rounds {recs[-1]['polish_done']}, "
-        f"rel obj {recs[-1]['rel_obj']:.3e}")
+    log(f"learned path: {ms_step:.3f} ms/step, NMF {nmf_ms:.3f} ms, rounds {recs[-1]['polish_done']} "
+        f"({recs[-1]['polish_bf16_done']} on p_bf16), rel obj {recs[-1]['rel_obj']:.3e}")
+    x_flag = last_x["x"].clone()
+    V_flag, D_flag = V.clone(), D.clone()
 
-    # Material decomposition tail (Alg. 2, eq. 7-9) on the reconstructed
-    # subspace volume, with the phantom's pure-material voxels as the region
-    # labels (timed on its own; not part of the step).
-    fmd = None
-    if not full:
+    # Material decomposition tail (Alg. 2, eq. 7-9) and "FHR with FBP" against
+    # DHR (Section V, Table II): the mid workload only (not part of the step).
+    fmd = fbp_cmp = None
+    if not full and not args.quick:
         frac = synth.volume_fractions(sc.objs, sc.n_cols, sc.n_rows, sc.n_mat)
         lab = np.where(frac.max(axis=-1) >= 0.999, frac.argmax(axis=-1), -1).astype(np.int32).ravel()
         lab_d = torch.from_numpy(lab).to(dev)
@@ -306,25 +331,14 @@ def main():
         fmd = {"ms": float(np.median(ts)), "voxels_per_s": xs.shape[0] / (float(np.median(ts)) * 1e-3),
                "voxels": int(xs.shape[0]), "materials": sc.n_mat, "labelled_voxels": int((lab >= 0).sum())}
         log(f"fmd tail: {fmd['ms']:.3f} ms for {xs.shape[0]} voxels")
-
-    # "FHR with FBP" against DHR (Section V, Table II): the paper's baseline
-    # reconstructs every wavelength bin by FBP; FHR reconstructs the K
-    # subspace sinograms and rehydrates x^h = x^s D^T (eq. 6) for every voxel
-    # and bin.  Both from the counts, timed once after a warm-up each; SNR as
-    # in the paper's SNR_FHR (mean over bins and materials of (region mean /
-    # background deviation)^2), with the phantom's pure-material voxels as
-    # the material regions and its empty voxels inside the field of view as
-    # the background.  Not part of the headline step.
-    fbp_cmp = None
-    if not full:
-        fbp_cmp = fbp_comparison(sc, y, yo, mlp, V, D, paths["learned"], f_star, last_x["x"])
+        fbp_cmp = fbp_comparison(sc, y, yo, mlp, V, D, paths["learned_fp32"], f_star, last_x["x"])
         log(f"fbp comparison: FHR with FBP {fbp_cmp['fhr_fbp_ms']:.2f} ms, DHR {fbp_cmp['dhr_fbp_ms']:.2f} ms "
             f"({fbp_cmp['speedup']:.1f}x); SNR FHR-FBP {fbp_cmp['snr_db']['fhr_fbp']:.2f} dB, "
             f"DHR {fbp_cmp['snr_db']['dhr_fbp']:.2f} dB, FHR-CGLS {fbp_cmp['snr_db']['fhr_cgls']:.2f} dB")
 
     compare = {}
     compare_prof = {}
-    for path in ("plain_fp32", "cold_bf16"):
+    for path in () if args.quick else ("plain_fp32", "cold_bf16", "learned_fp32"):
         step(path)
         ms_p, rp, _ = timed(path, args.compare_steps, False)
         _, rpp, pp = timed(path, args.compare_steps, True)
@@ -332,36 +346,37 @@ def main():
         nm = float(np.mean([r["ms"] for r in rp]))
         compare[path] = {"ms_per_step": ms_p, "nmf_ms": nm, "nmf_vpb_per_s": vpb / (nm * 1e-3),
                          "mu_iters": rp[-1]["iters"], "anls_rounds": rp[-1]["polish_done"],
+                         "anls_rounds_bf16": rp[-1]["polish_bf16_done"],
                          "rel_obj": rp[-1]["rel_obj"], "reached": all(r["rel_obj"] <= REL_OBJ for r in rp)}
-        log(f"{path}: {ms_p:.3f} ms/step, NMF {nm:.3f} ms, {rp[-1]['iters']} MU + {rp[-1]['polish_done']} ANLS, "
-            f"rel obj {rp[-1]['rel_obj']:.3e}")
+        log(f"{path}: {ms_p:.3f} ms/step, NMF {nm:.3f} ms, {rp[-1]['iters']} MU + {rp[-1]['polish_done']} ANLS "
+            f"({rp[-1]['polish_bf16_done']} on p_bf16), rel obj {rp[-1]['rel_obj']:.3e}")
 
     # Roofline of each profiled kernel kind over the timed region: algorithmic
     # bytes (or flops) per launch / average launch time.
-    rounds = sum(r["polish_done"] for r in recs_prof)
     elems = float(n_p) * n_k
     vb = 4.0 * n_p * K
+    rounds = sum(r["polish_done"] for r in recs_prof)
+    rounds_bf = sum(r["polish_bf16_done"] for r in recs_prof)
     taps = 2.0 * float(np.mean([max(abs(math.cos(v * math.pi / sc.n_views)), abs(math.sin(v * math.pi / sc.n_views)))
                                 for v in range(sc.n_views)]))
     triples = float(sc.n_views) * sc.n_rows * sc.n_cols * sc.n_cols * K
     mlp_flops_row = 2.0 * (256 * 128 + 128 * 128 + 128 * 16)
-    work = {  # kind -> (name, total algorithmic units over the timed region, bound, unit)
-        hsn.KERN_NORMALIZE: ("normalize_u16_kernel (u16 counts -> f32 p + pooled network input)",
-                             args.steps * (6.0 * elems + 2.0 * sc.n_rows * sc.n_cols * n_k +
-                                           (512.0 if mlp.precision == hsn.PREC_BF16 else 1024.0) * n_p), "hbm"),
-        hsn.KERN_NMF_PASS: ("pass_f32_kernel (N_V / N_D passes over f32 p)",
-                            args.steps * (4.0 * elems + vb) + rounds * 2 * (4.0 * elems + vb), "hbm"),
-        hsn.KERN_MLP_POOL: ("pool_kernel (bf16 p -> 256-bin pooled rows)",
-                            args.steps * (2.0 * elems + 512.0 * n_p), "hbm"),
+    pool_b = 512.0 if mlp.precision == hsn.PREC_BF16 else 1024.0
+    work = {  # kind -> (name, total algorithmic units over the timed region, bound)
+        hsn.KERN_NORMALIZE: ("normalize (u16 counts -> f32 p + bf16 p + pooled network input)",
+                             args.steps * (8.0 * elems + 2.0 * sc.n_rows * sc.n_cols * n_k + pool_b * n_p), "hbm"),
+        hsn.KERN_NMF_PASS_BF16: ("pass_bf16_kernel (fused ANLS rounds over bf16 p, MFMA)",
+                                 rounds_bf * (2.0 * elems + vb), "hbm"),
+        hsn.KERN_NMF_PASS: ("pass_f32_kernel (D0 solve and fused ANLS rounds over f32 p)",
+                            args.steps * (4.0 * elems + vb) + (rounds - rounds_bf) * (4.0 * elems + vb), "hbm"),
         hsn.KERN_MLP_ROWS: ("mlp_infer2_kernel (network inference, bf16 MFMA)",
                             args.steps * mlp_flops_row * n_p, "mfma"),
         hsn.KERN_PROJECT: ("project_lds_kernel (A, Joseph footprint, K channels, LDS-staged)", None, "alu"),
         hsn.KERN_BACKPROJECT: ("backproject_lds_kernel (A^T, LDS-staged)", None, "alu"),
     }
-    # Float32 passes that did work: one N_D pass for D0 per step and two passes
-    # per ANLS round; passes queued after the stop test fired return at once,
-    # their time stays in the total (so the rate is conservative).
-    real = {hsn.KERN_NMF_PASS: args.steps + 2 * rounds}
+    # Passes that did work: the D0 pass and every round run; passes queued after
+    # the stop test fired return at once (their time stays in the total).
+    real = {hsn.KERN_NMF_PASS: args.steps + rounds - rounds_bf, hsn.KERN_NMF_PASS_BF16: rounds_bf}
     roof = {}
     for kk, (name, units, bound) in work.items():
         ms, n = prof.get(kk, (0.0, 0))
@@ -369,6 +384,8 @@ def main():
             continue
         queued = n
         n = real.get(kk, n)
+        if n <= 0:
+            continue
         if bound == "alu":
             units = n * 2.0 * taps * triples
         peak, unit = {"hbm": (HBM_PEAK_GBS, "GB/s"), "alu": (VALU_PEAK_TFLOPS, "TFLOP/s"),
@@ -379,27 +396,29 @@ def main():
                       "alg_per_launch": units / n}
     # HBM bytes per launch from the committed counter runs, valid only while
     # the kernel's source is the one the counters were taken on.
-    traffic = load_traffic() if args.workload == "mid" else {}
+    traffic = load_traffic(args.workload)
     for name, r in roof.items():
         r["traffic"] = traffic.get(name.split(" ")[0])
-    # The comparison paths' streaming passes (their bulk is the largest HBM
-    # stream of the method): MU pass = p once + V read and written; each ANLS
-    # round = two passes of p once + V (or N_V) once.
     for path, (pp, rp) in compare_prof.items():
         it_ = sum(r["iters"] for r in rp)
         rd_ = sum(r["polish_done"] for r in rp)
-        bf = path == "cold_bf16"
-        kinds = [(hsn.KERN_NMF_PASS_BF16, it_ * (2.0 * elems + 2 * vb), it_)] if bf else []
-        kinds.append((hsn.KERN_NMF_PASS, (0 if bf else it_ * (4.0 * elems + 2 * vb)) + rd_ * 2 * (4.0 * elems + vb),
-                      (0 if bf else it_) + 2 * rd_))
+        rb_ = sum(r["polish_bf16_done"] for r in rp)
+        bf_bulk = paths[path].get("precision") == hsn.PREC_BF16
         ent = {}
-        for kk, by, nl in kinds:
-            ms, nq = pp.get(kk, (0.0, 0))
-            if nl and ms > 0:
-                ach = by / (ms * 1e-3) / 1e9
-                ent["bf16 MU pass" if kk == hsn.KERN_NMF_PASS_BF16 else "f32 passes"] = {
-                    "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                    "avg_launch_ms": ms / nl, "launches": nl, "queued": nq}
+        ms, nq = pp.get(hsn.KERN_NMF_PASS_BF16, (0.0, 0))
+        nl = (it_ if bf_bulk else 0) + rb_
+        if nl and ms > 0:
+            by = (it_ if bf_bulk else 0) * (2.0 * elems + 2 * vb) + rb_ * (2.0 * elems + vb)
+            ach = by / (ms * 1e-3) / 1e9
+            ent["bf16 passes"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": ms / nl, "launches": nl, "queued": nq}
+        ms, nq = pp.get(hsn.KERN_NMF_PASS, (0.0, 0))
+        nl = (0 if bf_bulk else it_) + (rd_ - rb_) + (1 if path == "learned_fp32" else 0) * len(rp)
+        if nl and ms > 0:
+            by = (0 if bf_bulk else it_) * (4.0 * elems + 2 * vb) + (nl - (0 if bf_bulk else it_)) * (4.0 * elems + vb)
+            ach = by / (ms * 1e-3) / 1e9
+            ent["f32 passes"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": ms / nl, "launches": nl, "queued": nq}
         gms, gn = pp.get(hsn.KERN_NNDSVD_GRAM, (0.0, 0))
         if gn:
             fl = 2.0 * n_p * n_k * n_k
@@ -429,18 +448,24 @@ def main():
         "data": "synthetic (seeded phantom, Bragg-edge-like spectra, Poisson counts)",
         "config": {"workload": f"{args.workload}: {sc.n_rows} slices x {sc.n_cols}^2, {sc.n_views} views, "
                                f"{n_k} bins, K={K}, flux {sc.flux:g}",
-                   "nmf": f"learned start (bf16 MFMA network, {n_train} training spectra) + ANLS polish until "
-                          f"rel obj {REL_OBJ:g}",
+                   "nmf": f"learned start (bf16 MFMA network, {n_train} training spectra) + fused ANLS rounds on "
+                          f"the bf16 p (bias-corrected stop) then on the f32 p until rel obj {REL_OBJ:g}",
                    "recon": f"CGLS {CGLS_ITERS} pairs", "parallelism": "single GPU"},
         "nmf": {"vpb_per_s": vpb / (nmf_ms * 1e-3), "ms": nmf_ms, "anls_rounds": recs[-1]["polish_done"],
-                "rel_obj": recs[-1]["rel_obj"], "reached": reached, "f_star": f_star, "references": refs},
+                "anls_rounds_bf16": recs[-1]["polish_bf16_done"], "rel_obj": recs[-1]["rel_obj"],
+                "reached": reached, "f_star": f_star, "references": refs,
+                "f_star_note": "lowest objective of the float32 ANLS reference runs; their last-100-round "
+                               "relative decrease bounds how far from stationary they ended"},
         "compare": compare,
-        "speedup_vs_plain_fp32": {"nmf": compare["plain_fp32"]["nmf_ms"] / nmf_ms,
-                                  "step": compare["plain_fp32"]["ms_per_step"] / ms_step},
+        "speedup_vs_plain_fp32": ({"nmf": compare["plain_fp32"]["nmf_ms"] / nmf_ms,
+                                   "step": compare["plain_fp32"]["ms_per_step"] / ms_step}
+                                  if "plain_fp32" in compare else None),
         "fmd_tail": fmd,
         "fbp_comparison": fbp_cmp,
-        "network": {"train_spectra": n_train, "epochs": args.mlp_epochs, "train_s": t_train,
-                    "loss_first": loss_hist[0], "loss_last": loss_hist[-1]},
+        "network": {"train_spectra": n_train, "train_scans": n_scans, "train_geometry": geo,
+                    "library": f"the workload's material library (spectra seed {cfg['seed']})",
+                    "epochs": args.mlp_epochs, "train_s": t_train, "loss_first": loss_hist[0],
+                    "loss_last": loss_hist[-1]},
         "projector": {"voxel_rays_per_s_A": triples / (prj["avg_launch_ms"] * 1e-3) if prj else None,
                       "voxel_rays_per_s_AT": triples / (bpj["avg_launch_ms"] * 1e-3) if bpj else None,
                       "ms_A": prj["avg_launch_ms"] if prj else None, "ms_AT": bpj["avg_launch_ms"] if bpj else None},
@@ -449,18 +474,22 @@ def main():
                      "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
                      "alg_per_launch": d["alg_per_launch"], "all_kernels": roof},
     }
-    if not args.no_cpu_baseline and not full:
-        out["cpu_baseline"] = cpu_baseline(sc, compare["plain_fp32"]["mu_iters"],
-                                           compare["plain_fp32"]["anls_rounds"])
+    if not args.no_cpu_baseline and not args.quick:
+        plain = compare.get("plain_fp32", {"mu_iters": BULK, "anls_rounds": 15})
+        cb, err = cpu_baseline(sc, y, yo, learned_bufs["p"], x_flag, V_flag, D_flag, plain["mu_iters"],
+                               plain["anls_rounds"])
+        out["cpu_baseline"] = cb
+        out["error_vs_fp64"] = err
     print(json.dumps(out), flush=True)
 
 
-def load_traffic():
-    """kernel -> HBM bytes per launch (mid workload) from profiles/pmc_traffic_mid.json
-    (rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy probe), for kernels
-    whose source file still hashes to the value recorded with the counters."""
+def load_traffic(workload):
+    """kernel -> HBM bytes per launch of the workload's kernels from
+    profiles/pmc_traffic_<workload>.json (rocprofv3 FETCH_SIZE / WRITE_SIZE
+    scaled by the copy probe), for kernels whose source file still hashes to
+    the value recorded with the counters."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pmc_traffic_mid.json")
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.json")
     if not os.path.exists(path):
         return {}
     with open(path) as f:
@@ -653,52 +682,138 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(sc, mu_iters, polish_rounds):
-    """The FP64 oracle as it stands, on a bounded sample of the same workload:
-    detector row 0 (1 of N_r slices), running the plain method (NNDSVDa, MU,
-    ANLS) with the iteration counts the plain FP32 GPU path needed.
-    Normalisation, NNDSVDa, CGLS and the expansion run in full on that slice;
-    the NMF iterations are timed on the first quarter of the slice's rays (10
-    MU iterations, 1 ANLS round) and extrapolated linearly in rows and per
-    iteration.  Rate in vpb/s of the slice."""
-    from threadpoolctl import threadpool_info
+def cpu_baseline(sc, y, yo, p_gpu, x_gpu, V_gpu, D_gpu, mu_iters, polish_rounds):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload
+    (detector row 0, one slice of N_r), running the plain method: the
+    normalisation, NNDSVDa, `mu_iters` MU iterations and `polish_rounds` ANLS
+    rounds (the counts the plain FP32 GPU path needed), CGLS and the
+    expansion.  Timed parts: normalisation and the expansion in full, two MU
+    iterations on the slice, NNDSVDa and one ANLS round on a quarter of its
+    rays, two CGLS iterations on the slice; each is extrapolated linearly (in
+    rays and iterations) to the slice's run, and the rate (vpb/s of the slice)
+    holds for the whole scan under linear extrapolation in N_r.  A second run
+    of the sampled parts on one thread gives the single-core rate.
+
+    The same leg measures each GPU result against the oracle on that sample
+    (error_vs_fp64): p, one exact ANLS round from the flagship's final (V, D)
+    (sampled V rows; the NNLS optimality of sampled D rows), A and A^T, three
+    CGLS iterations and the expansion, on slice 0."""
+    import platform
+    import torch
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import cgls as ocgls
     from oracle import expand as oexp
     from oracle import nmf as onmf
+    from oracle import nnls as onnls
+    from oracle import projector as oprj
     from oracle.normalize import normalize as onorm
+    import synth
+    from paper_2410_22500_amd import hsn
 
-    K = sc.n_mat
-    ysub = sc.y[:, :1]
-    yosub = sc.yo[:1]
-    t0 = time.perf_counter()
-    p, _, _ = onorm(ysub, yosub)
-    t_norm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    V, D = onmf.nndsvd(p, K, variant="a")
-    t_init = time.perf_counter() - t0
-    q = max(1, p.shape[0] // 4)
-    n_mu = min(mu_iters, 10)
-    t0 = time.perf_counter()
-    Vq, Dq, _, _ = onmf.mu_run(p[:q], V[:q], D, n_mu)
-    t_mu = (time.perf_counter() - t0) / max(n_mu, 1) * (p.shape[0] / q)
-    t0 = time.perf_counter()
-    onmf.anls_round(p[:q], Vq, Dq)
-    t_an = (time.perf_counter() - t0) * (p.shape[0] / q)
-    t0 = time.perf_counter()
-    sino = V.reshape(sc.n_views, 1, sc.n_cols, K)
-    x = ocgls.cgls(sino, sc.n_cols, CGLS_ITERS)
-    oexp.rehydrate(x.reshape(-1, K), D)
-    t_rec = time.perf_counter() - t0
-    t = t_norm + t_init + t_mu * mu_iters + t_an * polish_rounds + t_rec
+    K, n_k = sc.n_mat, sc.n_bins
+    n_v, n_r, n_c = sc.n_views, sc.n_rows, sc.n_cols
+    y0 = y[:, 0:1].cpu().numpy().view(np.uint16)
+    yo0 = yo[0:1].cpu().numpy().view(np.uint16)
+
+    def sample_times():
+        t = {}
+        t0 = time.perf_counter()
+        p0, _, _ = onorm(y0, yo0)
+        t["normalize"] = time.perf_counter() - t0
+        n0 = p0.shape[0]
+        q = n0 // 4
+        t0 = time.perf_counter()
+        Vq, Dq = onmf.nndsvd(p0[:q], K, variant="a")
+        t["nndsvda"] = (time.perf_counter() - t0) * n0 / q
+        V0, D0 = synth.random_factors(n0, n_k, K, 3)
+        t0 = time.perf_counter()
+        onmf.mu_run(p0, V0, D0, 2)
+        t["mu_iter"] = (time.perf_counter() - t0) / 2
+        t0 = time.perf_counter()
+        onmf.anls_round(p0[:q], Vq, Dq)
+        t["anls_round"] = (time.perf_counter() - t0) * n0 / q
+        sino = V0.reshape(n_v, 1, n_c, K)
+        t0 = time.perf_counter()
+        xs = ocgls.cgls(sino, n_c, 2)
+        t["cgls_iter"] = (time.perf_counter() - t0) / 2
+        t0 = time.perf_counter()
+        oexp.rehydrate(xs.reshape(-1, K), D0)
+        t["rehydrate"] = time.perf_counter() - t0
+        total = (t["normalize"] + t["nndsvda"] + mu_iters * t["mu_iter"] + polish_rounds * t["anls_round"]
+                 + CGLS_ITERS * t["cgls_iter"] + t["rehydrate"])
+        return p0, t, total
+
+    t_all = time.perf_counter()
+    p0, parts, total = sample_times()
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    vpb = p.shape[0] * p.shape[1]
-    return {"value": vpb / t, "unit": "vpb/s", "cores": threads, "kind": "oracle",
-            "sample": f"detector row 0 of {sc.n_rows} ({p.shape[0]} x {p.shape[1]}): normalise, NNDSVDa, "
-                      f"CGLS {CGLS_ITERS}, expansion in full; NMF iterations timed on {q} rays ({n_mu} MU, "
-                      f"1 ANLS) and extrapolated to {mu_iters} MU + {polish_rounds} ANLS on the slice; "
-                      f"{t:.1f}s total (estimate) on {os.cpu_count()} host cpus "
-                      f"({platform.processor() or platform.machine()})",
-            "seconds": t}
+    with threadpool_limits(limits=1):
+        _, parts1, total1 = sample_times()
+    vpb0 = p0.shape[0] * n_k
+    cpu_model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cb = {"value": vpb0 / total, "unit": "vpb/s", "cores": threads, "kind": "oracle",
+          "sample": f"detector row 0 of {n_r} ({p0.shape[0]} x {n_k}): the plain method (normalise, NNDSVDa, "
+                    f"{mu_iters} MU, {polish_rounds} ANLS, CGLS {CGLS_ITERS}, expansion) extrapolated from timed "
+                    f"parts (2 MU on the slice, NNDSVDa and 1 ANLS round on a quarter of its rays, 2 CGLS "
+                    f"iterations); extrapolated: {total:.1f} s for the slice, x {n_r} slices for the scan",
+          "extrapolated": True, "seconds_slice_estimate": total, "parts_s": parts,
+          "single_thread": {"value": vpb0 / total1, "seconds_slice_estimate": total1, "parts_s": parts1},
+          "host_cpus": os.cpu_count(), "cpu_model": cpu_model}
+
+    # --- error of the GPU results against the oracle on slice 0 ---------------
+    def rel(a, b):
+        a = np.asarray(a, np.float64)
+        b = np.asarray(b, np.float64)
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+    err = {"sample": "detector row 0 (slice 0)"}
+    ldp = p_gpu.shape[1]
+    pg0 = p_gpu.view(n_v, n_r, n_c, ldp)[:, 0, :, :n_k].reshape(-1, n_k).cpu().numpy().astype(np.float64)
+    rms = float(np.sqrt(np.mean(p0 * p0)))
+    err["p"] = {"rel_fro": rel(pg0, p0), "max_abs_over_rms": float(np.abs(pg0 - p0).max() / rms)}
+    # one exact ANLS round (the fused float32 pass) from the flagship's result
+    Vt, Dt = V_gpu.clone(), D_gpu.clone()
+    hsn.hsn_subspace_nmf(p_gpu, None, n_k, Vt, Dt, algo=hsn.ALGO_ANLS, max_iter=1, check_every=1)
+    d0 = D_gpu.cpu().numpy().astype(np.float64)
+    G = d0.T @ d0
+    rows = np.random.Generator(np.random.PCG64(11)).choice(p0.shape[0], size=min(2048, p0.shape[0]), replace=False)
+    rows.sort()
+    ref_v = np.stack([onnls.nnls_gram(G, p0[i] @ d0) for i in rows])
+    gpu_rows = (rows // n_c) * (n_r * n_c) + (rows % n_c)
+    got_v = Vt[torch.from_numpy(gpu_rows).to(Vt.device)].cpu().numpy().astype(np.float64)
+    err["anls_round_V_rows"] = {"rel_fro": rel(got_v, ref_v), "rows": int(len(rows))}
+    V1 = Vt.cpu().numpy().astype(np.float64)
+    GV = V1.T @ V1
+    D1 = Dt.cpu().numpy().astype(np.float64)
+    kkt = []
+    for b in np.linspace(0, n_k - 1, 8).astype(int):
+        h = V1.T @ p_gpu[:, b].cpu().numpy().astype(np.float64)
+        grad = GV @ D1[b] - h
+        kkt.append(float(np.linalg.norm(np.minimum(D1[b], grad)) / max(np.abs(h).max(), 1e-300)))
+    err["anls_round_D_rows_kkt"] = {"max_rel": max(kkt), "bins": 8,
+                                    "what": "||min(d, G_V d - V^T p_k)|| / max|V^T p_k| per sampled bin k"}
+    # projector, CGLS and expansion on slice 0
+    x0 = x_gpu[0:1].contiguous()
+    s_gpu = hsn.hsn_project(x0, n_v)
+    err["A"] = {"rel_fro": rel(s_gpu.cpu().numpy(), oprj.project(x0.cpu().numpy().astype(np.float64), n_v))}
+    s0 = V_gpu.view(n_v, n_r, n_c, K)[:, 0:1].contiguous()
+    xb = hsn.hsn_backproject(s0)
+    err["AT"] = {"rel_fro": rel(xb.cpu().numpy(), oprj.backproject(s0.cpu().numpy().astype(np.float64), n_c))}
+    xc = hsn.hsn_cgls(s0, 3)
+    err["cgls_3_iters"] = {"rel_fro": rel(xc.cpu().numpy(), ocgls.cgls(s0.cpu().numpy().astype(np.float64), n_c, 3))}
+    xs_flat = x_gpu.view(-1, K)
+    xh = hsn.hsn_rehydrate(xs_flat, D_gpu, vox=(0, 1024), bins=(0, n_k))
+    err["rehydrate"] = {"rel_fro": rel(xh.cpu().numpy(), oexp.rehydrate(
+        xs_flat[:1024].cpu().numpy().astype(np.float64), d0))}
+    cb["seconds_total"] = time.perf_counter() - t_all
+    return cb, err
 
 
 if __name__ == "__main__":

@@ -81,12 +81,18 @@ enum { HSN_U16 = 0, HSN_F32 = 1 };
  *           N_k..ldb-1 are written with zeros.  16-byte aligned.
  *   offset_b optional [N_v][N_k] float32 output of b (requires bg_mask).
  *   sumsq   optional device double: sum of p^2 over the float32 p values.
+ *   bf16_bias optional device double (requires p_bf16): -||p - p_bf16||^2.
+ *           For any V, D: ||p - V D^T||^2 = ||p_bf16 - V D^T||^2
+ *           - ||p - p_bf16||^2 + 2 <p - p_bf16, p - V D^T>, and the last term
+ *           (rounding errors against the residual) has zero mean, so an
+ *           objective measured on p_bf16 plus this bias estimates the
+ *           objective on p; hsn_nmf_opts.bf16_bias takes it.
  */
 hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *dims,
                          const void *y, int y_dtype, const void *y_open, int y_open_dtype,
                          const uint8_t *bg_mask, float count_floor, int clip_nonneg,
                          float *p, int64_t ldp, uint16_t *p_bf16, int64_t ldb,
-                         float *offset_b, double *sumsq, void *stream);
+                         float *offset_b, double *sumsq, double *bf16_bias, void *stream);
 
 /*
  * hsn_normalize plus the input of the learned warm start in the same pass:
@@ -102,8 +108,8 @@ hsn_status hsn_normalize_pooled(hsn_ctx *ctx, const hsn_dims *dims,
                                 const void *y, int y_dtype, const void *y_open, int y_open_dtype,
                                 const uint8_t *bg_mask, float count_floor, int clip_nonneg,
                                 float *p, int64_t ldp, uint16_t *p_bf16, int64_t ldb,
-                                float *offset_b, double *sumsq, void *pooled, int pooled_precision,
-                                void *stream);
+                                float *offset_b, double *sumsq, double *bf16_bias, void *pooled,
+                                int pooled_precision, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Subspace extraction: eq. (4) (V, D) = argmin_{V,D>=0} ||p - V D^T||^2 */
@@ -113,8 +119,7 @@ enum { HSN_ALGO_MU = 0,    /* Lee-Seung multiplicative updates, V then D      */
        HSN_ALGO_ANLS = 1,  /* exact row-wise NNLS for V, then for D            */
        HSN_ALGO_HALS = 2 };/* HALS column sweeps (the paper's Fast HALS), V then D */
 enum { HSN_PREC_FP32 = 0,  /* float32 p, float32 arithmetic               */
-       HSN_PREC_BF16 = 1 };/* bfloat16 p on MFMA, float32 accumulation;
-                              the polish rounds then use the float32 p    */
+       HSN_PREC_BF16 = 1 };/* bfloat16 p on MFMA, float32 accumulation   */
 enum { HSN_INIT_USER = 0,  /* V and D hold the start on entry                    */
        HSN_INIT_NNDSVDA = 1,  /* NNDSVD with zeros filled by mean(p) (Boutsidis &
                                  Gallopoulos; the paper's initialisation); needs p,
@@ -133,15 +138,18 @@ typedef struct {
   int init;           /* HSN_INIT_* */
   int max_iter;       /* bulk iterations, >= 0 */
   int check_every;    /* objective evaluated every this many iterations (>= 1) */
-  int polish_rounds;  /* rounds on the float32 p after the bulk (>= 0) */
+  int polish_rounds;  /* rounds after the bulk (>= 0) */
   int polish_algo;    /* HSN_ALGO_ANLS or HSN_ALGO_HALS for the polish rounds */
-  int polish_bf16_rounds; /* the first this many polish rounds run on p_bf16 (needs p_bf16) */
+  int polish_bf16_rounds; /* at most this many polish rounds run first on p_bf16 (needs p_bf16),
+                             the remaining ones on the float32 p (see the stop test below) */
   double rel_obj_tol; /* stop when (f - f_ref)/f_ref <= tol; ignored if f_ref <= 0 */
   double f_ref;       /* reference objective f* (> 0 enables the stop test) */
   const hsn_mlp *mlp; /* network for HSN_INIT_MLP (its k must equal k), else NULL */
   const void *mlp_pooled; /* optional for HSN_INIT_MLP: the network input already pooled
                              (hsn_normalize_pooled, in the network's precision, [N_p][256]);
                              NULL: pooled here from p_bf16 */
+  const double *bf16_bias; /* optional device double -||p - p_bf16||^2 (hsn_normalize's
+                              bf16_bias) for the stop test of steps on p_bf16; NULL = 0 */
 } hsn_nmf_opts;
 
 typedef struct {
@@ -153,25 +161,51 @@ typedef struct {
   int history_cap;    /* capacity of history */
   int history_len;    /* entries written */
   float ms;           /* device time of the call */
+  int polish_bf16_done; /* of polish_done, the rounds run on p_bf16 */
 } hsn_nmf_stats;
 
 /*
  * Runs the bulk iterations, then the polish rounds, on V [N_p][K] and
  * D [N_k][K] (float32, in/out, both strictly positive on entry for MU).
  * Each evaluated objective is f(V_{t+1}, D_t) = ||p - V_{t+1} D_t^T||_F^2 over
- * the float32 p (BF16 bulk iterations: over the bfloat16 p), computed from
- * the residual inside the pass, i.e. the objective after the V half-step; for
- * both algorithms it is non-increasing in exact arithmetic.
+ * the float32 p (steps on p_bf16: over the bfloat16 p), computed from the
+ * residual inside the pass, i.e. the objective after the V half-step; for
+ * every algorithm it is non-increasing in exact arithmetic.  An ANLS round
+ * solves every row of V exactly inside one streaming pass (the NNLS of a
+ * row by enumeration of its supports with the inverses of the principal
+ * submatrices of D^T D in float64), then every row of D (Lawson-Hanson with
+ * float64 Cholesky factors).  The stop test fires on a step whose objective
+ * meets (f - f_ref)/f_ref <= rel_obj_tol.  On a step over p_bf16 (a BF16
+ * bulk iteration or one of the first polish_bf16_rounds polish rounds) f is
+ * the bfloat16 objective plus *bf16_bias; when float32 polish rounds follow,
+ * such a stop only ends the steps on p_bf16 and the float32 rounds decide
+ * the stop on the float32 objective (stats count only the steps run).
  *   p      [N_p][ldp] float32, ldp % 4 == 0, 16-byte aligned (needed for FP32
- *          bulk and for any polish round; may be NULL otherwise)
- *   p_bf16 [N_p][ldb] bfloat16 with zero padding, ldb % 32 == 0 (BF16 bulk)
+ *          steps and for the NNDSVDa and learned starts; may be NULL otherwise)
+ *   p_bf16 [N_p][ldb] bfloat16 with zero padding, ldb % 32 == 0, ldb <= 2048
+ *          (steps on the bfloat16 p)
  * Returns HSN_OK also when max_iter is reached before the tolerance.  stats
- * (host) may be NULL; filling it synchronises the stream.
+ * (host) may be NULL; filling it synchronises the stream.  An evaluated
+ * objective that is NaN or infinite (NaN or Inf in p, overflowing factors)
+ * stops the run at that step; the call then returns HSN_ERR_NUMERIC when
+ * stats are requested or a stop test is on (otherwise the host never reads
+ * the device state, and the caller finds the non-finite values in V or D).
  */
 hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp,
                             const uint16_t *p_bf16, int64_t ldb,
                             int64_t n_p, int64_t n_k, float *V, float *D,
                             const hsn_nmf_opts *opts, hsn_nmf_stats *stats, void *stream);
+
+/*
+ * Form of the ANLS rounds of hsn_subspace_nmf on ctx (a tuning knob; both
+ * forms compute the same exact block minimisation of eq. (4)):
+ *   anls_passes 1 (default, also 0): one fused streaming pass per round;
+ *   anls_passes 2: a pass for N_V = P D, a kernel solving the V rows
+ *     (Lawson-Hanson), a pass for N_D = P^T V (float32 p only; rounds on
+ *     p_bf16 are always fused).
+ * Other values: HSN_ERR_INVALID_ARG.
+ */
+hsn_status hsn_nmf_set_launch(hsn_ctx *ctx, int anls_passes);
 
 /*
  * Many independent decompositions (eq. 4) of uneven size in one go: every
@@ -330,6 +364,10 @@ hsn_status hsn_fbp(hsn_ctx *ctx, const hsn_geom *g, const float *sino, int64_t l
  * stays in C.
  *   p [N_p][ldp] float32 and pooled [N_p][256] (learned start only, in the
  *   network's precision): caller-owned intermediates (device);
+ *   p_bf16 [N_p][ldb] (optional, device): also written by the normalisation
+ *   when given, with -||p - p_bf16||^2 into a context scratch double
+ *   that the NMF's opts.bf16_bias then points to (required when
+ *   opts.polish_bf16_rounds > 0 or opts.precision is HSN_PREC_BF16);
  *   V [N_p][K], D [N_k][K]: in/out as for hsn_subspace_nmf;
  *   x [N_r][N_c][N_c][K] float32 out; stats as for hsn_subspace_nmf.
  * Errors: those of the composed calls (the first failing one returns; the
@@ -337,10 +375,11 @@ hsn_status hsn_fbp(hsn_ctx *ctx, const hsn_geom *g, const float *sino, int64_t l
  * pointers or a learned start without opts.mlp or pooled.
  */
 hsn_status hsn_fhr_step(hsn_ctx *ctx, const hsn_dims *dims, const void *y, int y_dtype, const void *y_open,
-                        int y_open_dtype, float count_floor, float *p, int64_t ldp, void *pooled, float *V,
-                        float *D, const hsn_nmf_opts *opts, hsn_nmf_stats *stats, const double *angles,
-                        int cgls_iters, float *x, int64_t vox_begin, int64_t vox_end, int64_t bin_begin,
-                        int64_t bin_end, float *xh, int64_t ldh, void *stream);
+                        int y_open_dtype, float count_floor, float *p, int64_t ldp, uint16_t *p_bf16,
+                        int64_t ldb, void *pooled, float *V, float *D, const hsn_nmf_opts *opts,
+                        hsn_nmf_stats *stats, const double *angles, int cgls_iters, float *x, int64_t vox_begin,
+                        int64_t vox_end, int64_t bin_begin, int64_t bin_end, float *xh, int64_t ldh,
+                        void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Subspace expansion: eq. (6) x^h = x^s D^T over a voxel x bin range.   */

@@ -102,7 +102,7 @@ hsn_status hsn_profile_read(hsn_ctx *ctx, int kernel, double *total_ms, int64_t 
   return HSN_OK;
 }
 
-int hsn_version(void) { return 100; }
+int hsn_version(void) { return 200; }
 
 hsn_status hsn_create(hsn_ctx **out, int device) {
   if (!out) return HSN_ERR_INVALID_ARG;
@@ -117,8 +117,10 @@ hsn_status hsn_create(hsn_ctx **out, int device) {
   hsn::DeviceGuard g(device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
-  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
-    delete ctx;
+  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+      hipMalloc(&ctx->dscalars, 64 * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    hsn_destroy(ctx);
     return HSN_ERR_DEVICE;
   }
   *out = ctx;
@@ -134,6 +136,7 @@ void hsn_destroy(hsn_ctx *ctx) {
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->geom) (void)hipFree(ctx->geom);
+  if (ctx->dscalars) (void)hipFree(ctx->dscalars);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   for (auto &pool : ctx->prof_ev)

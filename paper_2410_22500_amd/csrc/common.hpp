@@ -36,6 +36,9 @@ struct hsn_ctx {
   // Projector launch shape (hsn_projector_set_launch; 0 = chosen from the
   // geometry, -1 = the gather kernels).
   int proj_views = 0, proj_split = 0, proj_voxels = 0, proj_threads = 0;
+  // ANLS round form of hsn_subspace_nmf (hsn_nmf_set_launch): 1 = one fused
+  // pass (the default), 2 = N_V pass, row solves, N_D pass.
+  int nmf_anls_passes = 1;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // Optional kernel timing: event pairs per kernel kind.
   bool prof = false;
@@ -46,6 +49,8 @@ struct hsn_ctx {
   // Stream used only to capture graphs (capture is not allowed on the null stream).
   hipStream_t cap_stream = nullptr;
   std::string last_plan_note;  // description of the last batched plan used
+  // Small device scalars owned by the context (hsn_fhr_step's bfloat16 bias).
+  double *dscalars = nullptr;
   // Pinned host staging for small device-to-host reads (control block, history).
   void *host_stage = nullptr;
   size_t host_stage_bytes = 0;

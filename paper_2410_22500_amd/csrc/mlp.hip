@@ -32,9 +32,11 @@ namespace hsn {
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
                      int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter);
+                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                     const double *ginv);
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
-                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img);
+                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img,
+                     const double *bias = nullptr);
 
 namespace {
 
@@ -927,7 +929,7 @@ hsn_status mlp_nmf_start(hsn_ctx *ctx, hipStream_t st, const hsn_mlp *m, const f
   ctrl_reset_kernel<<<1, 1, 0, st>>>(w.ctrl);
   prof_begin(ctx, HSN_KERN_NMF_PASS, st);
   launch_pass_f32(K, kModeND, false, n_k > 1024 ? 2 : 1, n_wg, st, p, ldp, n_p, n_k, V, nullptr, D, w.gd, w.chol,
-                  w.part_nd, w.part_gv, w.part_obj, w.ctrl, 0);
+                  w.part_nd, w.part_gv, w.part_obj, w.ctrl, 0, nullptr);
   prof_end(ctx, HSN_KERN_NMF_PASS, st);
   launch_update_d(K, kModeNV, st, D, w, n_wg, n_k, 0, false, 0.0, 0.0, false, 0);
   fill_zeros_kernel<<<1, 256, 0, st>>>(D, int64_t(n_k) * K, 1e-6f);

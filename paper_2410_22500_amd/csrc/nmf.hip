@@ -6,13 +6,17 @@
 //     fused pass [N_V = P D, row rule for V, N_D += P^T V_new, G_V, optional
 //     ||P - V_new D^T||^2]  ->  update_d [reductions, D row rule, G_D of D_new]
 //   ANLS round (exact row-wise non-negative least squares, V then D):
-//     pass N_V -> row solves of V (all rows in parallel, FP64 Cholesky factors
-//     of G_D's principal submatrices) -> pass N_D (+objective) -> update_d
-//     (row solves of D)
+//     fused pass [N_V = P D, exact NNLS of every V row by support enumeration
+//     with the FP64 inverses of G_D's principal submatrices, N_D += P^T V_new,
+//     objective] -> update_d (row solves of D); or, in the two-pass form,
+//     pass N_V -> row solves of V -> pass N_D -> update_d
 // The stop test runs on the device (update_d lowers stop_at), so the host
 // queues iterations in chunks and reads the control block once per chunk.
-// The float32 pass reads p once per MU/HALS iteration; the bfloat16 bulk runs
-// the same sequence with the MFMA pass over the bfloat16 copy of p.
+// The float32 pass reads p once per iteration or fused ANLS round; the
+// bfloat16 steps run the same sequence with the MFMA pass over the bfloat16
+// copy of p.  Polish rounds on the bfloat16 p end when the objective, plus
+// the bias -||p - p_bf16||^2 when given, meets the tolerance; the float32
+// rounds that follow decide the stop on the float32 objective.
 #include "nmf_common.hpp"
 
 #include <algorithm>
@@ -24,17 +28,20 @@ namespace hsn {
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
                      int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter);
+                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                     const double *ginv);
 bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
                       int64_t n_p, int n_k, float *V, const double *GD, const double *chol, const uint16_t *img,
-                      float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter);
+                      float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                      const double *ginv);
 int pass_bf16_wgs(hsn_ctx *ctx, int64_t n_p);
 size_t bf16_image_elems(int64_t ldb);
 int64_t bf16_image_ldb(int64_t ldb);
 void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWork &w, int want_chol, int64_t ldb);
 int update_d_blocks(int n_k);
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
-                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img);
+                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, const double *bias);
+void launch_nmf_resume(hipStream_t st, NmfCtrl *ctrl);
 void launch_nnls_rows(int K, hipStream_t st, const NmfWork &w, float *V, int64_t n_p, int n_blocks, int iter);
 size_t nndsvd_ws_bytes(int64_t n_p, int n_k, int K, int n_split);
 size_t mlp_pool_bytes(const hsn_mlp *m, int64_t n_p);
@@ -47,6 +54,8 @@ hsn_status nndsvd_init(hsn_ctx *ctx, hipStream_t st, const float *p, int64_t ldp
                        int64_t n_p, int n_k, int K, float *V, float *D, void *ws, int n_split);
 
 namespace {
+
+constexpr int kBf16PolishCheck = 4;
 
 // One step of the schedule, in issue order.
 struct Step {
@@ -64,49 +73,57 @@ struct Run {
   NmfWork w;
   int wg_f32 = 0, wg_bf16 = 0;  // persistent grid sizes of the two passes
   double f_ref = 0.0, tol = 0.0;
+  const double *bias = nullptr;  // device -||p - p_bf16||^2 for the bfloat16 stop test, or null
+  bool fused_anls = true;        // ANLS rounds as one fused pass (else N_V pass, row solves, N_D pass)
 };
 
 // Queue iteration `iter`.  MU / HALS: one streaming pass over p (row rule for
-// V, N_D and G_V partials, optional objective) and the D update.  ANLS: a pass
-// for N_V = P D, the exact row solves of V on all rows in parallel, a pass
-// for N_D = P^T V_new (+ objective), and the exact row solves of D.
+// V, N_D and G_V partials, optional objective) and the D update.  ANLS: the
+// fused pass (exact NNLS of the V rows inside the pass) or a pass for
+// N_V = P D, the exact row solves of V on all rows in parallel and a pass for
+// N_D = P^T V_new (+ objective); then the exact row solves of D.
 // next_exact: the following step solves V rows exactly (the update then also
 // factors G_D).
 hsn_status queue_step(Run &R, const Step &s, int iter, bool next_exact, const float *p, int64_t ldp,
                       const uint16_t *pb, int64_t ldb, float *V, float *D) {
   const int nq = R.n_k > 1024 ? 2 : 1;
   const int n_wg = s.bf16 ? R.wg_bf16 : R.wg_f32;
-  const bool obj = s.obj || s.rule == kModeANLS;
-  if (s.rule == kModeANLS) {
+  const bool obj = s.obj;
+  if (s.rule == kModeANLS && !s.bf16 && R.fused_anls) {
+    prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
+    launch_pass_f32(R.K, kModeANLS, true, nq, n_wg, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd, R.w.chol,
+                    R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter, R.w.ginv);
+    prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
+  } else if (s.rule == kModeANLS && !s.bf16) {
     prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
     // The N_V pass writes no per-workgroup partials, so it takes up to 8
     // workgroups per CU for latency hiding (same rows per workgroup rule,
     // same results): 98 -> 86 us at mid.
     const int wg_nv = int(std::min<int64_t>((R.n_p + 7) / 8, 8 * int64_t(R.ctx->num_cu)));
     launch_pass_f32(R.K, kModeNV, false, nq, wg_nv, R.st, p, ldp, R.n_p, R.n_k, V, R.w.nv, D, R.w.gd, R.w.chol,
-                    R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter);
+                    R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter, nullptr);
     prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
     const int nb = int(std::min<int64_t>((R.n_p + 255) / 256, 8 * int64_t(R.ctx->num_cu)));
     launch_nnls_rows(R.K, R.st, R.w, V, R.n_p, nb, iter);
     prof_begin(R.ctx, HSN_KERN_NMF_PASS, R.st);
     launch_pass_f32(R.K, kModeND, true, nq, n_wg, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd, R.w.chol,
-                    R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter);
+                    R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter, nullptr);
     prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
   } else {
     prof_begin(R.ctx, s.bf16 ? HSN_KERN_NMF_PASS_BF16 : HSN_KERN_NMF_PASS, R.st);
     if (s.bf16) {
       const bool ok = launch_pass_bf16(R.K, s.rule, obj, n_wg, R.st, pb, ldb, R.n_p, R.n_k, V, R.w.gd, R.w.chol,
-                                       R.w.img, R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter);
+                                       R.w.img, R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter, R.w.ginv);
       prof_end(R.ctx, HSN_KERN_NMF_PASS_BF16, R.st);
       if (!ok) return fail(R.ctx, HSN_ERR_UNSUPPORTED, "bf16 pass: unsupported shape (ldb <= 2048, k <= 8)");
     } else {
       launch_pass_f32(R.K, s.rule, obj, nq, n_wg, R.st, p, ldp, R.n_p, R.n_k, V, nullptr, D, R.w.gd, R.w.chol,
-                      R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter);
+                      R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter, nullptr);
       prof_end(R.ctx, HSN_KERN_NMF_PASS, R.st);
     }
   }
   launch_update_d(R.K, s.rule == kModeANLS ? kModeNV : s.rule, R.st, D, R.w, n_wg, R.n_k, iter, obj, R.f_ref,
-                  R.tol, next_exact, R.w.img ? bf16_image_ldb(ldb) : 0);
+                  R.tol, next_exact, R.w.img ? bf16_image_ldb(ldb) : 0, s.bf16 ? R.bias : nullptr);
   HSN_LAUNCHED(R.ctx);
   return HSN_OK;
 }
@@ -140,10 +157,8 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   if (!V || !D) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: V and D are required");
   const bool bf16 = o->precision == HSN_PREC_BF16;
   if (o->polish_bf16_rounds < 0) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: polish_bf16_rounds must be >= 0");
-  if (bf16 && o->algo == HSN_ALGO_ANLS && o->max_iter > 0)
-    return fail(ctx, HSN_ERR_UNSUPPORTED, "nmf: ANLS rounds run on the float32 p (bulk precision FP32)");
-  // bfloat16 polish rounds exist for HALS only (ANLS rounds read the float32 p).
-  const int pol_bf16 = (o->polish_algo == HSN_ALGO_HALS) ? std::min(o->polish_bf16_rounds, o->polish_rounds) : 0;
+  // The first polish_bf16_rounds polish rounds (ANLS or HALS) read the bfloat16 p.
+  const int pol_bf16 = std::min(o->polish_bf16_rounds, o->polish_rounds);
   const bool need_f32 = (!bf16 && o->max_iter > 0) || o->polish_rounds > pol_bf16 || o->init != HSN_INIT_USER;
   if (need_f32) {
     if (!p) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: float32 p is required");
@@ -168,9 +183,11 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   const int wg_bf16 = any_bf16 ? pass_bf16_wgs(ctx, n_p) : 0;
   const int n_wg = std::max(wg_f32, wg_bf16);
   const int hist_cap = o->max_iter + o->polish_rounds + 2;
-  const bool need_nv = o->algo == HSN_ALGO_ANLS || (o->polish_rounds > 0 && o->polish_algo == HSN_ALGO_ANLS);
+  const bool two_pass = ctx->nmf_anls_passes == 2;
+  const bool need_nv = two_pass && (o->algo == HSN_ALGO_ANLS || (o->polish_rounds > 0 && o->polish_algo == HSN_ALGO_ANLS));
   const int n_upd = update_d_blocks(int(n_k));
   const size_t need = Carver::need({sizeof(NmfCtrl), sizeof(double) * 64, sizeof(double) * 256 * kCholStride,
+                                    sizeof(double) * kCholStride * kInvStride,
                                     sizeof(float) * size_t(n_wg) * n_k * K, sizeof(double) * size_t(n_wg) * K * K,
                                     sizeof(double) * n_wg, sizeof(double) * size_t(n_upd) * K * K,
                                     need_nv ? sizeof(float) * n_p * K : 0, sizeof(double) * hist_cap,
@@ -194,6 +211,7 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   R.w.ctrl = cv.take<NmfCtrl>(1);
   R.w.gd = cv.take<double>(64);
   R.w.chol = cv.take<double>(256 * kCholStride);
+  R.w.ginv = cv.take<double>(size_t(kCholStride) * kInvStride);
   R.w.part_nd = cv.take<float>(size_t(n_wg) * n_k * K);
   R.w.part_gv = cv.take<double>(size_t(n_wg) * K * K);
   R.w.part_obj = cv.take<double>(n_wg);
@@ -208,19 +226,35 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   const bool stop_test = o->f_ref > 0.0;
   R.f_ref = stop_test ? o->f_ref : 0.0;
   R.tol = o->rel_obj_tol;
+  R.bias = o->bf16_bias;
+  R.fused_anls = !two_pass;
 
   // The schedule: bulk iterations, then polish rounds (global indices 0..n-1).
   std::vector<Step> steps;
   steps.reserve(size_t(o->max_iter) + o->polish_rounds);
   for (int it = 0; it < o->max_iter; ++it) {
-    const bool obj = ((it + 1) % o->check_every == 0) || (it + 1 == o->max_iter);
     const int rule = o->algo == HSN_ALGO_MU ? kModeMU : (o->algo == HSN_ALGO_HALS ? kModeHALS : kModeANLS);
-    steps.push_back({rule, bf16 && rule != kModeANLS, obj});
+    // float32 ANLS steps always evaluate the objective (the pass has it for free)
+    const bool obj = ((it + 1) % o->check_every == 0) || (it + 1 == o->max_iter) || (rule == kModeANLS && !bf16);
+    steps.push_back({rule, bf16, obj});
   }
   for (int r = 0; r < o->polish_rounds; ++r) {
     const int rule = o->polish_algo == HSN_ALGO_ANLS ? kModeANLS : kModeHALS;
-    steps.push_back({rule, r < pol_bf16 && rule != kModeANLS, true});
+    // Polish rounds on p_bf16 evaluate the objective every kBf16PolishCheck-th
+    // round and on the last one (the objective costs the bfloat16 pass a third
+    // of its time; those rounds only approach the tolerance, the float32 rounds
+    // decide the stop); float32 polish rounds evaluate it every round.
+    const bool on_bf16 = r < pol_bf16;
+    const bool obj = !on_bf16 || (r + 1) % kBf16PolishCheck == 0 || r + 1 == pol_bf16;
+    steps.push_back({rule, on_bf16, obj});
   }
+  // The steps on p_bf16 form one run [bf16_lo, first_f32): the bulk when its
+  // precision is BF16, then the first pol_bf16 polish rounds.  A stop fired
+  // inside that run only ends it when float32 polish rounds follow; they
+  // then decide the stop on the float32 objective.
+  const int bf16_lo = (bf16 && o->max_iter > 0) ? 0 : o->max_iter;
+  const int bf16_hi = o->max_iter + pol_bf16;
+  const int first_f32_polish = (bf16_hi > bf16_lo && o->polish_rounds > pol_bf16) ? bf16_hi : -1;
 
   if (stats) HSN_HIP(ctx, hipEventRecord(ctx->ev0, st));
   if (o->init == HSN_INIT_NNDSVDA &&
@@ -252,10 +286,11 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     hh = reinterpret_cast<double *>(static_cast<char *>(ctx->host_stage) + sizeof(NmfCtrl));
   }
   bool staged = false;
+  int bf16_phase_end = -1;  // step index where a stop ended the bfloat16 polish rounds
   while (issued < int(steps.size())) {
     int end = issued, n_obj = 0;
     while (end < int(steps.size()) && n_obj < chunk_obj) {
-      if (steps[end].obj || steps[end].rule == kModeANLS) ++n_obj;
+      if (steps[end].obj) ++n_obj;
       ++end;
     }
     chunk_obj = std::min(2 * chunk_obj, 32);
@@ -265,7 +300,8 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     }
     issued = end;
     staged = false;
-    if (stop_test && issued < int(steps.size())) {
+    const bool phase_pending = first_f32_polish >= 0 && bf16_phase_end < 0;
+    if (stop_test && (issued < int(steps.size()) || phase_pending)) {
       if (stats) {
         HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
         HSN_HIP(ctx, hipMemcpyAsync(hcp, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
@@ -277,7 +313,20 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
         HSN_HIP(ctx, hipMemcpyAsync(&hc, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
         HSN_HIP(ctx, hipStreamSynchronize(st));
       }
-      if (hc.stop_at <= issued) break;
+      if (hc.stop_at <= issued) {
+        if (!hc.numeric && phase_pending && hc.stop_at > bf16_lo && hc.stop_at <= first_f32_polish) {
+          // the bfloat16 rounds met the (bias-corrected) tolerance: the float32
+          // rounds take over, re-queued from the first one
+          bf16_phase_end = hc.stop_at;
+          launch_nmf_resume(st, R.w.ctrl);
+          HSN_LAUNCHED(ctx);
+          issued = first_f32_polish;
+          chunk_obj = 1;
+          hc.stop_at = INT32_MAX;
+          continue;
+        }
+        break;
+      }
     }
   }
   if (stats) {
@@ -295,7 +344,14 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     const int done = std::min(hc.stop_at, issued);
     stats->ms = ms;
     stats->iters = std::min(done, o->max_iter);
-    stats->polish_done = std::max(0, done - o->max_iter);
+    if (bf16_phase_end >= 0) {
+      stats->iters = std::min(bf16_phase_end, o->max_iter);
+      stats->polish_bf16_done = std::max(0, bf16_phase_end - o->max_iter);
+      stats->polish_done = stats->polish_bf16_done + std::max(0, done - first_f32_polish);
+    } else {
+      stats->polish_done = std::max(0, done - o->max_iter);
+      stats->polish_bf16_done = std::min(stats->polish_done, pol_bf16);
+    }
     stats->history_len = 0;
     double last = NAN;
     const int len = std::min(hc.hist_len, hist_cap);
@@ -307,7 +363,17 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     }
     stats->objective = last;
     stats->rel_obj = stop_test ? (last - o->f_ref) / o->f_ref : NAN;
-    if (len > 0 && std::isnan(last)) return fail(ctx, HSN_ERR_NUMERIC, "nmf: objective is NaN");
   }
+  if ((stats || stop_test) && (hc.numeric || (stats && hc.hist_len > 0 && !std::isfinite(stats->objective))))
+    return fail(ctx, HSN_ERR_NUMERIC, "nmf: the objective became %s at step %d (NaN or Inf in p or the factors)",
+                std::isnan(stats ? stats->objective : NAN) ? "NaN" : "non-finite", hc.stop_at - 1);
+  return HSN_OK;
+}
+
+extern "C" hsn_status hsn_nmf_set_launch(hsn_ctx *ctx, int anls_passes) {
+  if (!ctx) return HSN_ERR_INVALID_ARG;
+  if (anls_passes < 0 || anls_passes > 2)
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "nmf launch: anls_passes must be 0, 1 or 2 (got %d)", anls_passes);
+  ctx->nmf_anls_passes = anls_passes == 2 ? 2 : 1;
   return HSN_OK;
 }

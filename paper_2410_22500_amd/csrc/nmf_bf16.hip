@@ -10,7 +10,8 @@
 //      into bfloat16 hi/lo halves packed as 16 columns [D_hi | D_lo], so one
 //      instruction gives both products and N_V = C[:, j] + C[:, 8 + j];
 //   3. the per-wave N_V partials are summed in LDS (fixed order) and the row
-//      rule (Lee-Seung MU or HALS) updates V in float64 registers;
+//      rule updates V in float64 registers: Lee-Seung MU, HALS, or (ANLS) the
+//      exact NNLS of each row, 32 lanes per row enumerating the supports;
 //   4. N_D += P^T V_new on MFMA 16x16x16: A = P^T (16 bins x 16 rows, read
 //      transposed from the LDS tile), B = [V_hi | V_lo]; the accumulators
 //      stay in registers for the whole pass;
@@ -44,10 +45,14 @@ __host__ __device__ inline int64_t bf16_ldb_pad(int64_t ldb) {
 __host__ __device__ inline int bf16_pitch(int64_t ldb) { return int(2 * bf16_ldb_pad(ldb) + 8); }
 
 struct Bf16Lds {
-  int tile, db1, red, vsp, vnw, vold, gd, obj, total;
+  int tile, db1, red, vsp, vnw, vold, gd, obj, hsum, ginv, total;
 };
 
-__host__ __device__ inline Bf16Lds bf16_lds_layout(int64_t ldb, int K) {
+// The inverses of G_D's principal submatrices (fused ANLS) are staged in LDS
+// for K <= 6 (tri(K) x 2^K doubles, at most 10.5 KB) and read from the caches above.
+__host__ __device__ constexpr bool bf16_inv_in_lds(int K) { return K <= 6; }
+
+__host__ __device__ inline Bf16Lds bf16_lds_layout(int64_t ldb, int K, bool anls = false) {
   Bf16Lds L;
   int o = 0;
   L.tile = o;
@@ -67,8 +72,12 @@ __host__ __device__ inline Bf16Lds bf16_lds_layout(int64_t ldb, int K) {
   o += 64 * 8;
   L.obj = o;
   o += kBWaves * 8;
+  L.hsum = o;
+  o += anls ? kBRows * 8 * 4 : 0;
+  o = (o + 15) & ~15;
+  L.ginv = o;
+  o += (anls && bf16_inv_in_lds(K)) ? (1 << K) * tri(K) * 8 : 0;
   L.total = o;
-  (void)K;
   return L;
 }
 
@@ -82,10 +91,11 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
                                                               float *__restrict__ part_nd,
                                                               double *__restrict__ part_gv,
                                                               double *__restrict__ part_obj,
-                                                              NmfCtrl *__restrict__ ctrl, int iter) {
+                                                              NmfCtrl *__restrict__ ctrl, int iter,
+                                                              const double *__restrict__ ginv) {
   if (iter >= ctrl->stop_at) return;
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const Bf16Lds L = bf16_lds_layout(ldb, K);
+  const Bf16Lds L = bf16_lds_layout(ldb, K, MODE == kModeANLS);
   char *tileL = smem + L.tile;
   uint4 *db1L = reinterpret_cast<uint4 *>(smem + L.db1);
   float *red = reinterpret_cast<float *>(smem + L.red);        // [8][16][16]
@@ -106,6 +116,14 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
   for (int i = t; i < nks * 64; i += kBThreads) db1L[i] = db1g[i];
   for (int i = t; i < 16 * 16; i += kBThreads) vsp[i] = 0;
   if (t < K * K) gd_s[t] = GD[t];
+  float *hsum = reinterpret_cast<float *>(smem + L.hsum);  // [16][8]
+  const double *ginv_s = ginv;
+  if constexpr (MODE == kModeANLS && bf16_inv_in_lds(K)) {
+    // entry-major, stride 2^K
+    double *g = reinterpret_cast<double *>(smem + L.ginv);
+    for (int i = t; i < (1 << K) * tri(K); i += kBThreads) g[i] = ginv[(i >> K) * kInvStride + (i & ((1 << K) - 1))];
+    ginv_s = g;
+  }
 
   f32x4 acc2[2 * kKSW];
 #pragma unroll
@@ -119,9 +137,12 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
   // without a branch, so the loads stay unconditional and in flight.
   auto load_tile = [&](uint4 (&pr)[kKSW], float &vv, int64_t row0) {
     const int64_t rows = (n_p - row0) < kBRows ? (n_p - row0) : kBRows;
-    const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float *>(V) + row0 * K, 0, int(rows * K * 4), 0x00020000);
-    vv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, t < kBRows * K ? 4 * t : 0x7FFFFFF0, 0, 0));
+    if constexpr (MODE != kModeANLS) {  // an exact row solve does not read the old V
+      const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(V) + row0 * K, 0, int(rows * K * 4), 0x00020000);
+      vv = __builtin_bit_cast(float,
+                              __builtin_amdgcn_raw_buffer_load_b32(rv, t < kBRows * K ? 4 * t : 0x7FFFFFF0, 0, 0));
+    }
     const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint16_t *>(Pb) + row0 * ldb, 0, int(rows * ldb * 2), 0x00020000);
 #pragma unroll
@@ -179,7 +200,31 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
     __syncthreads();
 
     // 3. row rule
-    if (MODE == kModeHALS || MODE == kModeANLS) {
+    if (MODE == kModeANLS) {
+      // exact NNLS of the 16 rows: h into LDS, then 32 lanes per row
+      if (t < kBRows * K) {
+        const int r = t / K, j = t - (t / K) * K;
+        float s = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + r) * 16 + j] + red[(ww * 16 + r) * 16 + 8 + j];
+        hsum[r * 8 + j] = s;
+      }
+      __syncthreads();
+      const int r = t >> 5, l = t & 31;
+      const int64_t row = row0 + r;
+      float h[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) h[j] = hsum[r * 8 + j];
+      const double xl = nnls_enum_group<K, bf16_inv_in_lds(K) ? (1 << K) : kInvStride>(ginv_s, h, l);
+      if (l < K) {
+        float vn = float(xl);
+        if (row >= n_p) vn = 0.0f;
+        if (row < n_p) V[row * K + l] = vn;
+        vnw[r * 8 + l] = vn;
+        vsp[r * 16 + l] = bf_hi(vn);
+        vsp[r * 16 + 8 + l] = bf_lo(vn);
+      }
+    } else if (MODE == kModeHALS) {
       if (t < kBRows) {
         const int r = t;
         const int64_t row = row0 + r;
@@ -192,10 +237,7 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
           h[j] = s;
           x[j] = (row < n_p) ? double(vold[r * K + j]) : 0.0;
         }
-        if (MODE == kModeHALS)
-          hals_row<K>(gd_s, h, x);
-        else
-          nnls_gram_row<K>(gd_s, chol, h, x);
+        hals_row<K>(gd_s, h, x);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const float vn = (row < n_p) ? float(x[j]) : 0.0f;
@@ -318,8 +360,9 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
 template <int K, int MODE, bool OBJ, int NW, int NBUF>
 static bool launch_bf16_inst(int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p, int n_k,
                              float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
-                             float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
-  const int lds = bf16_lds_layout(ldb, K).total;
+                             float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                             const double *ginv) {
+  const int lds = bf16_lds_layout(ldb, K, MODE == kModeANLS).total;
   static bool attr_set = false;
   if (!attr_set) {
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(&pass_bf16_kernel<K, MODE, OBJ, NW, NBUF>),
@@ -328,17 +371,19 @@ static bool launch_bf16_inst(int n_wg, hipStream_t st, const uint16_t *Pb, int64
     attr_set = true;
   }
   pass_bf16_kernel<K, MODE, OBJ, NW, NBUF><<<n_wg, kBThreads, lds, st>>>(Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd,
-                                                                part_gv, part_obj, ctrl, iter);
+                                                                part_gv, part_obj, ctrl, iter, ginv);
   return true;
 }
 
 template <int K, int NW, int NBUF>
 static bool launch_bf16_kw(int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p,
                            int n_k, float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
-                           float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
+                           float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                           const double *ginv) {
 #define HSN_INST(M_, O_) \
   launch_bf16_inst<K, M_, O_, NW, NBUF>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd, part_gv, part_obj, \
-                                        ctrl, iter)
+                                        ctrl, iter, ginv)
+  if (mode == kModeANLS) return obj ? HSN_INST(kModeANLS, true) : HSN_INST(kModeANLS, false);
   if (mode == kModeMU) return obj ? HSN_INST(kModeMU, true) : HSN_INST(kModeMU, false);
   if (mode == kModeHALS) return obj ? HSN_INST(kModeHALS, true) : HSN_INST(kModeHALS, false);
   return false;
@@ -348,12 +393,13 @@ static bool launch_bf16_kw(int mode, bool obj, int n_wg, hipStream_t st, const u
 template <int K>
 static bool launch_bf16_k(int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p,
                           int n_k, float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
-                          float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
+                          float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                          const double *ginv) {
   const int64_t nw = bf16_ldb_pad(ldb) / 256;
 #define HSN_NW(NW_, NB_)                                                                                           \
   if (nw == NW_)                                                                                                   \
     return launch_bf16_kw<K, NW_, NB_>(mode, obj, n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd,     \
-                                       part_gv, part_obj, ctrl, iter);
+                                       part_gv, part_obj, ctrl, iter, ginv);
   HSN_NW(1, 2) HSN_NW(2, 2) HSN_NW(4, 2) HSN_NW(8, 1)
 #undef HSN_NW
   return false;
@@ -369,9 +415,10 @@ size_t bf16_image_elems(int64_t ldb) {
 
 bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
                       int64_t n_p, int n_k, float *V, const double *GD, const double *chol, const uint16_t *img,
-                      float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
+                      float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                      const double *ginv) {
   if (ldb > kMaxLdb || ldb % 32 != 0 || K < 1 || K > 8 ||
-      (mode != kModeMU && mode != kModeHALS))
+      (mode != kModeMU && mode != kModeHALS && mode != kModeANLS) || (mode == kModeANLS && !ginv))
     return false;
   const uint4 *db1 = reinterpret_cast<const uint4 *>(img);
   const uint4 *db3 = db1 + (bf16_ldb_pad(ldb) / 32) * 64;
@@ -379,7 +426,7 @@ bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const
 #define HSN_K(KK)                                                                                                  \
   case KK:                                                                                                         \
     return launch_bf16_k<KK>(mode, obj, n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd, part_gv,     \
-                             part_obj, ctrl, iter);
+                             part_obj, ctrl, iter, ginv);
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
   }

@@ -12,7 +12,9 @@ enum PassMode {
   kModeNV = 1,  // N_V = P D only (written out; the rows are solved separately)
   kModeND = 2,  // N_D += P^T V_new only (V_new given)
   kModeHALS = 3,  // fused: N_V = P D, HALS column sweep of V, then N_D += P^T V_new
-  kModeANLS = 4,  // ANLS round: N_V pass, exact row solves of V, N_D pass (driver step kind)
+  kModeANLS = 4,  // ANLS round.  As a pass mode: fused, N_V = P D, exact NNLS of every V row
+                  // (nnls_enum_group), then N_D += P^T V_new.  As a driver step: that pass or
+                  // the two-pass form (N_V pass, row solves, N_D pass), then the D row solves
 };
 
 // One HALS sweep of a row x given its right-hand side h and Gram G: for each
@@ -42,7 +44,8 @@ struct NmfCtrl {
   int upd_ticket;   // arrival counter of the D-update blocks (last block finishes G_D)
   int hist_len;     // objective values written so far
   int iter_base;    // batched runs: index of the first step of the replayed chunk
-  int pad[4];
+  int numeric;      // set (with a stop) when an evaluated objective is NaN or infinite
+  int pad[3];
   double gvo[65];   // G_V = V^T V (K*K) and the objective of the last pass, reduced
 };
 
@@ -56,6 +59,7 @@ struct NmfWork {
   double *part_obj;  // [n_wg]
   double *part_gd;   // [update blocks][K*K]
   float *nv;         // [n_p][K] N_V for the row-wise NNLS
+  double *ginv;      // [36][kInvStride] inverses of the principal submatrices of G_D (entry-major)
   double *hist;      // [hist_cap] objective history (device)
   uint16_t *img;     // bfloat16 operand images of D for the MFMA pass (or null)
   int n_wg;
@@ -212,6 +216,73 @@ __device__ inline void nnls_gram_row(const double *__restrict__ G, const double 
       w[i] = v;
     }
   }
+}
+
+// Entry (i, j) of a packed symmetric K x K matrix (lower triangle, row order).
+__host__ __device__ constexpr int sym(int i, int j) { return i >= j ? tri(i) + j : tri(j) + i; }
+
+// Inverses of the principal submatrices of a K x K Gram, entry-major: entry
+// e (the packed symmetric index sym(i, j) of a K x K matrix) of mask m at
+// [e * stride + m].  Per mask, G[S,S]^-1 is embedded in a K x K matrix with
+// zeros outside S; a NaN entry 0 marks a singular G[S,S].  The NMF workspace
+// holds them with stride kInvStride; the passes stage the tri(K) entries of
+// the 2^K masks in LDS with stride 2^K (consecutive masks in consecutive
+// words: the lanes of a group read them without bank conflicts).
+constexpr int kInvStride = 256;
+
+// Exact non-negative least squares of one row, min_{x >= 0} 1/2 x'Gx - h'x,
+// by enumeration of the supports S (bit masks), spread over a group of 32
+// lanes (lane l of the group takes masks l, l + 32, ...).  For every S whose
+// principal submatrix is positive definite, z_S = G[S,S]^-1 h_S.  Each z
+// with all entries on S positive is a feasible point, of cost
+// q = -1/2 h_S' z_S; the NNLS minimiser is such a point (its support's
+// face-restricted stationary point), so the feasible z of least cost is the
+// minimiser (unique when G is positive definite).  Ties in q go to the lower
+// mask, x = 0 (empty support, q = 0) is always a candidate.  Lane l < K of
+// the group then forms x_l = z_l of the winning support itself and returns
+// it (the other lanes return 0), so no lane keeps a z.  The 32 lanes must be
+// converged.  ginv: entry-major inverses with stride STRIDE (see above).
+template <int K, int STRIDE>
+__device__ __forceinline__ double nnls_enum_group(const double *__restrict__ ginv, const float (&h)[K], int l) {
+  double best_q = 0.0;
+  int best_m = 0;
+  for (int m = l; m < (1 << K); m += 32) {
+    if (m == 0 || isnan(ginv[m])) continue;
+    bool feasible = true;
+    double q = 0.0;
+    // one row of z at a time (rolled): few registers live beside the pass's own
+#pragma unroll 1
+    for (int i = 0; i < K; ++i) {
+      double s = 0.0, hi = 0.0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        s = fma(ginv[sym(i, j) * STRIDE + m], double(h[j]), s);
+        hi = (j == i) ? double(h[j]) : hi;
+      }
+      // z_i = s; outside S the embedded inverse gives s = 0 and no cost
+      feasible = feasible && (!((m >> i) & 1) || s > 0.0);
+      q = fma(-0.5 * hi, s, q);
+    }
+    if (feasible && (q < best_q || (q == best_q && m < best_m))) {
+      best_q = q;
+      best_m = m;
+    }
+  }
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) {
+    const double oq = __shfl_xor(best_q, off, 64);
+    const int om = __shfl_xor(best_m, off, 64);
+    if (oq < best_q || (oq == best_q && om < best_m)) {
+      best_q = oq;
+      best_m = om;
+    }
+  }
+  double x = 0.0;
+  if (l < K && best_m != 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) x = fma(ginv[sym(l, j) * STRIDE + best_m], double(h[j]), x);
+  }
+  return x;
 }
 
 // Sum of f(w) for w = g, g + G, g + 2G, ... < n in a fixed order, with eight

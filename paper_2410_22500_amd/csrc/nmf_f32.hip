@@ -15,15 +15,21 @@ constexpr int kPassThreads = 256;
 constexpr int kRows = 8;
 
 // LDS of one pass workgroup: red [4][kRows*K] f32 | vnew, vold [kRows][K] f32 |
-// gd_s [K*K] f64 | obj_s [4] f64.
+// gd_s [K*K] f64 | obj_s [4] f64 | (fused ANLS) hrow [kRows][K] f32 and, for
+// K <= 6, the inverses of G_D's principal submatrices [2^K][36] f64.
 template <int K>
+constexpr bool kInvInLds = K <= 6;
+
+template <int K, int MODE>
 struct PassLds {
   static constexpr int red = 0;
   static constexpr int vnew = red + (kPassThreads / 64) * kRows * K * 4;
   static constexpr int vold = vnew + kRows * K * 4;
   static constexpr int gd = (vold + kRows * K * 4 + 7) / 8 * 8;
   static constexpr int obj = gd + K * K * 8;
-  static constexpr int bytes = obj + (kPassThreads / 64) * 8;
+  static constexpr int hrow = obj + (kPassThreads / 64) * 8;
+  static constexpr int ginv = (hrow + (MODE == kModeANLS ? kRows * K * 4 : 0) + 15) / 16 * 16;
+  static constexpr int bytes = ginv + ((MODE == kModeANLS && kInvInLds<K>) ? (1 << K) * tri(K) * 8 : 0);
 };
 
 // One workgroup `wg` of `n_wg` of the pass (the kernels below supply the
@@ -33,11 +39,12 @@ __device__ __forceinline__ void pass_f32_body(
     const float *__restrict__ P, int64_t ldp, int64_t n_p, int n_k, float *__restrict__ V, float *__restrict__ NV,
     const float *__restrict__ D, const double *__restrict__ GD, const double *__restrict__ chol,
     float *__restrict__ part_nd, double *__restrict__ part_gv, double *__restrict__ part_obj,
-    NmfCtrl *__restrict__ ctrl, int iter, int wg, int n_wg, char *__restrict__ lds) {
+    NmfCtrl *__restrict__ ctrl, int iter, int wg, int n_wg, char *__restrict__ lds,
+    const double *__restrict__ ginv = nullptr) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  using L = PassLds<K>;
+  using L = PassLds<K, MODE>;
   float(*red)[kRows * K] = reinterpret_cast<float(*)[kRows * K]>(lds + L::red);
   float(*vnew)[K] = reinterpret_cast<float(*)[K]>(lds + L::vnew);
   float(*vold)[K] = reinterpret_cast<float(*)[K]>(lds + L::vold);
@@ -63,6 +70,14 @@ __device__ __forceinline__ void pass_f32_body(
   double gv = 0.0;
   double obj = 0.0;
   if ((MODE == kModeMU || MODE == kModeHALS || MODE == kModeANLS) && t < K * K) gd_s[t] = GD[t];
+  float *hrow = reinterpret_cast<float *>(lds + L::hrow);
+  const double *ginv_s = ginv;
+  if constexpr (MODE == kModeANLS && kInvInLds<K>) {
+    // entry-major, stride 2^K
+    double *g = reinterpret_cast<double *>(lds + L::ginv);
+    for (int i = t; i < (1 << K) * tri(K); i += kPassThreads) g[i] = ginv[(i >> K) * kInvStride + (i & ((1 << K) - 1))];
+    ginv_s = g;
+  }
   __syncthreads();
 
   const int64_t n_tiles = (n_p + kRows - 1) / kRows;
@@ -71,7 +86,7 @@ __device__ __forceinline__ void pass_f32_body(
     // The tile's V values (one per thread t < kRows*K) are loaded with the
     // tile, so the row rule does not wait on a global load.
     float vcur = 0.0f;
-    if (MODE != kModeNV && t < kRows * K && row0 * K + t < n_p * K) vcur = V[row0 * K + t];
+    if (MODE != kModeNV && MODE != kModeANLS && t < kRows * K && row0 * K + t < n_p * K) vcur = V[row0 * K + t];
     float p[kRows][NQ][4];
 #pragma unroll
     for (int r = 0; r < kRows; ++r)
@@ -102,7 +117,28 @@ __device__ __forceinline__ void pass_f32_body(
           if (lane == 63) red[wave][r * K + j] = s;
         }
       __syncthreads();
-      if (MODE == kModeHALS || MODE == kModeANLS) {
+      if (MODE == kModeANLS) {
+        // Exact NNLS of the tile's rows: 32 lanes per row enumerate the supports.
+        if (t < kRows * K) {
+          float s = 0.0f;
+#pragma unroll
+          for (int w = 0; w < kPassThreads / 64; ++w) s += red[w][t];
+          hrow[t] = s;
+        }
+        __syncthreads();
+        const int r = t >> 5, l = t & 31;
+        const int64_t row = row0 + r;
+        float h[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) h[j] = hrow[r * K + j];
+        const double xl = nnls_enum_group<K, kInvInLds<K> ? (1 << K) : kInvStride>(ginv_s, h, l);
+        if (l < K) {
+          float vn = float(xl);
+          if (row >= n_p) vn = 0.0f;
+          if (row < n_p) V[row * K + l] = vn;
+          vnew[r][l] = vn;
+        }
+      } else if (MODE == kModeHALS) {
         if (t < kRows) {
           const int r = t;
           const int64_t row = row0 + r;
@@ -115,10 +151,7 @@ __device__ __forceinline__ void pass_f32_body(
             h[j] = s;
             x[j] = (row < n_p) ? double(vold[r][j]) : 0.0;
           }
-          if (MODE == kModeHALS)
-            hals_row<K>(gd_s, h, x);
-          else
-            nnls_gram_row<K>(gd_s, chol, h, x);
+          hals_row<K>(gd_s, h, x);
 #pragma unroll
           for (int j = 0; j < K; ++j) {
             const float vn = (row < n_p) ? float(x[j]) : 0.0f;
@@ -232,10 +265,10 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
     const float *__restrict__ P, int64_t ldp, int64_t n_p, int n_k, float *__restrict__ V, float *__restrict__ NV,
     const float *__restrict__ D, const double *__restrict__ GD, const double *__restrict__ chol,
     float *__restrict__ part_nd, double *__restrict__ part_gv, double *__restrict__ part_obj,
-    NmfCtrl *__restrict__ ctrl, int iter) {
-  __shared__ __attribute__((aligned(16))) char lds[PassLds<K>::bytes];
+    NmfCtrl *__restrict__ ctrl, int iter, const double *__restrict__ ginv) {
+  __shared__ __attribute__((aligned(16))) char lds[PassLds<K, MODE>::bytes];
   pass_f32_body<K, NQ, MODE, OBJ>(P, ldp, n_p, n_k, V, NV, D, GD, chol, part_nd, part_gv, part_obj, ctrl, iter,
-                                  int(blockIdx.x), int(gridDim.x), lds);
+                                  int(blockIdx.x), int(gridDim.x), lds, ginv);
 }
 
 // ---------------------------------------------------------------------------
@@ -248,7 +281,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_f32_kernel(
 template <int K, int NQ, int MODE, bool OBJ>
 __global__ __launch_bounds__(kPassThreads) void batched_pass_kernel(const BatchInst *__restrict__ d, int n_inst,
                                                                     int iter_local) {
-  __shared__ __attribute__((aligned(16))) char lds[PassLds<K>::bytes];
+  __shared__ __attribute__((aligned(16))) char lds[PassLds<K, MODE>::bytes];
   const int i = batch_find(n_inst, int(blockIdx.x), [&](int j) { return d[j].wg0; });
   const BatchInst &b = d[i];
   const int wg = int(blockIdx.x) - b.wg0;
@@ -294,12 +327,15 @@ void launch_batched_pass(int K, int nq, int mode, bool obj, int n_blocks, hipStr
 template <int K>
 void launch_pass_f32_k(int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp, int64_t n_p,
                        int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                       float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
+                       float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                       const double *ginv) {
 #define HSN_PASS(NQ_, M_, O_)                                                                                   \
   pass_f32_kernel<K, NQ_, M_, O_><<<n_wg, kPassThreads, 0, st>>>(P, ldp, n_p, n_k, V, NV, D, GD, chol, part_nd,    \
-                                                                 part_gv, part_obj, ctrl, iter)
+                                                                 part_gv, part_obj, ctrl, iter, ginv)
   if (nq == 1) {
-    if (mode == kModeMU) {
+    if (mode == kModeANLS) {
+      HSN_PASS(1, kModeANLS, true);
+    } else if (mode == kModeMU) {
       if (obj) HSN_PASS(1, kModeMU, true); else HSN_PASS(1, kModeMU, false);
     } else if (mode == kModeHALS) {
       if (obj) HSN_PASS(1, kModeHALS, true); else HSN_PASS(1, kModeHALS, false);
@@ -309,7 +345,9 @@ void launch_pass_f32_k(int mode, bool obj, int nq, int n_wg, hipStream_t st, con
       HSN_PASS(1, kModeND, true);
     }
   } else {
-    if (mode == kModeMU) {
+    if (mode == kModeANLS) {
+      HSN_PASS(2, kModeANLS, true);
+    } else if (mode == kModeMU) {
       if (obj) HSN_PASS(2, kModeMU, true); else HSN_PASS(2, kModeMU, false);
     } else if (mode == kModeHALS) {
       if (obj) HSN_PASS(2, kModeHALS, true); else HSN_PASS(2, kModeHALS, false);
@@ -324,12 +362,13 @@ void launch_pass_f32_k(int mode, bool obj, int nq, int n_wg, hipStream_t st, con
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
                      int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter) {
+                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                     const double *ginv) {
   switch (K) {
 #define HSN_K(KK)                                                                                                  \
   case KK:                                                                                                         \
     launch_pass_f32_k<KK>(mode, obj, nq, n_wg, st, P, ldp, n_p, n_k, V, NV, D, GD, chol, part_nd, part_gv,      \
-                          part_obj, ctrl, iter);                                                                   \
+                          part_obj, ctrl, iter, ginv);                                                             \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K

@@ -51,21 +51,55 @@ __device__ inline void write_images_row(uint16_t *__restrict__ img, int64_t ldb,
     }
 }
 
-// Factors of all principal submatrices of G (K x K, in LDS) -> chol.
+// Factors of all principal submatrices G[S,S] of G (K x K, in LDS) -> chol
+// (packed lower, compact index order); with ginv, also their inverses
+// G[S,S]^-1 = L^-T L^-1, embedded in a packed symmetric K x K matrix with
+// zeros outside S, entry-major with stride kInvStride (the operand of
+// nnls_enum_group).  A singular G[S,S] gets NaN as the first entry of both.
 template <int K>
-__device__ inline void factor_all(const double *G, double *__restrict__ chol) {
+__device__ inline void factor_all(const double *G, double *__restrict__ chol, double *__restrict__ ginv = nullptr) {
   for (int m = threadIdx.x; m < (1 << K); m += blockDim.x) {
     if (m == 0) continue;
     double L[kCholStride];
-    if (!chol_sub(G, K, unsigned(m), L)) L[0] = NAN;
+    const bool ok = chol_sub(G, K, unsigned(m), L);
+    if (!ok) L[0] = NAN;
     for (int i = 0; i < kCholStride; ++i) chol[size_t(m) * kCholStride + i] = L[i];
+    if (!ginv) continue;
+    double *out = ginv + m;  // entry e at out[e * kInvStride]
+    if (!ok) {
+      out[0] = NAN;
+      for (int e = 1; e < tri(K); ++e) out[e * kInvStride] = 0.0;
+      continue;
+    }
+    int idx[8];
+    int s = 0;
+    for (int i = 0; i < K; ++i)
+      if (m & (1 << i)) idx[s++] = i;
+    // M = L^-1 (lower), by forward substitution column by column
+    double M[kCholStride];
+    for (int c = 0; c < s; ++c) {
+      for (int a = c; a < s; ++a) {
+        double v = (a == c) ? 1.0 : 0.0;
+        for (int b = c; b < a; ++b) v -= L[tri(a) + b] * M[tri(b) + c];
+        M[tri(a) + c] = v / L[tri(a) + a];
+      }
+    }
+    for (int e = 0; e < tri(K); ++e) out[e * kInvStride] = 0.0;
+    // (M^T M)[a][b] = sum over c >= max(a, b) of M[c][a] M[c][b]
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b <= a; ++b) {
+        double v = 0.0;
+        for (int c = a; c < s; ++c) v += M[tri(c) + a] * M[tri(c) + b];
+        out[sym(idx[a], idx[b]) * kInvStride] = v;
+      }
   }
 }
 
 template <int K>
 __device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n_k, double *__restrict__ GD,
                                               double *__restrict__ chol, int want_chol, uint16_t *__restrict__ img,
-                                              int64_t ldb, NmfCtrl *__restrict__ ctrl) {
+                                              int64_t ldb, NmfCtrl *__restrict__ ctrl,
+                                              double *__restrict__ ginv = nullptr) {
   const int t = threadIdx.x;
   __shared__ double red[kUpdThreads / 64][K * K];
   __shared__ double g_s[K * K];
@@ -106,17 +140,18 @@ __device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n
     ctrl->upd_ticket = 0;
     ctrl->hist_len = 0;
     ctrl->iter_base = 0;
+    ctrl->numeric = 0;
   }
   __syncthreads();
-  if (want_chol) factor_all<K>(g_s, chol);
+  if (want_chol) factor_all<K>(g_s, chol, ginv);
 }
 
 template <int K>
 __global__ __launch_bounds__(kUpdThreads) void nmf_init_kernel(const float *__restrict__ D, int n_k, double *__restrict__ GD,
                                                                double *__restrict__ chol, int want_chol,
                                                                uint16_t *__restrict__ img, int64_t ldb,
-                                                               NmfCtrl *__restrict__ ctrl) {
-  nmf_init_body<K>(D, n_k, GD, chol, want_chol, img, ldb, ctrl);
+                                                               NmfCtrl *__restrict__ ctrl, double *__restrict__ ginv) {
+  nmf_init_body<K>(D, n_k, GD, chol, want_chol, img, ldb, ctrl, ginv);
 }
 
 // RULE: kModeMU (Lee-Seung), kModeHALS (column sweep), kModeNV (exact NNLS rows)
@@ -180,7 +215,7 @@ __device__ __forceinline__ void update_d_body(
     int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
     int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int blk, int n_blk,
-    char *__restrict__ lds) {
+    char *__restrict__ lds, const double *__restrict__ bias = nullptr) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   using L = UpdLds<K, RULE>;
@@ -222,7 +257,16 @@ __device__ __forceinline__ void update_d_body(
     const int h = ctrl->hist_len;
     hist[h] = obj_s;
     ctrl->hist_len = h + 1;
-    if (f_ref > 0.0 && (obj_s - f_ref) / f_ref <= tol) ctrl->stop_at = iter + 1;
+    // bias: the stop test of a pass over the bfloat16 p compares
+    // obj - ||p - p_bf16||^2, an estimate of the float32 objective
+    const double ob = bias ? obj_s + *bias : obj_s;
+    if (!isfinite(obj_s)) {
+      // a non-finite objective (NaN or Inf in p or in the factors) ends the run
+      ctrl->numeric = 1;
+      ctrl->stop_at = iter + 1;
+    } else if (f_ref > 0.0 && (ob - f_ref) / f_ref <= tol) {
+      ctrl->stop_at = iter + 1;
+    }
   }
   __syncthreads();
 
@@ -285,7 +329,7 @@ template <int K>
 __device__ __forceinline__ void finish_gd_body(const double *__restrict__ part_gd, int n_blk, double *__restrict__ GD,
                                                double *__restrict__ chol, int next_chol,
                                                const NmfCtrl *__restrict__ ctrl, int iter, double *__restrict__ red,
-                                               double *__restrict__ gd_s) {
+                                               double *__restrict__ gd_s, double *__restrict__ ginv = nullptr) {
   if (iter >= ctrl->stop_at) return;
   constexpr int G = kUpdThreads / (K * K);
   const int t = threadIdx.x;
@@ -301,17 +345,17 @@ __device__ __forceinline__ void finish_gd_body(const double *__restrict__ part_g
     GD[t] = s;
   }
   __syncthreads();
-  if (next_chol) factor_all<K>(gd_s, chol);
+  if (next_chol) factor_all<K>(gd_s, chol, ginv);
 }
 
 template <int K>
 __global__ __launch_bounds__(kUpdThreads) void finish_gd_kernel(const double *__restrict__ part_gd, int n_blk,
                                                                 double *__restrict__ GD, double *__restrict__ chol,
                                                                 int next_chol, const NmfCtrl *__restrict__ ctrl,
-                                                                int iter) {
+                                                                int iter, double *__restrict__ ginv) {
   __shared__ double red[kUpdThreads];
   __shared__ double gd_s[K * K];
-  finish_gd_body<K>(part_gd, n_blk, GD, chol, next_chol, ctrl, iter, red, gd_s);
+  finish_gd_body<K>(part_gd, n_blk, GD, chol, next_chol, ctrl, iter, red, gd_s, ginv);
 }
 
 template <int K, int RULE>
@@ -319,10 +363,11 @@ __global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
     float *__restrict__ D, const float *__restrict__ part_nd, int n_wg, int n_k, NmfCtrl *__restrict__ ctrl, int iter,
     int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
-    int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb) {
+    int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb,
+    const double *__restrict__ bias) {
   __shared__ __attribute__((aligned(16))) char lds[UpdLds<K, RULE>::bytes];
   update_d_body<K, RULE>(D, part_nd, n_wg, n_k, ctrl, iter, has_obj, f_ref, tol, hist, GD, chol, next_chol, part_gd,
-                         img, ldb, int(blockIdx.x), int(gridDim.x), lds);
+                         img, ldb, int(blockIdx.x), int(gridDim.x), lds, bias);
 }
 
 template <int K>
@@ -439,7 +484,7 @@ __global__ void batched_advance_kernel(const BatchInst *__restrict__ d, int n_in
 void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWork &w, int want_chol, int64_t ldb) {
   switch (K) {
 #define HSN_K(KK) \
-  case KK: nmf_init_kernel<KK><<<1, kUpdThreads, 0, st>>>(D, n_k, w.gd, w.chol, want_chol, w.img, ldb, w.ctrl); break;
+  case KK: nmf_init_kernel<KK><<<1, kUpdThreads, 0, st>>>(D, n_k, w.gd, w.chol, want_chol, w.img, ldb, w.ctrl, w.ginv); break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
   }
@@ -448,7 +493,7 @@ void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWo
 int update_d_blocks(int n_k) { return (n_k + kUpdRows - 1) / kUpdRows; }
 
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
-                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img) {
+                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, const double *bias) {
   const int nb = update_d_blocks(n_k);
   uint16_t *img = ldb_img > 0 ? w.img : nullptr;
   switch (K) {
@@ -463,15 +508,15 @@ void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w
     if (rule == kModeMU)                                                                                          \
       update_d_kernel<KK, kModeMU><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
-                                                               w.chol, next_chol, w.part_gd, img, ldb_img);       \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bias); \
     else if (rule == kModeHALS)                                                                                   \
       update_d_kernel<KK, kModeHALS><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                          \
                                                                  w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd, \
-                                                                 w.chol, next_chol, w.part_gd, img, ldb_img);     \
+                                                                 w.chol, next_chol, w.part_gd, img, ldb_img, bias); \
     else                                                                                                          \
       update_d_kernel<KK, kModeNV><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
-                                                               w.chol, next_chol, w.part_gd, img, ldb_img);       \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bias); \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
@@ -479,7 +524,7 @@ void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w
   switch (K) {
 #define HSN_K(KK)                                                                                                  \
   case KK:                                                                                                         \
-    finish_gd_kernel<KK><<<1, kUpdThreads, 0, st>>>(w.part_gd, nb, w.gd, w.chol, next_chol, w.ctrl, iter);          \
+    finish_gd_kernel<KK><<<1, kUpdThreads, 0, st>>>(w.part_gd, nb, w.gd, w.chol, next_chol, w.ctrl, iter, w.ginv);  \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
@@ -538,6 +583,12 @@ void launch_batched_rows(int K, int n_blocks, hipStream_t st, const BatchInst *d
 #undef HSN_K
   }
 }
+
+// Re-opens a decomposition whose stop test fired (stop_at back to "never"):
+// the driver's switch from the bfloat16 polish rounds to the float32 ones.
+__global__ void nmf_resume_kernel(NmfCtrl *__restrict__ ctrl) { ctrl->stop_at = INT_MAX; }
+
+void launch_nmf_resume(hipStream_t st, NmfCtrl *ctrl) { nmf_resume_kernel<<<1, 1, 0, st>>>(ctrl); }
 
 void launch_batched_advance(int n_inst, int steps, hipStream_t st, const BatchInst *d) {
   batched_advance_kernel<<<(n_inst + 63) / 64, 64, 0, st>>>(d, n_inst, steps);

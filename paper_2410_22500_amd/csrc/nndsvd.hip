@@ -406,7 +406,8 @@ __global__ void qinit_kernel(double *__restrict__ Q, int n_k, int L) {
 
 void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st, const float *P, int64_t ldp,
                      int64_t n_p, int n_k, float *V, float *NV, const float *D, const double *GD, const double *chol,
-                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter);
+                     float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                     const double *ginv);
 
 size_t nndsvd_ws_bytes(int64_t n_p, int n_k, int K, int n_split) {
   const int n_tb = (n_k + kGT - 1) / kGT;
@@ -460,7 +461,7 @@ hsn_status nndsvd_init(hsn_ctx *ctx, hipStream_t st, const float *p, int64_t ldp
   const int64_t n_tiles = (n_p + 7) / 8;
   const int wg = int(std::min<int64_t>(n_tiles, 2 * int64_t(ctx->num_cu)));
   launch_pass_f32(K, kModeNV, false, n_k > 1024 ? 2 : 1, wg, st, p, ldp, n_p, n_k, nullptr, U, vK, nullptr, nullptr,
-                  nullptr, nullptr, nullptr, ctrl, 0);
+                  nullptr, nullptr, nullptr, ctrl, 0, nullptr);
   const int nbu = 1024, nbv = 64, nbp = 1024;
   split_norms_kernel<float><<<nbu, 256, 0, st>>>(U, n_p, K, part_u);
   split_norms_kernel<double><<<nbv, 256, 0, st>>>(vs, n_k, K, part_v);

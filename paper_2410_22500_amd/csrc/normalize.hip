@@ -4,7 +4,8 @@
 //   b[v][k] = mean over background pixels B of the unclipped -ln(y / y^o).
 //
 // One HBM stream: counts in, float32 p and (optionally) its bfloat16 copy
-// out, with per-block float64 partials of sum(p^2) reduced in a fixed order.
+// out, with per-block float64 partials of sum(p^2) (and, with the bfloat16
+// copy, of -sum((p - bf16(p))^2)) reduced in a fixed order.
 #include "common.hpp"
 
 namespace {
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void normalize_kernel(
   const int rr = cpr <= kThreads ? t / cpr : 0;
   const int ch0 = cpr <= kThreads ? t - rr * cpr : t;
   const int nki = int(nk);
-  double ss = 0.0;
+  double ss = 0.0, sb = 0.0;
   for (int64_t g0 = int64_t(blockIdx.x) * R; g0 < n_rows; g0 += int64_t(gridDim.x) * R) {
     const int64_t row = g0 + rr;
     const bool row_ok = rr < R && row < n_rows;
@@ -121,6 +122,10 @@ __global__ __launch_bounds__(kThreads) void normalize_kernel(
         }
         out[e] = pv;
         ss += double(pv) * double(pv);
+        if (pb) {
+          const double e = double(pv) - double(hsn::bf16_bits_to_f32(hsn::f32_to_bf16_bits(pv)));
+          sb -= e * e;
+        }
       }
       if (p) {
         if (VEC && k0 + 8 <= nki) {
@@ -169,20 +174,28 @@ __global__ __launch_bounds__(kThreads) void normalize_kernel(
     }
   }
   // Block reduction of the float64 sum of squares, fixed order.
-  __shared__ double red[kThreads / 64];
+  __shared__ double red[2][kThreads / 64];
   ss = hsn::wave_sum_all(ss);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+  sb = hsn::wave_sum_all(sb);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = ss;
+    red[1][threadIdx.x >> 6] = sb;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double tt = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) tt += red[w];
+    double tt = 0.0, tb = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      tt += red[0][w];
+      tb += red[1][w];
+    }
     partial[blockIdx.x] = tt;
+    partial[kSumBlocks + blockIdx.x] = tb;
   }
 }
 
 // Fast path for uint16 counts whose rows split into whole 8-bin chunks
 // (n_k % 8 == 0, n_k <= 2048, 16-byte aligned rows, p present, p_bf16 absent
-// or unpadded): one chunk per thread per row group, straight-line code with
+// or 16-byte aligned, its row at most 2048 wide): one chunk per thread per row group, straight-line code with
 // the options fixed at compile time.  Same values, the same rows per block
 // and the same summation order as normalize_kernel (bitwise equal outputs);
 // measured about 25 % faster at 1024 and 2000 bins.
@@ -192,14 +205,20 @@ __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
     const float *__restrict__ b, float floor_, int clip, float *__restrict__ p, int64_t ldp,
     uint16_t *__restrict__ pb, int64_t ldb, void *__restrict__ pooled, double *__restrict__ partial) {
   __shared__ float rowbuf[POOL ? kPoolMaxBins : 1];
+  // Thread t takes chunk t % cpw of row t / cpw of the group, cpw = the
+  // chunks of the widest output row (the padded bfloat16 row when there is
+  // one), as normalize_kernel does; chunks past the bins only zero the pad.
   const int cpr = nk >> 3;
-  const int R = kThreads / cpr;
+  const int cpw = HAS_PB ? int(ldb >> 3) : cpr;
+  const int R = kThreads / cpw;
   const int t = threadIdx.x;
-  const int rr = t / cpr, k0 = (t - rr * cpr) * 8;
-  double ss = 0.0;
+  const int rr = t / cpw, k0 = (t - rr * cpw) * 8;
+  double ss = 0.0, sb = 0.0;
   for (int64_t g0 = int64_t(blockIdx.x) * R; g0 < n_rows; g0 += int64_t(gridDim.x) * R) {
     const int64_t row = g0 + rr;
-    if (rr < R && row < n_rows) {
+    if (HAS_PB && rr < R && row < n_rows && k0 >= nk)
+      *reinterpret_cast<uint4 *>(pb + row * ldb + k0) = make_uint4(0, 0, 0, 0);
+    if (rr < R && row < n_rows && k0 < nk) {
       const int64_t v = row / n_pix, px = row - v * n_pix;
       const uint4 yv = *reinterpret_cast<const uint4 *>(y + row * nk + k0);
       const uint4 ov = *reinterpret_cast<const uint4 *>(yo + px * nk + k0);
@@ -215,6 +234,10 @@ __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
         if (clip) pv = fmaxf(pv, 0.0f);
         out[e] = pv;
         ss += double(pv) * double(pv);
+        if constexpr (HAS_PB) {
+          const double e = double(pv) - double(hsn::bf16_bits_to_f32(hsn::f32_to_bf16_bits(pv)));
+          sb -= e * e;
+        }
       }
       float4 *dst = reinterpret_cast<float4 *>(p + row * ldp + k0);
       dst[0] = make_float4(out[0], out[1], out[2], out[3]);
@@ -249,14 +272,22 @@ __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
       __syncthreads();
     }
   }
-  __shared__ double red[kThreads / 64];
+  __shared__ double red[2][kThreads / 64];
   ss = hsn::wave_sum_all(ss);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+  sb = hsn::wave_sum_all(sb);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = ss;
+    red[1][threadIdx.x >> 6] = sb;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double tt = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) tt += red[w];
+    double tt = 0.0, tb = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      tt += red[0][w];
+      tb += red[1][w];
+    }
     partial[blockIdx.x] = tt;
+    partial[kSumBlocks + blockIdx.x] = tb;
   }
 }
 
@@ -297,21 +328,31 @@ void launch_norm(int64_t n_rows, int64_t n_pix, int64_t nk, const TY *y, const T
                                                                        ldp, pb, ldb, pooled, partial);
 }
 
+// scratch: 2 kSumBlocks doubles of per-block partials, and (when the offset
+// is computed but not returned) N_v N_k floats for b; null: taken from the
+// context's workspace.  With scratch given nothing is allocated and no
+// profiling events are recorded.
 template <typename TY, typename TO>
 hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo, const uint8_t *mask,
                       float floor_, int clip, float *p, int64_t ldp, uint16_t *pb, int64_t ldb,
-                      float *offset_b, double *sumsq, void *pooled, int pool_mode, hipStream_t st) {
+                      float *offset_b, double *sumsq, double *bf16_bias, void *pooled, int pool_mode,
+                      hipStream_t st, double *scratch = nullptr) {
   const int64_t n_pix = d->n_rows * d->n_cols;
   const int64_t n_rows = d->n_views * n_pix;
   const int64_t nk = d->n_bins;
-  size_t need = hsn::Carver::need({sizeof(double) * kSumBlocks, mask ? sizeof(float) * d->n_views * nk : 0});
-  hsn_status s = hsn::ensure_ws(ctx, need);
-  if (s != HSN_OK) return s;
-  hsn::Carver cv(ctx->ws);
-  double *partial = cv.take<double>(kSumBlocks);
+  double *partial = scratch;
   float *b = nullptr;
+  float *b_scratch = nullptr;
+  if (!scratch) {
+    size_t need = hsn::Carver::need({sizeof(double) * 2 * kSumBlocks, mask ? sizeof(float) * d->n_views * nk : 0});
+    hsn_status s = hsn::ensure_ws(ctx, need);
+    if (s != HSN_OK) return s;
+    hsn::Carver cv(ctx->ws);
+    partial = cv.take<double>(2 * kSumBlocks);
+    if (mask && !offset_b) b_scratch = cv.take<float>(d->n_views * nk);
+  }
   if (mask) {
-    b = offset_b ? offset_b : cv.take<float>(d->n_views * nk);
+    b = offset_b ? offset_b : b_scratch;
     dim3 grid(unsigned((nk + kThreads - 1) / kThreads), unsigned(d->n_views));
     offset_kernel<TY, TO><<<grid, kThreads, 0, st>>>(y, yo, mask, n_pix, nk, floor_, b);
     HSN_LAUNCHED(ctx);
@@ -320,11 +361,11 @@ hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo
                    (reinterpret_cast<uintptr_t>(y) % 16 == 0) && (reinterpret_cast<uintptr_t>(yo) % 16 == 0) &&
                    (!p || (ldp % 4 == 0 && reinterpret_cast<uintptr_t>(p) % 16 == 0)) &&
                    (!pb || reinterpret_cast<uintptr_t>(pb) % 16 == 0);
-  hsn::prof_begin(ctx, HSN_KERN_NORMALIZE, st);
+  if (!scratch) hsn::prof_begin(ctx, HSN_KERN_NORMALIZE, st);
 #define HSN_NORM(V, P) launch_norm<TY, TO, V, P>(n_rows, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st)
   bool fast = false;
   if constexpr (std::is_same<TY, uint16_t>::value && std::is_same<TO, uint16_t>::value) {
-    fast = vec && p && nk <= kPoolMaxBins && (!pb || ldb == nk);
+    fast = vec && p && nk <= kPoolMaxBins && (!pb || ldb <= 8 * kThreads);
     if (fast) {
       if (pool_mode == 0)
         launch_norm_u16<0>(n_rows, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st);
@@ -340,10 +381,14 @@ hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo
     if (pool_mode == 0) HSN_NORM(false, 0); else if (pool_mode == 1) HSN_NORM(false, 1); else HSN_NORM(false, 2);
   }
 #undef HSN_NORM
-  hsn::prof_end(ctx, HSN_KERN_NORMALIZE, st);
+  if (!scratch) hsn::prof_end(ctx, HSN_KERN_NORMALIZE, st);
   HSN_LAUNCHED(ctx);
   if (sumsq) {
     sum_partials_kernel<<<1, kThreads, 0, st>>>(partial, kSumBlocks, sumsq);
+    HSN_LAUNCHED(ctx);
+  }
+  if (bf16_bias) {
+    sum_partials_kernel<<<1, kThreads, 0, st>>>(partial + kSumBlocks, kSumBlocks, bf16_bias);
     HSN_LAUNCHED(ctx);
   }
   return HSN_OK;
@@ -354,7 +399,8 @@ hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo
 static hsn_status normalize_impl(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype, const void *y_open,
                           int y_open_dtype, const uint8_t *bg_mask, float count_floor, int clip_nonneg, float *p,
                           int64_t ldp, uint16_t *p_bf16, int64_t ldb, float *offset_b, double *sumsq,
-                          void *pooled, int pool_mode, void *stream) {
+                          double *bf16_bias, void *pooled, int pool_mode, void *stream,
+                          double *(*scratch_of)(hsn_ctx *) = nullptr) {
   if (!ctx) return HSN_ERR_INVALID_ARG;
   if (!d || !y || !y_open) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: dims, y and y_open are required");
   if (!p && !p_bf16 && !pooled)
@@ -369,36 +415,41 @@ static hsn_status normalize_impl(hsn_ctx *ctx, const hsn_dims *d, const void *y,
   if (p_bf16 && (ldb < d->n_bins || ldb % 32 != 0 || reinterpret_cast<uintptr_t>(p_bf16) % 16 != 0))
     return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: ldb must be >= n_bins, a multiple of 32, 16-byte aligned");
   if (offset_b && !bg_mask) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: offset_b requires bg_mask");
+  if (bf16_bias && !p_bf16) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: bf16_bias requires p_bf16");
   if (!(count_floor >= 0.0f)) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize: count_floor must be >= 0");
   hsn::DeviceGuard g(ctx->device);
+  double *scratch = nullptr;
+  if (scratch_of && !(scratch = scratch_of(ctx))) return HSN_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool yu = y_dtype == HSN_U16, ou = y_open_dtype == HSN_U16;
   if (yu && ou)
     return launch_all(ctx, d, (const uint16_t *)y, (const uint16_t *)y_open, bg_mask, count_floor, clip_nonneg, p,
-                      ldp, p_bf16, ldb, offset_b, sumsq, pooled, pool_mode, st);
+                      ldp, p_bf16, ldb, offset_b, sumsq, bf16_bias, pooled, pool_mode, st, scratch);
   if (yu && !ou)
     return launch_all(ctx, d, (const uint16_t *)y, (const float *)y_open, bg_mask, count_floor, clip_nonneg, p, ldp,
-                      p_bf16, ldb, offset_b, sumsq, pooled, pool_mode, st);
+                      p_bf16, ldb, offset_b, sumsq, bf16_bias, pooled, pool_mode, st, scratch);
   if (!yu && ou)
     return launch_all(ctx, d, (const float *)y, (const uint16_t *)y_open, bg_mask, count_floor, clip_nonneg, p, ldp,
-                      p_bf16, ldb, offset_b, sumsq, pooled, pool_mode, st);
+                      p_bf16, ldb, offset_b, sumsq, bf16_bias, pooled, pool_mode, st, scratch);
   return launch_all(ctx, d, (const float *)y, (const float *)y_open, bg_mask, count_floor, clip_nonneg, p, ldp,
-                    p_bf16, ldb, offset_b, sumsq, pooled, pool_mode, st);
+                    p_bf16, ldb, offset_b, sumsq, bf16_bias, pooled, pool_mode, st, scratch);
 }
+
 
 extern "C" hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype,
                                     const void *y_open, int y_open_dtype, const uint8_t *bg_mask,
                                     float count_floor, int clip_nonneg, float *p, int64_t ldp, uint16_t *p_bf16,
-                                    int64_t ldb, float *offset_b, double *sumsq, void *stream) {
+                                    int64_t ldb, float *offset_b, double *sumsq, double *bf16_bias,
+                                    void *stream) {
   return normalize_impl(ctx, d, y, y_dtype, y_open, y_open_dtype, bg_mask, count_floor, clip_nonneg, p, ldp, p_bf16,
-                        ldb, offset_b, sumsq, nullptr, 0, stream);
+                        ldb, offset_b, sumsq, bf16_bias, nullptr, 0, stream);
 }
 
 extern "C" hsn_status hsn_normalize_pooled(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype,
                                            const void *y_open, int y_open_dtype, const uint8_t *bg_mask,
                                            float count_floor, int clip_nonneg, float *p, int64_t ldp,
                                            uint16_t *p_bf16, int64_t ldb, float *offset_b, double *sumsq,
-                                           void *pooled, int pooled_precision, void *stream) {
+                                           double *bf16_bias, void *pooled, int pooled_precision, void *stream) {
   if (!ctx) return HSN_ERR_INVALID_ARG;
   if (!pooled) return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize_pooled: pooled is required");
   if (pooled_precision != HSN_PREC_BF16 && pooled_precision != HSN_PREC_FP32)
@@ -406,5 +457,6 @@ extern "C" hsn_status hsn_normalize_pooled(hsn_ctx *ctx, const hsn_dims *d, cons
   if (reinterpret_cast<uintptr_t>(pooled) % 4 != 0)
     return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize_pooled: pooled must be 4-byte aligned");
   return normalize_impl(ctx, d, y, y_dtype, y_open, y_open_dtype, bg_mask, count_floor, clip_nonneg, p, ldp, p_bf16,
-                        ldb, offset_b, sumsq, pooled, pooled_precision == HSN_PREC_BF16 ? 1 : 2, stream);
+                        ldb, offset_b, sumsq, bf16_bias, pooled, pooled_precision == HSN_PREC_BF16 ? 1 : 2, stream);
 }
+

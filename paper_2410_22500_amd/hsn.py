@@ -42,7 +42,7 @@ class NmfOpts(C.Structure):
     _fields_ = [("k", C.c_int), ("algo", C.c_int), ("precision", C.c_int), ("init", C.c_int),
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("polish_rounds", C.c_int),
                 ("polish_algo", C.c_int), ("polish_bf16_rounds", C.c_int), ("rel_obj_tol", C.c_double),
-                ("f_ref", C.c_double), ("mlp", C.c_void_p), ("mlp_pooled", C.c_void_p)]
+                ("f_ref", C.c_double), ("mlp", C.c_void_p), ("mlp_pooled", C.c_void_p), ("bf16_bias", C.c_void_p)]
 
 
 class TrainOpts(C.Structure):
@@ -53,7 +53,7 @@ class TrainOpts(C.Structure):
 class NmfStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("polish_done", C.c_int), ("objective", C.c_double), ("rel_obj", C.c_double),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int),
-                ("ms", C.c_float)]
+                ("ms", C.c_float), ("polish_bf16_done", C.c_int)]
 
 
 class NmfProblem(C.Structure):
@@ -78,14 +78,16 @@ _lib.hsn_last_error.argtypes = [_P]
 _lib.hsn_last_error.restype = C.c_char_p
 _lib.hsn_version.restype = C.c_int
 _lib.hsn_normalize.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, _P, C.c_float, C.c_int,
-                               _P, C.c_int64, _P, C.c_int64, _P, _P, _P]
+                               _P, C.c_int64, _P, C.c_int64, _P, _P, _P, _P]
 _lib.hsn_normalize.restype = C.c_int
 _lib.hsn_normalize_pooled.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, _P, C.c_float, C.c_int,
-                                      _P, C.c_int64, _P, C.c_int64, _P, _P, _P, C.c_int, _P]
+                                      _P, C.c_int64, _P, C.c_int64, _P, _P, _P, _P, C.c_int, _P]
 _lib.hsn_normalize_pooled.restype = C.c_int
 _lib.hsn_subspace_nmf.argtypes = [_P, _P, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int64, _P, _P,
                                   C.POINTER(NmfOpts), C.POINTER(NmfStats), _P]
 _lib.hsn_subspace_nmf.restype = C.c_int
+_lib.hsn_nmf_set_launch.argtypes = [_P, C.c_int]
+_lib.hsn_nmf_set_launch.restype = C.c_int
 _lib.hsn_subspace_nmf_batched.argtypes = [_P, C.c_int, C.POINTER(NmfProblem), C.POINTER(NmfOpts), C.c_int,
                                           C.POINTER(NmfStats), _P]
 _lib.hsn_subspace_nmf_batched.restype = C.c_int
@@ -99,9 +101,9 @@ _lib.hsn_cgls.argtypes = [_P, C.POINTER(Geom), _P, _P, C.c_int, _P, _P]
 _lib.hsn_cgls.restype = C.c_int
 _lib.hsn_fbp.argtypes = [_P, C.POINTER(Geom), _P, C.c_int64, _P, _P]
 _lib.hsn_fbp.restype = C.c_int
-_lib.hsn_fhr_step.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, C.c_float, _P, C.c_int64, _P, _P, _P,
-                             C.POINTER(NmfOpts), C.POINTER(NmfStats), _P, C.c_int, _P, C.c_int64, C.c_int64, C.c_int64,
-                             C.c_int64, _P, C.c_int64, _P]
+_lib.hsn_fhr_step.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, C.c_float, _P, C.c_int64, _P,
+                             C.c_int64, _P, _P, _P, C.POINTER(NmfOpts), C.POINTER(NmfStats), _P, C.c_int, _P,
+                             C.c_int64, C.c_int64, C.c_int64, C.c_int64, _P, C.c_int64, _P]
 _lib.hsn_fhr_step.restype = C.c_int
 _lib.hsn_mbir.argtypes = [_P, C.POINTER(Geom), _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
                          C.c_double, C.c_int, C.c_int, _P]
@@ -252,9 +254,11 @@ def _check_counts(y, yo, bg_mask=None):
 
 def hsn_normalize(y: torch.Tensor, yo: torch.Tensor, bg_mask: Optional[torch.Tensor] = None,
                   count_floor: float = 1.0, clip: bool = True, want_f32: bool = True, want_bf16: bool = False,
-                  want_offset: bool = False, ldp: Optional[int] = None, ldb: Optional[int] = None):
+                  want_offset: bool = False, ldp: Optional[int] = None, ldb: Optional[int] = None,
+                  want_bias: bool = False):
     """y [N_v][N_r][N_c][N_k] (uint16 as int16/uint16 bits or float32), yo [N_r][N_c][N_k].
-    Returns (p [N_p][ldp] f32 or None, p_bf16 [N_p][ldb] int16 bits or None, b or None, sumsq f64 scalar)."""
+    Returns (p [N_p][ldp] f32 or None, p_bf16 [N_p][ldb] int16 bits or None, b or None, sumsq f64 scalar);
+    with want_bias (needs want_bf16) a fifth item, the f64 scalar -||p - p_bf16||^2."""
     _check_counts(y, yo, bg_mask)
     dev = _dev(y)
     ctx = context(dev)
@@ -269,16 +273,19 @@ def hsn_normalize(y: torch.Tensor, yo: torch.Tensor, bg_mask: Optional[torch.Ten
     pb = torch.empty((n_p, ldb), dtype=torch.int16, device=y.device) if want_bf16 else None
     b = torch.empty((n_v, n_k), dtype=torch.float32, device=y.device) if (want_offset and bg_mask is not None) else None
     ss = torch.empty((), dtype=torch.float64, device=y.device)
+    bias = torch.empty((), dtype=torch.float64, device=y.device) if want_bias else None
     _check(_lib.hsn_normalize(ctx, C.byref(dims), _ptr(y), yd, _ptr(yo), od, _ptr(bg_mask), float(count_floor),
-                              int(clip), _ptr(p), ldp, _ptr(pb), ldb, _ptr(b), _ptr(ss), _stream(dev)), ctx)
-    return p, pb, b, ss
+                              int(clip), _ptr(p), ldp, _ptr(pb), ldb, _ptr(b), _ptr(ss), _ptr(bias), _stream(dev)), ctx)
+    return (p, pb, b, ss, bias) if want_bias else (p, pb, b, ss)
 
 
 def hsn_normalize_pooled(y: torch.Tensor, yo: torch.Tensor, pooled_precision: int, bg_mask: Optional[torch.Tensor] = None,
                          count_floor: float = 1.0, clip: bool = True, want_f32: bool = True, want_bf16: bool = False,
-                         want_offset: bool = False, ldp: Optional[int] = None, ldb: Optional[int] = None):
+                         want_offset: bool = False, ldp: Optional[int] = None, ldb: Optional[int] = None,
+                         want_bias: bool = False):
     """hsn_normalize plus the learned start's pooled input [N_p][256] (bfloat16 bits as int16 for
-    PREC_BF16, float32 for PREC_FP32).  Returns (p, p_bf16, pooled, b, sumsq)."""
+    PREC_BF16, float32 for PREC_FP32).  Returns (p, p_bf16, pooled, b, sumsq), plus the bias
+    -||p - p_bf16||^2 with want_bias."""
     _check_counts(y, yo, bg_mask)
     dev = _dev(y)
     ctx = context(dev)
@@ -295,10 +302,11 @@ def hsn_normalize_pooled(y: torch.Tensor, yo: torch.Tensor, pooled_precision: in
                          device=y.device)
     b = torch.empty((n_v, n_k), dtype=torch.float32, device=y.device) if (want_offset and bg_mask is not None) else None
     ss = torch.empty((), dtype=torch.float64, device=y.device)
+    bias = torch.empty((), dtype=torch.float64, device=y.device) if want_bias else None
     _check(_lib.hsn_normalize_pooled(ctx, C.byref(dims), _ptr(y), yd, _ptr(yo), od, _ptr(bg_mask), float(count_floor),
-                                     int(clip), _ptr(p), ldp, _ptr(pb), ldb, _ptr(b), _ptr(ss), _ptr(pooled),
-                                     int(pooled_precision), _stream(dev)), ctx)
-    return p, pb, pooled, b, ss
+                                     int(clip), _ptr(p), ldp, _ptr(pb), ldb, _ptr(b), _ptr(ss), _ptr(bias),
+                                     _ptr(pooled), int(pooled_precision), _stream(dev)), ctx)
+    return (p, pb, pooled, b, ss, bias) if want_bias else (p, pb, pooled, b, ss)
 
 
 def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], n_k: int, V: torch.Tensor,
@@ -306,8 +314,10 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
                      check_every: int = 10, polish_rounds: int = 0, polish_algo: int = ALGO_ANLS,
                      polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0,
                      init: int = INIT_USER, mlp: Optional["Mlp"] = None, history_cap: int = 4096,
-                     mlp_pooled: Optional[torch.Tensor] = None) -> dict:
-    """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device)."""
+                     mlp_pooled: Optional[torch.Tensor] = None, bf16_bias: Optional[torch.Tensor] = None) -> dict:
+    """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device).  bf16_bias: the f64
+    device scalar -||p - p_bf16||^2 (hsn_normalize want_bias) for the stop test of the
+    polish rounds on p_bf16."""
     _need(V, "V", torch.float32, shape=(None, None))
     n_p, k = V.shape
     _need(D, "D", torch.float32, shape=(n_k, k), device=V.device)
@@ -320,17 +330,28 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
         raise ValueError(f"hsn: p and p_bf16 rows must hold n_k = {n_k} bins")
     dev = _dev(V)
     ctx = context(dev)
+    _opt(bf16_bias, "bf16_bias", torch.float64, shape=(), device=V.device)
     opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo,
                    polish_bf16_rounds, rel_obj_tol, f_ref, mlp.handle if mlp is not None else None,
-                   _ptr(mlp_pooled))
+                   _ptr(mlp_pooled), _ptr(bf16_bias))
     hist = (C.c_double * max(history_cap, 1))()
-    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0)
+    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0, 0)
     ldp = p.stride(0) if p is not None else 0
     ldb = p_bf16.stride(0) if p_bf16 is not None else 0
     _check(_lib.hsn_subspace_nmf(ctx, _ptr(p), ldp, _ptr(p_bf16), ldb, n_p, n_k, _ptr(V), _ptr(D), C.byref(opts),
                                  C.byref(stats), _stream(dev)), ctx)
-    return dict(iters=stats.iters, polish_done=stats.polish_done, objective=stats.objective, rel_obj=stats.rel_obj,
-                history=[hist[i] for i in range(stats.history_len)], ms=stats.ms)
+    return _stats(stats, hist)
+
+
+def _stats(s, hist) -> dict:
+    return dict(iters=s.iters, polish_done=s.polish_done, polish_bf16_done=s.polish_bf16_done, objective=s.objective,
+                rel_obj=s.rel_obj, history=[hist[i] for i in range(s.history_len)], ms=s.ms)
+
+
+def hsn_nmf_set_launch(anls_passes: int = 0, device: int = 0) -> None:
+    """Form of the ANLS rounds: 0 or 1 = one fused pass (default), 2 = N_V pass, row solves, N_D pass."""
+    ctx = context(device)
+    _check(_lib.hsn_nmf_set_launch(ctx, int(anls_passes)), ctx)
 
 
 def hsn_subspace_nmf_batched(problems, max_iter: int = 100, check_every: int = 10, polish_rounds: int = 0,
@@ -354,14 +375,13 @@ def hsn_subspace_nmf_batched(problems, max_iter: int = 100, check_every: int = 1
         arr[i] = NmfProblem(p.data_ptr(), p.stride(0), V.shape[0], n_k, V.shape[1], V.data_ptr(), D.data_ptr(),
                             float(f_ref or 0.0))
     opts = NmfOpts(1, ALGO_MU, PREC_FP32, INIT_USER, max_iter, check_every, polish_rounds, ALGO_ANLS, 0,
-                   rel_obj_tol, 0.0, None)
+                   rel_obj_tol, 0.0, None, None, None)
     hists = [(C.c_double * max(history_cap, 1))() for _ in range(n)]
     stats = (NmfStats * n)()
     for i in range(n):
-        stats[i] = NmfStats(0, 0, 0.0, 0.0, C.cast(hists[i], C.POINTER(C.c_double)), history_cap, 0, 0.0)
+        stats[i] = NmfStats(0, 0, 0.0, 0.0, C.cast(hists[i], C.POINTER(C.c_double)), history_cap, 0, 0.0, 0)
     _check(_lib.hsn_subspace_nmf_batched(ctx, n, arr, C.byref(opts), flags, stats, _stream(dev)), ctx)
-    return [dict(iters=s.iters, polish_done=s.polish_done, objective=s.objective, rel_obj=s.rel_obj,
-                 history=[hists[i][j] for j in range(s.history_len)], ms=s.ms) for i, s in enumerate(stats)]
+    return [_stats(s, hists[i]) for i, s in enumerate(stats)]
 
 
 def hsn_batched_plan_info(device: int = 0) -> str:
@@ -451,6 +471,11 @@ def hsn_fhr_step(y: torch.Tensor, yo: torch.Tensor, V: torch.Tensor, D: torch.Te
     ldp = round_up(n_k, 4)
     if "p" not in bufs:
         bufs["p"] = torch.empty((n_p, ldp), dtype=torch.float32, device=y.device)
+    ldb = round_up(n_k, 32)
+    uses_bf16 = polish_bf16_rounds > 0 or (precision == PREC_BF16 and max_iter > 0)
+    if uses_bf16 and "p_bf16" not in bufs:
+        bufs["p_bf16"] = torch.empty((n_p, ldb), dtype=torch.int16, device=y.device)
+    pb = bufs.get("p_bf16") if uses_bf16 else None
     learned = init == INIT_MLP
     if learned and mlp is not None and "pooled" not in bufs:
         bufs["pooled"] = torch.empty((n_p, MLP_IN), dtype=mlp.x_dtype, device=y.device)
@@ -462,19 +487,17 @@ def hsn_fhr_step(y: torch.Tensor, yo: torch.Tensor, V: torch.Tensor, D: torch.Te
         bufs["xh"] = torch.empty((ve - vb, be - bb), dtype=torch.float32, device=y.device)
     xh = bufs.get("xh") if vox is not None else None
     opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo, polish_bf16_rounds,
-                   rel_obj_tol, f_ref, mlp.handle if mlp is not None else None, None)
+                   rel_obj_tol, f_ref, mlp.handle if mlp is not None else None, None, None)
     hist = (C.c_double * max(history_cap, 1))()
-    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0)
+    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0, 0)
     keep = (C.c_double * n_v)(*[float(a) for a in angles]) if angles is not None else None
     yd = F32 if y.dtype == torch.float32 else U16
     od = F32 if yo.dtype == torch.float32 else U16
     _check(_lib.hsn_fhr_step(ctx, C.byref(dims), _ptr(y), yd, _ptr(yo), od, float(count_floor), _ptr(bufs["p"]), ldp,
-                             _ptr(bufs.get("pooled") if learned else None), _ptr(V), _ptr(D), C.byref(opts),
-                             C.byref(stats), keep, int(cgls_iters), _ptr(bufs["x"]), vb, ve, bb, be, _ptr(xh),
-                             be - bb, _stream(dev)), ctx)
-    st = dict(iters=stats.iters, polish_done=stats.polish_done, objective=stats.objective, rel_obj=stats.rel_obj,
-              history=[hist[i] for i in range(stats.history_len)], ms=stats.ms)
-    return bufs["x"], xh, st
+                             _ptr(pb), ldb if pb is not None else 0, _ptr(bufs.get("pooled") if learned else None),
+                             _ptr(V), _ptr(D), C.byref(opts), C.byref(stats), keep, int(cgls_iters), _ptr(bufs["x"]),
+                             vb, ve, bb, be, _ptr(xh), be - bb, _stream(dev)), ctx)
+    return bufs["x"], xh, _stats(stats, hist)
 
 
 def hsn_mbir(sino: torch.Tensor, sigma_v, sigma_x, p: float = 1.2, T: float = 1.0, n_outer: int = 10,

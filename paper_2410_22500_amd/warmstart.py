@@ -33,14 +33,16 @@ MID_GEOMETRY = dict(n_views=60, n_rows=16, n_cols=128, n_bins=1024, flux=2e3)
 MID_SEED = 2
 
 
-def scans(seed0: int, count: int, k: int = N_MAT, library_seed: int = LIBRARY_SEED, geometry=None):
+def scans(seed0: int, count: int, k: int = N_MAT, library_seed: int = LIBRARY_SEED, geometry=None,
+          counts: bool = True):
     """The first `count` scans from seeds seed0, seed0+1, ...  A seed whose
-    objects cannot be placed without overlap is skipped (deterministically)."""
+    objects cannot be placed without overlap is skipped (deterministically).
+    counts=False leaves the counts to be drawn on the GPU (scan_to_device)."""
     geometry = dict(geometry or TRAIN_GEOMETRY)
     s, got = seed0, 0
     while got < count:
         try:
-            scan = synth.make_scan(n_mat=k, seed=s, library_seed=library_seed, **geometry)
+            scan = synth.make_scan(n_mat=k, seed=s, library_seed=library_seed, counts=counts, **geometry)
         except RuntimeError:
             s += 1
             continue
@@ -49,11 +51,23 @@ def scans(seed0: int, count: int, k: int = N_MAT, library_seed: int = LIBRARY_SE
         got += 1
 
 
-def scan_to_device(scan):
-    y = torch.from_numpy(scan.y.view(np.int16)).cuda()
-    yo = torch.from_numpy(scan.yo.view(np.int16)).cuda()
+def scan_to_device(scan, seed: int = 0):
+    """Normalised p (float32) and its bfloat16 copy on the GPU; a scan made
+    without counts gets them drawn on the GPU from `seed`."""
+    if scan.y is None:
+        y, yo = synth.device_counts(scan, seed=seed)
+    else:
+        y = torch.from_numpy(scan.y.view(np.int16)).cuda()
+        yo = torch.from_numpy(scan.yo.view(np.int16)).cuda()
     p, pb, _, _ = hsn.hsn_normalize(y, yo, want_bf16=True)
     return p, pb
+
+
+def workload_geometry(n_bins: int, flux: float):
+    """Training geometry for a workload: the tiny workload's phantoms and
+    views (90 views, one 64-column slice) at the workload's own spectral
+    sampling and flux, so that the pooled spectra carry its noise level."""
+    return dict(TRAIN_GEOMETRY, n_bins=int(n_bins), flux=float(flux))
 
 
 def plain_decomposition(p, pb, n_k: int, k: int, mu_iters: int = 200, polish: int = 60,
@@ -85,13 +99,15 @@ def make_training_set(n_scans: int, seed0: int = 40, k: int = N_MAT, library_see
     T = torch.empty((N, k), dtype=torch.float32, device="cuda")
     P_all = Pb_all = None
     t_gen = t_dec = 0.0
-    it = scans(seed0, n_scans, k, library_seed, geometry)
+    # counts of wide spectra are drawn on the GPU (seeded), narrow ones on the host
+    host_counts = n_k <= 256
+    it = scans(seed0, n_scans, k, library_seed, geometry, counts=host_counts)
     lib = None
     for i in range(n_scans):
         t0 = time.perf_counter()
-        _, scan = next(it)
+        s, scan = next(it)
         t1 = time.perf_counter()
-        p, pb = scan_to_device(scan)
+        p, pb = scan_to_device(scan, seed=7919 * s + 1)
         if lib is None:
             lib = torch.from_numpy(scan.mu.astype(np.float32)).cuda()
         rows = slice(i * n_p, (i + 1) * n_p)
@@ -164,14 +180,15 @@ def time_to_tol(p, pb, n_k: int, k: int, f_ref: float, tol: float = 1e-4, mlp=No
 
 
 def compare_held_out(mlp, n_scans: int, seed0: int = HELD_OUT_SEED0, k: int = N_MAT, geometry=None,
-                     tol: float = 1e-4):
+                     tol: float = 1e-4, library_seed: int = LIBRARY_SEED):
     """Warm versus cold on held-out scans: passes over p and device ms to
-    rel obj <= tol (f* from reference_objective)."""
+    rel obj <= tol (f* from reference_objective).  library_seed other than
+    the training library's gives scans of materials the network never saw."""
     geometry = dict(geometry or TRAIN_GEOMETRY)
     n_k = geometry["n_bins"]
     rows = []
-    for s, scan in scans(seed0, n_scans, k, LIBRARY_SEED, geometry):
-        p, pb = scan_to_device(scan)
+    for s, scan in scans(seed0, n_scans, k, library_seed, geometry, counts=n_k <= 256):
+        p, pb = scan_to_device(scan, seed=7919 * s + 1)
         f_ref = reference_objective(p, pb, n_k, k, mlp)
         cold = time_to_tol(p, pb, n_k, k, f_ref, tol)
         warm = time_to_tol(p, pb, n_k, k, f_ref, tol, mlp=mlp)

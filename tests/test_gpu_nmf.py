@@ -77,8 +77,13 @@ def test_mu_200_steps_tiny(hsn):
     assert np.all(np.diff(h) <= 1e-6 * h[0])
 
 
-@pytest.mark.parametrize("shape,k", [((5760, 256), 3), ((503, 1100), 6)])
-def test_anls_round(hsn, shape, k):
+@pytest.mark.parametrize("passes", [1, 2])
+@pytest.mark.parametrize("shape,k", [((5760, 256), 3), ((503, 1100), 6), ((95, 2048), 5), ((1001, 37), 7),
+                                     ((333, 64), 8), ((17, 8), 1)])
+def test_anls_round(hsn, shape, k, passes):
+    # One fused pass (the V rows solved inside the pass by support
+    # enumeration) and the two-pass form (N_V pass, Lawson-Hanson row
+    # solves, N_D pass) against the oracle's exact block minimisation.
     n_p, n_k = shape
     g = np.random.Generator(np.random.PCG64(k))
     if shape == (5760, 256):
@@ -88,14 +93,61 @@ def test_anls_round(hsn, shape, k):
     p = _as32(p)
     V0, D0 = synth.random_factors(n_p, n_k, k, 9)
     V0, D0 = _as32(V0), _as32(D0)
-    show("anls round", n_p=n_p, n_k=n_k, k=k)
+    show("anls round", n_p=n_p, n_k=n_k, k=k, passes=passes)
     V1, D1, fh, ff = onmf.anls_round(p, V0, D0)
     V = to_dev(V0, torch.float32)
     D = to_dev(D0, torch.float32)
-    st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, algo=hsn.ALGO_ANLS, max_iter=1, check_every=1)
-    assert rel_fro(V.cpu().numpy(), V1) <= 1e-5
-    assert rel_fro(D.cpu().numpy(), D1) <= 1e-5
+    hsn.hsn_nmf_set_launch(passes)
+    try:
+        st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, algo=hsn.ALGO_ANLS, max_iter=1, check_every=1)
+    finally:
+        hsn.hsn_nmf_set_launch(0)
+    # The exact solves map float32 rounding of N_V = P D and N_D = P^T V
+    # (2^-24 relative) through G_D = D^T D and G_V = V^T V: bounds cond(G) 2^-24.
+    tol_v = max(1e-5, np.linalg.cond(D0.T @ D0) * 2.0 ** -24)
+    tol_d = max(1e-5, np.linalg.cond(V1.T @ V1) * 2.0 ** -24)
+    show("  err", V=rel_fro(V.cpu().numpy(), V1), D=rel_fro(D.cpu().numpy(), D1), tol_v=tol_v, tol_d=tol_d)
+    assert rel_fro(V.cpu().numpy(), V1) <= tol_v
+    assert rel_fro(D.cpu().numpy(), D1) <= tol_d
     assert abs(st["history"][0] - fh) <= 1e-5 * fh
+
+
+def test_anls_rounds_with_active_constraints(hsn):
+    # Rows whose NNLS solutions sit on faces of the orthant (many zeros):
+    # p built from sparse non-negative coefficients plus noise, three fused
+    # rounds against the oracle, and the fused and two-pass forms agree.
+    g = np.random.Generator(np.random.PCG64(77))
+    n_p, n_k, k = 2000, 300, 5
+    C = g.uniform(0, 1, (n_p, k)) * (g.uniform(0, 1, (n_p, k)) < 0.4)
+    p = _as32(np.maximum(C @ g.uniform(0, 1, (k, n_k)) + 0.05 * g.standard_normal((n_p, n_k)), 0))
+    V0, D0 = synth.random_factors(n_p, n_k, k, 78)
+    V0, D0 = _as32(V0), _as32(D0)
+    Vr, Dr = V0, D0
+    fhs = []
+    for _ in range(3):
+        Vr, Dr, fh, _ = onmf.anls_round(p, Vr, Dr)
+        fhs.append(fh)
+    assert np.mean(Vr == 0) > 0.01  # the case exercises active constraints
+    outs = []
+    for passes in (1, 2):
+        V = to_dev(V0, torch.float32)
+        D = to_dev(D0, torch.float32)
+        hsn.hsn_nmf_set_launch(passes)
+        try:
+            st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, algo=hsn.ALGO_ANLS, max_iter=3, check_every=1)
+        finally:
+            hsn.hsn_nmf_set_launch(0)
+        show("anls active", passes=passes, V=rel_fro(V.cpu().numpy(), Vr), D=rel_fro(D.cpu().numpy(), Dr))
+        np.testing.assert_allclose(st["history"], fhs, rtol=1e-5)
+        assert rel_fro(V.cpu().numpy(), Vr) <= 1e-5 and rel_fro(D.cpu().numpy(), Dr) <= 1e-5
+        outs.append(V.cpu().numpy())
+    assert rel_fro(outs[0], outs[1]) <= 1e-6
+
+
+def test_nmf_launch_knob_rejects_bad_values(hsn):
+    for bad in (-1, 3):
+        with pytest.raises(hsn.HsnError):
+            hsn.hsn_nmf_set_launch(bad)
 
 
 @pytest.mark.parametrize("shape,k", [((5760, 256), 3), ((1001, 1500), 5), ((333, 64), 8)])
@@ -183,3 +235,42 @@ def test_bad_arguments_raise(hsn):
     with pytest.raises(hsn.HsnError) as e:
         hsn.hsn_subspace_nmf(torch.ones((10, 20), device="cuda"), None, 20, V9, D9, max_iter=1)
     assert e.value.status == hsn.ERR_SHAPE
+
+
+@pytest.mark.parametrize("algo", ["mu", "anls"])
+def test_nan_in_p_stops_with_numeric_error(hsn, algo):
+    # A NaN planted in p (host side, ordinary data): the first objective is
+    # NaN, the run stops there and the call reports HSN_ERR_NUMERIC.
+    g = np.random.Generator(np.random.PCG64(90))
+    p = _as32(g.uniform(0, 1, (300, 40)))
+    p[123, 7] = np.nan
+    V0, D0 = synth.random_factors(300, 40, 3, 91)
+    V = to_dev(_as32(V0), torch.float32)
+    D = to_dev(_as32(D0), torch.float32)
+    code = {"mu": hsn.ALGO_MU, "anls": hsn.ALGO_ANLS}[algo]
+    with pytest.raises(hsn.HsnError) as e:
+        hsn.hsn_subspace_nmf(_p_dev(p), None, 40, V, D, algo=code, max_iter=50, check_every=1)
+    assert e.value.status == hsn.ERR_NUMERIC
+    assert "step 0" in str(e.value)
+
+
+def test_zero_column_in_d_stays_finite(hsn):
+    # A zero column of D (a material absent from the start): its Gram is
+    # singular; MU keeps the column at zero, ANLS never enters a support with
+    # a singular principal submatrix.  Results stay finite and match the oracle.
+    g = np.random.Generator(np.random.PCG64(92))
+    n_p, n_k, k = 400, 64, 4
+    p = _as32(np.maximum(g.uniform(0, 1, (n_p, k)) @ g.uniform(0, 1, (k, n_k)) + 0.05 * g.standard_normal((n_p, n_k)), 0))
+    V0, D0 = synth.random_factors(n_p, n_k, k, 93)
+    V0, D0 = _as32(V0), _as32(D0)
+    D0[:, 2] = 0.0
+    for algo, step in ((hsn.ALGO_MU, onmf.mu_step), (hsn.ALGO_ANLS, onmf.anls_round)):
+        V1, D1, fh, _ = step(p, V0, D0)
+        V = to_dev(V0, torch.float32)
+        D = to_dev(D0, torch.float32)
+        st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, algo=algo, max_iter=1, check_every=1)
+        Vg, Dg = V.cpu().numpy(), D.cpu().numpy()
+        show("zero column", algo=algo, V=rel_fro(Vg, V1), D=rel_fro(Dg, D1))
+        assert np.all(np.isfinite(Vg)) and np.all(np.isfinite(Dg))
+        assert rel_fro(Vg, V1) <= 1e-5 and rel_fro(Dg, D1) <= 1e-5
+        assert abs(st["history"][0] - fh) <= 1e-5 * fh

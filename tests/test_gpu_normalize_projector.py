@@ -83,10 +83,14 @@ def test_normalize_fast_kernel_matches_general(hsn, n_k, mask):
     if bg is not None:
         bg[0, 0] = 1
     show("normalize fast vs general", n_k=n_k, mask=mask)
-    p0, _, pooled0, b0, ss0 = hsn.hsn_normalize_pooled(y, yo, hsn.PREC_BF16, bg_mask=bg, want_offset=mask)
-    p1, _, pooled1, b1, ss1 = hsn.hsn_normalize_pooled(y, yo_odd, hsn.PREC_BF16, bg_mask=bg, want_offset=mask)
+    p0, pb0, pooled0, b0, ss0, e0 = hsn.hsn_normalize_pooled(y, yo, hsn.PREC_BF16, bg_mask=bg, want_offset=mask,
+                                                              want_bf16=True, want_bias=True)
+    p1, pb1, pooled1, b1, ss1, e1 = hsn.hsn_normalize_pooled(y, yo_odd, hsn.PREC_BF16, bg_mask=bg, want_offset=mask,
+                                                              want_bf16=True, want_bias=True)
     assert torch.equal(p0[:, :n_k], p1[:, :n_k]) and torch.equal(pooled0, pooled1)
-    assert float(ss0) == float(ss1)
+    assert torch.equal(pb0, pb1) and pb0.shape[1] >= n_k   # the padded bfloat16 copy, pad columns zero
+    assert not torch.any(pb0[:, n_k:])
+    assert float(ss0) == float(ss1) and float(e0) == float(e1)
     if mask:
         assert torch.equal(b0, b1)
 
