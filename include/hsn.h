@@ -83,10 +83,11 @@ enum { HSN_U16 = 0, HSN_F32 = 1 };
  *   sumsq   optional device double: sum of p^2 over the float32 p values.
  *   bf16_bias optional device double (requires p_bf16): -||p - p_bf16||^2.
  *           For any V, D: ||p - V D^T||^2 = ||p_bf16 - V D^T||^2
- *           - ||p - p_bf16||^2 + 2 <p - p_bf16, p - V D^T>, and the last term
- *           (rounding errors against the residual) has zero mean, so an
- *           objective measured on p_bf16 plus this bias estimates the
- *           objective on p; hsn_nmf_opts.bf16_bias takes it.
+ *           - ||p - p_bf16||^2 + 2 <p - p_bf16, p - V D^T>, and the last
+ *           term is small when the rounding error is uncorrelated with the
+ *           float32 residual, so an objective measured on p_bf16 plus this
+ *           bias estimates the objective on p; hsn_nmf_opts.bf16_bias takes
+ *           it (the NMF calibrates what is left against a float32 round).
  */
 hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *dims,
                          const void *y, int y_dtype, const void *y_open, int y_open_dtype,
@@ -124,10 +125,12 @@ enum { HSN_INIT_USER = 0,  /* V and D hold the start on entry                   
        HSN_INIT_NNDSVDA = 1,  /* NNDSVD with zeros filled by mean(p) (Boutsidis &
                                  Gallopoulos; the paper's initialisation); needs p,
                                  uses p_bf16 for the Gram P^T P when given      */
-       HSN_INIT_MLP = 2 };    /* learned warm start: V0 = opts.mlp(pooled p_bf16),
+       HSN_INIT_MLP = 2,      /* learned warm start: V0 = opts.mlp(pooled p_bf16),
                                  D0 = argmin_{D>=0} ||p - V0 D^T|| row by row, exact
                                  zeros of D0 set to 1e-6 mean(D0); needs p, and
                                  p_bf16 unless opts.mlp_pooled is given */
+       HSN_INIT_NNDSVD = 3 }; /* plain NNDSVD (the paper's start with its exact zeros
+                                 kept), for HALS and ANLS; MU keeps zero entries zero */
 
 typedef struct hsn_mlp hsn_mlp;
 
@@ -177,9 +180,12 @@ typedef struct {
  * float64 Cholesky factors).  The stop test fires on a step whose objective
  * meets (f - f_ref)/f_ref <= rel_obj_tol.  On a step over p_bf16 (a BF16
  * bulk iteration or one of the first polish_bf16_rounds polish rounds) f is
- * the bfloat16 objective plus *bf16_bias; when float32 polish rounds follow,
- * such a stop only ends the steps on p_bf16 and the float32 rounds decide
- * the stop on the float32 objective (stats count only the steps run).
+ * the bfloat16 objective plus *bf16_bias plus a calibration (0 at first).
+ * When float32 polish rounds follow, such a stop is confirmed by one float32
+ * round; if that round misses the tolerance, the calibration is set to the
+ * float32 objective minus the last bfloat16 estimate and the bfloat16 rounds
+ * resume (at most twice; then the float32 rounds run).  The float32 rounds
+ * decide the stop on the float32 objective (stats count only the steps run).
  *   p      [N_p][ldp] float32, ldp % 4 == 0, 16-byte aligned (needed for FP32
  *          steps and for the NNDSVDa and learned starts; may be NULL otherwise)
  *   p_bf16 [N_p][ldb] bfloat16 with zero padding, ldb % 32 == 0, ldb <= 2048

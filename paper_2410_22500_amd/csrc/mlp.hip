@@ -35,8 +35,12 @@ void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st
                      float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
                      const double *ginv);
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
-                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img,
+                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, int bf16 = 0,
                      const double *bias = nullptr);
+bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
+                      int64_t n_p, int n_k, float *V, const double *GD, const double *chol, const uint16_t *img,
+                      float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
+                      const double *ginv);
 
 namespace {
 
@@ -917,20 +921,31 @@ int mlp_k(const hsn_mlp *m) { return m->k; }
 int mlp_device(const hsn_mlp *m) { return m->device; }
 
 // The learned start of the NMF: V0 from the network, then D0 by exact
-// row-wise NNLS against V0 (one N_D pass over the float32 p and the NNLS row
-// rule), exact zeros of D0 set to 1e-6 mean(D0) so that multiplicative
-// updates can move them.  Leaves the control block open for the run.
+// row-wise NNLS against V0 (one N_D pass and the NNLS row rule), exact zeros
+// of D0 set to 1e-6 mean(D0) so that multiplicative updates can move them.
+// The N_D pass reads the float32 p, or the bfloat16 copy when wg_bf16 > 0
+// (its grid; the decomposition's first rounds then run on that copy too).
+// Leaves the control block open for the run.
 hsn_status mlp_nmf_start(hsn_ctx *ctx, hipStream_t st, const hsn_mlp *m, const float *p, int64_t ldp,
                          const uint16_t *pb, int64_t ldb, int64_t n_p, int n_k, float *V, float *D, void *xbuf,
-                         const void *pooled, const NmfWork &w, int n_wg) {
+                         const void *pooled, const NmfWork &w, int n_wg, int wg_bf16) {
   hsn_status rc = mlp_infer_into(ctx, m, pb, ldb, n_p, n_k, V, xbuf, pooled, st);
   if (rc != HSN_OK) return rc;
   const int K = m->k;
   ctrl_reset_kernel<<<1, 1, 0, st>>>(w.ctrl);
-  prof_begin(ctx, HSN_KERN_NMF_PASS, st);
-  launch_pass_f32(K, kModeND, false, n_k > 1024 ? 2 : 1, n_wg, st, p, ldp, n_p, n_k, V, nullptr, D, w.gd, w.chol,
-                  w.part_nd, w.part_gv, w.part_obj, w.ctrl, 0, nullptr);
-  prof_end(ctx, HSN_KERN_NMF_PASS, st);
+  if (wg_bf16 > 0) {
+    prof_begin(ctx, HSN_KERN_NMF_PASS_BF16, st);
+    const bool ok = launch_pass_bf16(K, kModeND, false, wg_bf16, st, pb, ldb, n_p, n_k, V, w.gd, w.chol, w.img,
+                                     w.part_nd, w.part_gv, w.part_obj, w.ctrl, 0, nullptr);
+    prof_end(ctx, HSN_KERN_NMF_PASS_BF16, st);
+    if (!ok) return fail(ctx, HSN_ERR_UNSUPPORTED, "learned start: bf16 N_D pass unsupported for this shape");
+    n_wg = wg_bf16;
+  } else {
+    prof_begin(ctx, HSN_KERN_NMF_PASS, st);
+    launch_pass_f32(K, kModeND, false, n_k > 1024 ? 2 : 1, n_wg, st, p, ldp, n_p, n_k, V, nullptr, D, w.gd, w.chol,
+                    w.part_nd, w.part_gv, w.part_obj, w.ctrl, 0, nullptr);
+    prof_end(ctx, HSN_KERN_NMF_PASS, st);
+  }
   launch_update_d(K, kModeNV, st, D, w, n_wg, n_k, 0, false, 0.0, 0.0, false, 0);
   fill_zeros_kernel<<<1, 256, 0, st>>>(D, int64_t(n_k) * K, 1e-6f);
   HSN_LAUNCHED(ctx);

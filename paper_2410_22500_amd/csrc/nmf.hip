@@ -15,8 +15,10 @@
 // The float32 pass reads p once per iteration or fused ANLS round; the
 // bfloat16 steps run the same sequence with the MFMA pass over the bfloat16
 // copy of p.  Polish rounds on the bfloat16 p end when the objective, plus
-// the bias -||p - p_bf16||^2 when given, meets the tolerance; the float32
-// rounds that follow decide the stop on the float32 objective.
+// the bias -||p - p_bf16||^2 when given and a calibration, meets the
+// tolerance; one float32 round confirms such a stop or calibrates the
+// estimate (the bfloat16 rounds then resume), and the float32 rounds decide
+// the stop on the float32 objective.
 #include "nmf_common.hpp"
 
 #include <algorithm>
@@ -40,8 +42,10 @@ int64_t bf16_image_ldb(int64_t ldb);
 void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWork &w, int want_chol, int64_t ldb);
 int update_d_blocks(int n_k);
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
-                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, const double *bias);
+                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, int bf16,
+                     const double *bias);
 void launch_nmf_resume(hipStream_t st, NmfCtrl *ctrl);
+void launch_nmf_calibrate(hipStream_t st, NmfCtrl *ctrl, const double *hist, const double *bias);
 void launch_nnls_rows(int K, hipStream_t st, const NmfWork &w, float *V, int64_t n_p, int n_blocks, int iter);
 size_t nndsvd_ws_bytes(int64_t n_p, int n_k, int K, int n_split);
 size_t mlp_pool_bytes(const hsn_mlp *m, int64_t n_p);
@@ -49,13 +53,14 @@ int mlp_k(const hsn_mlp *m);
 int mlp_device(const hsn_mlp *m);
 hsn_status mlp_nmf_start(hsn_ctx *ctx, hipStream_t st, const hsn_mlp *m, const float *p, int64_t ldp,
                          const uint16_t *pb, int64_t ldb, int64_t n_p, int n_k, float *V, float *D, void *xbuf,
-                         const void *pooled, const NmfWork &w, int n_wg);
+                         const void *pooled, const NmfWork &w, int n_wg, int wg_bf16);
 hsn_status nndsvd_init(hsn_ctx *ctx, hipStream_t st, const float *p, int64_t ldp, const uint16_t *pb, int64_t ldb,
-                       int64_t n_p, int n_k, int K, float *V, float *D, void *ws, int n_split);
+                       int64_t n_p, int n_k, int K, float *V, float *D, void *ws, int n_split, bool fill);
 
 namespace {
 
 constexpr int kBf16PolishCheck = 4;
+constexpr int kBf16Calibrations = 2;
 
 // One step of the schedule, in issue order.
 struct Step {
@@ -123,7 +128,7 @@ hsn_status queue_step(Run &R, const Step &s, int iter, bool next_exact, const fl
     }
   }
   launch_update_d(R.K, s.rule == kModeANLS ? kModeNV : s.rule, R.st, D, R.w, n_wg, R.n_k, iter, obj, R.f_ref,
-                  R.tol, next_exact, R.w.img ? bf16_image_ldb(ldb) : 0, s.bf16 ? R.bias : nullptr);
+                  R.tol, next_exact, R.w.img ? bf16_image_ldb(ldb) : 0, s.bf16 ? 1 : 0, s.bf16 ? R.bias : nullptr);
   HSN_LAUNCHED(R.ctx);
   return HSN_OK;
 }
@@ -145,8 +150,10 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: polish_algo must be HSN_ALGO_ANLS or HSN_ALGO_HALS");
   if (o->precision != HSN_PREC_FP32 && o->precision != HSN_PREC_BF16)
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: bad precision");
-  if (o->init != HSN_INIT_USER && o->init != HSN_INIT_NNDSVDA && o->init != HSN_INIT_MLP)
+  if (o->init != HSN_INIT_USER && o->init != HSN_INIT_NNDSVDA && o->init != HSN_INIT_MLP &&
+      o->init != HSN_INIT_NNDSVD)
     return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: bad init");
+  const bool nndsvd = o->init == HSN_INIT_NNDSVDA || o->init == HSN_INIT_NNDSVD;
   if (o->init == HSN_INIT_MLP) {
     if (!o->mlp) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: HSN_INIT_MLP needs opts.mlp");
     if (mlp_k(o->mlp) != o->k) return fail(ctx, HSN_ERR_SHAPE, "nmf: the network's k differs from opts.k");
@@ -196,7 +203,7 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   // share the workspace with the decomposition's.
   int n_split = 1;
   size_t need_init = 0;
-  if (o->init == HSN_INIT_NNDSVDA) {
+  if (nndsvd) {
     const int64_t n_tb = (n_k + 127) / 128;
     n_split = int(std::max<int64_t>(1, std::min<int64_t>(1024 / (n_tb * (n_tb + 1) / 2), n_p / 32)));
     need_init = nndsvd_ws_bytes(n_p, int(n_k), K, n_split);
@@ -257,12 +264,12 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   const int first_f32_polish = (bf16_hi > bf16_lo && o->polish_rounds > pol_bf16) ? bf16_hi : -1;
 
   if (stats) HSN_HIP(ctx, hipEventRecord(ctx->ev0, st));
-  if (o->init == HSN_INIT_NNDSVDA &&
-      (rc = nndsvd_init(ctx, st, p, ldp, p_bf16, ldb, n_p, int(n_k), K, V, D, ctx->ws, n_split)) != HSN_OK)
+  if (nndsvd && (rc = nndsvd_init(ctx, st, p, ldp, p_bf16, ldb, n_p, int(n_k), K, V, D, ctx->ws, n_split,
+                                 o->init == HSN_INIT_NNDSVDA)) != HSN_OK)
     return rc;
   if (o->init == HSN_INIT_MLP &&
       (rc = mlp_nmf_start(ctx, st, o->mlp, p, ldp, p_bf16, ldb, n_p, int(n_k), V, D, pool_buf, o->mlp_pooled, R.w,
-                          wg_f32)) != HSN_OK)
+                          wg_f32, (!steps.empty() && steps[0].bf16) ? wg_bf16 : 0)) != HSN_OK)
     return rc;
   launch_nmf_init(K, st, D, int(n_k), R.w, !steps.empty() && steps[0].rule == kModeANLS ? 1 : 0,
                   any_bf16 ? bf16_image_ldb(ldb) : 0);
@@ -286,47 +293,80 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     hh = reinterpret_cast<double *>(static_cast<char *>(ctx->host_stage) + sizeof(NmfCtrl));
   }
   bool staged = false;
-  int bf16_phase_end = -1;  // step index where a stop ended the bfloat16 polish rounds
+  // Host counts of the steps that ran: every step queued since the last
+  // read-back whose index is below the stop index then read.
+  std::vector<std::pair<int, int>> pending;  // queued index ranges [a, b)
+  int ran_bulk = 0, ran_bf16 = 0, ran_f32 = 0;
+  auto settle = [&](int stop_at) {
+    for (const auto &r : pending)
+      for (int i = r.first; i < std::min(r.second, stop_at); ++i) {
+        if (i < o->max_iter) ++ran_bulk;
+        else if (steps[i].bf16) ++ran_bf16;
+        else ++ran_f32;
+      }
+    pending.clear();
+  };
+  auto read_back = [&]() -> hsn_status {
+    if (stats) {
+      HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
+      HSN_HIP(ctx, hipMemcpyAsync(hcp, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
+      HSN_HIP(ctx, hipMemcpyAsync(hh, R.w.hist, sizeof(double) * hist_cap, hipMemcpyDeviceToHost, st));
+      HSN_HIP(ctx, hipStreamSynchronize(st));
+      hc = *hcp;
+      staged = true;
+    } else {
+      HSN_HIP(ctx, hipMemcpyAsync(&hc, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
+      HSN_HIP(ctx, hipStreamSynchronize(st));
+    }
+    settle(hc.stop_at);
+    return HSN_OK;
+  };
+  // A stop inside the bfloat16 steps [bf16_lo, bf16_hi) is confirmed by one
+  // float32 round (the next unused one, f32_next) followed by a calibration
+  // of the bfloat16 estimate against it; when that round misses the
+  // tolerance, the bfloat16 polish rounds resume (up to kBf16Calibrations
+  // times; a stop inside a bfloat16 bulk goes on with the float32 rounds),
+  // then the float32 rounds run to the end.
+  int f32_next = first_f32_polish;
+  int cal_left = kBf16Calibrations;
   while (issued < int(steps.size())) {
     int end = issued, n_obj = 0;
     while (end < int(steps.size()) && n_obj < chunk_obj) {
       if (steps[end].obj) ++n_obj;
       ++end;
+      if (end == bf16_hi && f32_next > bf16_hi) break;  // the float32 rounds continue at f32_next
     }
     chunk_obj = std::min(2 * chunk_obj, 32);
     for (int i = issued; i < end; ++i) {
       const bool next_exact = (i + 1 < int(steps.size())) && steps[i + 1].rule == kModeANLS;
       if ((rc = queue_step(R, steps[i], i, next_exact, p, ldp, p_bf16, ldb, V, D)) != HSN_OK) return rc;
     }
+    pending.push_back({issued, end});
     issued = end;
+    if (issued == bf16_hi && f32_next > bf16_hi) issued = f32_next;
     staged = false;
-    const bool phase_pending = first_f32_polish >= 0 && bf16_phase_end < 0;
-    if (stop_test && (issued < int(steps.size()) || phase_pending)) {
-      if (stats) {
-        HSN_HIP(ctx, hipEventRecord(ctx->ev1, st));
-        HSN_HIP(ctx, hipMemcpyAsync(hcp, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
-        HSN_HIP(ctx, hipMemcpyAsync(hh, R.w.hist, sizeof(double) * hist_cap, hipMemcpyDeviceToHost, st));
-        HSN_HIP(ctx, hipStreamSynchronize(st));
-        hc = *hcp;
-        staged = true;
-      } else {
-        HSN_HIP(ctx, hipMemcpyAsync(&hc, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
-        HSN_HIP(ctx, hipStreamSynchronize(st));
-      }
-      if (hc.stop_at <= issued) {
-        if (!hc.numeric && phase_pending && hc.stop_at > bf16_lo && hc.stop_at <= first_f32_polish) {
-          // the bfloat16 rounds met the (bias-corrected) tolerance: the float32
-          // rounds take over, re-queued from the first one
-          bf16_phase_end = hc.stop_at;
-          launch_nmf_resume(st, R.w.ctrl);
-          HSN_LAUNCHED(ctx);
-          issued = first_f32_polish;
-          chunk_obj = 1;
-          hc.stop_at = INT32_MAX;
-          continue;
-        }
-        break;
-      }
+    const bool confirm_possible = f32_next >= 0 && f32_next < int(steps.size());
+    if (!stop_test || (issued >= int(steps.size()) && !confirm_possible)) continue;
+    if ((rc = read_back()) != HSN_OK) return rc;
+    if (hc.stop_at == INT32_MAX) continue;
+    const int s = hc.stop_at - 1;  // the step whose objective met the tolerance
+    if (hc.numeric || !(s >= bf16_lo && s < bf16_hi) || !confirm_possible) break;
+    // confirm on p: one float32 round, then the calibration of the estimate
+    launch_nmf_resume(st, R.w.ctrl);
+    const int f = f32_next++;
+    const bool next_exact = (f + 1 < int(steps.size())) && steps[f + 1].rule == kModeANLS;
+    if ((rc = queue_step(R, steps[f], f, next_exact, p, ldp, p_bf16, ldb, V, D)) != HSN_OK) return rc;
+    launch_nmf_calibrate(st, R.w.ctrl, R.w.hist, R.bias);
+    HSN_LAUNCHED(ctx);
+    pending.push_back({f, f + 1});
+    if ((rc = read_back()) != HSN_OK) return rc;
+    if (hc.stop_at != INT32_MAX) break;  // met on p (or numeric)
+    chunk_obj = 1;
+    if (cal_left > 0 && s >= o->max_iter && s + 1 < bf16_hi) {
+      --cal_left;
+      issued = s + 1;  // the bfloat16 rounds resume with the calibrated estimate
+    } else {
+      issued = f32_next;
     }
   }
   if (stats) {
@@ -337,21 +377,15 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
       HSN_HIP(ctx, hipMemcpyAsync(hcp, R.w.ctrl, sizeof(NmfCtrl), hipMemcpyDeviceToHost, st));
       HSN_HIP(ctx, hipMemcpyAsync(hh, R.w.hist, sizeof(double) * hist_cap, hipMemcpyDeviceToHost, st));
       HSN_HIP(ctx, hipStreamSynchronize(st));
+      hc = *hcp;
     }
-    hc = *hcp;
+    settle(hc.stop_at);
     float ms = 0.f;
     HSN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    const int done = std::min(hc.stop_at, issued);
     stats->ms = ms;
-    stats->iters = std::min(done, o->max_iter);
-    if (bf16_phase_end >= 0) {
-      stats->iters = std::min(bf16_phase_end, o->max_iter);
-      stats->polish_bf16_done = std::max(0, bf16_phase_end - o->max_iter);
-      stats->polish_done = stats->polish_bf16_done + std::max(0, done - first_f32_polish);
-    } else {
-      stats->polish_done = std::max(0, done - o->max_iter);
-      stats->polish_bf16_done = std::min(stats->polish_done, pol_bf16);
-    }
+    stats->iters = ran_bulk;
+    stats->polish_bf16_done = ran_bf16;
+    stats->polish_done = ran_bf16 + ran_f32;
     stats->history_len = 0;
     double last = NAN;
     const int len = std::min(hc.hist_len, hist_cap);

@@ -12,6 +12,7 @@
 //   3. the per-wave N_V partials are summed in LDS (fixed order) and the row
 //      rule updates V in float64 registers: Lee-Seung MU, HALS, or (ANLS) the
 //      exact NNLS of each row, 32 lanes per row enumerating the supports;
+//      (N_D alone: steps 2 and 3 are skipped and the given V is used);
 //   4. N_D += P^T V_new on MFMA 16x16x16: A = P^T (16 bins x 16 rows, read
 //      transposed from the LDS tile), B = [V_hi | V_lo]; the accumulators
 //      stay in registers for the whole pass;
@@ -113,7 +114,8 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
   const int s0 = w * NW;
   constexpr int cpr = 4 * NW;   // 16-byte chunks per row in this wave's bins
 
-  for (int i = t; i < nks * 64; i += kBThreads) db1L[i] = db1g[i];
+  if constexpr (MODE != kModeND)  // N_D alone needs no operand image of D
+    for (int i = t; i < nks * 64; i += kBThreads) db1L[i] = db1g[i];
   for (int i = t; i < 16 * 16; i += kBThreads) vsp[i] = 0;
   if (t < K * K) gd_s[t] = GD[t];
   float *hsum = reinterpret_cast<float *>(smem + L.hsum);  // [16][8]
@@ -181,7 +183,8 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
     if (tile + NBUF * G < n_tiles) load_tile(pr, vv, (tile + NBUF * G) * kBRows);
     __syncthreads();
 
-    // 2. N_V partial over this wave's bins
+    // 2. N_V partial over this wave's bins (not for N_D alone)
+    if constexpr (MODE != kModeND) {
     f32x4 acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < kKSW; ++i) {
@@ -198,9 +201,19 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
 #pragma unroll
     for (int i = 0; i < 4; ++i) red[(w * 16 + 4 * (lane >> 4) + i) * 16 + (lane & 15)] = acc1[i];
     __syncthreads();
+    }
 
     // 3. row rule
-    if (MODE == kModeANLS) {
+    if (MODE == kModeND) {
+      // N_D = P^T V for the given V: the tile's V as loaded
+      if (t < kBRows * K) {
+        const int r = t / K, j = t - (t / K) * K;
+        const float vn = (row0 + r < n_p) ? vold[t] : 0.0f;
+        vnw[r * 8 + j] = vn;
+        vsp[r * 16 + j] = bf_hi(vn);
+        vsp[r * 16 + 8 + j] = bf_lo(vn);
+      }
+    } else if (MODE == kModeANLS) {
       // exact NNLS of the 16 rows: h into LDS, then 32 lanes per row
       if (t < kBRows * K) {
         const int r = t / K, j = t - (t / K) * K;
@@ -384,6 +397,7 @@ static bool launch_bf16_kw(int mode, bool obj, int n_wg, hipStream_t st, const u
   launch_bf16_inst<K, M_, O_, NW, NBUF>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd, part_gv, part_obj, \
                                         ctrl, iter, ginv)
   if (mode == kModeANLS) return obj ? HSN_INST(kModeANLS, true) : HSN_INST(kModeANLS, false);
+  if (mode == kModeND) return HSN_INST(kModeND, false);
   if (mode == kModeMU) return obj ? HSN_INST(kModeMU, true) : HSN_INST(kModeMU, false);
   if (mode == kModeHALS) return obj ? HSN_INST(kModeHALS, true) : HSN_INST(kModeHALS, false);
   return false;
@@ -418,7 +432,7 @@ bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const
                       float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
                       const double *ginv) {
   if (ldb > kMaxLdb || ldb % 32 != 0 || K < 1 || K > 8 ||
-      (mode != kModeMU && mode != kModeHALS && mode != kModeANLS) || (mode == kModeANLS && !ginv))
+      (mode != kModeMU && mode != kModeHALS && mode != kModeANLS && mode != kModeND) || (mode == kModeANLS && !ginv))
     return false;
   const uint4 *db1 = reinterpret_cast<const uint4 *>(img);
   const uint4 *db3 = db1 + (bf16_ldb_pad(ldb) / 32) * 64;

@@ -46,6 +46,8 @@ struct NmfCtrl {
   int iter_base;    // batched runs: index of the first step of the replayed chunk
   int numeric;      // set (with a stop) when an evaluated objective is NaN or infinite
   int pad[3];
+  double last16;    // objective of the last step on p_bf16 that evaluated one
+  double adj;       // calibration added to the bfloat16 stop estimate (objective + bias + adj)
   double gvo[65];   // G_V = V^T V (K*K) and the objective of the last pass, reduced
 };
 
@@ -242,6 +244,21 @@ constexpr int kInvStride = 256;
 // the group then forms x_l = z_l of the winning support itself and returns
 // it (the other lanes return 0), so no lane keeps a z.  The 32 lanes must be
 // converged.  ginv: entry-major inverses with stride STRIDE (see above).
+// One exchange of the (cost, mask) minimum with the partner lane that DPP
+// control CTRL names (a permutation within each row of 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ void enum_min_step(double &q, int &m) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, q);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false);
+  const int om = __builtin_amdgcn_update_dpp(0, m, CTRL, 0xF, 0xF, false);
+  const double oq = __builtin_bit_cast(double, (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+  if (oq < q || (oq == q && om < m)) {
+    q = oq;
+    m = om;
+  }
+}
+
 template <int K, int STRIDE>
 __device__ __forceinline__ double nnls_enum_group(const double *__restrict__ ginv, const float (&h)[K], int l) {
   double best_q = 0.0;
@@ -268,10 +285,22 @@ __device__ __forceinline__ double nnls_enum_group(const double *__restrict__ gin
       best_m = m;
     }
   }
-#pragma unroll
-  for (int off = 16; off >= 1; off >>= 1) {
-    const double oq = __shfl_xor(best_q, off, 64);
-    const int om = __shfl_xor(best_m, off, 64);
+  // (q, m) minimum over the 32 lanes: four in-row DPP exchanges (partner
+  // lane xor 1, xor 2, mirrored in 8, mirrored in 16), then a swizzle with
+  // the lane 16 apart; the combine is order-free, every lane ends with the
+  // group's minimum.
+  enum_min_step<0xB1>(best_q, best_m);   // quad_perm [1, 0, 3, 2]
+  enum_min_step<0x4E>(best_q, best_m);   // quad_perm [2, 3, 0, 1]
+  enum_min_step<0x141>(best_q, best_m);  // row_half_mirror
+  enum_min_step<0x140>(best_q, best_m);  // row_mirror
+  {
+    constexpr int kXor16 = 0x1F | (0x10 << 10);  // ds_swizzle bit mode: and 0x1F, xor 0x10
+    const double oq = __builtin_bit_cast(
+        double, (uint64_t(uint32_t(__builtin_amdgcn_ds_swizzle(int(__builtin_bit_cast(uint64_t, best_q) >> 32),
+                                                                kXor16)))
+                 << 32) |
+                    uint32_t(__builtin_amdgcn_ds_swizzle(int(__builtin_bit_cast(uint64_t, best_q)), kXor16)));
+    const int om = __builtin_amdgcn_ds_swizzle(best_m, kXor16);
     if (oq < best_q || (oq == best_q && om < best_m)) {
       best_q = oq;
       best_m = om;

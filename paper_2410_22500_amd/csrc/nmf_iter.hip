@@ -141,6 +141,8 @@ __device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n
     ctrl->hist_len = 0;
     ctrl->iter_base = 0;
     ctrl->numeric = 0;
+    ctrl->last16 = 0.0;
+    ctrl->adj = 0.0;
   }
   __syncthreads();
   if (want_chol) factor_all<K>(g_s, chol, ginv);
@@ -215,7 +217,7 @@ __device__ __forceinline__ void update_d_body(
     int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
     int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int blk, int n_blk,
-    char *__restrict__ lds, const double *__restrict__ bias = nullptr) {
+    char *__restrict__ lds, int bf16 = 0, const double *__restrict__ bias = nullptr) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   using L = UpdLds<K, RULE>;
@@ -257,9 +259,14 @@ __device__ __forceinline__ void update_d_body(
     const int h = ctrl->hist_len;
     hist[h] = obj_s;
     ctrl->hist_len = h + 1;
-    // bias: the stop test of a pass over the bfloat16 p compares
-    // obj - ||p - p_bf16||^2, an estimate of the float32 objective
-    const double ob = bias ? obj_s + *bias : obj_s;
+    // a step on the bfloat16 p (bf16 != 0) compares obj + bias + adj, an
+    // estimate of the float32 objective (bias: the normalisation's
+    // -||p - p_bf16||^2 or null; adj: the calibration against a float32 round)
+    double ob = obj_s;
+    if (bf16) {
+      ctrl->last16 = obj_s;
+      ob = obj_s + (bias ? *bias : 0.0) + ctrl->adj;
+    }
     if (!isfinite(obj_s)) {
       // a non-finite objective (NaN or Inf in p or in the factors) ends the run
       ctrl->numeric = 1;
@@ -363,11 +370,11 @@ __global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
     float *__restrict__ D, const float *__restrict__ part_nd, int n_wg, int n_k, NmfCtrl *__restrict__ ctrl, int iter,
     int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
-    int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb,
+    int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int bf16,
     const double *__restrict__ bias) {
   __shared__ __attribute__((aligned(16))) char lds[UpdLds<K, RULE>::bytes];
   update_d_body<K, RULE>(D, part_nd, n_wg, n_k, ctrl, iter, has_obj, f_ref, tol, hist, GD, chol, next_chol, part_gd,
-                         img, ldb, int(blockIdx.x), int(gridDim.x), lds, bias);
+                         img, ldb, int(blockIdx.x), int(gridDim.x), lds, bf16, bias);
 }
 
 template <int K>
@@ -493,7 +500,8 @@ void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWo
 int update_d_blocks(int n_k) { return (n_k + kUpdRows - 1) / kUpdRows; }
 
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
-                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, const double *bias) {
+                     bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, int bf16,
+                     const double *bias) {
   const int nb = update_d_blocks(n_k);
   uint16_t *img = ldb_img > 0 ? w.img : nullptr;
   switch (K) {
@@ -508,15 +516,15 @@ void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w
     if (rule == kModeMU)                                                                                          \
       update_d_kernel<KK, kModeMU><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
-                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bias); \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias); \
     else if (rule == kModeHALS)                                                                                   \
       update_d_kernel<KK, kModeHALS><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                          \
                                                                  w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd, \
-                                                                 w.chol, next_chol, w.part_gd, img, ldb_img, bias); \
+                                                                 w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias); \
     else                                                                                                          \
       update_d_kernel<KK, kModeNV><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
-                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bias); \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias); \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
@@ -589,6 +597,21 @@ void launch_batched_rows(int K, int n_blocks, hipStream_t st, const BatchInst *d
 __global__ void nmf_resume_kernel(NmfCtrl *__restrict__ ctrl) { ctrl->stop_at = INT_MAX; }
 
 void launch_nmf_resume(hipStream_t st, NmfCtrl *ctrl) { nmf_resume_kernel<<<1, 1, 0, st>>>(ctrl); }
+
+// After a float32 round that confirms a stop of the bfloat16 rounds: the
+// calibration that makes the estimate of the last bfloat16 objective equal
+// to the float32 objective just measured (the last history entry).  The
+// round between them changes the objective by far less than the tolerance
+// near convergence.
+__global__ void nmf_calibrate_kernel(NmfCtrl *__restrict__ ctrl, const double *__restrict__ hist,
+                                     const double *__restrict__ bias) {
+  const int h = ctrl->hist_len;
+  if (h > 0) ctrl->adj = hist[h - 1] - (ctrl->last16 + (bias ? *bias : 0.0));
+}
+
+void launch_nmf_calibrate(hipStream_t st, NmfCtrl *ctrl, const double *hist, const double *bias) {
+  nmf_calibrate_kernel<<<1, 1, 0, st>>>(ctrl, hist, bias);
+}
 
 void launch_batched_advance(int n_inst, int steps, hipStream_t st, const BatchInst *d) {
   batched_advance_kernel<<<(n_inst + 63) / 64, 64, 0, st>>>(d, n_inst, steps);

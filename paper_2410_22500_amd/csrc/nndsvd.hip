@@ -372,17 +372,18 @@ __global__ void nndsvd_coef_kernel(const double *__restrict__ part_u, int nbu, c
 }
 
 // X[r][j] <- scale_j * part_j(X[r][j]) with part = |x| (j = 0), max(x,0)
-// (sign +1) or max(-x,0) (sign -1); exact zeros become mean(p).
+// (sign +1) or max(-x,0) (sign -1); with fill, exact zeros become mean(p)
+// (NNDSVDa), else they stay (plain NNDSVD).
 template <typename T>
 __global__ void nndsvd_apply_kernel(const T *__restrict__ X, int64_t n, int K, const double *__restrict__ info,
-                                    int which, float *__restrict__ out) {
+                                    int which, int fill, float *__restrict__ out) {
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n * K; e += int64_t(gridDim.x) * blockDim.x) {
     const int j = int(e % K);
     const double x = double(X[e]);
     const double sg = info[2 * K + j];
     const double part = (sg == 0.0) ? fabs(x) : (sg > 0.0 ? fmax(x, 0.0) : fmax(-x, 0.0));
     const double v = info[which * K + j] * part;
-    out[e] = (v == 0.0) ? float(info[3 * K]) : float(v);
+    out[e] = (v == 0.0 && fill) ? float(info[3 * K]) : float(v);
   }
 }
 
@@ -420,7 +421,7 @@ size_t nndsvd_ws_bytes(int64_t n_p, int n_k, int K, int n_split) {
 
 // Writes V0 [n_p][K] and D0 [n_k][K].  ws: nndsvd_ws_bytes of device memory.
 hsn_status nndsvd_init(hsn_ctx *ctx, hipStream_t st, const float *p, int64_t ldp, const uint16_t *pb, int64_t ldb,
-                       int64_t n_p, int n_k, int K, float *V, float *D, void *ws, int n_split) {
+                       int64_t n_p, int n_k, int K, float *V, float *D, void *ws, int n_split, bool fill) {
   const int n_tb = (n_k + kGT - 1) / kGT;
   const size_t npad = size_t(n_tb) * kGT;
   const int L = std::min(kL, n_k);
@@ -467,8 +468,8 @@ hsn_status nndsvd_init(hsn_ctx *ctx, hipStream_t st, const float *p, int64_t ldp
   split_norms_kernel<double><<<nbv, 256, 0, st>>>(vs, n_k, K, part_v);
   psum_kernel<<<nbp, 256, 0, st>>>(p, ldp, n_p, n_k, part_p);
   nndsvd_coef_kernel<<<1, 64, 0, st>>>(part_u, nbu, part_v, nbv, part_p, nbp, double(n_p) * n_k, sigma, K, info);
-  nndsvd_apply_kernel<float><<<2048, 256, 0, st>>>(U, n_p, K, info, 0, V);
-  nndsvd_apply_kernel<double><<<64, 256, 0, st>>>(vs, n_k, K, info, 1, D);
+  nndsvd_apply_kernel<float><<<2048, 256, 0, st>>>(U, n_p, K, info, 0, fill ? 1 : 0, V);
+  nndsvd_apply_kernel<double><<<64, 256, 0, st>>>(vs, n_k, K, info, 1, fill ? 1 : 0, D);
   HSN_LAUNCHED(ctx);
   return HSN_OK;
 }

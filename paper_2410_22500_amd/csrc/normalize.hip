@@ -435,7 +435,6 @@ static hsn_status normalize_impl(hsn_ctx *ctx, const hsn_dims *d, const void *y,
                     p_bf16, ldb, offset_b, sumsq, bf16_bias, pooled, pool_mode, st, scratch);
 }
 
-
 extern "C" hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype,
                                     const void *y_open, int y_open_dtype, const uint8_t *bg_mask,
                                     float count_floor, int clip_nonneg, float *p, int64_t ldp, uint16_t *p_bf16,
@@ -459,4 +458,3 @@ extern "C" hsn_status hsn_normalize_pooled(hsn_ctx *ctx, const hsn_dims *d, cons
   return normalize_impl(ctx, d, y, y_dtype, y_open, y_open_dtype, bg_mask, count_floor, clip_nonneg, p, ldp, p_bf16,
                         ldb, offset_b, sumsq, bf16_bias, pooled, pooled_precision == HSN_PREC_BF16 ? 1 : 2, stream);
 }
-

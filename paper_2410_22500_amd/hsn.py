@@ -26,7 +26,7 @@ OK, ERR_INVALID_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_OOM, ERR_DEVICE, ERR_NUMERI
 U16, F32 = 0, 1
 ALGO_MU, ALGO_ANLS, ALGO_HALS = 0, 1, 2
 PREC_FP32, PREC_BF16 = 0, 1
-INIT_USER, INIT_NNDSVDA, INIT_MLP = 0, 1, 2
+INIT_USER, INIT_NNDSVDA, INIT_MLP, INIT_NNDSVD = 0, 1, 2, 3
 MLP_IN, MLP_HIDDEN = 256, 128
 
 (KERN_NMF_PASS, KERN_PROJECT, KERN_BACKPROJECT, KERN_NORMALIZE, KERN_NMF_PASS_BF16, KERN_MLP_ROWS,

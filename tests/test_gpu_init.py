@@ -80,6 +80,38 @@ def test_nndsvda_matches_oracle(hsn, case, k):
     _mu50_matches(hsn, P, pd, n_k, V, D, W, H, 1e-3 if unique else 1e-2)
 
 
+@pytest.mark.parametrize("case,k", [("tiny", 3), ((3000, 700), 5)])
+def test_plain_nndsvd_matches_oracle(hsn, case, k):
+    # Plain NNDSVD (the paper's start): the same pairs, exact zeros kept.
+    # Compared where determined as above; entries the oracle sets to zero
+    # are zero or small on the GPU (a sign split of a near-zero entry may
+    # differ), and HALS from both starts reaches the same objective.
+    if case == "tiny":
+        sc = synth.config_scan("tiny")
+        p32 = onorm(sc.y, sc.yo)[0].astype(np.float32)
+    else:
+        p32 = _random_problem(*case, k, case[0] + k)
+    P = p32.astype(np.float64)
+    n_p, n_k = P.shape
+    W, H = onmf.nndsvd(P, k, variant="plain")
+    assert np.any(W == 0) and np.any(H == 0)
+    pd = torch.zeros((n_p, (n_k + 3) // 4 * 4), dtype=torch.float32, device="cuda")
+    pd[:, :n_k] = torch.from_numpy(p32).cuda()
+    V = torch.zeros((n_p, k), dtype=torch.float32, device="cuda")
+    D = torch.zeros((n_k, k), dtype=torch.float32, device="cuda")
+    show("nndsvd plain", case=case, k=k)
+    hsn.hsn_subspace_nmf(pd, None, n_k, V, D, init=hsn.INIT_NNDSVD, max_iter=0)
+    Vg, Dg = V.cpu().numpy(), D.cpu().numpy()
+    _check(Vg, Dg, W, H, _gaps(P, k))
+    zv = W[:, 0] == 0
+    assert np.mean(Vg == 0) > 0.5 * np.mean(W == 0)   # zeros are kept, not filled
+    assert not np.any(zv) or np.abs(Vg[zv, 0]).max() <= TOL * np.abs(W[:, 0]).max()
+    _, _, fh, _ = onmf.hals_step(P, W, H)
+    st = hsn.hsn_subspace_nmf(pd, None, n_k, V, D, algo=hsn.ALGO_HALS, max_iter=1, check_every=1)
+    show("  hals1", gpu=st["history"][-1], ref=fh)
+    assert abs(st["history"][-1] - fh) <= 1e-2 * fh
+
+
 def test_nndsvda_mid_with_bf16_gram(hsn):
     # Mid workload: the Gram from the library's bfloat16 copy of p.
     sc = synth.config_scan("mid")

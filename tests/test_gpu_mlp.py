@@ -247,6 +247,22 @@ def test_nmf_learned_start(hsn):
     D2 = torch.zeros_like(D)
     hsn.hsn_subspace_nmf(p, None, n_k, V2, D2, init=hsn.INIT_MLP, mlp=m, max_iter=0, mlp_pooled=pooled)
     assert torch.equal(V2, V) and torch.equal(D2, D)
+    # first rounds on p_bf16: D0 comes from the bfloat16 pass (N_D = P_bf16^T V0),
+    # then one bfloat16 ANLS round; against the oracle on the bfloat16-rounded p,
+    # at the cond(G) 2^-16 bound of the split products
+    V3 = torch.zeros_like(V)
+    D3 = torch.zeros_like(D)
+    hsn.hsn_subspace_nmf(p, pb, n_k, V3, D3, init=hsn.INIT_MLP, mlp=m, max_iter=0, polish_rounds=1,
+                         polish_bf16_rounds=1, polish_algo=hsn.ALGO_ANLS)
+    Pq = hsn.bf16_bits_to_float(pb[:, :n_k]).cpu().numpy().astype(np.float64)
+    Dq = nnls_rows(V0.T @ V0, Pq.T @ V0)
+    Dq[Dq == 0] = 1e-6 * Dq.mean()
+    V1r = nnls_rows(Dq.T @ Dq, Pq @ Dq)
+    D1r = nnls_rows(V1r.T @ V1r, Pq.T @ V1r)
+    tv = max(2e-5, np.linalg.cond(Dq.T @ Dq) * np.linalg.cond(V0.T @ V0) * 2.0 ** -16)
+    td = max(2e-5, np.linalg.cond(V1r.T @ V1r) * 2.0 ** -16 + tv)
+    show("  bf16 D0 + round", V=rel_fro(V3.cpu().numpy(), V1r), D=rel_fro(D3.cpu().numpy(), D1r), tv=tv, td=td)
+    assert rel_fro(V3.cpu().numpy(), V1r) <= tv and rel_fro(D3.cpu().numpy(), D1r) <= td
     # rejected: missing network, mismatched k, neither p_bf16 nor pooled rows
     with pytest.raises(hsn.HsnError):
         hsn.hsn_subspace_nmf(p, None, n_k, V, D, init=hsn.INIT_MLP, mlp=m, max_iter=0)

@@ -136,8 +136,8 @@ def test_bf16_rejects_wide_rows(hsn):
 
 
 def test_normalize_bf16_bias(hsn):
-    # -||p - p_bf16||^2 from the normalisation pass equals the sum over the
-    # returned p and p_bf16 (float64, another order: 1e-9 relative)
+    # -||p - p_bf16||^2 from the normalisation pass equals minus the sum over
+    # the returned p and p_bf16 (float64, another order: 1e-9 relative)
     sc = synth.config_scan("tiny")
     y = torch.from_numpy(sc.y.view(np.int16)).cuda()
     yo = torch.from_numpy(sc.yo.view(np.int16)).cuda()
@@ -147,17 +147,18 @@ def test_normalize_bf16_bias(hsn):
     q64 = _bits_to_f64(pb.cpu().numpy().view(np.uint16)[:, :n_k])
     ref = -float(np.sum((p64 - q64) ** 2))
     show("bf16 bias", gpu=float(bias), ref=ref, sumsq=float(ss))
-    assert ref < 0 and abs(float(bias) - ref) <= 1e-9 * abs(ref)
+    assert ref < 0 and abs(float(bias) - ref) <= -1e-9 * ref
     assert abs(float(ss) - float(np.sum(p64 * p64))) <= 1e-12 * float(ss)
 
 
 def test_bf16_anls_polish_then_fp32_decides_the_stop(hsn):
     # MU bulk on the float32 p, then ANLS polish rounds on p_bf16 until the
     # bias-corrected objective meets the tolerance, then float32 ANLS rounds
-    # that decide the stop on the float32 objective.  The bias estimate's
-    # error, 2 <p - p_bf16, residual>, has zero mean and a spread of about
-    # 2 sqrt(N) 2^-9 |p| sigma_noise: 3e-4 of f* on this 1.5 M-entry scan
-    # (relatively less on larger ones), so the tolerance here is 1e-3.
+    # that confirm (or calibrate the estimate and resume the bfloat16 rounds)
+    # and decide the stop on the float32 objective.  The estimate's error,
+    # 2 <p - p_bf16, p - V D^T>, spreads by about 2 sqrt(N) 2^-9 |p|
+    # sigma_noise: 3e-4 of f* on this 1.5 M-entry scan (relatively less on
+    # larger ones), so the tolerance here is 1e-3.
     import json
     import os
     sc = synth.config_scan("tiny")
