@@ -96,6 +96,24 @@ hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *dims,
                          float *offset_b, double *sumsq, double *bf16_bias, void *stream);
 
 /*
+ * hsn_normalize for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, same kernels and results, but no workspace is allocated.
+ * The only scratch, 2 x 2048 doubles (32 KB) of per-block partial sums,
+ * lives in a static device array of the library that each GPU holds until
+ * the process ends; it is independent of the input size.  With bg_mask the
+ * caller must pass offset_b (the offset is not kept in scratch), else
+ * HSN_ERR_INVALID_ARG.  Calls on one GPU share that array: calls whose work
+ * overlaps on one GPU (different streams or threads) race; calls ordered on
+ * one stream do not.  No profiling events are recorded.
+ */
+hsn_status hsn_normalize_noalloc(hsn_ctx *ctx, const hsn_dims *dims,
+                                 const void *y, int y_dtype, const void *y_open, int y_open_dtype,
+                                 const uint8_t *bg_mask, float count_floor, int clip_nonneg,
+                                 float *p, int64_t ldp, uint16_t *p_bf16, int64_t ldb,
+                                 float *offset_b, double *sumsq, double *bf16_bias, void *stream);
+
+/*
  * hsn_normalize plus the input of the learned warm start in the same pass:
  * pooled [N_p][256], row i of p average-pooled to 256 values exactly as
  * hsn_mlp_pool pools p_bf16 (bfloat16-rounded p, bin j covering

@@ -8,6 +8,8 @@
 // copy, of -sum((p - bf16(p))^2)) reduced in a fixed order.
 #include "common.hpp"
 
+#include <mutex>
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -435,6 +437,41 @@ static hsn_status normalize_impl(hsn_ctx *ctx, const hsn_dims *d, const void *y,
                     p_bf16, ldb, offset_b, sumsq, bf16_bias, pooled, pool_mode, st, scratch);
 }
 
+// ---------------------------------------------------------------------------
+// No-allocation form: the per-block partials live in a file-scope device
+// array (each GPU holds its own copy, at its own address).  Its address is
+// looked up once per device, with that device current, and only that
+// address is handed to kernels: in host code the array's name is a host
+// stand-in, not a device address.
+// ---------------------------------------------------------------------------
+// Every call rewrites all 2 kSumBlocks slots (the grid is fixed), so nothing
+// needs clearing between calls; calls that overlap on one GPU race on it.
+static __device__ __align__(256) double scratch[2 * kSumBlocks];  // 32 KB per GPU, kept until the process ends
+namespace {
+constexpr int kNoAllocMaxDevices = 64;
+double *g_scratch_ptr[kNoAllocMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+double *noalloc_scratch(hsn_ctx *ctx) {
+  if (ctx->device < 0 || ctx->device >= kNoAllocMaxDevices) {
+    hsn::fail(ctx, HSN_ERR_DEVICE, "normalize_noalloc: device index %d beyond %d", ctx->device, kNoAllocMaxDevices);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void *ptr = nullptr;  // the caller's DeviceGuard made ctx->device current
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      hsn::fail(ctx, HSN_ERR_DEVICE, "normalize_noalloc: hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[ctx->device] = static_cast<double *>(ptr);
+  }
+  return g_scratch_ptr[ctx->device];
+}
+}  // namespace
+
 extern "C" hsn_status hsn_normalize(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype,
                                     const void *y_open, int y_open_dtype, const uint8_t *bg_mask,
                                     float count_floor, int clip_nonneg, float *p, int64_t ldp, uint16_t *p_bf16,
@@ -457,4 +494,16 @@ extern "C" hsn_status hsn_normalize_pooled(hsn_ctx *ctx, const hsn_dims *d, cons
     return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize_pooled: pooled must be 4-byte aligned");
   return normalize_impl(ctx, d, y, y_dtype, y_open, y_open_dtype, bg_mask, count_floor, clip_nonneg, p, ldp, p_bf16,
                         ldb, offset_b, sumsq, bf16_bias, pooled, pooled_precision == HSN_PREC_BF16 ? 1 : 2, stream);
+}
+
+extern "C" hsn_status hsn_normalize_noalloc(hsn_ctx *ctx, const hsn_dims *d, const void *y, int y_dtype,
+                                            const void *y_open, int y_open_dtype, const uint8_t *bg_mask,
+                                            float count_floor, int clip_nonneg, float *p, int64_t ldp,
+                                            uint16_t *p_bf16, int64_t ldb, float *offset_b, double *sumsq,
+                                            double *bf16_bias, void *stream) {
+  if (!ctx) return HSN_ERR_INVALID_ARG;
+  if (bg_mask && !offset_b)
+    return hsn::fail(ctx, HSN_ERR_INVALID_ARG, "normalize_noalloc: bg_mask needs the caller's offset_b buffer");
+  return normalize_impl(ctx, d, y, y_dtype, y_open, y_open_dtype, bg_mask, count_floor, clip_nonneg, p, ldp, p_bf16,
+                        ldb, offset_b, sumsq, bf16_bias, nullptr, 0, stream, noalloc_scratch);
 }

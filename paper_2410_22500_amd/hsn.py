@@ -80,6 +80,9 @@ _lib.hsn_version.restype = C.c_int
 _lib.hsn_normalize.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, _P, C.c_float, C.c_int,
                                _P, C.c_int64, _P, C.c_int64, _P, _P, _P, _P]
 _lib.hsn_normalize.restype = C.c_int
+_lib.hsn_normalize_noalloc.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, _P, C.c_float, C.c_int,
+                                       _P, C.c_int64, _P, C.c_int64, _P, _P, _P, _P]
+_lib.hsn_normalize_noalloc.restype = C.c_int
 _lib.hsn_normalize_pooled.argtypes = [_P, C.POINTER(Dims), _P, C.c_int, _P, C.c_int, _P, C.c_float, C.c_int,
                                       _P, C.c_int64, _P, C.c_int64, _P, _P, _P, _P, C.c_int, _P]
 _lib.hsn_normalize_pooled.restype = C.c_int
@@ -277,6 +280,33 @@ def hsn_normalize(y: torch.Tensor, yo: torch.Tensor, bg_mask: Optional[torch.Ten
     _check(_lib.hsn_normalize(ctx, C.byref(dims), _ptr(y), yd, _ptr(yo), od, _ptr(bg_mask), float(count_floor),
                               int(clip), _ptr(p), ldp, _ptr(pb), ldb, _ptr(b), _ptr(ss), _ptr(bias), _stream(dev)), ctx)
     return (p, pb, b, ss, bias) if want_bias else (p, pb, b, ss)
+
+
+def hsn_normalize_noalloc(y: torch.Tensor, yo: torch.Tensor, p: Optional[torch.Tensor] = None,
+                          p_bf16: Optional[torch.Tensor] = None, bg_mask: Optional[torch.Tensor] = None,
+                          offset_b: Optional[torch.Tensor] = None, sumsq: Optional[torch.Tensor] = None,
+                          bf16_bias: Optional[torch.Tensor] = None, count_floor: float = 1.0,
+                          clip: bool = True) -> None:
+    """hsn_normalize into caller-owned outputs (p [N_p][ldp] f32, p_bf16 [N_p][ldb] int16 bits, offset_b
+    [N_v][N_k] f32 (required with bg_mask), sumsq and bf16_bias f64 scalars); the library allocates
+    nothing for the call."""
+    _check_counts(y, yo, bg_mask)
+    n_v, n_r, n_c, n_k = y.shape
+    n_p = n_v * n_r * n_c
+    _opt(p, "p", torch.float32, shape=(n_p, None), layout="rows", device=y.device)
+    _opt(p_bf16, "p_bf16", _U16, shape=(n_p, None), layout="rows", device=y.device)
+    _opt(offset_b, "offset_b", torch.float32, shape=(n_v, n_k), device=y.device)
+    _opt(sumsq, "sumsq", torch.float64, shape=(), device=y.device)
+    _opt(bf16_bias, "bf16_bias", torch.float64, shape=(), device=y.device)
+    dev = _dev(y)
+    ctx = context(dev)
+    dims = Dims(n_v, n_r, n_c, n_k)
+    yd = F32 if y.dtype == torch.float32 else U16
+    od = F32 if yo.dtype == torch.float32 else U16
+    _check(_lib.hsn_normalize_noalloc(ctx, C.byref(dims), _ptr(y), yd, _ptr(yo), od, _ptr(bg_mask),
+                                      float(count_floor), int(clip), _ptr(p), p.stride(0) if p is not None else 0,
+                                      _ptr(p_bf16), p_bf16.stride(0) if p_bf16 is not None else 0, _ptr(offset_b),
+                                      _ptr(sumsq), _ptr(bf16_bias), _stream(dev)), ctx)
 
 
 def hsn_normalize_pooled(y: torch.Tensor, yo: torch.Tensor, pooled_precision: int, bg_mask: Optional[torch.Tensor] = None,
