@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy of 1 GiB (reference for HBM counters) and exit")
+    ap.add_argument("--counters", action="store_true",
+                    help="for rocprofv3 --pmc runs: only the full-size kernels of one step (normalisation with "
+                         "the pooled input, 4 bfloat16 and 2 float32 ANLS rounds from a seeded start, 3 CGLS "
+                         "iterations), no network training, no references, and exit")
     ap.add_argument("--traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="turn two rocprofv3 --pmc runs of this benchmark on --workload (FETCH_SIZE, WRITE_SIZE; "
                          "csv) into HBM bytes per launch of its kernels, scaled by the copy probe, and exit")
@@ -80,7 +84,7 @@ TRAFFIC_KERNELS = {
         "mbir_step_kernel": ("mbir_step_kernel<4>", _PRJ),
     },
     "full": {
-        "pass_bf16_kernel": ("pass_bf16_kernel<5, 4, true, 8, 1>", "paper_2410_22500_amd/csrc/nmf_bf16.hip"),
+        "pass_bf16_kernel": ("pass_bf16_kernel<5, 4, ", "paper_2410_22500_amd/csrc/nmf_bf16.hip"),
         "pass_f32_kernel": ("pass_f32_kernel<5, 2, 4, true>", "paper_2410_22500_amd/csrc/nmf_f32.hip"),
         "normalize": ("normalize_", "paper_2410_22500_amd/csrc/normalize.hip"),
         "project_lds_kernel": ("project_lds_kernel<5,", _PRJ),
@@ -161,6 +165,40 @@ def copy_probe():
                       "gbs_read_plus_write": 8.0 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def counter_run(args):
+    """The hot path's kernels at the workload's shape, each launched as in a
+    timed step, and nothing else at another shape: the run that rocprofv3
+    --pmc counts (FETCH_SIZE, WRITE_SIZE, SQ counters).  The bfloat16 ANLS
+    rounds keep the timed path's mix (the objective on every 4th round)."""
+    import torch
+    import synth
+    from paper_2410_22500_amd import hsn
+
+    dev = torch.device("cuda:0")
+    cfg = synth.CONFIGS[args.workload]
+    full = args.workload == "full"
+    sc = synth.config_scan(args.workload, counts=not full)
+    K, n_p, n_k = sc.n_mat, sc.n_p, sc.n_bins
+    if full:
+        y, yo = synth.device_counts(sc, seed=cfg["seed"] * 7919 + 1, device=dev)
+    else:
+        y = torch.from_numpy(sc.y.view(np.int16)).to(dev)
+        yo = torch.from_numpy(sc.yo.view(np.int16)).to(dev)
+    p, pb, _, _, _, bias = hsn.hsn_normalize_pooled(y, yo, hsn.PREC_BF16, want_bf16=True, want_bias=True)
+    del y, yo
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    V = torch.rand((n_p, K), device=dev, generator=g) + 0.05
+    D = torch.rand((n_k, K), device=dev, generator=g) + 0.05
+    st = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, max_iter=0, polish_rounds=6, polish_bf16_rounds=4,
+                              polish_algo=hsn.ALGO_ANLS, bf16_bias=bias)
+    del p, pb
+    x = hsn.hsn_cgls(V.view(sc.n_views, sc.n_rows, sc.n_cols, K), 3)
+    torch.cuda.synchronize()
+    log(f"counter run {args.workload}: {st['polish_bf16_done']} bf16 + "
+        f"{st['polish_done'] - st['polish_bf16_done']} f32 ANLS rounds, CGLS 3, |x| {float(x.norm()):.4g}")
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -179,6 +217,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.counters:
+        counter_run(args)
         return
 
     import torch
@@ -242,9 +283,18 @@ def main():
     paths = {
         # learned start, ANLS rounds on the bfloat16 p until the bias-corrected
         # objective meets the tolerance, then float32 ANLS rounds decide the stop
-        "learned": dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0, polish_bf16_rounds=bf16_rounds),
-        "learned_fp32": dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0),
+        # (a learned start whose first objective is more than 50 % above f* is
+        # replaced by NNDSVDa: a guard against a network that does not fit the scan)
+        "learned": dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0, polish_bf16_rounds=bf16_rounds,
+                        mlp_fallback_rel=0.5),
+        "learned_fp32": dict(init=hsn.INIT_MLP, mlp=mlp, max_iter=0, mlp_fallback_rel=0.5),
         "plain_fp32": dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, precision=hsn.PREC_FP32),
+        # the paper's solver: plain NNDSVD start and Fast HALS (float32), then
+        # the same ANLS rounds; with the MU bulk from the same start beside it,
+        # both checking the objective every 10 bulk iterations
+        "nndsvd_hals_fp32": dict(init=hsn.INIT_NNDSVD, algo=hsn.ALGO_HALS, max_iter=BULK,
+                                 precision=hsn.PREC_FP32, check_every=10),
+        "nndsvd_mu_fp32": dict(init=hsn.INIT_NNDSVD, max_iter=BULK, precision=hsn.PREC_FP32, check_every=10),
         "cold_bf16": dict(init=hsn.INIT_NNDSVDA, max_iter=BULK, precision=hsn.PREC_BF16,
                           polish_bf16_rounds=bf16_rounds),
     }
@@ -263,9 +313,11 @@ def main():
         else:
             want_b = paths[path].get("polish_bf16_rounds", 0) > 0 or paths[path].get("precision") == hsn.PREC_BF16
             p, pb, _, _, bias = hsn.hsn_normalize(y, yo, want_bf16=True, want_bias=True)
-            s = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, check_every=BULK, polish_rounds=POLISH_CAP,
+            kw = dict(paths[path])
+            kw.setdefault("check_every", BULK)
+            s = hsn.hsn_subspace_nmf(p, pb, n_k, V, D, polish_rounds=POLISH_CAP,
                                      polish_algo=hsn.ALGO_ANLS, rel_obj_tol=REL_OBJ, f_ref=f_star,
-                                     bf16_bias=bias if want_b else None, **paths[path])
+                                     bf16_bias=bias if want_b else None, **kw)
             del p, pb
             sino = V.view(sc.n_views, sc.n_rows, sc.n_cols, K)
             x = hsn.hsn_cgls(sino, CGLS_ITERS)
@@ -305,6 +357,8 @@ def main():
     ms_step_prof, recs_prof, prof = timed("learned", args.steps, True)
     nmf_ms = float(np.mean([r["ms"] for r in recs]))
     reached = all(r["rel_obj"] <= REL_OBJ for r in recs)
+    if any(r["fell_back"] for r in recs):
+        log("learned path: the learned start fell back to NNDSVDa")
     log(f"learned path: {ms_step:.3f} ms/step, NMF {nmf_ms:.3f} ms, rounds {recs[-1]['polish_done']} "
         f"({recs[-1]['polish_bf16_done']} on p_bf16), rel obj {recs[-1]['rel_obj']:.3e}")
     x_flag = last_x["x"].clone()
@@ -338,17 +392,20 @@ def main():
 
     compare = {}
     compare_prof = {}
-    for path in () if args.quick else ("plain_fp32", "cold_bf16", "learned_fp32"):
+    for path in () if args.quick else ("plain_fp32", "nndsvd_hals_fp32", "nndsvd_mu_fp32", "cold_bf16",
+                                       "learned_fp32"):
         step(path)
         ms_p, rp, _ = timed(path, args.compare_steps, False)
         _, rpp, pp = timed(path, args.compare_steps, True)
         compare_prof[path] = (pp, rpp)
         nm = float(np.mean([r["ms"] for r in rp]))
         compare[path] = {"ms_per_step": ms_p, "nmf_ms": nm, "nmf_vpb_per_s": vpb / (nm * 1e-3),
+                         "bulk": "HALS" if paths[path].get("algo") == hsn.ALGO_HALS else "MU",
                          "mu_iters": rp[-1]["iters"], "anls_rounds": rp[-1]["polish_done"],
                          "anls_rounds_bf16": rp[-1]["polish_bf16_done"],
                          "rel_obj": rp[-1]["rel_obj"], "reached": all(r["rel_obj"] <= REL_OBJ for r in rp)}
-        log(f"{path}: {ms_p:.3f} ms/step, NMF {nm:.3f} ms, {rp[-1]['iters']} MU + {rp[-1]['polish_done']} ANLS "
+        log(f"{path}: {ms_p:.3f} ms/step, NMF {nm:.3f} ms, {rp[-1]['iters']} {compare[path]['bulk']} + "
+            f"{rp[-1]['polish_done']} ANLS "
             f"({rp[-1]['polish_bf16_done']} on p_bf16), rel obj {rp[-1]['rel_obj']:.3e}")
 
     # Roofline of each profiled kernel kind over the timed region: algorithmic
@@ -365,18 +422,19 @@ def main():
     work = {  # kind -> (name, total algorithmic units over the timed region, bound)
         hsn.KERN_NORMALIZE: ("normalize (u16 counts -> f32 p + bf16 p + pooled network input)",
                              args.steps * (8.0 * elems + 2.0 * sc.n_rows * sc.n_cols * n_k + pool_b * n_p), "hbm"),
-        hsn.KERN_NMF_PASS_BF16: ("pass_bf16_kernel (fused ANLS rounds over bf16 p, MFMA)",
-                                 rounds_bf * (2.0 * elems + vb), "hbm"),
-        hsn.KERN_NMF_PASS: ("pass_f32_kernel (D0 solve and fused ANLS rounds over f32 p)",
-                            args.steps * (4.0 * elems + vb) + (rounds - rounds_bf) * (4.0 * elems + vb), "hbm"),
+        hsn.KERN_NMF_PASS_BF16: ("pass_bf16_kernel (D0 solve and fused ANLS rounds over bf16 p, MFMA)",
+                                 (args.steps + rounds_bf) * (2.0 * elems + vb), "hbm"),
+        hsn.KERN_NMF_PASS: ("pass_f32_kernel (fused ANLS rounds over f32 p)",
+                            (rounds - rounds_bf) * (4.0 * elems + vb), "hbm"),
         hsn.KERN_MLP_ROWS: ("mlp_infer2_kernel (network inference, bf16 MFMA)",
                             args.steps * mlp_flops_row * n_p, "mfma"),
         hsn.KERN_PROJECT: ("project_lds_kernel (A, Joseph footprint, K channels, LDS-staged)", None, "alu"),
         hsn.KERN_BACKPROJECT: ("backproject_lds_kernel (A^T, LDS-staged)", None, "alu"),
     }
-    # Passes that did work: the D0 pass and every round run; passes queued after
-    # the stop test fired return at once (their time stays in the total).
-    real = {hsn.KERN_NMF_PASS: args.steps + rounds - rounds_bf, hsn.KERN_NMF_PASS_BF16: rounds_bf}
+    # Passes that did work: the learned start's D0 pass (on p_bf16, since the
+    # first round is) and every round run; passes queued after the stop test
+    # fired return at once (their time stays in the total).
+    real = {hsn.KERN_NMF_PASS: rounds - rounds_bf, hsn.KERN_NMF_PASS_BF16: args.steps + rounds_bf}
     roof = {}
     for kk, (name, units, bound) in work.items():
         ms, n = prof.get(kk, (0.0, 0))
@@ -453,7 +511,8 @@ def main():
                    "recon": f"CGLS {CGLS_ITERS} pairs", "parallelism": "single GPU"},
         "nmf": {"vpb_per_s": vpb / (nmf_ms * 1e-3), "ms": nmf_ms, "anls_rounds": recs[-1]["polish_done"],
                 "anls_rounds_bf16": recs[-1]["polish_bf16_done"], "rel_obj": recs[-1]["rel_obj"],
-                "reached": reached, "f_star": f_star, "references": refs,
+                "reached": reached, "fell_back": any(r["fell_back"] for r in recs), "f_star": f_star,
+                "references": refs,
                 "f_star_note": "lowest objective of the float32 ANLS reference runs; their last-100-round "
                                "relative decrease bounds how far from stationary they ended"},
         "compare": compare,

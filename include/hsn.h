@@ -171,6 +171,10 @@ typedef struct {
                              NULL: pooled here from p_bf16 */
   const double *bf16_bias; /* optional device double -||p - p_bf16||^2 (hsn_normalize's
                               bf16_bias) for the stop test of steps on p_bf16; NULL = 0 */
+  double mlp_fallback_rel; /* HSN_INIT_MLP with the stop test on: when the first evaluated
+                              objective of the learned start has (f - f_ref)/f_ref above this
+                              (or is NaN/Inf), the run restarts from NNDSVDa with the same
+                              schedule (stats.fell_back = 1); <= 0: off */
 } hsn_nmf_opts;
 
 typedef struct {
@@ -183,6 +187,8 @@ typedef struct {
   int history_len;    /* entries written */
   float ms;           /* device time of the call */
   int polish_bf16_done; /* of polish_done, the rounds run on p_bf16 */
+  int fell_back;      /* 1 when a learned start was replaced by NNDSVDa (the counts and the
+                         history are those of the restarted run) */
 } hsn_nmf_stats;
 
 /*

@@ -203,7 +203,9 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   // share the workspace with the decomposition's.
   int n_split = 1;
   size_t need_init = 0;
-  if (nndsvd) {
+  // A learned start may be replaced by NNDSVDa after its first stop test.
+  const bool fallback = o->init == HSN_INIT_MLP && o->mlp_fallback_rel > 0.0 && o->f_ref > 0.0;
+  if (nndsvd || fallback) {
     const int64_t n_tb = (n_k + 127) / 128;
     n_split = int(std::max<int64_t>(1, std::min<int64_t>(1024 / (n_tb * (n_tb + 1) / 2), n_p / 32)));
     need_init = nndsvd_ws_bytes(n_p, int(n_k), K, n_split);
@@ -329,6 +331,7 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   // then the float32 rounds run to the end.
   int f32_next = first_f32_polish;
   int cal_left = kBf16Calibrations;
+  bool fell_back = false, first_test = true;
   while (issued < int(steps.size())) {
     int end = issued, n_obj = 0;
     while (end < int(steps.size()) && n_obj < chunk_obj) {
@@ -348,6 +351,30 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     const bool confirm_possible = f32_next >= 0 && f32_next < int(steps.size());
     if (!stop_test || (issued >= int(steps.size()) && !confirm_possible)) continue;
     if ((rc = read_back()) != HSN_OK) return rc;
+    if (fallback && first_test && hc.hist_len > 0 &&
+        (hc.numeric || !std::isfinite(hc.last_est) || (hc.last_est - R.f_ref) / R.f_ref > o->mlp_fallback_rel)) {
+      // The learned start is off: restart from NNDSVDa with the same
+      // schedule (its scratch shares the workspace, whose NMF arrays the
+      // initialisation below sets up again; the stream has drained).
+      if ((rc = nndsvd_init(ctx, st, p, ldp, p_bf16, ldb, n_p, int(n_k), K, V, D, ctx->ws, n_split, true)) != HSN_OK)
+        return rc;
+      launch_nmf_init(K, st, D, int(n_k), R.w, !steps.empty() && steps[0].rule == kModeANLS ? 1 : 0,
+                      any_bf16 ? bf16_image_ldb(ldb) : 0);
+      HSN_LAUNCHED(ctx);
+      fell_back = true;
+      first_test = false;
+      issued = 0;
+      chunk_obj = 1;
+      f32_next = first_f32_polish;
+      cal_left = kBf16Calibrations;
+      hc = NmfCtrl{};
+      hc.stop_at = INT32_MAX;
+      pending.clear();
+      ran_bulk = ran_bf16 = ran_f32 = 0;
+      staged = false;
+      continue;
+    }
+    if (hc.hist_len > 0) first_test = false;
     if (hc.stop_at == INT32_MAX) continue;
     const int s = hc.stop_at - 1;  // the step whose objective met the tolerance
     if (hc.numeric || !(s >= bf16_lo && s < bf16_hi) || !confirm_possible) break;
@@ -386,6 +413,7 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
     stats->iters = ran_bulk;
     stats->polish_bf16_done = ran_bf16;
     stats->polish_done = ran_bf16 + ran_f32;
+    stats->fell_back = fell_back ? 1 : 0;
     stats->history_len = 0;
     double last = NAN;
     const int len = std::min(hc.hist_len, hist_cap);

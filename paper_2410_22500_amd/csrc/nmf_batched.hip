@@ -569,6 +569,8 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
       s.ms = ms;
       s.iters = std::min(fin, o->max_iter);
       s.polish_done = std::max(0, fin - o->max_iter);
+      s.polish_bf16_done = 0;
+      s.fell_back = 0;
       s.history_len = 0;
       s.objective = NAN;
       const int len = std::min(hc[j].hist_len, pl->hist_cap);

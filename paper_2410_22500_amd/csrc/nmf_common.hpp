@@ -48,6 +48,7 @@ struct NmfCtrl {
   int pad[3];
   double last16;    // objective of the last step on p_bf16 that evaluated one
   double adj;       // calibration added to the bfloat16 stop estimate (objective + bias + adj)
+  double last_est;  // the value the last stop test compared (the estimate on p_bf16 steps)
   double gvo[65];   // G_V = V^T V (K*K) and the objective of the last pass, reduced
 };
 

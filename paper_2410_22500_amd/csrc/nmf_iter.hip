@@ -143,6 +143,7 @@ __device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n
     ctrl->numeric = 0;
     ctrl->last16 = 0.0;
     ctrl->adj = 0.0;
+    ctrl->last_est = 0.0;
   }
   __syncthreads();
   if (want_chol) factor_all<K>(g_s, chol, ginv);
@@ -267,6 +268,7 @@ __device__ __forceinline__ void update_d_body(
       ctrl->last16 = obj_s;
       ob = obj_s + (bias ? *bias : 0.0) + ctrl->adj;
     }
+    ctrl->last_est = ob;
     if (!isfinite(obj_s)) {
       // a non-finite objective (NaN or Inf in p or in the factors) ends the run
       ctrl->numeric = 1;

@@ -65,15 +65,19 @@ __global__ __launch_bounds__(kThreads) void offset_kernel(const TY *__restrict__
 constexpr int kPoolIn = 256;
 constexpr int kPoolMaxBins = 2048;
 
-// Main stream.  A block walks groups of R = max(1, 256 / cpr) rows, cpr =
-// ceil(width / 8) chunks of 8 bins per row; thread t takes row t / cpr of
-// the group and chunk t % cpr (rows longer than 2048 bins: one row per
-// group, chunks t, t + 256, ...).  POOL (1: bfloat16 out, 2: float32 out)
-// also writes the pooled rows, from a copy of the group's bfloat16-rounded
-// rows in LDS (R * N_k <= 2048 floats).
+// Main stream.  A group is R = max(1, 256 / cpr) consecutive detector
+// pixels of one view, cpr = ceil(width / 8) chunks of 8 bins per row;
+// thread t takes pixel t / cpr of the group and chunk t % cpr (rows longer
+// than 2048 bins: one row per group, chunks t, t + 256, ...).  A block walks
+// units u = blockIdx.x, + gridDim.x, ...: unit u is pixel group u / n_ch and
+// views [vc c, vc c + vc) with c = u % n_ch, taken view by view, so that
+// the open-beam row y^o of a pixel is read once per unit instead of once per
+// view.  POOL (1: bfloat16 out, 2: float32 out) also writes the pooled rows,
+// from a copy of the group's bfloat16-rounded rows in LDS (R * N_k <= 2048
+// floats).
 template <typename TY, typename TO, bool VEC, int POOL>
 __global__ __launch_bounds__(kThreads) void normalize_kernel(
-    const TY *__restrict__ y, const TO *__restrict__ yo, int64_t n_rows, int64_t n_pix, int64_t nk,
+    const TY *__restrict__ y, const TO *__restrict__ yo, int64_t n_v, int64_t vc, int64_t n_pix, int64_t nk,
     const float *__restrict__ b, float floor_, int clip, float *__restrict__ p, int64_t ldp,
     uint16_t *__restrict__ pb, int64_t ldb, void *__restrict__ pooled, double *__restrict__ partial) {
   __shared__ float rowbuf[POOL ? kPoolMaxBins : 1];
@@ -85,11 +89,14 @@ __global__ __launch_bounds__(kThreads) void normalize_kernel(
   const int ch0 = cpr <= kThreads ? t - rr * cpr : t;
   const int nki = int(nk);
   double ss = 0.0, sb = 0.0;
-  for (int64_t g0 = int64_t(blockIdx.x) * R; g0 < n_rows; g0 += int64_t(gridDim.x) * R) {
-    const int64_t row = g0 + rr;
-    const bool row_ok = rr < R && row < n_rows;
-    const int64_t v = row_ok ? row / n_pix : 0;
-    const int64_t px = row - v * n_pix;
+  const int64_t n_pg = (n_pix + R - 1) / R, n_ch = (n_v + vc - 1) / vc;
+  for (int64_t u = blockIdx.x; u < n_pg * n_ch; u += gridDim.x) {
+   const int64_t pg = u / n_ch, v0 = (u - pg * n_ch) * vc;
+   const int64_t v1 = v0 + vc < n_v ? v0 + vc : n_v;
+   const int64_t px = pg * R + rr;
+   const bool row_ok = rr < R && px < n_pix;
+   for (int64_t v = v0; v < v1; ++v) {
+    const int64_t row = v * n_pix + px;
     for (int ch = ch0; row_ok && ch < cpr; ch += kThreads) {
       const int k0 = ch * 8;
       float out[8];
@@ -161,8 +168,8 @@ __global__ __launch_bounds__(kThreads) void normalize_kernel(
       __syncthreads();
       for (int o = t; o < R * kPoolIn; o += kThreads) {
         const int orow = o / kPoolIn, i = o - orow * kPoolIn;
-        const int64_t prow = g0 + orow;
-        if (prow >= n_rows) continue;
+        if (pg * R + orow >= n_pix) continue;
+        const int64_t prow = v * n_pix + pg * R + orow;
         const int lo = (i * nki) / kPoolIn, hi = ((i + 1) * nki + kPoolIn - 1) / kPoolIn;
         float sum = 0.0f;
         for (int c = lo; c < hi; ++c) sum += rowbuf[orow * nki + c];
@@ -174,6 +181,7 @@ __global__ __launch_bounds__(kThreads) void normalize_kernel(
       }
       __syncthreads();
     }
+   }
   }
   // Block reduction of the float64 sum of squares, fixed order.
   __shared__ double red[2][kThreads / 64];
@@ -197,13 +205,14 @@ __global__ __launch_bounds__(kThreads) void normalize_kernel(
 
 // Fast path for uint16 counts whose rows split into whole 8-bin chunks
 // (n_k % 8 == 0, n_k <= 2048, 16-byte aligned rows, p present, p_bf16 absent
-// or 16-byte aligned, its row at most 2048 wide): one chunk per thread per row group, straight-line code with
-// the options fixed at compile time.  Same values, the same rows per block
-// and the same summation order as normalize_kernel (bitwise equal outputs);
-// measured about 25 % faster at 1024 and 2000 bins.
+// or 16-byte aligned, its row at most 2048 wide): one chunk per thread per
+// row, straight-line code with the options fixed at compile time, and the
+// open-beam chunk kept in registers across the unit's views.  Same values,
+// the same units per block and the same summation order as normalize_kernel
+// (bitwise equal outputs).
 template <int POOL, bool HAS_B, bool HAS_PB>
 __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
-    const uint16_t *__restrict__ y, const uint16_t *__restrict__ yo, int64_t n_rows, int64_t n_pix, int nk,
+    const uint16_t *__restrict__ y, const uint16_t *__restrict__ yo, int64_t n_v, int64_t vc, int64_t n_pix, int nk,
     const float *__restrict__ b, float floor_, int clip, float *__restrict__ p, int64_t ldp,
     uint16_t *__restrict__ pb, int64_t ldb, void *__restrict__ pooled, double *__restrict__ partial) {
   __shared__ float rowbuf[POOL ? kPoolMaxBins : 1];
@@ -216,14 +225,20 @@ __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
   const int t = threadIdx.x;
   const int rr = t / cpw, k0 = (t - rr * cpw) * 8;
   double ss = 0.0, sb = 0.0;
-  for (int64_t g0 = int64_t(blockIdx.x) * R; g0 < n_rows; g0 += int64_t(gridDim.x) * R) {
-    const int64_t row = g0 + rr;
-    if (HAS_PB && rr < R && row < n_rows && k0 >= nk)
+  const int64_t n_pg = (n_pix + R - 1) / R, n_ch = (n_v + vc - 1) / vc;
+  for (int64_t u = blockIdx.x; u < n_pg * n_ch; u += gridDim.x) {
+   const int64_t pg = u / n_ch, v0 = (u - pg * n_ch) * vc;
+   const int64_t v1 = v0 + vc < n_v ? v0 + vc : n_v;
+   const int64_t px = pg * R + rr;
+   const bool ok = rr < R && px < n_pix;
+   uint4 ov = make_uint4(0, 0, 0, 0);
+   if (ok && k0 < nk) ov = *reinterpret_cast<const uint4 *>(yo + px * nk + k0);
+   for (int64_t v = v0; v < v1; ++v) {
+    const int64_t row = v * n_pix + px;
+    if (HAS_PB && ok && k0 >= nk)
       *reinterpret_cast<uint4 *>(pb + row * ldb + k0) = make_uint4(0, 0, 0, 0);
-    if (rr < R && row < n_rows && k0 < nk) {
-      const int64_t v = row / n_pix, px = row - v * n_pix;
+    if (ok && k0 < nk) {
       const uint4 yv = *reinterpret_cast<const uint4 *>(y + row * nk + k0);
-      const uint4 ov = *reinterpret_cast<const uint4 *>(yo + px * nk + k0);
       const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w};
       const uint32_t ow[4] = {ov.x, ov.y, ov.z, ov.w};
       float out[8];
@@ -260,8 +275,8 @@ __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
       __syncthreads();
       for (int o = t; o < R * kPoolIn; o += kThreads) {
         const int orow = o / kPoolIn, i = o - orow * kPoolIn;
-        const int64_t prow = g0 + orow;
-        if (prow >= n_rows) continue;
+        if (pg * R + orow >= n_pix) continue;
+        const int64_t prow = v * n_pix + pg * R + orow;
         const int lo = (i * nk) / kPoolIn, hi = ((i + 1) * nk + kPoolIn - 1) / kPoolIn;
         float sum = 0.0f;
         for (int c = lo; c < hi; ++c) sum += rowbuf[orow * nk + c];
@@ -273,6 +288,7 @@ __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
       }
       __syncthreads();
     }
+   }
   }
   __shared__ double red[2][kThreads / 64];
   ss = hsn::wave_sum_all(ss);
@@ -294,11 +310,11 @@ __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
 }
 
 template <int POOL>
-void launch_norm_u16(int64_t n_rows, int64_t n_pix, int64_t nk, const uint16_t *y, const uint16_t *yo, const float *b,
+void launch_norm_u16(int64_t n_v, int64_t vc, int64_t n_pix, int64_t nk, const uint16_t *y, const uint16_t *yo, const float *b,
                      float floor_, int clip, float *p, int64_t ldp, uint16_t *pb, int64_t ldb, void *pooled,
                      double *partial, hipStream_t st) {
 #define HSN_NORM16(B, PB)                                                                                    \
-  normalize_u16_kernel<POOL, B, PB><<<kSumBlocks, kThreads, 0, st>>>(y, yo, n_rows, n_pix, int(nk), b, floor_, \
+  normalize_u16_kernel<POOL, B, PB><<<kSumBlocks, kThreads, 0, st>>>(y, yo, n_v, vc, n_pix, int(nk), b, floor_, \
                                                                      clip, p, ldp, pb, ldb, pooled, partial)
   if (b) {
     if (pb) HSN_NORM16(true, true); else HSN_NORM16(true, false);
@@ -323,10 +339,10 @@ __global__ void sum_partials_kernel(const double *__restrict__ partial, int n, d
 }
 
 template <typename TY, typename TO, bool VEC, int POOL>
-void launch_norm(int64_t n_rows, int64_t n_pix, int64_t nk, const TY *y, const TO *yo, const float *b, float floor_,
+void launch_norm(int64_t n_v, int64_t vc, int64_t n_pix, int64_t nk, const TY *y, const TO *yo, const float *b, float floor_,
                  int clip, float *p, int64_t ldp, uint16_t *pb, int64_t ldb, void *pooled, double *partial,
                  hipStream_t st) {
-  normalize_kernel<TY, TO, VEC, POOL><<<kSumBlocks, kThreads, 0, st>>>(y, yo, n_rows, n_pix, nk, b, floor_, clip, p,
+  normalize_kernel<TY, TO, VEC, POOL><<<kSumBlocks, kThreads, 0, st>>>(y, yo, n_v, vc, n_pix, nk, b, floor_, clip, p,
                                                                        ldp, pb, ldb, pooled, partial);
 }
 
@@ -340,7 +356,16 @@ hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo
                       float *offset_b, double *sumsq, double *bf16_bias, void *pooled, int pool_mode,
                       hipStream_t st, double *scratch = nullptr) {
   const int64_t n_pix = d->n_rows * d->n_cols;
-  const int64_t n_rows = d->n_views * n_pix;
+  const int64_t n_v = d->n_views;
+  // Views per unit: all of them while the pixel groups alone give every
+  // block at least 8 units, else fewer (the units' count is n_pg n_ch).
+  const int64_t width = (pb && ldb > d->n_bins) ? ldb : d->n_bins;
+  const int64_t cpr = (width + 7) / 8;
+  const int64_t R = cpr <= kThreads ? kThreads / cpr : 1;
+  const int64_t n_pg = (n_pix + R - 1) / R;
+  const int64_t want_ch = (8 * int64_t(kSumBlocks) + n_pg - 1) / n_pg;
+  const int64_t n_ch = want_ch < 1 ? 1 : (want_ch > n_v ? n_v : want_ch);
+  const int64_t vc = (n_v + n_ch - 1) / n_ch;
   const int64_t nk = d->n_bins;
   double *partial = scratch;
   float *b = nullptr;
@@ -364,17 +389,17 @@ hsn_status launch_all(hsn_ctx *ctx, const hsn_dims *d, const TY *y, const TO *yo
                    (!p || (ldp % 4 == 0 && reinterpret_cast<uintptr_t>(p) % 16 == 0)) &&
                    (!pb || reinterpret_cast<uintptr_t>(pb) % 16 == 0);
   if (!scratch) hsn::prof_begin(ctx, HSN_KERN_NORMALIZE, st);
-#define HSN_NORM(V, P) launch_norm<TY, TO, V, P>(n_rows, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st)
+#define HSN_NORM(V, P) launch_norm<TY, TO, V, P>(n_v, vc, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st)
   bool fast = false;
   if constexpr (std::is_same<TY, uint16_t>::value && std::is_same<TO, uint16_t>::value) {
     fast = vec && p && nk <= kPoolMaxBins && (!pb || ldb <= 8 * kThreads);
     if (fast) {
       if (pool_mode == 0)
-        launch_norm_u16<0>(n_rows, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st);
+        launch_norm_u16<0>(n_v, vc, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st);
       else if (pool_mode == 1)
-        launch_norm_u16<1>(n_rows, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st);
+        launch_norm_u16<1>(n_v, vc, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st);
       else
-        launch_norm_u16<2>(n_rows, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st);
+        launch_norm_u16<2>(n_v, vc, n_pix, nk, y, yo, b, floor_, clip, p, ldp, pb, ldb, pooled, partial, st);
     }
   }
   if (!fast && vec) {

@@ -42,7 +42,8 @@ class NmfOpts(C.Structure):
     _fields_ = [("k", C.c_int), ("algo", C.c_int), ("precision", C.c_int), ("init", C.c_int),
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("polish_rounds", C.c_int),
                 ("polish_algo", C.c_int), ("polish_bf16_rounds", C.c_int), ("rel_obj_tol", C.c_double),
-                ("f_ref", C.c_double), ("mlp", C.c_void_p), ("mlp_pooled", C.c_void_p), ("bf16_bias", C.c_void_p)]
+                ("f_ref", C.c_double), ("mlp", C.c_void_p), ("mlp_pooled", C.c_void_p), ("bf16_bias", C.c_void_p),
+                ("mlp_fallback_rel", C.c_double)]
 
 
 class TrainOpts(C.Structure):
@@ -53,7 +54,7 @@ class TrainOpts(C.Structure):
 class NmfStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("polish_done", C.c_int), ("objective", C.c_double), ("rel_obj", C.c_double),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int),
-                ("ms", C.c_float), ("polish_bf16_done", C.c_int)]
+                ("ms", C.c_float), ("polish_bf16_done", C.c_int), ("fell_back", C.c_int)]
 
 
 class NmfProblem(C.Structure):
@@ -344,10 +345,12 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
                      check_every: int = 10, polish_rounds: int = 0, polish_algo: int = ALGO_ANLS,
                      polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0,
                      init: int = INIT_USER, mlp: Optional["Mlp"] = None, history_cap: int = 4096,
-                     mlp_pooled: Optional[torch.Tensor] = None, bf16_bias: Optional[torch.Tensor] = None) -> dict:
+                     mlp_pooled: Optional[torch.Tensor] = None, bf16_bias: Optional[torch.Tensor] = None,
+                     mlp_fallback_rel: float = 0.0) -> dict:
     """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device).  bf16_bias: the f64
     device scalar -||p - p_bf16||^2 (hsn_normalize want_bias) for the stop test of the
-    polish rounds on p_bf16."""
+    polish rounds on p_bf16.  mlp_fallback_rel > 0: a learned start whose first objective is
+    further than this above f_ref is replaced by NNDSVDa (stats fell_back)."""
     _need(V, "V", torch.float32, shape=(None, None))
     n_p, k = V.shape
     _need(D, "D", torch.float32, shape=(n_k, k), device=V.device)
@@ -363,9 +366,9 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
     _opt(bf16_bias, "bf16_bias", torch.float64, shape=(), device=V.device)
     opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo,
                    polish_bf16_rounds, rel_obj_tol, f_ref, mlp.handle if mlp is not None else None,
-                   _ptr(mlp_pooled), _ptr(bf16_bias))
+                   _ptr(mlp_pooled), _ptr(bf16_bias), float(mlp_fallback_rel))
     hist = (C.c_double * max(history_cap, 1))()
-    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0, 0)
+    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0, 0, 0)
     ldp = p.stride(0) if p is not None else 0
     ldb = p_bf16.stride(0) if p_bf16 is not None else 0
     _check(_lib.hsn_subspace_nmf(ctx, _ptr(p), ldp, _ptr(p_bf16), ldb, n_p, n_k, _ptr(V), _ptr(D), C.byref(opts),
@@ -375,7 +378,8 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
 
 def _stats(s, hist) -> dict:
     return dict(iters=s.iters, polish_done=s.polish_done, polish_bf16_done=s.polish_bf16_done, objective=s.objective,
-                rel_obj=s.rel_obj, history=[hist[i] for i in range(s.history_len)], ms=s.ms)
+                rel_obj=s.rel_obj, history=[hist[i] for i in range(s.history_len)], ms=s.ms,
+                fell_back=bool(s.fell_back))
 
 
 def hsn_nmf_set_launch(anls_passes: int = 0, device: int = 0) -> None:
@@ -485,7 +489,7 @@ def hsn_fhr_step(y: torch.Tensor, yo: torch.Tensor, V: torch.Tensor, D: torch.Te
                  bufs: Optional[dict] = None, algo: int = ALGO_MU, precision: int = PREC_FP32, max_iter: int = 100,
                  check_every: int = 10, polish_rounds: int = 0, polish_algo: int = ALGO_ANLS,
                  polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0, init: int = INIT_USER,
-                 mlp: Optional["Mlp"] = None, history_cap: int = 4096):
+                 mlp: Optional["Mlp"] = None, history_cap: int = 4096, mlp_fallback_rel: float = 0.0):
     """The whole FHR path of one scan in one C call: counts y [N_v][N_r][N_c][N_k] and y^o (uint16 bits
     as int16) -> V, D in place, x [N_r][N_c][N_c][K], and x^h over vox x bins (None if vox is None).
     bufs: optional dict that keeps the intermediates (p, pooled) and outputs (x, xh) between calls."""
@@ -517,9 +521,10 @@ def hsn_fhr_step(y: torch.Tensor, yo: torch.Tensor, V: torch.Tensor, D: torch.Te
         bufs["xh"] = torch.empty((ve - vb, be - bb), dtype=torch.float32, device=y.device)
     xh = bufs.get("xh") if vox is not None else None
     opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo, polish_bf16_rounds,
-                   rel_obj_tol, f_ref, mlp.handle if mlp is not None else None, None, None)
+                   rel_obj_tol, f_ref, mlp.handle if mlp is not None else None, None, None,
+                   float(mlp_fallback_rel))
     hist = (C.c_double * max(history_cap, 1))()
-    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0, 0)
+    stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0, 0, 0)
     keep = (C.c_double * n_v)(*[float(a) for a in angles]) if angles is not None else None
     yd = F32 if y.dtype == torch.float32 else U16
     od = F32 if yo.dtype == torch.float32 else U16

@@ -271,3 +271,39 @@ def test_nmf_learned_start(hsn):
     m4 = hsn.hsn_mlp_create(4, hsn.PREC_BF16, None)
     with pytest.raises(hsn.HsnError):
         hsn.hsn_subspace_nmf(p, pb, n_k, V, D, init=hsn.INIT_MLP, mlp=m4, max_iter=0)
+
+
+def test_learned_start_falls_back_to_nndsvda(hsn):
+    # A learned start whose first objective is too far above f_ref (here an
+    # untrained network and a threshold no start meets) is replaced by
+    # NNDSVDa: the run then equals, bit for bit, the same schedule started
+    # from NNDSVDa directly, and reports fell_back.  With a loose threshold
+    # the learned start is kept.
+    sc = synth.config_scan("tiny")
+    y = torch.from_numpy(sc.y.view(np.int16)).cuda()
+    yo = torch.from_numpy(sc.yo.view(np.int16)).cuda()
+    p, pb, _, _, bias = hsn.hsn_normalize(y, yo, want_bf16=True, want_bias=True)
+    n_p, n_k, k = sc.n_p, sc.n_bins, 3
+    kw = dict(max_iter=0, polish_rounds=24, polish_bf16_rounds=16, polish_algo=hsn.ALGO_ANLS, bf16_bias=bias)
+    Vr = torch.zeros((n_p, k), device="cuda")
+    Dr = torch.zeros((n_k, k), device="cuda")
+    ref = hsn.hsn_subspace_nmf(p, pb, n_k, Vr, Dr, init=hsn.INIT_NNDSVDA, max_iter=0, polish_rounds=60,
+                               polish_algo=hsn.ALGO_ANLS)
+    f_ref = min(ref["history"])
+    kw.update(rel_obj_tol=1e-3, f_ref=f_ref)
+    V1 = torch.zeros((n_p, k), device="cuda")
+    D1 = torch.zeros((n_k, k), device="cuda")
+    st1 = hsn.hsn_subspace_nmf(p, pb, n_k, V1, D1, init=hsn.INIT_NNDSVDA, **kw)
+    m = hsn.hsn_mlp_create(k, hsn.PREC_BF16, _params(k, 120))
+    V2 = torch.zeros_like(V1)
+    D2 = torch.zeros_like(D1)
+    show("learned start fallback")
+    st2 = hsn.hsn_subspace_nmf(p, pb, n_k, V2, D2, init=hsn.INIT_MLP, mlp=m, mlp_fallback_rel=1e-12, **kw)
+    assert st2["fell_back"] and not st1["fell_back"]
+    assert torch.equal(V2, V1) and torch.equal(D2, D1)
+    for key in ("polish_done", "polish_bf16_done", "history"):
+        assert st2[key] == st1[key]
+    V3 = torch.zeros_like(V1)
+    D3 = torch.zeros_like(D1)
+    st3 = hsn.hsn_subspace_nmf(p, pb, n_k, V3, D3, init=hsn.INIT_MLP, mlp=m, mlp_fallback_rel=1e12, **kw)
+    assert not st3["fell_back"]

@@ -209,6 +209,39 @@ def test_bf16_anls_polish_without_stop_runs_every_round(hsn):
     assert np.all(np.diff(st["history"][1:]) <= 1e-6 * st["history"][1])
 
 
+@pytest.mark.parametrize("algo", ["anls", "hals"])
+def test_bf16_polish_rounds_then_fp32_against_oracle(hsn, algo):
+    # polish_bf16_rounds honoured for both polish algorithms: 2 rounds on the
+    # bfloat16 p, then 1 on the float32 p, against the oracle's same three
+    # rounds (on the bfloat16-rounded p, then on p).  Each round adds at most
+    # its one-round bound (2e-5, or cond(G) 2^-16 for the exact solves).
+    p32 = _problem((400, 96), 3, 5)
+    n_p, n_k = p32.shape
+    pb, bits = _bf16_dev(p32, n_k)
+    pq = _bits_to_f64(bits)
+    pf = torch.from_numpy(np.ascontiguousarray(p32)).cuda()
+    V0, D0 = synth.random_factors(n_p, n_k, 3, 8)
+    V0 = V0.astype(np.float32).astype(np.float64)
+    D0 = D0.astype(np.float32).astype(np.float64)
+    step = {"anls": onmf.anls_round, "hals": onmf.hals_step}[algo]
+    Vr, Dr = V0, D0
+    conds = []
+    for P in (pq, pq, p32.astype(np.float64)):
+        conds.append(max(np.linalg.cond(Dr.T @ Dr), np.linalg.cond(Vr.T @ Vr)))
+        Vr, Dr, _, _ = step(P, Vr, Dr)
+    V = to_dev(V0, torch.float32)
+    D = to_dev(D0, torch.float32)
+    code = {"anls": hsn.ALGO_ANLS, "hals": hsn.ALGO_HALS}[algo]
+    st = hsn.hsn_subspace_nmf(pf, pb, n_k, V, D, max_iter=0, polish_rounds=3, polish_bf16_rounds=2,
+                              polish_algo=code)
+    assert st["polish_done"] == 3 and st["polish_bf16_done"] == 2
+    ev, ed = rel_fro(V.cpu().numpy(), Vr), rel_fro(D.cpu().numpy(), Dr)
+    per = [2e-5 if algo == "hals" else max(2e-5, c * 2.0 ** -16) for c in conds]
+    tol = 3 * sum(per)
+    show("bf16 polish rounds then fp32", algo=algo, V=ev, D=ed, tol=tol)
+    assert ev <= tol and ed <= tol
+
+
 def test_mid_bf16_bulk_then_fp32_polish_against_oracle(hsn):
     # The mid workload's BF16 schedule (100 MU iterations on the bfloat16 p
     # on MFMA, then 15 float32 ANLS rounds) against the float64 oracle's run
