@@ -118,7 +118,8 @@ hsn_status queue_step(Run &R, const Step &s, int iter, bool next_exact, const fl
     prof_begin(R.ctx, s.bf16 ? HSN_KERN_NMF_PASS_BF16 : HSN_KERN_NMF_PASS, R.st);
     if (s.bf16) {
       const bool ok = launch_pass_bf16(R.K, s.rule, obj, n_wg, R.st, pb, ldb, R.n_p, R.n_k, V, R.w.gd, R.w.chol,
-                                       R.w.img, R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter, R.w.ginv);
+                                       R.w.img, R.w.part_nd, R.w.part_gv, R.w.part_obj, R.w.ctrl, iter,
+                                       R.w.ginv16 ? R.w.ginv16 : R.w.ginv);
       prof_end(R.ctx, HSN_KERN_NMF_PASS_BF16, R.st);
       if (!ok) return fail(R.ctx, HSN_ERR_UNSUPPORTED, "bf16 pass: unsupported shape (ldb <= 2048, k <= 8)");
     } else {
@@ -198,7 +199,9 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
                                     sizeof(float) * size_t(n_wg) * n_k * K, sizeof(double) * size_t(n_wg) * K * K,
                                     sizeof(double) * n_wg, sizeof(double) * size_t(n_upd) * K * K,
                                     need_nv ? sizeof(float) * n_p * K : 0, sizeof(double) * hist_cap,
-                                    any_bf16 ? sizeof(uint16_t) * bf16_image_elems(ldb) : 0});
+                                    any_bf16 ? sizeof(uint16_t) * bf16_image_elems(ldb) : 0,
+                                    any_bf16 ? sizeof(double) * size_t(n_upd) * K * K : 0,
+                                    any_bf16 ? sizeof(double) * kCholStride * kInvStride : 0});
   // NNDSVD runs before any NMF kernel on the same stream, so its scratch can
   // share the workspace with the decomposition's.
   int n_split = 1;
@@ -228,6 +231,11 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   R.w.nv = need_nv ? cv.take<float>(n_p * K) : nullptr;
   R.w.hist = cv.take<double>(hist_cap);
   R.w.img = any_bf16 ? cv.take<uint16_t>(bf16_image_elems(ldb)) : nullptr;
+  // The steps on p_bf16 solve V rows with G_D' (the Gram of the bfloat16
+  // split of D that their products use), so that a row's least cost gives
+  // its objective exactly.
+  R.w.part_gd16 = any_bf16 ? cv.take<double>(size_t(n_upd) * K * K) : nullptr;
+  R.w.ginv16 = any_bf16 ? cv.take<double>(size_t(kCholStride) * kInvStride) : nullptr;
   void *pool_buf = need_pool ? cv.take<char>(need_pool - 256) : nullptr;
   R.w.n_wg = n_wg;
   R.wg_f32 = wg_f32;
@@ -249,12 +257,12 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   }
   for (int r = 0; r < o->polish_rounds; ++r) {
     const int rule = o->polish_algo == HSN_ALGO_ANLS ? kModeANLS : kModeHALS;
-    // Polish rounds on p_bf16 evaluate the objective every kBf16PolishCheck-th
-    // round and on the last one (the objective costs the bfloat16 pass a third
-    // of its time; those rounds only approach the tolerance, the float32 rounds
-    // decide the stop); float32 polish rounds evaluate it every round.
+    // HALS polish rounds on p_bf16 evaluate the objective every
+    // kBf16PolishCheck-th round and on the last one (its reconstruction costs
+    // the bfloat16 pass a third of its time); ANLS rounds have it from their
+    // row solves and float32 rounds from their residual: every round.
     const bool on_bf16 = r < pol_bf16;
-    const bool obj = !on_bf16 || (r + 1) % kBf16PolishCheck == 0 || r + 1 == pol_bf16;
+    const bool obj = !on_bf16 || rule == kModeANLS || (r + 1) % kBf16PolishCheck == 0 || r + 1 == pol_bf16;
     steps.push_back({rule, on_bf16, obj});
   }
   // The steps on p_bf16 form one run [bf16_lo, first_f32): the bulk when its

@@ -18,7 +18,10 @@
 //      stay in registers for the whole pass;
 //   5. on objective iterations, V_new D^T is rebuilt on MFMA 16x16x32 from
 //      [V_hi | V_lo | V_hi] x [D_hi ; D_hi ; D_lo] and ||P - V_new D^T||^2 is
-//      accumulated against the same bfloat16 P values.
+//      accumulated against the same bfloat16 P values (MU, HALS); an ANLS
+//      pass solves each row exactly for D' = D_hi + D_lo (inverses of G_D'),
+//      so a row's objective is ||p_row||^2 + 2 q_min with q_min the least
+//      cost of its enumeration, and ||p_row||^2 comes from the N_V operands.
 // p is read from HBM exactly once per iteration; everything else stays on chip.
 #include "nmf_common.hpp"
 
@@ -37,13 +40,19 @@ constexpr int kMaxLdb = 2048;
 // at or beyond ldb load as zeros.  The load code is branch-free (clamped
 // address + select) so the compiler can count outstanding loads exactly and
 // the prefetched tiles stay in flight across the tile's compute.  With NW <= 4
-// the registers left over hold a second tile of loads in flight (NBUF = 2).
+// the registers left over hold a second tile of loads in flight (NBUF = 2);
+// with NW = 8 a second tile did not fit (MU, HALS) or ran slower (ANLS:
+// 8.1 against 7.7 ms at 2000 bins).
 __host__ __device__ inline int64_t bf16_ldb_pad(int64_t ldb) {
   const int64_t nw = (ldb + 255) / 256;
   return 256 * (nw <= 1 ? 1 : nw <= 2 ? 2 : nw <= 4 ? 4 : 8);
 }
 
-__host__ __device__ inline int bf16_pitch(int64_t ldb) { return int(2 * bf16_ldb_pad(ldb) + 8); }
+// Row pitch of the LDS tile in bytes: 4 (mod 64) banks past a whole row, so
+// the 16-byte reads of the N_V operand (16 rows, one 16-byte chunk each per
+// 16 lanes) and the 2-byte transposed reads of the N_D operand (rows 4 g + q,
+// 16 bins, g = lane / 16) fall on distinct banks.
+__host__ __device__ inline int bf16_pitch(int64_t ldb) { return int(2 * bf16_ldb_pad(ldb) + 16); }
 
 struct Bf16Lds {
   int tile, db1, red, vsp, vnw, vold, gd, obj, hsum, ginv, total;
@@ -166,22 +175,21 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
 
   auto do_tile = [&](uint4 (&pr)[kKSW], float &vv, int64_t tile) {
     const int64_t row0 = tile * kBRows;
-    // 1. this wave's bins of the tile -> LDS (8-byte stores: the padded pitch
-    //    keeps the transposed reads below free of bank conflicts)
+    // 1. this wave's bins of the tile -> LDS (16-byte stores)
 #pragma unroll
     for (int i = 0; i < kKSW; ++i) {
       if (i < nw) {
         const int c = lane + 64 * i;
         const int r = c / cpr, cc = c - (c / cpr) * cpr;
-        uint2 *dst = reinterpret_cast<uint2 *>(tileL + r * pitch + 2 * (32 * s0 + 8 * cc));
-        dst[0] = make_uint2(pr[i].x, pr[i].y);
-        dst[1] = make_uint2(pr[i].z, pr[i].w);
+        *reinterpret_cast<uint4 *>(tileL + r * pitch + 2 * (32 * s0 + 8 * cc)) = pr[i];
       }
     }
-    if (t < kBRows * K) vold[t] = vv;
+    if (MODE != kModeANLS && t < kBRows * K) vold[t] = vv;
     // prefetch the tile NBUF steps ahead into the same registers
     if (tile + NBUF * G < n_tiles) load_tile(pr, vv, (tile + NBUF * G) * kBRows);
-    __syncthreads();
+    // A wave reads only its own bins of the tile, so only vold (not used by
+    // the exact solves) needs the barrier.
+    if constexpr (MODE != kModeANLS) __syncthreads();
 
     // 2. N_V partial over this wave's bins (not for N_D alone)
     if constexpr (MODE != kModeND) {
@@ -190,12 +198,23 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
     for (int i = 0; i < kKSW; ++i) {
       if (i < nw) {
         const int s = s0 + i;
-        const uint2 *src = reinterpret_cast<const uint2 *>(tileL + (lane & 15) * pitch + 2 * (32 * s + 8 * (lane >> 4)));
-        const uint2 lo = src[0], hi = src[1];
-        const uint4 av = make_uint4(lo.x, lo.y, hi.x, hi.y);
+        const uint4 av =
+            *reinterpret_cast<const uint4 *>(tileL + (lane & 15) * pitch + 2 * (32 * s + 8 * (lane >> 4)));
         const uint4 bv = db1L[s * 64 + lane];
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
                                                        acc1, 0, 0, 0);
+        if constexpr (OBJ && MODE == kModeANLS) {
+          // ||p||^2 of the tile: every element once over (wave, k-step, lane);
+          // the squares are exact in float32
+          const uint32_t wd[4] = {av.x, av.y, av.z, av.w};
+          float sq = 0.0f;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float v = bf16_bits_to_f32(uint16_t(wd[e >> 1] >> (16 * (e & 1))));
+            sq = fmaf(v, v, sq);
+          }
+          obj += double(sq);
+        }
       }
     }
 #pragma unroll
@@ -228,7 +247,11 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
       float h[K];
 #pragma unroll
       for (int j = 0; j < K; ++j) h[j] = hsum[r * 8 + j];
-      const double xl = nnls_enum_group<K, bf16_inv_in_lds(K) ? (1 << K) : kInvStride>(ginv_s, h, l);
+      double qmin = 0.0;
+      const double xl =
+          nnls_enum_group<K, bf16_inv_in_lds(K) ? (1 << K) : kInvStride>(ginv_s, h, l, OBJ ? &qmin : nullptr);
+      // the row's objective at its exact solution is ||p_row||^2 + 2 qmin
+      if (OBJ && l == 0 && row < n_p) obj += 2.0 * qmin;
       if (l < K) {
         float vn = float(xl);
         if (row >= n_p) vn = 0.0f;
@@ -295,7 +318,10 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
 #pragma unroll
     for (int q = 0; q < 4; ++q) b2[q] = short(vsp[(4 * (lane >> 4) + q) * 16 + (lane & 15)]);
     bf16x8 a3;
-    if (OBJ) {
+    // the reconstruction objective (MU, HALS); an ANLS pass has its objective
+    // from the row solves
+    constexpr bool RECON = OBJ && MODE != kModeANLS;
+    if (RECON) {
       const int g = lane >> 4, row = lane & 15;
       uint16_t u[8];
 #pragma unroll
@@ -315,7 +341,7 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
 #pragma unroll
           for (int q = 0; q < 4; ++q) a2[q] = *reinterpret_cast<const short *>(col + (4 * (lane >> 4) + q) * pitch);
           acc2[2 * i + hh] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, b2, acc2[2 * i + hh], 0, 0, 0);
-          if (OBJ) {
+          if (RECON) {
             const uint4 b3 = db3g[(bin0 / 16) * 64 + lane];
             f32x4 rec = {0.f, 0.f, 0.f, 0.f};
             rec = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, __builtin_bit_cast(bf16x8, b3), rec, 0, 0, 0);
@@ -328,7 +354,7 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
         }
       }
     }
-    if (OBJ) obj += double(objf);
+    if (RECON) obj += double(objf);
   };
   if (NBUF == 2) {
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += 2 * G) {
@@ -388,18 +414,20 @@ static bool launch_bf16_inst(int n_wg, hipStream_t st, const uint16_t *Pb, int64
   return true;
 }
 
-template <int K, int NW, int NBUF>
+// NB_MU: tiles in flight for MU and HALS (their objective reconstruction
+// needs registers), NB_X: for ANLS and N_D alone.
+template <int K, int NW, int NB_MU, int NB_X>
 static bool launch_bf16_kw(int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb, int64_t n_p,
                            int n_k, float *V, const uint4 *db1, const uint4 *db3, const double *GD, const double *chol,
                            float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
                            const double *ginv) {
-#define HSN_INST(M_, O_) \
-  launch_bf16_inst<K, M_, O_, NW, NBUF>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd, part_gv, part_obj, \
-                                        ctrl, iter, ginv)
-  if (mode == kModeANLS) return obj ? HSN_INST(kModeANLS, true) : HSN_INST(kModeANLS, false);
-  if (mode == kModeND) return HSN_INST(kModeND, false);
-  if (mode == kModeMU) return obj ? HSN_INST(kModeMU, true) : HSN_INST(kModeMU, false);
-  if (mode == kModeHALS) return obj ? HSN_INST(kModeHALS, true) : HSN_INST(kModeHALS, false);
+#define HSN_INST(M_, O_, NB_) \
+  launch_bf16_inst<K, M_, O_, NW, NB_>(n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd, part_gv, part_obj, \
+                                       ctrl, iter, ginv)
+  if (mode == kModeANLS) return obj ? HSN_INST(kModeANLS, true, NB_X) : HSN_INST(kModeANLS, false, NB_X);
+  if (mode == kModeND) return HSN_INST(kModeND, false, NB_X);
+  if (mode == kModeMU) return obj ? HSN_INST(kModeMU, true, NB_MU) : HSN_INST(kModeMU, false, NB_MU);
+  if (mode == kModeHALS) return obj ? HSN_INST(kModeHALS, true, NB_MU) : HSN_INST(kModeHALS, false, NB_MU);
   return false;
 #undef HSN_INST
 }
@@ -410,11 +438,11 @@ static bool launch_bf16_k(int mode, bool obj, int n_wg, hipStream_t st, const ui
                           float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,
                           const double *ginv) {
   const int64_t nw = bf16_ldb_pad(ldb) / 256;
-#define HSN_NW(NW_, NB_)                                                                                           \
+#define HSN_NW(NW_, NB_MU_, NB_X_)                                                                                 \
   if (nw == NW_)                                                                                                   \
-    return launch_bf16_kw<K, NW_, NB_>(mode, obj, n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol, part_nd,     \
-                                       part_gv, part_obj, ctrl, iter, ginv);
-  HSN_NW(1, 2) HSN_NW(2, 2) HSN_NW(4, 2) HSN_NW(8, 1)
+    return launch_bf16_kw<K, NW_, NB_MU_, NB_X_>(mode, obj, n_wg, st, Pb, ldb, n_p, n_k, V, db1, db3, GD, chol,    \
+                                                 part_nd, part_gv, part_obj, ctrl, iter, ginv);
+  HSN_NW(1, 2, 2) HSN_NW(2, 2, 2) HSN_NW(4, 2, 2) HSN_NW(8, 1, 1)
 #undef HSN_NW
   return false;
 }

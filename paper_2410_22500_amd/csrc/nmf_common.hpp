@@ -63,6 +63,8 @@ struct NmfWork {
   double *part_gd;   // [update blocks][K*K]
   float *nv;         // [n_p][K] N_V for the row-wise NNLS
   double *ginv;      // [36][kInvStride] inverses of the principal submatrices of G_D (entry-major)
+  double *part_gd16; // [update blocks][K*K] partials of G_D' (or null), D' = the bfloat16 hi + lo split of D
+  double *ginv16;    // [36][kInvStride] inverses of the principal submatrices of G_D' (or null)
   double *hist;      // [hist_cap] objective history (device)
   uint16_t *img;     // bfloat16 operand images of D for the MFMA pass (or null)
   int n_wg;
@@ -243,8 +245,9 @@ constexpr int kInvStride = 256;
 // minimiser (unique when G is positive definite).  Ties in q go to the lower
 // mask, x = 0 (empty support, q = 0) is always a candidate.  Lane l < K of
 // the group then forms x_l = z_l of the winning support itself and returns
-// it (the other lanes return 0), so no lane keeps a z.  The 32 lanes must be
-// converged.  ginv: entry-major inverses with stride STRIDE (see above).
+// it (the other lanes return 0), so no lane keeps a z; q_min (optional)
+// receives the least cost in every lane.  The 32 lanes must be converged.
+// ginv: entry-major inverses with stride STRIDE (see above).
 // One exchange of the (cost, mask) minimum with the partner lane that DPP
 // control CTRL names (a permutation within each row of 16 lanes).
 template <int CTRL>
@@ -261,7 +264,8 @@ __device__ __forceinline__ void enum_min_step(double &q, int &m) {
 }
 
 template <int K, int STRIDE>
-__device__ __forceinline__ double nnls_enum_group(const double *__restrict__ ginv, const float (&h)[K], int l) {
+__device__ __forceinline__ double nnls_enum_group(const double *__restrict__ ginv, const float (&h)[K], int l,
+                                                  double *__restrict__ q_min = nullptr) {
   double best_q = 0.0;
   int best_m = 0;
   for (int m = l; m < (1 << K); m += 32) {
@@ -307,6 +311,7 @@ __device__ __forceinline__ double nnls_enum_group(const double *__restrict__ gin
       best_m = om;
     }
   }
+  if (q_min) *q_min = best_q;  // the row's least cost: its objective is ||p_row||^2 + 2 q_min
   double x = 0.0;
   if (l < K && best_m != 0) {
 #pragma unroll

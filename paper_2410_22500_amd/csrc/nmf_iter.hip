@@ -51,11 +51,18 @@ __device__ inline void write_images_row(uint16_t *__restrict__ img, int64_t ldb,
     }
 }
 
+// D' entry of a float32 D entry: the bfloat16 hi + lo split that the MFMA
+// pass multiplies with (exact in float32: 8 + 8 significand bits).
+__device__ __forceinline__ float split_value(float v) {
+  return bf16_bits_to_f32(bf_hi(v)) + bf16_bits_to_f32(bf_lo(v));
+}
+
 // Factors of all principal submatrices G[S,S] of G (K x K, in LDS) -> chol
 // (packed lower, compact index order); with ginv, also their inverses
 // G[S,S]^-1 = L^-T L^-1, embedded in a packed symmetric K x K matrix with
 // zeros outside S, entry-major with stride kInvStride (the operand of
 // nnls_enum_group).  A singular G[S,S] gets NaN as the first entry of both.
+// chol may be null (inverses only).
 template <int K>
 __device__ inline void factor_all(const double *G, double *__restrict__ chol, double *__restrict__ ginv = nullptr) {
   for (int m = threadIdx.x; m < (1 << K); m += blockDim.x) {
@@ -63,7 +70,8 @@ __device__ inline void factor_all(const double *G, double *__restrict__ chol, do
     double L[kCholStride];
     const bool ok = chol_sub(G, K, unsigned(m), L);
     if (!ok) L[0] = NAN;
-    for (int i = 0; i < kCholStride; ++i) chol[size_t(m) * kCholStride + i] = L[i];
+    if (chol)
+      for (int i = 0; i < kCholStride; ++i) chol[size_t(m) * kCholStride + i] = L[i];
     if (!ginv) continue;
     double *out = ginv + m;  // entry e at out[e * kInvStride]
     if (!ok) {
@@ -95,26 +103,47 @@ __device__ inline void factor_all(const double *G, double *__restrict__ chol, do
   }
 }
 
+// G = D^T D over the n_k rows of D (split: of D', the bfloat16 hi + lo
+// split of D) by one block, fixed order; g_s (LDS, K*K) holds it on return.
 template <int K>
-__device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n_k, double *__restrict__ GD,
-                                              double *__restrict__ chol, int want_chol, uint16_t *__restrict__ img,
-                                              int64_t ldb, NmfCtrl *__restrict__ ctrl,
-                                              double *__restrict__ ginv = nullptr) {
+__device__ __forceinline__ void block_gram_d(const float *__restrict__ D, int n_k, bool split,
+                                             double (*red)[K * K], double *__restrict__ g_s) {
   const int t = threadIdx.x;
-  __shared__ double red[kUpdThreads / 64][K * K];
-  __shared__ double g_s[K * K];
   double acc[K * K];
 #pragma unroll
   for (int i = 0; i < K * K; ++i) acc[i] = 0.0;
   for (int k = t; k < n_k; k += kUpdThreads) {
     float d[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) d[j] = D[size_t(k) * K + j];
+    for (int j = 0; j < K; ++j) d[j] = split ? split_value(D[size_t(k) * K + j]) : D[size_t(k) * K + j];
 #pragma unroll
     for (int i = 0; i < K; ++i)
 #pragma unroll
       for (int j = 0; j < K; ++j) acc[i * K + j] += double(d[i]) * double(d[j]);
   }
+#pragma unroll
+  for (int i = 0; i < K * K; ++i) {
+    const double v = wave_sum_all(acc[i]);
+    if ((t & 63) == 0) red[t >> 6][i] = v;
+  }
+  __syncthreads();
+  if (t < K * K) {
+    double v = 0.0;
+    for (int w = 0; w < kUpdThreads / 64; ++w) v += red[w][t];
+    g_s[t] = v;
+  }
+  __syncthreads();
+}
+
+template <int K>
+__device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n_k, double *__restrict__ GD,
+                                              double *__restrict__ chol, int want_chol, uint16_t *__restrict__ img,
+                                              int64_t ldb, NmfCtrl *__restrict__ ctrl,
+                                              double *__restrict__ ginv = nullptr,
+                                              double *__restrict__ ginv16 = nullptr) {
+  const int t = threadIdx.x;
+  __shared__ double red[kUpdThreads / 64][K * K];
+  __shared__ double g_s[K * K];
   if (img) {
     for (int64_t k = t; k < ldb; k += kUpdThreads) {
       float d[K];
@@ -122,18 +151,6 @@ __device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n
       for (int j = 0; j < K; ++j) d[j] = (k < n_k) ? D[k * K + j] : 0.0f;
       write_images_row<K>(img, ldb, k, d, k >= n_k);
     }
-  }
-#pragma unroll
-  for (int i = 0; i < K * K; ++i) {
-    const double s = wave_sum_all(acc[i]);
-    if ((t & 63) == 0) red[t >> 6][i] = s;
-  }
-  __syncthreads();
-  if (t < K * K) {
-    double s = 0.0;
-    for (int w = 0; w < kUpdThreads / 64; ++w) s += red[w][t];
-    g_s[t] = s;
-    GD[t] = s;
   }
   if (t == 0) {
     ctrl->stop_at = INT_MAX;
@@ -145,16 +162,23 @@ __device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n
     ctrl->adj = 0.0;
     ctrl->last_est = 0.0;
   }
-  __syncthreads();
+  block_gram_d<K>(D, n_k, false, red, g_s);
+  if (t < K * K) GD[t] = g_s[t];
   if (want_chol) factor_all<K>(g_s, chol, ginv);
+  if (ginv16 && want_chol) {
+    __syncthreads();
+    block_gram_d<K>(D, n_k, true, red, g_s);
+    factor_all<K>(g_s, nullptr, ginv16);
+  }
 }
 
 template <int K>
 __global__ __launch_bounds__(kUpdThreads) void nmf_init_kernel(const float *__restrict__ D, int n_k, double *__restrict__ GD,
                                                                double *__restrict__ chol, int want_chol,
                                                                uint16_t *__restrict__ img, int64_t ldb,
-                                                               NmfCtrl *__restrict__ ctrl, double *__restrict__ ginv) {
-  nmf_init_body<K>(D, n_k, GD, chol, want_chol, img, ldb, ctrl, ginv);
+                                                               NmfCtrl *__restrict__ ctrl, double *__restrict__ ginv,
+                                                               double *__restrict__ ginv16) {
+  nmf_init_body<K>(D, n_k, GD, chol, want_chol, img, ldb, ctrl, ginv, ginv16);
 }
 
 // RULE: kModeMU (Lee-Seung), kModeHALS (column sweep), kModeNV (exact NNLS rows)
@@ -218,7 +242,8 @@ __device__ __forceinline__ void update_d_body(
     int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
     int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int blk, int n_blk,
-    char *__restrict__ lds, int bf16 = 0, const double *__restrict__ bias = nullptr) {
+    char *__restrict__ lds, int bf16 = 0, const double *__restrict__ bias = nullptr,
+    double *__restrict__ part_gd16 = nullptr) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   using L = UpdLds<K, RULE>;
@@ -320,12 +345,18 @@ __device__ __forceinline__ void update_d_body(
     for (int j = 0; j < K; ++j) dn_s[t][j] = dn[j];
   }
   __syncthreads();
-  // This block's share of G_D for the next pass (summed by the finish kernel).
+  // This block's share of G_D for the next pass (summed by the finish kernel),
+  // and of G_D' (the split D of the MFMA pass) when asked for.
   if (t < K * K) {
     const int i = t / K, j = t % K;
     double s = 0.0;
     for (int r = 0; r < kUpdRows; ++r) s += double(dn_s[r][i]) * double(dn_s[r][j]);
     part_gd[size_t(blk) * K * K + t] = s;
+  } else if (part_gd16 && t >= 64 && t < 64 + K * K) {
+    const int e = t - 64, i = e / K, j = e % K;
+    double s = 0.0;
+    for (int r = 0; r < kUpdRows; ++r) s += double(split_value(dn_s[r][i])) * double(split_value(dn_s[r][j]));
+    part_gd16[size_t(blk) * K * K + e] = s;
   }
 }
 
@@ -338,33 +369,42 @@ template <int K>
 __device__ __forceinline__ void finish_gd_body(const double *__restrict__ part_gd, int n_blk, double *__restrict__ GD,
                                                double *__restrict__ chol, int next_chol,
                                                const NmfCtrl *__restrict__ ctrl, int iter, double *__restrict__ red,
-                                               double *__restrict__ gd_s, double *__restrict__ ginv = nullptr) {
+                                               double *__restrict__ gd_s, double *__restrict__ ginv = nullptr,
+                                               const double *__restrict__ part_gd16 = nullptr,
+                                               double *__restrict__ ginv16 = nullptr) {
   if (iter >= ctrl->stop_at) return;
   constexpr int G = kUpdThreads / (K * K);
   const int t = threadIdx.x;
-  if (t < G * K * K) {
-    const int e = t % (K * K), g = t / (K * K);
-    red[g * K * K + e] = strided_sum(g, G, n_blk, [&](int b) { return part_gd[size_t(b) * K * K + e]; });
+  for (int pass = 0; pass < ((part_gd16 && ginv16 && next_chol) ? 2 : 1); ++pass) {
+    const double *src = pass == 0 ? part_gd : part_gd16;
+    if (t < G * K * K) {
+      const int e = t % (K * K), g = t / (K * K);
+      red[g * K * K + e] = strided_sum(g, G, n_blk, [&](int b) { return src[size_t(b) * K * K + e]; });
+    }
+    __syncthreads();
+    if (t < K * K) {
+      double s = 0.0;
+      for (int g = 0; g < G; ++g) s += red[g * K * K + t];
+      gd_s[t] = s;
+      if (pass == 0) GD[t] = s;
+    }
+    __syncthreads();
+    // G_D -> chol, ginv; G_D' -> ginv16 (inverses only)
+    if (next_chol) factor_all<K>(gd_s, pass == 0 ? chol : nullptr, pass == 0 ? ginv : ginv16);
+    __syncthreads();
   }
-  __syncthreads();
-  if (t < K * K) {
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) s += red[g * K * K + t];
-    gd_s[t] = s;
-    GD[t] = s;
-  }
-  __syncthreads();
-  if (next_chol) factor_all<K>(gd_s, chol, ginv);
 }
 
 template <int K>
 __global__ __launch_bounds__(kUpdThreads) void finish_gd_kernel(const double *__restrict__ part_gd, int n_blk,
                                                                 double *__restrict__ GD, double *__restrict__ chol,
                                                                 int next_chol, const NmfCtrl *__restrict__ ctrl,
-                                                                int iter, double *__restrict__ ginv) {
+                                                                int iter, double *__restrict__ ginv,
+                                                                const double *__restrict__ part_gd16,
+                                                                double *__restrict__ ginv16) {
   __shared__ double red[kUpdThreads];
   __shared__ double gd_s[K * K];
-  finish_gd_body<K>(part_gd, n_blk, GD, chol, next_chol, ctrl, iter, red, gd_s, ginv);
+  finish_gd_body<K>(part_gd, n_blk, GD, chol, next_chol, ctrl, iter, red, gd_s, ginv, part_gd16, ginv16);
 }
 
 template <int K, int RULE>
@@ -373,10 +413,10 @@ __global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
     int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
     int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int bf16,
-    const double *__restrict__ bias) {
+    const double *__restrict__ bias, double *__restrict__ part_gd16) {
   __shared__ __attribute__((aligned(16))) char lds[UpdLds<K, RULE>::bytes];
   update_d_body<K, RULE>(D, part_nd, n_wg, n_k, ctrl, iter, has_obj, f_ref, tol, hist, GD, chol, next_chol, part_gd,
-                         img, ldb, int(blockIdx.x), int(gridDim.x), lds, bf16, bias);
+                         img, ldb, int(blockIdx.x), int(gridDim.x), lds, bf16, bias, part_gd16);
 }
 
 template <int K>
@@ -493,7 +533,8 @@ __global__ void batched_advance_kernel(const BatchInst *__restrict__ d, int n_in
 void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWork &w, int want_chol, int64_t ldb) {
   switch (K) {
 #define HSN_K(KK) \
-  case KK: nmf_init_kernel<KK><<<1, kUpdThreads, 0, st>>>(D, n_k, w.gd, w.chol, want_chol, w.img, ldb, w.ctrl, w.ginv); break;
+  case KK: nmf_init_kernel<KK><<<1, kUpdThreads, 0, st>>>(D, n_k, w.gd, w.chol, want_chol, w.img, ldb, w.ctrl, w.ginv, \
+                                                          w.ginv16); break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
   }
@@ -518,15 +559,15 @@ void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w
     if (rule == kModeMU)                                                                                          \
       update_d_kernel<KK, kModeMU><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
-                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias); \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias, w.part_gd16); \
     else if (rule == kModeHALS)                                                                                   \
       update_d_kernel<KK, kModeHALS><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                          \
                                                                  w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd, \
-                                                                 w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias); \
+                                                                 w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias, w.part_gd16); \
     else                                                                                                          \
       update_d_kernel<KK, kModeNV><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
-                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias); \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias, w.part_gd16); \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
@@ -534,7 +575,8 @@ void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w
   switch (K) {
 #define HSN_K(KK)                                                                                                  \
   case KK:                                                                                                         \
-    finish_gd_kernel<KK><<<1, kUpdThreads, 0, st>>>(w.part_gd, nb, w.gd, w.chol, next_chol, w.ctrl, iter, w.ginv);  \
+    finish_gd_kernel<KK><<<1, kUpdThreads, 0, st>>>(w.part_gd, nb, w.gd, w.chol, next_chol, w.ctrl, iter, w.ginv, \
+                                                    w.part_gd16, w.ginv16);                                            \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
