@@ -239,20 +239,29 @@ hsn_status hsn_nmf_set_launch(hsn_ctx *ctx, int anls_passes);
 
 /*
  * Many independent decompositions (eq. 4) of uneven size in one go: every
- * phase of an iteration is ONE launch over the workgroups of all instances
- * (per-instance descriptors and block ranges), and with HSN_BATCH_GRAPH the
- * iteration chunks are captured once into hipGraphs and replayed.  Schedule
- * (from opts; opts.k is ignored, each problem has its own k): opts.max_iter
- * float32 MU iterations (objective every check_every), then up to
- * opts.polish_rounds ANLS rounds; algo must be HSN_ALGO_MU, precision
- * HSN_PREC_FP32, init HSN_INIT_USER, polish_algo HSN_ALGO_ANLS.  Instance i
- * stops on its own when f_ref > 0 and its relative objective reaches
- * opts.rel_obj_tol; its kernels then return at once.
+ * phase of an iteration is ONE launch per kernel shape over the workgroups
+ * of all its instances (per-instance descriptors and block ranges), and with
+ * HSN_BATCH_GRAPH the iteration chunks are captured once into hipGraphs and
+ * replayed.  Schedule (from opts; opts.k is ignored, each problem has its
+ * own k): opts.max_iter MU iterations (objective every check_every) on the
+ * float32 p (precision HSN_PREC_FP32) or on the bfloat16 p on the matrix
+ * cores (HSN_PREC_BF16: each problem's p_bf16), then up to
+ * opts.polish_rounds float32 ANLS rounds (N_V pass, row solves, N_D pass);
+ * algo must be HSN_ALGO_MU, init HSN_INIT_USER, polish_algo HSN_ALGO_ANLS,
+ * polish_bf16_rounds 0.  Instance i stops on its own when f_ref > 0 and its
+ * relative objective reaches opts.rel_obj_tol; its kernels then return at
+ * once.  Bulk iterations on the bfloat16 p record their objective (on
+ * p_bf16) but never stop an instance: the float32 rounds decide.
  * Flags: HSN_BATCH_GRAPH captures and replays graphs (cached in ctx per batch
- * shape); HSN_BATCH_AUTOTUNE times candidate workgroup budgets (rows of p per
- * workgroup) on the first call for a batch shape and keeps the fastest.
+ * shape); HSN_BATCH_AUTOTUNE, on the first call for a batch shape, times the
+ * candidate partitions and keeps the fastest: workgroup budgets of the
+ * float32 pass (rows of p per workgroup) and, for the bfloat16 bulk, 1, 2, 4
+ * or 8 16-row tiles per MFMA-pass workgroup.  With the environment variable
+ * HSN_TUNE_CACHE naming a file, tuned choices are kept there (a JSON object
+ * keyed by device and batch shape) and reused by later processes.
  * Without AUTOTUNE every instance is partitioned exactly as hsn_subspace_nmf
- * would partition it alone, so its results are bitwise those of that call.
+ * would partition it alone (ANLS rounds in the two-pass form,
+ * hsn_nmf_set_launch(ctx, 2)), so its results are bitwise those of that call.
  * stats: optional host array [n]; ms is the device time of the whole batch.
  */
 typedef struct {
@@ -263,6 +272,9 @@ typedef struct {
   float *V;         /* [n_p][k] in/out */
   float *D;         /* [n_k][k] in/out */
   double f_ref;     /* > 0 enables this instance's stop test */
+  const uint16_t *p_bf16; /* HSN_PREC_BF16: [n_p][ldb] bfloat16 p with zero padding, 16-byte
+                             aligned, n_k <= ldb <= 2048, ldb % 32 == 0; else ignored */
+  int64_t ldb;
 } hsn_nmf_problem;
 
 enum { HSN_BATCH_GRAPH = 1, HSN_BATCH_AUTOTUNE = 2 };

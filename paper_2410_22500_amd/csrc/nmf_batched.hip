@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -42,7 +43,13 @@ void launch_batched_pass(int K, int nq, int mode, bool obj, int n_blocks, hipStr
                          int n_inst, int iter_local);
 void launch_batched_init(int n_inst, int want_chol, hipStream_t st, const BatchInst *d);
 void launch_batched_update(int rule, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
-                           int iter_local, bool has_obj, bool next_chol);
+                           int iter_local, bool has_obj, bool next_chol, bool bf16);
+bool launch_batched_pass_bf16(int K, int nw, bool obj, int n_blocks, hipStream_t st, const BatchInst *d, int n_inst,
+                              int iter_local);
+int bf16_k_steps_class(int64_t ldb);
+int pass_bf16_wgs(hsn_ctx *ctx, int64_t n_p);
+size_t bf16_image_elems(int64_t ldb);
+int64_t bf16_image_ldb(int64_t ldb);
 void launch_batched_rows(int K, int n_blocks, hipStream_t st, const BatchInst *d, int n_inst, int iter_local);
 void launch_batched_advance(int n_inst, int steps, hipStream_t st, const BatchInst *d);
 int update_d_blocks(int n_k);
@@ -57,14 +64,19 @@ __global__ void set_limit_kernel(const BatchInst *__restrict__ d, int n, int lim
   if (i < n) d[i].ctrl->stop_at = limit;
 }
 
+constexpr int kBf16Rows = 16;  // rows per tile of the bfloat16 pass
+
 struct Shape {
   int64_t n_p, n_k, ldp;
   int k;
+  int64_t ldb;  // bfloat16 p pitch (bfloat16 bulk), else 0
+  int nw;       // k-step class of the bfloat16 pass (1, 2, 4, 8), else 0
 };
 
 struct Group {
   int K, nq, i0, i1;  // instances [i0, i1) of the plan order
   int n_wg, n_rb;     // blocks of the group's pass / row-solve launches
+  int nw = 0;         // bfloat16 groups: k-step class
 };
 
 // The instances a chunk launches: all of them, or after some have stopped
@@ -73,6 +85,7 @@ struct Group {
 struct View {
   std::string key;           // "all" or the active set
   std::vector<Group> groups;
+  std::vector<Group> groups16;  // (K, k-step class) groups of the bfloat16 pass
   int n = 0, total_ub = 0;
   BatchInst *d = nullptr;
 };
@@ -82,6 +95,9 @@ struct Plan : Owned {
   int n = 0;
   std::vector<int> order;   // plan position -> problem index
   std::vector<Group> groups;
+  std::vector<Group> groups16;    // bfloat16 bulk: (K, k-step class) groups
+  bool bf16 = false;
+  std::vector<int> wgb;           // bfloat16 pass workgroups per instance (chosen)
   int max_k = 1;
   bool need_nv = false;
   std::vector<Shape> shapes;
@@ -117,13 +133,96 @@ struct Plan : Owned {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ---------------------------------------------------------------------------
+// On-disk cache of tuned partitions (HSN_TUNE_CACHE names the file; unset:
+// no cache).  A JSON object with one entry per line,
+//   "<device>|<plan signature>": {"budget_index": b, "bf16_tiles_index": t},
+// read when a tuned plan is built and rewritten with the new entry after
+// tuning.
+// ---------------------------------------------------------------------------
+std::string device_key(const hsn_ctx *ctx) {
+  hipDeviceProp_t p;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&p, ctx->device) == hipSuccess) arch = p.gcnArchName;
+  else (void)hipGetLastError();
+  return arch + ":" + std::to_string(ctx->num_cu) + "cu";
+}
+
+const char *tune_cache_path() {
+  const char *p = std::getenv("HSN_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+struct TuneEntry {
+  std::string key;
+  int budget, tiles;
+};
+
+std::vector<TuneEntry> tune_cache_read() {
+  std::vector<TuneEntry> out;
+  const char *path = tune_cache_path();
+  if (!path) return out;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return out;
+  char line[8192];
+  while (std::fgets(line, sizeof(line), f)) {
+    const char *q0 = std::strchr(line, '"');
+    if (!q0) continue;
+    const char *q1 = std::strchr(q0 + 1, '"');
+    if (!q1) continue;
+    const char *b = std::strstr(q1, "\"budget_index\":");
+    const char *t = std::strstr(q1, "\"bf16_tiles_index\":");
+    int bv = -1, tv = -1;
+    if (!b || !t || std::sscanf(b + 15, "%d", &bv) != 1 || std::sscanf(t + 19, "%d", &tv) != 1) continue;
+    out.push_back({std::string(q0 + 1, q1), bv, tv});
+  }
+  std::fclose(f);
+  return out;
+}
+
+bool tune_cache_lookup(const std::string &key, int &budget, int &tiles) {
+  for (const TuneEntry &e : tune_cache_read())
+    if (e.key == key) {
+      budget = e.budget;
+      tiles = e.tiles;
+      return true;
+    }
+  return false;
+}
+
+void tune_cache_store(const std::string &key, int budget, int tiles) {
+  const char *path = tune_cache_path();
+  if (!path) return;
+  std::vector<TuneEntry> ent = tune_cache_read();
+  bool found = false;
+  for (TuneEntry &e : ent)
+    if (e.key == key) {
+      e.budget = budget;
+      e.tiles = tiles;
+      found = true;
+    }
+  if (!found) ent.push_back({key, budget, tiles});
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < ent.size(); ++i)
+    std::fprintf(f, "\"%s\": {\"budget_index\": %d, \"bf16_tiles_index\": %d}%s\n", ent[i].key.c_str(),
+                 ent[i].budget, ent[i].tiles, i + 1 < ent.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
 // Lays out descriptors (plan order) for the partition `wgs`; pass and
 // row-solve block ranges count from the first instance of the group, update
 // blocks from the first instance of the batch.  Fills groups' block totals.
-void layout(Plan &pl, const std::vector<int> &wgs, const hsn_nmf_problem *probs, double tol,
-            std::vector<BatchInst> &out, std::vector<Group> &groups, int &tot_ub, int num_cu) {
+void layout(Plan &pl, const std::vector<int> &wgs, const std::vector<int> &wgb, const hsn_nmf_problem *probs,
+            double tol, std::vector<BatchInst> &out, std::vector<Group> &groups, std::vector<Group> &groups16,
+            int &tot_ub, int num_cu) {
   out.assign(pl.n, BatchInst{});
   groups = pl.groups;
+  groups16 = pl.groups16;
   tot_ub = 0;
   for (Group &g : groups) {
     g.n_wg = g.n_rb = 0;
@@ -150,13 +249,24 @@ void layout(Plan &pl, const std::vector<int> &wgs, const hsn_nmf_problem *probs,
       b.rb0 = g.n_rb;
       b.n_rb = int(std::min<int64_t>((s.n_p + 255) / 256, 8 * int64_t(num_cu)));
       g.n_rb += b.n_rb;
+      b.Pb = (probs && pl.bf16) ? probs[q].p_bf16 : nullptr;
+      b.ldb = s.ldb;
+      b.ldb_img = pl.bf16 ? bf16_image_ldb(s.ldb) : 0;
+    }
+  }
+  for (Group &g : groups16) {
+    g.n_wg = 0;
+    for (int i = g.i0; i < g.i1; ++i) {
+      out[i].wg0b = g.n_wg;
+      out[i].n_wgb = wgb[i];
+      g.n_wg += wgb[i];
     }
   }
 }
 
 // Byte offsets of instance i's arrays inside the plan memory (region A).
 struct InstMem {
-  size_t gd, chol, part_nd, part_gv, part_obj, part_gd, nv, hist, dcopy;
+  size_t gd, chol, part_nd, part_gv, part_obj, part_gd, nv, hist, dcopy, img, vcopy;
 };
 
 std::vector<InstMem> mem_layout(const Plan &pl, size_t &total) {
@@ -181,6 +291,8 @@ std::vector<InstMem> mem_layout(const Plan &pl, size_t &total) {
     x.nv = pl.need_nv ? take(sizeof(float) * size_t(s.n_p) * K) : 0;
     x.hist = take(sizeof(double) * size_t(pl.hist_cap));
     x.dcopy = take(sizeof(float) * size_t(s.n_k) * K);  // tuning: scratch D
+    x.img = pl.bf16 ? take(sizeof(uint16_t) * bf16_image_elems(s.ldb)) : 0;
+    x.vcopy = take(sizeof(float) * size_t(s.n_p) * K);  // tuning: scratch V (passes and row solves write V)
   }
   total = off + 256;
   return m;
@@ -220,8 +332,10 @@ void fill_pointers(Plan &pl, const std::vector<InstMem> &m, std::vector<BatchIns
     b.NV = pl.need_nv ? reinterpret_cast<float *>(pl.mem + m[i].nv) : nullptr;
     b.hist = reinterpret_cast<double *>(pl.mem + m[i].hist);
     b.ctrl = ctrl + i;
+    b.img = pl.bf16 ? reinterpret_cast<uint16_t *>(pl.mem + m[i].img) : nullptr;
     if (tune) {
       b.D = reinterpret_cast<float *>(pl.mem + m[i].dcopy);
+      b.V = reinterpret_cast<float *>(pl.mem + m[i].vcopy);
       b.f_ref = 0.0;
     }
   }
@@ -230,6 +344,11 @@ void fill_pointers(Plan &pl, const std::vector<InstMem> &m, std::vector<BatchIns
 // One pass launch per (K, bin class) group.
 void pass_groups(const std::vector<Group> &gs, int mode, bool obj, hipStream_t st, const BatchInst *d, int s) {
   for (const Group &g : gs) launch_batched_pass(g.K, g.nq, mode, obj, g.n_wg, st, d + g.i0, g.i1 - g.i0, s);
+}
+
+// One bfloat16 MU pass launch per (K, k-step class) group.
+void pass_groups16(const std::vector<Group> &gs, bool obj, hipStream_t st, const BatchInst *d, int s) {
+  for (const Group &g : gs) launch_batched_pass_bf16(g.K, g.nw, obj, g.n_wg, st, d + g.i0, g.i1 - g.i0, s);
 }
 
 // One row-solve launch per group (its kernel is compiled for the group's K).
@@ -244,14 +363,17 @@ void queue_chunk(const Plan &pl, const View &v, hipStream_t st, int kind, int st
   for (int s = 0; s < steps; ++s) {
     const bool last = s + 1 == steps;
     if (kind == 0) {
-      pass_groups(v.groups, kModeMU, obj_last && last, st, v.d, s);
+      if (pl.bf16)
+        pass_groups16(v.groups16, obj_last && last, st, v.d, s);
+      else
+        pass_groups(v.groups, kModeMU, obj_last && last, st, v.d, s);
       launch_batched_update(kModeMU, v.total_ub, pl.upd_lds_mu, st, v.d, v.n, s, obj_last && last,
-                            chol_last && last);
+                            chol_last && last, pl.bf16);
     } else {
       pass_groups(v.groups, kModeNV, false, st, v.d, s);
       rows_groups(v.groups, st, v.d, s);
       pass_groups(v.groups, kModeND, true, st, v.d, s);
-      launch_batched_update(kModeNV, v.total_ub, pl.upd_lds_nv, st, v.d, v.n, s, true, true);
+      launch_batched_update(kModeNV, v.total_ub, pl.upd_lds_nv, st, v.d, v.n, s, true, true, false);
     }
   }
   launch_batched_advance(v.n, steps, st, v.d);
@@ -261,6 +383,7 @@ void queue_chunk(const Plan &pl, const View &v, hipStream_t st, int kind, int st
 void compact(const Plan &pl, const std::vector<char> &act, BatchInst *dst, std::vector<BatchInst> &h, View &v) {
   h.clear();
   v.groups.clear();
+  v.groups16.clear();
   v.key.assign(act.begin(), act.end());
   v.total_ub = 0;
   for (int j = 0; j < pl.n; ++j) {
@@ -277,6 +400,18 @@ void compact(const Plan &pl, const std::vector<char> &act, BatchInst *dst, std::
     g.n_rb += b.n_rb;
     b.ub0 = v.total_ub;
     v.total_ub += b.n_ub;
+    if (pl.bf16) {
+      const int nw = pl.shapes[j].nw;
+      if (v.groups16.empty() || v.groups16.back().K != b.K || v.groups16.back().nw != nw) {
+        Group g16{b.K, b.nq, i, i, 0, 0};
+        g16.nw = nw;
+        v.groups16.push_back(g16);
+      }
+      Group &gb = v.groups16.back();
+      gb.i1 = i + 1;
+      b.wg0b = gb.n_wg;
+      gb.n_wg += b.n_wgb;
+    }
     h.push_back(b);
   }
   v.n = int(h.size());
@@ -333,9 +468,12 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
   if (!ctx) return HSN_ERR_INVALID_ARG;
   if (n < 1 || n > 4096 || !probs) return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: need 1 <= n <= 4096 problems");
   if (!o) return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: opts is NULL");
-  if (o->algo != HSN_ALGO_MU || o->precision != HSN_PREC_FP32 || o->init != HSN_INIT_USER ||
-      (o->polish_rounds > 0 && o->polish_algo != HSN_ALGO_ANLS))
-    return fail(ctx, HSN_ERR_UNSUPPORTED, "batched nmf: float32 MU bulk + ANLS polish from a user start only");
+  if (o->algo != HSN_ALGO_MU || (o->precision != HSN_PREC_FP32 && o->precision != HSN_PREC_BF16) ||
+      o->init != HSN_INIT_USER || (o->polish_rounds > 0 && o->polish_algo != HSN_ALGO_ANLS) ||
+      o->polish_bf16_rounds > 0)
+    return fail(ctx, HSN_ERR_UNSUPPORTED,
+                "batched nmf: MU bulk (float32 or bfloat16) + float32 ANLS polish from a user start only");
+  const bool bf16 = o->precision == HSN_PREC_BF16 && o->max_iter > 0;
   if (o->max_iter < 0 || o->check_every < 1 || o->polish_rounds < 0)
     return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: max_iter >= 0, check_every >= 1, polish_rounds >= 0 required");
   if (flags & ~(HSN_BATCH_GRAPH | HSN_BATCH_AUTOTUNE)) return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: bad flags");
@@ -347,6 +485,11 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
     if (!q.p || !q.V || !q.D) return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: problem %d: NULL pointer", i);
     if (q.ldp < q.n_k || q.ldp % 4 != 0 || reinterpret_cast<uintptr_t>(q.p) % 16 != 0)
       return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: problem %d: ldp >= n_k, ldp %% 4 == 0, 16-byte aligned p", i);
+    if (bf16 && (!q.p_bf16 || q.ldb < q.n_k || q.ldb % 32 != 0 || q.ldb > 2048 ||
+                 reinterpret_cast<uintptr_t>(q.p_bf16) % 16 != 0))
+      return fail(ctx, HSN_ERR_INVALID_ARG,
+                  "batched nmf: problem %d: the bfloat16 bulk needs p_bf16 (16-byte aligned) with n_k <= ldb <= 2048, "
+                  "ldb %% 32 == 0", i);
     if (stats && stats[i].history_cap > 0 && !stats[i].history)
       return fail(ctx, HSN_ERR_INVALID_ARG, "batched nmf: stats[%d].history is NULL", i);
   }
@@ -359,43 +502,73 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
 
   // Plan lookup: batch shape + schedule sizes + flags.
   std::string sig = "n=" + std::to_string(n) + ";h=" + std::to_string(hist_cap) + ";nv=" + std::to_string(need_nv) +
-                    ";t=" + std::to_string(tune);
+                    ";t=" + std::to_string(tune) + ";b=" + std::to_string(bf16);
   for (int i = 0; i < n; ++i)
     sig += ";" + std::to_string(probs[i].n_p) + "," + std::to_string(probs[i].n_k) + "," +
-           std::to_string(probs[i].ldp) + "," + std::to_string(probs[i].k);
+           std::to_string(probs[i].ldp) + "," + std::to_string(probs[i].k) +
+           (bf16 ? "," + std::to_string(probs[i].ldb) : std::string());
   Plan *pl = nullptr;
   for (Owned *ow : ctx->plans) {
     Plan *c = dynamic_cast<Plan *>(ow);
     if (c && c->sig == sig) pl = c;
   }
   const double tol = o->rel_obj_tol;
+  hsn_status rc0 = HSN_OK;
   if (!pl) {
     auto np = new Plan;
     np->sig = sig;
     np->n = n;
     np->need_nv = need_nv;
     np->hist_cap = hist_cap;
-    // plan order: by (K, bin class), stable
+    np->bf16 = bf16;
+    // plan order: by (K, bin class), stable; with the bfloat16 bulk by (K,
+    // k-step class), which refines the bin class (n_k > 1024 <=> 8 k-steps per wave)
     np->order.resize(n);
     for (int i = 0; i < n; ++i) np->order[i] = i;
-    auto key = [&](int i) { return probs[i].k * 4 + (probs[i].n_k > 1024 ? 2 : 1); };
+    auto nwc = [&](int i) { return bf16 ? bf16_k_steps_class(probs[i].ldb) : 0; };
+    auto key = [&](int i) { return bf16 ? probs[i].k * 16 + nwc(i) : probs[i].k * 4 + (probs[i].n_k > 1024 ? 2 : 1); };
+    auto key32 = [&](int i) { return probs[i].k * 4 + (probs[i].n_k > 1024 ? 2 : 1); };
     std::stable_sort(np->order.begin(), np->order.end(), [&](int a, int b) { return key(a) < key(b); });
     for (int j = 0; j < n; ++j) {
       const int i = np->order[j];
-      np->shapes.push_back({probs[i].n_p, probs[i].n_k, probs[i].ldp, probs[i].k});
+      np->shapes.push_back({probs[i].n_p, probs[i].n_k, probs[i].ldp, probs[i].k, bf16 ? probs[i].ldb : 0, nwc(i)});
       np->max_k = std::max(np->max_k, probs[i].k);
-      if (np->groups.empty() || key(np->order[np->groups.back().i0]) != key(i))
+      if (np->groups.empty() || key32(np->order[np->groups.back().i0]) != key32(i))
         np->groups.push_back({probs[i].k, probs[i].n_k > 1024 ? 2 : 1, j, j + 1, 0, 0});
       else
         np->groups.back().i1 = j + 1;
+      if (bf16) {
+        if (np->groups16.empty() || key(np->order[np->groups16.back().i0]) != key(i)) {
+          Group g{probs[i].k, probs[i].n_k > 1024 ? 2 : 1, j, j + 1, 0, 0};
+          g.nw = nwc(i);
+          np->groups16.push_back(g);
+        } else {
+          np->groups16.back().i1 = j + 1;
+        }
+      }
     }
     const int nc = ctx->num_cu;
     const int budgets[] = {0, 2 * nc, 4 * nc, 8 * nc, 16 * nc};
     const std::vector<int> cands[] = {partition(*np, budgets[0], nc), partition(*np, budgets[1], nc),
                                       partition(*np, budgets[2], nc), partition(*np, budgets[3], nc),
                                       partition(*np, budgets[4], nc)};
+    // bfloat16 pass: at least `tiles` 16-row tiles per workgroup (1 = the
+    // single-instance partition); more tiles per workgroup stage the D
+    // operand image fewer times on small instances
+    const int tile_cands[] = {1, 2, 4, 8};
+    std::vector<int> bcands[4];
+    for (int c = 0; c < 4; ++c) {
+      bcands[c].assign(n, 0);
+      for (int j = 0; bf16 && j < n; ++j) {
+        const int64_t tiles = (np->shapes[j].n_p + kBf16Rows - 1) / kBf16Rows;
+        bcands[c][j] = int(std::max<int64_t>(
+            1, std::min<int64_t>(nc, (tiles + tile_cands[c] - 1) / tile_cands[c])));
+      }
+    }
     np->wg_cap.assign(n, 1);
     for (auto &c : cands)
+      for (int i = 0; i < n; ++i) np->wg_cap[i] = std::max(np->wg_cap[i], c[i]);
+    for (auto &c : bcands)
       for (int i = 0; i < n; ++i) np->wg_cap[i] = std::max(np->wg_cap[i], c[i]);
     size_t total = 0;
     const std::vector<InstMem> m = mem_layout(*np, total);
@@ -418,53 +591,108 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
       return fail(ctx, HSN_ERR_DEVICE, "batched nmf: kernel attribute setup failed");
     }
     np->wg = cands[0];
-    if (tune) {
-      // Time pass (N_D form) + D update per candidate on the tuning copy
-      // (scratch D, control and history; V and p only read).
-      float best = 1e30f;
-      int best_c = 0;
+    np->wgb = bcands[0];
+    int best_c = 0, best_b = 0;
+    const std::string cache_key = device_key(ctx) + "|" + sig;
+    const bool cached = tune && tune_cache_lookup(cache_key, best_c, best_b) && best_c >= 0 && best_c < 5 &&
+                        best_b >= 0 && best_b < 4;
+    if (tune && cached) {
+      np->tune_note = "cached: budget " + std::to_string(budgets[best_c]) + ", bf16 tiles per workgroup " +
+                      std::to_string(tile_cands[best_b]);
+    } else if (tune) {
+      // Time each candidate on the tuning copy (scratch V and D, control
+      // and history of their own; p only read): the float32 budgets with one
+      // ANLS round (N_V pass, row solves, N_D pass, D update) when polish
+      // rounds follow, else one float32 MU iteration; the bfloat16
+      // partitions with one MU iteration on the matrix cores.  A candidate
+      // replaces the default only when it is 3 % faster (timing noise).
       hipEvent_t e0, e1;
       HSN_HIP(ctx, hipEventCreate(&e0));
       HSN_HIP(ctx, hipEventCreate(&e1));
-      for (int c = 0; c < 5; ++c) {
+      auto time_candidate = [&](const std::vector<int> &wgs, const std::vector<int> &wgb, bool on_bf16,
+                                float &out_ms) -> hsn_status {
         std::vector<BatchInst> v;
-        std::vector<Group> tg;
+        std::vector<Group> tg, tg16;
         int tu;
-        layout(*np, cands[c], probs, 0.0, v, tg, tu, ctx->num_cu);
+        layout(*np, wgs, wgb, probs, 0.0, v, tg, tg16, tu, ctx->num_cu);
         fill_pointers(*np, m, v, tctrl, true);
         HSN_HIP(ctx, hipMemcpyAsync(np->d_tune, v.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice, st));
         for (int j = 0; j < n; ++j) {
           const int i = np->order[j];
           HSN_HIP(ctx, hipMemcpyAsync(v[j].D, probs[i].D, sizeof(float) * probs[i].n_k * probs[i].k,
                                       hipMemcpyDeviceToDevice, st));
+          HSN_HIP(ctx, hipMemcpyAsync(v[j].V, probs[i].V, sizeof(float) * probs[i].n_p * probs[i].k,
+                                      hipMemcpyDeviceToDevice, st));
         }
-        launch_batched_init(n, 0, st, np->d_tune);
-        float ms_c = 0.f;
+        launch_batched_init(n, need_nv && !on_bf16 ? 1 : 0, st, np->d_tune);
+        out_ms = 0.f;
         for (int rep = 0; rep < 3; ++rep) {
           HSN_HIP(ctx, hipEventRecord(e0, st));
-          pass_groups(tg, kModeND, true, st, np->d_tune, 0);
-          launch_batched_update(kModeMU, tu, np->upd_lds_mu, st, np->d_tune, n, 0, false, false);
+          if (on_bf16) {
+            pass_groups16(tg16, false, st, np->d_tune, 0);
+            launch_batched_update(kModeMU, tu, np->upd_lds_mu, st, np->d_tune, n, 0, false, false, true);
+          } else if (need_nv) {
+            pass_groups(tg, kModeNV, false, st, np->d_tune, 0);
+            rows_groups(tg, st, np->d_tune, 0);
+            pass_groups(tg, kModeND, true, st, np->d_tune, 0);
+            launch_batched_update(kModeNV, tu, np->upd_lds_nv, st, np->d_tune, n, 0, true, true, false);
+          } else {
+            pass_groups(tg, kModeMU, false, st, np->d_tune, 0);
+            launch_batched_update(kModeMU, tu, np->upd_lds_mu, st, np->d_tune, n, 0, false, false, false);
+          }
           HSN_HIP(ctx, hipEventRecord(e1, st));
           HSN_HIP(ctx, hipEventSynchronize(e1));
           float ms = 0.f;
           HSN_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-          if (rep > 0) ms_c += ms;
+          if (rep > 0) out_ms += ms;
         }
         HSN_LAUNCHED(ctx);
-        if (ms_c < best) {
-          best = ms_c;
+        out_ms /= 2;
+        return HSN_OK;
+      };
+      float best = 1e30f;
+      for (int c = 0; c < 5; ++c) {
+        float ms = 0.f;
+        if ((rc0 = time_candidate(cands[c], bcands[0], false, ms)) != HSN_OK) {
+          delete np;
+          return rc0;
+        }
+        if (c == 0 || ms < 0.97f * best) {
+          best = ms;
           best_c = c;
         }
         char buf[96];
-        std::snprintf(buf, sizeof(buf), "%sbudget %d: %.3f ms", c ? "; " : "", budgets[c], ms_c / 2);
+        std::snprintf(buf, sizeof(buf), "%sbudget %d: %.3f ms", c ? "; " : "", budgets[c], ms);
         np->tune_note += buf;
+      }
+      np->tune_note += " -> budget " + std::to_string(budgets[best_c]);
+      if (bf16) {
+        best = 1e30f;
+        for (int c = 0; c < 4; ++c) {
+          float ms = 0.f;
+          if ((rc0 = time_candidate(cands[best_c], bcands[c], true, ms)) != HSN_OK) {
+            delete np;
+            return rc0;
+          }
+          if (c == 0 || ms < 0.97f * best) {
+            best = ms;
+            best_b = c;
+          }
+          char buf[96];
+          std::snprintf(buf, sizeof(buf), "; bf16 %d tiles/wg: %.3f ms", tile_cands[c], ms);
+          np->tune_note += buf;
+        }
+        np->tune_note += " -> " + std::to_string(tile_cands[best_b]) + " tiles/wg";
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
-      np->wg = cands[best_c];
-      np->tune_note += " -> budget " + std::to_string(budgets[best_c]);
+      tune_cache_store(cache_key, best_c, best_b);
     }
-    layout(*np, np->wg, nullptr, tol, np->h, np->groups, np->total_ub, ctx->num_cu);
+    if (tune) {
+      np->wg = cands[best_c];
+      np->wgb = bcands[best_b];
+    }
+    layout(*np, np->wg, np->wgb, nullptr, tol, np->h, np->groups, np->groups16, np->total_ub, ctx->num_cu);
     fill_pointers(*np, m, np->h, np->ctrl, false);
     for (int i = 0; i < n; ++i) np->hist_off.push_back(m[i].hist);
     {
@@ -488,6 +716,7 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
     pl->h[j].D = probs[i].D;
     pl->h[j].f_ref = probs[i].f_ref > 0.0 ? probs[i].f_ref : 0.0;
     pl->h[j].tol = tol;
+    pl->h[j].Pb = bf16 ? probs[i].p_bf16 : nullptr;
   }
   const int n_steps = o->max_iter + o->polish_rounds;
   const bool first_exact = o->max_iter == 0 && o->polish_rounds > 0;
@@ -516,6 +745,7 @@ extern "C" hsn_status hsn_subspace_nmf_batched(hsn_ctx *ctx, int n, const hsn_nm
   View full;
   full.key = "all";
   full.groups = pl->groups;
+  full.groups16 = pl->groups16;
   full.n = n;
   full.total_ub = pl->total_ub;
   full.d = pl->d;

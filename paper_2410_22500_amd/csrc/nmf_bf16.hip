@@ -91,20 +91,18 @@ __host__ __device__ inline Bf16Lds bf16_lds_layout(int64_t ldb, int K, bool anls
   return L;
 }
 
+// The pass of one decomposition by workgroup blk of nblk (persistent,
+// tiles blk, blk + nblk, ...); smem: the dynamic LDS (bf16_lds_layout).
 template <int K, int MODE, bool OBJ, int NW, int NBUF>
-__global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__restrict__ Pb, int64_t ldb,
-                                                              int64_t n_p, int n_k, float *__restrict__ V,
-                                                              const uint4 *__restrict__ db1g,
-                                                              const uint4 *__restrict__ db3g,
-                                                              const double *__restrict__ GD,
-                                                              const double *__restrict__ chol,
-                                                              float *__restrict__ part_nd,
-                                                              double *__restrict__ part_gv,
-                                                              double *__restrict__ part_obj,
-                                                              NmfCtrl *__restrict__ ctrl, int iter,
-                                                              const double *__restrict__ ginv) {
+__device__ __forceinline__ void pass_bf16_body(const uint16_t *__restrict__ Pb, int64_t ldb, int64_t n_p, int n_k,
+                                               float *__restrict__ V, const uint4 *__restrict__ db1g,
+                                               const uint4 *__restrict__ db3g, const double *__restrict__ GD,
+                                               const double *__restrict__ chol, float *__restrict__ part_nd,
+                                               double *__restrict__ part_gv, double *__restrict__ part_obj,
+                                               NmfCtrl *__restrict__ ctrl, int iter,
+                                               const double *__restrict__ ginv, int blk, int nblk,
+                                               char *__restrict__ smem) {
   if (iter >= ctrl->stop_at) return;
-  extern __shared__ __attribute__((aligned(16))) char smem[];
   const Bf16Lds L = bf16_lds_layout(ldb, K, MODE == kModeANLS);
   char *tileL = smem + L.tile;
   uint4 *db1L = reinterpret_cast<uint4 *>(smem + L.db1);
@@ -168,9 +166,9 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
 
   // NBUF register buffers keep NBUF tiles of loads in flight per wave.
   const int64_t n_tiles = (n_p + kBRows - 1) / kBRows;
-  const int64_t G = gridDim.x;
-  if (int64_t(blockIdx.x) < n_tiles) load_tile(prA, vA, int64_t(blockIdx.x) * kBRows);
-  if (NBUF == 2 && int64_t(blockIdx.x) + G < n_tiles) load_tile(prB, vB, (int64_t(blockIdx.x) + G) * kBRows);
+  const int64_t G = nblk;
+  if (int64_t(blk) < n_tiles) load_tile(prA, vA, int64_t(blk) * kBRows);
+  if (NBUF == 2 && int64_t(blk) + G < n_tiles) load_tile(prB, vB, (int64_t(blk) + G) * kBRows);
   __syncthreads();
 
   auto do_tile = [&](uint4 (&pr)[kKSW], float &vv, int64_t tile) {
@@ -357,16 +355,16 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
     if (RECON) obj += double(objf);
   };
   if (NBUF == 2) {
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += 2 * G) {
+    for (int64_t tile = blk; tile < n_tiles; tile += 2 * G) {
       do_tile(prA, vA, tile);
       if (tile + G < n_tiles) do_tile(prB, vB, tile + G);
     }
   } else {
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += G) do_tile(prA, vA, tile);
+    for (int64_t tile = blk; tile < n_tiles; tile += G) do_tile(prA, vA, tile);
   }
 
   // Partials: N_D[bin][j] = C[bin][j] + C[bin][8 + j] (lanes n and n + 8).
-  float *dst = part_nd + size_t(blockIdx.x) * n_k * K;
+  float *dst = part_nd + size_t(blk) * n_k * K;
   const int n = lane & 15;
 #pragma unroll
   for (int i = 0; i < kKSW; ++i) {
@@ -383,7 +381,7 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
       }
     }
   }
-  if (t < K * K) part_gv[size_t(blockIdx.x) * K * K + t] = gv;
+  if (t < K * K) part_gv[size_t(blk) * K * K + t] = gv;
   if (OBJ) {
     obj = wave_sum_all(obj);
     if (lane == 0) obj_s[w] = obj;
@@ -391,9 +389,47 @@ __global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__
     if (t == 0) {
       double s = 0.0;
       for (int ww = 0; ww < kBWaves; ++ww) s += obj_s[ww];
-      part_obj[blockIdx.x] = s;
+      part_obj[blk] = s;
     }
   }
+}
+
+
+template <int K, int MODE, bool OBJ, int NW, int NBUF>
+__global__ __launch_bounds__(kBThreads) void pass_bf16_kernel(const uint16_t *__restrict__ Pb, int64_t ldb,
+                                                              int64_t n_p, int n_k, float *__restrict__ V,
+                                                              const uint4 *__restrict__ db1g,
+                                                              const uint4 *__restrict__ db3g,
+                                                              const double *__restrict__ GD,
+                                                              const double *__restrict__ chol,
+                                                              float *__restrict__ part_nd,
+                                                              double *__restrict__ part_gv,
+                                                              double *__restrict__ part_obj,
+                                                              NmfCtrl *__restrict__ ctrl, int iter,
+                                                              const double *__restrict__ ginv) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  pass_bf16_body<K, MODE, OBJ, NW, NBUF>(Pb, ldb, n_p, n_k, V, db1g, db3g, GD, chol, part_nd, part_gv, part_obj, ctrl,
+                                         iter, ginv, int(blockIdx.x), int(gridDim.x), smem);
+}
+
+// Batched MU iterations on the bfloat16 p: one launch over the instances
+// d[0 .. n_inst) of one (K, k-step class) group; block b belongs to the
+// instance whose range [wg0b, wg0b + n_wgb) holds it (wg0b counted from the
+// group's first instance) and runs that instance's pass as workgroup
+// b - wg0b of n_wgb, so each instance computes what its own call computes.
+template <int K, bool OBJ, int NW, int NBUF>
+__global__ __launch_bounds__(kBThreads) void batched_pass_bf16_kernel(const BatchInst *__restrict__ d, int n_inst,
+                                                                      int iter_local) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int i = batch_find(n_inst, int(blockIdx.x), [&](int j) { return d[j].wg0b; });
+  const BatchInst &b = d[i];
+  const int wg = int(blockIdx.x) - b.wg0b;
+  if (wg >= b.n_wgb) return;
+  const int iter = b.ctrl->iter_base + iter_local;
+  const uint4 *db1 = reinterpret_cast<const uint4 *>(b.img);
+  const uint4 *db3 = db1 + (bf16_ldb_pad(b.ldb) / 32) * 64;
+  pass_bf16_body<K, kModeMU, OBJ, NW, NBUF>(b.Pb, b.ldb, b.n_p, b.n_k, b.V, db1, db3, b.gd, b.chol, b.part_nd,
+                                            b.part_gv, b.part_obj, b.ctrl, iter, nullptr, wg, b.n_wgb, smem);
 }
 
 template <int K, int MODE, bool OBJ, int NW, int NBUF>
@@ -474,6 +510,45 @@ bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const
   }
   return false;
 }
+
+template <int K, int NW, int NBUF>
+static bool launch_batched_bf16_inst(bool obj, int n_blocks, int lds, hipStream_t st, const BatchInst *d,
+                                     int n_inst, int iter_local) {
+  static bool attr_set[2] = {false, false};
+  const void *fn = obj ? reinterpret_cast<const void *>(&batched_pass_bf16_kernel<K, true, NW, NBUF>)
+                       : reinterpret_cast<const void *>(&batched_pass_bf16_kernel<K, false, NW, NBUF>);
+  if (!attr_set[obj]) {
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return false;
+    attr_set[obj] = true;
+  }
+  if (obj)
+    batched_pass_bf16_kernel<K, true, NW, NBUF><<<n_blocks, kBThreads, lds, st>>>(d, n_inst, iter_local);
+  else
+    batched_pass_bf16_kernel<K, false, NW, NBUF><<<n_blocks, kBThreads, lds, st>>>(d, n_inst, iter_local);
+  return true;
+}
+
+// One batched MU pass over a (K, k-step class) group: nw = bf16_ldb_pad(ldb)
+// / 256 of its instances (tiles in flight as for the single-instance MU pass).
+bool launch_batched_pass_bf16(int K, int nw, bool obj, int n_blocks, hipStream_t st, const BatchInst *d, int n_inst,
+                              int iter_local) {
+  if (K < 1 || K > 8) return false;
+  const int lds = bf16_lds_layout(256 * int64_t(nw), K, false).total;
+  switch (K) {
+#define HSN_K(KK)                                                                                              \
+  case KK:                                                                                                     \
+    if (nw == 1) return launch_batched_bf16_inst<KK, 1, 2>(obj, n_blocks, lds, st, d, n_inst, iter_local);    \
+    if (nw == 2) return launch_batched_bf16_inst<KK, 2, 2>(obj, n_blocks, lds, st, d, n_inst, iter_local);    \
+    if (nw == 4) return launch_batched_bf16_inst<KK, 4, 2>(obj, n_blocks, lds, st, d, n_inst, iter_local);    \
+    if (nw == 8) return launch_batched_bf16_inst<KK, 8, 1>(obj, n_blocks, lds, st, d, n_inst, iter_local);    \
+    return false;
+    HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
+#undef HSN_K
+  }
+  return false;
+}
+
+int bf16_k_steps_class(int64_t ldb) { return int(bf16_ldb_pad(ldb) / 256); }
 
 int pass_bf16_wgs(hsn_ctx *ctx, int64_t n_p) {
   const int64_t n_tiles = (n_p + kBRows - 1) / kBRows;

@@ -85,6 +85,12 @@ struct BatchInst {
   int ub0, n_ub;   // D-update blocks
   int rb0, n_rb;   // row-solve blocks
   double f_ref, tol;
+  // bfloat16 MU bulk (or null Pb): the bfloat16 p, its pitch, the operand
+  // images of D (ldb_img = their padded width) and the MFMA pass's workgroups
+  const uint16_t *Pb;
+  int64_t ldb, ldb_img;
+  uint16_t *img;
+  int wg0b, n_wgb;
 };
 
 // Instance of a batch that owns grid block b: the last i with first(i) <= b

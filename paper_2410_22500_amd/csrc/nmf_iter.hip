@@ -243,7 +243,7 @@ __device__ __forceinline__ void update_d_body(
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
     int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int blk, int n_blk,
     char *__restrict__ lds, int bf16 = 0, const double *__restrict__ bias = nullptr,
-    double *__restrict__ part_gd16 = nullptr) {
+    double *__restrict__ part_gd16 = nullptr, int no_stop = 0) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   using L = UpdLds<K, RULE>;
@@ -298,7 +298,7 @@ __device__ __forceinline__ void update_d_body(
       // a non-finite objective (NaN or Inf in p or in the factors) ends the run
       ctrl->numeric = 1;
       ctrl->stop_at = iter + 1;
-    } else if (f_ref > 0.0 && (ob - f_ref) / f_ref <= tol) {
+    } else if (!no_stop && f_ref > 0.0 && (ob - f_ref) / f_ref <= tol) {
       ctrl->stop_at = iter + 1;
     }
   }
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(kUpdThreads) void batched_init_kernel(const BatchIn
   const BatchInst &b = d[blockIdx.x];
   switch (b.K) {
 #define HSN_K(KK) \
-  case KK: nmf_init_body<KK>(b.D, b.n_k, b.gd, b.chol, want_chol, nullptr, 0, b.ctrl); break;
+  case KK: nmf_init_body<KK>(b.D, b.n_k, b.gd, b.chol, want_chol, b.img, b.img ? b.ldb_img : 0, b.ctrl); break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
     default: break;
@@ -462,13 +462,14 @@ __global__ __launch_bounds__(kUpdThreads) void batched_init_kernel(const BatchIn
 
 // One block per instance.
 __global__ __launch_bounds__(kUpdThreads) void batched_reduce_gv_kernel(const BatchInst *__restrict__ d, int iter_local,
-                                                                        int has_obj) {
+                                                                        int has_obj, int bf16) {
   __shared__ double red[kUpdThreads];
   const BatchInst &b = d[blockIdx.x];
   const int iter = b.ctrl->iter_base + iter_local;
+  const int n_wg = bf16 ? b.n_wgb : b.n_wg;  // partials of the pass that ran
   switch (b.K) {
 #define HSN_K(KK) \
-  case KK: reduce_gv_body<KK>(b.part_gv, b.part_obj, b.n_wg, has_obj, b.ctrl, iter, red); break;
+  case KK: reduce_gv_body<KK>(b.part_gv, b.part_obj, n_wg, has_obj, b.ctrl, iter, red); break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
     default: break;
@@ -493,18 +494,21 @@ __global__ __launch_bounds__(kUpdThreads) void batched_finish_gd_kernel(const Ba
 
 template <int RULE>
 __global__ __launch_bounds__(kUpdThreads) void batched_update_kernel(const BatchInst *__restrict__ d, int n_inst,
-                                                                     int iter_local, int has_obj, int next_chol) {
+                                                                     int iter_local, int has_obj, int next_chol,
+                                                                     int bf16) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int i = batch_find(n_inst, int(blockIdx.x), [&](int j) { return d[j].ub0; });
   const BatchInst &b = d[i];
   const int blk = int(blockIdx.x) - b.ub0;
   if (blk >= b.n_ub) return;
   const int iter = b.ctrl->iter_base + iter_local;
+  const int n_wg = bf16 ? b.n_wgb : b.n_wg;
   switch (b.K) {
 #define HSN_K(KK)                                                                                                 \
   case KK:                                                                                                        \
-    update_d_body<KK, RULE>(b.D, b.part_nd, b.n_wg, b.n_k, b.ctrl, iter, has_obj, b.f_ref, b.tol, b.hist, b.gd, \
-                            b.chol, next_chol, b.part_gd, nullptr, 0, blk, b.n_ub, lds);                        \
+    update_d_body<KK, RULE>(b.D, b.part_nd, n_wg, b.n_k, b.ctrl, iter, has_obj, b.f_ref, b.tol, b.hist, b.gd,   \
+                            b.chol, next_chol, b.part_gd, b.img, b.img ? b.ldb_img : 0, blk, b.n_ub, lds, bf16, \
+                            nullptr, nullptr, bf16);                                                             \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
@@ -617,12 +621,14 @@ void launch_batched_init(int n_inst, int want_chol, hipStream_t st, const BatchI
 }
 
 void launch_batched_update(int rule, int n_blocks, size_t lds, hipStream_t st, const BatchInst *d, int n_inst,
-                           int iter_local, bool has_obj, bool next_chol) {
-  batched_reduce_gv_kernel<<<n_inst, kUpdThreads, 0, st>>>(d, iter_local, has_obj);
+                           int iter_local, bool has_obj, bool next_chol, bool bf16) {
+  batched_reduce_gv_kernel<<<n_inst, kUpdThreads, 0, st>>>(d, iter_local, has_obj, bf16 ? 1 : 0);
   if (rule == kModeNV)
-    batched_update_kernel<kModeNV><<<n_blocks, kUpdThreads, lds, st>>>(d, n_inst, iter_local, has_obj, next_chol);
+    batched_update_kernel<kModeNV><<<n_blocks, kUpdThreads, lds, st>>>(d, n_inst, iter_local, has_obj, next_chol,
+                                                                        bf16 ? 1 : 0);
   else
-    batched_update_kernel<kModeMU><<<n_blocks, kUpdThreads, lds, st>>>(d, n_inst, iter_local, has_obj, next_chol);
+    batched_update_kernel<kModeMU><<<n_blocks, kUpdThreads, lds, st>>>(d, n_inst, iter_local, has_obj, next_chol,
+                                                                        bf16 ? 1 : 0);
   batched_finish_gd_kernel<<<n_inst, kUpdThreads, 0, st>>>(d, iter_local, next_chol);
 }
 

@@ -59,7 +59,8 @@ class NmfStats(C.Structure):
 
 class NmfProblem(C.Structure):
     _fields_ = [("p", C.c_void_p), ("ldp", C.c_int64), ("n_p", C.c_int64), ("n_k", C.c_int64), ("k", C.c_int),
-                ("V", C.c_void_p), ("D", C.c_void_p), ("f_ref", C.c_double)]
+                ("V", C.c_void_p), ("D", C.c_void_p), ("f_ref", C.c_double), ("p_bf16", C.c_void_p),
+                ("ldb", C.c_int64)]
 
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -389,31 +390,44 @@ def hsn_nmf_set_launch(anls_passes: int = 0, device: int = 0) -> None:
 
 
 def hsn_subspace_nmf_batched(problems, max_iter: int = 100, check_every: int = 10, polish_rounds: int = 0,
-                             rel_obj_tol: float = 0.0, flags: int = BATCH_GRAPH, history_cap: int = 4096):
-    """problems: list of (p [N_p][ldp] f32, n_k, V [N_p][K], D [N_k][K], f_ref); V and D in place.
-    Float32 MU bulk then ANLS polish, one launch per phase over all instances."""
+                             rel_obj_tol: float = 0.0, flags: int = BATCH_GRAPH, history_cap: int = 4096,
+                             precision: int = PREC_FP32):
+    """problems: list of (p [N_p][ldp] f32, n_k, V [N_p][K], D [N_k][K], f_ref) or, with
+    precision=PREC_BF16, (p, n_k, V, D, f_ref, p_bf16 [N_p][ldb] int16 bits); V and D in place.
+    MU bulk (float32 or bfloat16 MFMA) then float32 ANLS polish, one launch per phase and kernel
+    shape over all instances."""
     if not problems:
         raise ValueError("hsn: no problems")
+    bf16 = precision == PREC_BF16 and max_iter > 0
     dev0 = problems[0][2].device if isinstance(problems[0][2], torch.Tensor) else None
-    for i, (p, n_k, V, D, _) in enumerate(problems):
+    for i, prob in enumerate(problems):
+        p, n_k, V, D = prob[:4]
         _need(V, f"problems[{i}].V", torch.float32, shape=(None, None), device=dev0)
         _need(D, f"problems[{i}].D", torch.float32, shape=(n_k, V.shape[1]), device=dev0)
         _need(p, f"problems[{i}].p", torch.float32, shape=(V.shape[0], None), layout="rows", device=dev0)
         if p.shape[1] < n_k:
             raise ValueError(f"hsn: problems[{i}].p rows must hold n_k = {n_k} bins")
+        if bf16:
+            if len(prob) < 6 or prob[5] is None:
+                raise ValueError(f"hsn: problems[{i}]: the bfloat16 bulk needs p_bf16 (sixth item)")
+            _need(prob[5], f"problems[{i}].p_bf16", _U16, shape=(V.shape[0], None), layout="rows", device=dev0)
+            if prob[5].shape[1] < n_k:
+                raise ValueError(f"hsn: problems[{i}].p_bf16 rows must hold n_k = {n_k} bins")
     dev = _dev(problems[0][2])
     ctx = context(dev)
     n = len(problems)
     arr = (NmfProblem * n)()
-    for i, (p, n_k, V, D, f_ref) in enumerate(problems):
+    for i, prob in enumerate(problems):
+        p, n_k, V, D, f_ref = prob[:5]
+        pb = prob[5] if bf16 else None
         arr[i] = NmfProblem(p.data_ptr(), p.stride(0), V.shape[0], n_k, V.shape[1], V.data_ptr(), D.data_ptr(),
-                            float(f_ref or 0.0))
-    opts = NmfOpts(1, ALGO_MU, PREC_FP32, INIT_USER, max_iter, check_every, polish_rounds, ALGO_ANLS, 0,
+                            float(f_ref or 0.0), _ptr(pb), pb.stride(0) if pb is not None else 0)
+    opts = NmfOpts(1, ALGO_MU, precision, INIT_USER, max_iter, check_every, polish_rounds, ALGO_ANLS, 0,
                    rel_obj_tol, 0.0, None, None, None)
     hists = [(C.c_double * max(history_cap, 1))() for _ in range(n)]
     stats = (NmfStats * n)()
     for i in range(n):
-        stats[i] = NmfStats(0, 0, 0.0, 0.0, C.cast(hists[i], C.POINTER(C.c_double)), history_cap, 0, 0.0, 0)
+        stats[i] = NmfStats(0, 0, 0.0, 0.0, C.cast(hists[i], C.POINTER(C.c_double)), history_cap, 0, 0.0, 0, 0)
     _check(_lib.hsn_subspace_nmf_batched(ctx, n, arr, C.byref(opts), flags, stats, _stream(dev)), ctx)
     return [_stats(s, hists[i]) for i, s in enumerate(stats)]
 

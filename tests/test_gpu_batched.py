@@ -108,3 +108,88 @@ def test_batched_rejects_bad_input(hsn):
     with pytest.raises(hsn.HsnError):  # misaligned pitch
         p = torch.zeros((V.shape[0], insts[0]["n_k"] + 1), device="cuda")
         hsn.hsn_subspace_nmf_batched([(p, insts[0]["n_k"], V, D, 0.0)])
+
+
+def _c3(seed=33):
+    """The 32 uneven instances of the batched workload (views x columns rows,
+    512-2048 bins, K 2-6): low-rank non-negative data plus noise, clipped,
+    drawn on the device from a seeded generator, with the bfloat16 copy
+    (round to nearest even) and seeded strictly positive starts."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    out = []
+    for d in synth.batched_instances(32):
+        n_p, n_k, k = d["n_views"] * d["n_cols"], d["n_bins"], d["n_mat"]
+        U = torch.rand((n_p, k), generator=g, device="cuda")
+        W = torch.rand((k, n_k), generator=g, device="cuda")
+        P = torch.clamp(U @ W + 0.05 * torch.randn((n_p, n_k), generator=g, device="cuda"), min=0.0)
+        p = torch.zeros((n_p, (n_k + 3) // 4 * 4), dtype=torch.float32, device="cuda")
+        p[:, :n_k] = P
+        pb = torch.zeros((n_p, (n_k + 31) // 32 * 32), dtype=torch.int16, device="cuda")
+        pb[:, :n_k] = P.to(torch.bfloat16).view(torch.int16)
+        V0 = torch.rand((n_p, k), generator=g, device="cuda") + 0.1
+        D0 = torch.rand((n_k, k), generator=g, device="cuda") + 0.1
+        out.append(dict(p=p, pb=pb, n_k=n_k, k=k, V0=V0, D0=D0))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_c3_batched_is_bitwise_per_instance(hsn, prec):
+    # 32 uneven instances in one batched call (graphs) against 32 calls of
+    # hsn_subspace_nmf (ANLS rounds in the two-pass form the batched call
+    # runs): V, D and the objective history bit for bit.
+    insts = _c3()
+    code = hsn.PREC_BF16 if prec == "bf16" else hsn.PREC_FP32
+    kw = dict(max_iter=20, check_every=10, polish_rounds=4)
+    show("c3 batched bitwise", prec=prec, n=len(insts))
+    hsn.hsn_nmf_set_launch(2)
+    try:
+        ref = []
+        for x in insts:
+            V, D = x["V0"].clone(), x["D0"].clone()
+            st = hsn.hsn_subspace_nmf(x["p"], x["pb"] if prec == "bf16" else None, x["n_k"], V, D, precision=code,
+                                      polish_algo=hsn.ALGO_ANLS, **kw)
+            ref.append((V, D, st))
+    finally:
+        hsn.hsn_nmf_set_launch(0)
+    Vs = [x["V0"].clone() for x in insts]
+    Ds = [x["D0"].clone() for x in insts]
+    sts = hsn.hsn_subspace_nmf_batched([(x["p"], x["n_k"], V, D, 0.0, x["pb"]) for x, V, D in zip(insts, Vs, Ds)],
+                                       flags=hsn.BATCH_GRAPH, precision=code, **kw)
+    for i, (V, D, st, (Vr, Dr, sr)) in enumerate(zip(Vs, Ds, sts, ref)):
+        assert torch.equal(V, Vr) and torch.equal(D, Dr), i
+        assert st["history"] == sr["history"], i
+        assert st["iters"] == 20 and st["polish_done"] == 4
+
+
+def test_c3_autotuned_bf16_step_matches_oracle_and_caches(hsn, tmp_path, monkeypatch):
+    # The tuned partition changes only the summation order of the partials:
+    # one bfloat16 MU step of sampled instances against the oracle on the
+    # bfloat16-rounded p at the split products' 2e-5 bound.  The tuned choice
+    # is written to the HSN_TUNE_CACHE file.
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("HSN_TUNE_CACHE", str(cache))
+    insts = _c3(34)
+    Vs = [x["V0"].clone() for x in insts]
+    Ds = [x["D0"].clone() for x in insts]
+    show("c3 batched bf16 autotuned")
+    sts = hsn.hsn_subspace_nmf_batched([(x["p"], x["n_k"], V, D, 0.0, x["pb"]) for x, V, D in zip(insts, Vs, Ds)],
+                                       max_iter=1, check_every=1, flags=hsn.BATCH_GRAPH | hsn.BATCH_AUTOTUNE,
+                                       precision=hsn.PREC_BF16)
+    info = hsn.hsn_batched_plan_info()
+    show("  plan", info=info)
+    assert "tiles/wg" in info
+    text = cache.read_text()
+    assert text.count("budget_index") == 1 and "bf16_tiles_index" in text
+    order = sorted(range(len(insts)), key=lambda i: insts[i]["p"].shape[0] * insts[i]["n_k"])
+    for i in order[:3] + order[-1:]:
+        x = insts[i]
+        n_k = x["n_k"]
+        pq = x["pb"][:, :n_k].cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+        pq = pq.view(np.float32).astype(np.float64)
+        V1, D1, fh, _ = onmf.mu_step(pq, x["V0"].cpu().numpy().astype(np.float64),
+                                     x["D0"].cpu().numpy().astype(np.float64))
+        ev, ed = rel_fro(Vs[i].cpu().numpy(), V1), rel_fro(Ds[i].cpu().numpy(), D1)
+        show("  inst", i=i, shape=tuple(x["p"].shape), V=ev, D=ed)
+        assert ev <= 2e-5 and ed <= 2e-5, i
+        assert abs(sts[i]["history"][0] - fh) <= 2e-5 * fh, i
