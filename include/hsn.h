@@ -175,6 +175,11 @@ typedef struct {
                               objective of the learned start has (f - f_ref)/f_ref above this
                               (or is NaN/Inf), the run restarts from NNDSVDa with the same
                               schedule (stats.fell_back = 1); <= 0: off */
+  int anls_extrapolate;    /* 1: ANLS rounds (polish, or an ANLS bulk) extrapolate D between
+                              rounds (Ang & Gillis 2019): D_hat = max(0, D_new + beta
+                              (D_new - D_prev)) feeds the next round's V solve, with beta
+                              adapted from the round objectives (a rise resets the round to its
+                              exact D); needs the objective every round.  0: plain ANLS */
 } hsn_nmf_opts;
 
 typedef struct {

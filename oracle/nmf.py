@@ -74,6 +74,48 @@ def anls_round(P, V, D):
     return V_new, D_new, f_half, objective(P, V_new, D_new)
 
 
+def anls_extrapolated_run(P, V, D, rounds: int, f_ref: float = 0.0, tol: float = 0.0, beta0: float = 0.5,
+                          grow: float = 1.05, cap_grow: float = 1.01, shrink: float = 1.5):
+    """ANLS rounds with extrapolation of D between rounds (Ang & Gillis,
+    Neural Computation 31(2), 2019), in the form the library runs.
+
+    Round k solves every row of V exactly for D_hat (the start D at k = 0),
+    records e_k = f(V, D_hat), then solves every row of D exactly for V
+    (D_new).  The weight beta (start beta0, cap 1) is adapted from the
+    recorded objectives: if e_k <= e_{k-1}, beta <- min(cap, grow beta),
+    cap <- min(1, cap_grow cap) and D_hat <- max(0, D_new + beta (D_new -
+    D_prev)); otherwise cap <- beta, beta <- beta / shrink and D_hat <- D_new.
+    D_prev <- D_new.  With f_ref > 0 the run stops at the first e_k with
+    (e_k - f_ref)/f_ref <= tol, keeping that round's D_new.
+    Returns (V, D_hat, history of e_k)."""
+    P = np.asarray(P, np.float64)
+    D_hat = np.array(D, np.float64)
+    D_prev = D_hat.copy()
+    beta, cap, e_prev = beta0, 1.0, np.inf
+    hist = []
+    for _ in range(rounds):
+        V = nnls_rows(D_hat.T @ D_hat, P @ D_hat)
+        e = objective(P, V, D_hat)
+        hist.append(e)
+        D_new = nnls_rows(V.T @ V, P.T @ V)
+        stop = f_ref > 0.0 and (e - f_ref) / f_ref <= tol
+        use = 0.0
+        if not stop:
+            if e <= e_prev:
+                beta = min(cap, grow * beta)
+                cap = min(1.0, cap_grow * cap)
+                use = beta
+            else:
+                cap = beta
+                beta = beta / shrink
+        e_prev = e
+        D_hat = np.maximum(0.0, D_new + use * (D_new - D_prev)) if use > 0.0 else D_new
+        D_prev = D_new
+        if stop:
+            break
+    return V, D_hat, np.array(hist)
+
+
 def hals_step(P, V, D):
     """One HALS sweep: columns of V in order, then columns of D, each set to
     its exact non-negative minimiser with the other columns fixed."""

@@ -36,7 +36,7 @@ void launch_pass_f32(int K, int mode, bool obj, int nq, int n_wg, hipStream_t st
                      const double *ginv);
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
                      bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, int bf16 = 0,
-                     const double *bias = nullptr);
+                     const double *bias = nullptr, bool extrap = false);
 bool launch_pass_bf16(int K, int mode, bool obj, int n_wg, hipStream_t st, const uint16_t *Pb, int64_t ldb,
                       int64_t n_p, int n_k, float *V, const double *GD, const double *chol, const uint16_t *img,
                       float *part_nd, double *part_gv, double *part_obj, NmfCtrl *ctrl, int iter,

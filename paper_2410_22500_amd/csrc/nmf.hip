@@ -43,7 +43,7 @@ void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWo
 int update_d_blocks(int n_k);
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
                      bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, int bf16,
-                     const double *bias);
+                     const double *bias, bool extrap);
 void launch_nmf_resume(hipStream_t st, NmfCtrl *ctrl);
 void launch_nmf_calibrate(hipStream_t st, NmfCtrl *ctrl, const double *hist, const double *bias);
 void launch_nnls_rows(int K, hipStream_t st, const NmfWork &w, float *V, int64_t n_p, int n_blocks, int iter);
@@ -129,7 +129,8 @@ hsn_status queue_step(Run &R, const Step &s, int iter, bool next_exact, const fl
     }
   }
   launch_update_d(R.K, s.rule == kModeANLS ? kModeNV : s.rule, R.st, D, R.w, n_wg, R.n_k, iter, obj, R.f_ref,
-                  R.tol, next_exact, R.w.img ? bf16_image_ldb(ldb) : 0, s.bf16 ? 1 : 0, s.bf16 ? R.bias : nullptr);
+                  R.tol, next_exact, R.w.img ? bf16_image_ldb(ldb) : 0, s.bf16 ? 1 : 0, s.bf16 ? R.bias : nullptr,
+                  s.rule == kModeANLS && R.w.dprev != nullptr);
   HSN_LAUNCHED(R.ctx);
   return HSN_OK;
 }
@@ -165,6 +166,8 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   if (!V || !D) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: V and D are required");
   const bool bf16 = o->precision == HSN_PREC_BF16;
   if (o->polish_bf16_rounds < 0) return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: polish_bf16_rounds must be >= 0");
+  if (o->anls_extrapolate != 0 && o->anls_extrapolate != 1)
+    return fail(ctx, HSN_ERR_INVALID_ARG, "nmf: anls_extrapolate must be 0 or 1");
   // The first polish_bf16_rounds polish rounds (ANLS or HALS) read the bfloat16 p.
   const int pol_bf16 = std::min(o->polish_bf16_rounds, o->polish_rounds);
   const bool need_f32 = (!bf16 && o->max_iter > 0) || o->polish_rounds > pol_bf16 || o->init != HSN_INIT_USER;
@@ -201,7 +204,8 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
                                     need_nv ? sizeof(float) * n_p * K : 0, sizeof(double) * hist_cap,
                                     any_bf16 ? sizeof(uint16_t) * bf16_image_elems(ldb) : 0,
                                     any_bf16 ? sizeof(double) * size_t(n_upd) * K * K : 0,
-                                    any_bf16 ? sizeof(double) * kCholStride * kInvStride : 0});
+                                    any_bf16 ? sizeof(double) * kCholStride * kInvStride : 0,
+                                    o->anls_extrapolate ? sizeof(float) * size_t(n_k) * K : 0});
   // NNDSVD runs before any NMF kernel on the same stream, so its scratch can
   // share the workspace with the decomposition's.
   int n_split = 1;
@@ -236,6 +240,8 @@ extern "C" hsn_status hsn_subspace_nmf(hsn_ctx *ctx, const float *p, int64_t ldp
   // its objective exactly.
   R.w.part_gd16 = any_bf16 ? cv.take<double>(size_t(n_upd) * K * K) : nullptr;
   R.w.ginv16 = any_bf16 ? cv.take<double>(size_t(kCholStride) * kInvStride) : nullptr;
+  // Extrapolated ANLS keeps the previous round's exact D.
+  R.w.dprev = o->anls_extrapolate ? cv.take<float>(size_t(n_k) * K) : nullptr;
   void *pool_buf = need_pool ? cv.take<char>(need_pool - 256) : nullptr;
   R.w.n_wg = n_wg;
   R.wg_f32 = wg_f32;

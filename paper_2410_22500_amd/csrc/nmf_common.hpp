@@ -49,6 +49,10 @@ struct NmfCtrl {
   double last16;    // objective of the last step on p_bf16 that evaluated one
   double adj;       // calibration added to the bfloat16 stop estimate (objective + bias + adj)
   double last_est;  // the value the last stop test compared (the estimate on p_bf16 steps)
+  // extrapolated ANLS (hsn_nmf_opts.anls_extrapolate): the extrapolation
+  // weight, its cap, the previous round's objective and the weight this
+  // round's D update applies (0: no extrapolation)
+  double beta, beta_bar, e_prev, beta_use;
   double gvo[65];   // G_V = V^T V (K*K) and the objective of the last pass, reduced
 };
 
@@ -67,6 +71,7 @@ struct NmfWork {
   double *ginv16;    // [36][kInvStride] inverses of the principal submatrices of G_D' (or null)
   double *hist;      // [hist_cap] objective history (device)
   uint16_t *img;     // bfloat16 operand images of D for the MFMA pass (or null)
+  float *dprev;      // [n_k][K] extrapolated ANLS: the previous round's exact D (or null)
   int n_wg;
 };
 
@@ -106,6 +111,13 @@ __device__ __forceinline__ int batch_find(int n, int b, F first) {
 }
 
 constexpr int kCholStride = 36;  // packed lower triangle of an 8x8 matrix
+
+// Extrapolated ANLS (Ang & Gillis, Neural Computation 2019): the weight
+// starts at kExtrapBeta0 with cap 1; after a round whose objective did not
+// rise it grows by kExtrapGrow (capped) and the cap by kExtrapCapGrow (at
+// most 1); after a rise the cap becomes the weight, the weight shrinks by
+// kExtrapShrink and that round's D is taken without extrapolation.
+constexpr double kExtrapBeta0 = 0.5, kExtrapGrow = 1.05, kExtrapCapGrow = 1.01, kExtrapShrink = 1.5;
 
 __host__ __device__ constexpr int tri(int a) { return a * (a + 1) / 2; }
 

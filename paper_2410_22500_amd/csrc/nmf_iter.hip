@@ -140,10 +140,13 @@ __device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n
                                               double *__restrict__ chol, int want_chol, uint16_t *__restrict__ img,
                                               int64_t ldb, NmfCtrl *__restrict__ ctrl,
                                               double *__restrict__ ginv = nullptr,
-                                              double *__restrict__ ginv16 = nullptr) {
+                                              double *__restrict__ ginv16 = nullptr,
+                                              float *__restrict__ dprev = nullptr) {
   const int t = threadIdx.x;
   __shared__ double red[kUpdThreads / 64][K * K];
   __shared__ double g_s[K * K];
+  if (dprev)
+    for (int e = t; e < n_k * K; e += kUpdThreads) dprev[e] = D[e];
   if (img) {
     for (int64_t k = t; k < ldb; k += kUpdThreads) {
       float d[K];
@@ -161,6 +164,10 @@ __device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n
     ctrl->last16 = 0.0;
     ctrl->adj = 0.0;
     ctrl->last_est = 0.0;
+    ctrl->beta = kExtrapBeta0;
+    ctrl->beta_bar = 1.0;
+    ctrl->e_prev = INFINITY;
+    ctrl->beta_use = 0.0;
   }
   block_gram_d<K>(D, n_k, false, red, g_s);
   if (t < K * K) GD[t] = g_s[t];
@@ -177,8 +184,8 @@ __global__ __launch_bounds__(kUpdThreads) void nmf_init_kernel(const float *__re
                                                                double *__restrict__ chol, int want_chol,
                                                                uint16_t *__restrict__ img, int64_t ldb,
                                                                NmfCtrl *__restrict__ ctrl, double *__restrict__ ginv,
-                                                               double *__restrict__ ginv16) {
-  nmf_init_body<K>(D, n_k, GD, chol, want_chol, img, ldb, ctrl, ginv, ginv16);
+                                                               double *__restrict__ ginv16, float *__restrict__ dprev) {
+  nmf_init_body<K>(D, n_k, GD, chol, want_chol, img, ldb, ctrl, ginv, ginv16, dprev);
 }
 
 // RULE: kModeMU (Lee-Seung), kModeHALS (column sweep), kModeNV (exact NNLS rows)
@@ -243,7 +250,7 @@ __device__ __forceinline__ void update_d_body(
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
     int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int blk, int n_blk,
     char *__restrict__ lds, int bf16 = 0, const double *__restrict__ bias = nullptr,
-    double *__restrict__ part_gd16 = nullptr, int no_stop = 0) {
+    double *__restrict__ part_gd16 = nullptr, int no_stop = 0, float *__restrict__ dprev = nullptr) {
   if (iter >= ctrl->stop_at) return;
   const int t = threadIdx.x;
   using L = UpdLds<K, RULE>;
@@ -331,6 +338,18 @@ __device__ __forceinline__ void update_d_body(
       } else {
         nnls_gram_row<K>(gv_s, chol_s, nd, x);
       }
+      if (RULE == kModeNV && dprev) {
+        // extrapolated ANLS: D_hat = max(0, D_new + beta (D_new - D_prev)),
+        // D_prev <- D_new; the next round solves V for D_hat
+        const double bu = ctrl->beta_use;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float dnew = float(x[j]);
+          const double dp = dprev[size_t(k) * K + j];
+          dprev[size_t(k) * K + j] = dnew;
+          if (bu > 0.0) x[j] = fmax(0.0, double(dnew) + bu * (double(dnew) - dp));
+        }
+      }
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         dn[j] = float(x[j]);
@@ -413,10 +432,10 @@ __global__ __launch_bounds__(kUpdThreads) void update_d_kernel(
     int has_obj,
     double f_ref, double tol, double *__restrict__ hist, double *__restrict__ GD, double *__restrict__ chol,
     int next_chol, double *__restrict__ part_gd, uint16_t *__restrict__ img, int64_t ldb, int bf16,
-    const double *__restrict__ bias, double *__restrict__ part_gd16) {
+    const double *__restrict__ bias, double *__restrict__ part_gd16, float *__restrict__ dprev) {
   __shared__ __attribute__((aligned(16))) char lds[UpdLds<K, RULE>::bytes];
   update_d_body<K, RULE>(D, part_nd, n_wg, n_k, ctrl, iter, has_obj, f_ref, tol, hist, GD, chol, next_chol, part_gd,
-                         img, ldb, int(blockIdx.x), int(gridDim.x), lds, bf16, bias, part_gd16);
+                         img, ldb, int(blockIdx.x), int(gridDim.x), lds, bf16, bias, part_gd16, 0, dprev);
 }
 
 template <int K>
@@ -531,6 +550,32 @@ __global__ void batched_advance_kernel(const BatchInst *__restrict__ d, int n_in
   if (i < n_inst) d[i].ctrl->iter_base += steps;
 }
 
+// Extrapolated ANLS: this round's weight, from the objective the pass just
+// reduced (the stop estimate on p_bf16 steps).  A round whose estimate meets
+// the stop test takes its exact D (the returned factors are then at least
+// as good as the reported objective).  One thread; runs between the G_V
+// reduction and the D update, so every update block reads the same weight.
+__global__ void anls_beta_kernel(NmfCtrl *__restrict__ ctrl, int iter, int obj_index, double f_ref, double tol,
+                                 int bf16, const double *__restrict__ bias) {
+  if (iter >= ctrl->stop_at) return;
+  double ob = ctrl->gvo[obj_index];
+  if (bf16) ob += (bias ? *bias : 0.0) + ctrl->adj;
+  const bool stop = !isfinite(ob) || (f_ref > 0.0 && (ob - f_ref) / f_ref <= tol);
+  double use = 0.0;
+  if (!stop) {
+    if (ob <= ctrl->e_prev) {
+      ctrl->beta = fmin(ctrl->beta_bar, kExtrapGrow * ctrl->beta);
+      ctrl->beta_bar = fmin(1.0, kExtrapCapGrow * ctrl->beta_bar);
+      use = ctrl->beta;
+    } else {
+      ctrl->beta_bar = ctrl->beta;
+      ctrl->beta = ctrl->beta / kExtrapShrink;
+    }
+  }
+  ctrl->e_prev = ob;
+  ctrl->beta_use = use;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers for a runtime K.
 // ---------------------------------------------------------------------------
@@ -538,7 +583,7 @@ void launch_nmf_init(int K, hipStream_t st, const float *D, int n_k, const NmfWo
   switch (K) {
 #define HSN_K(KK) \
   case KK: nmf_init_kernel<KK><<<1, kUpdThreads, 0, st>>>(D, n_k, w.gd, w.chol, want_chol, w.img, ldb, w.ctrl, w.ginv, \
-                                                          w.ginv16); break;
+                                                          w.ginv16, w.dprev); break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
   }
@@ -548,7 +593,7 @@ int update_d_blocks(int n_k) { return (n_k + kUpdRows - 1) / kUpdRows; }
 
 void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w, int n_wg, int n_k, int iter,
                      bool has_obj, double f_ref, double tol, bool next_chol, int64_t ldb_img, int bf16,
-                     const double *bias) {
+                     const double *bias, bool extrap) {
   const int nb = update_d_blocks(n_k);
   uint16_t *img = ldb_img > 0 ? w.img : nullptr;
   switch (K) {
@@ -557,21 +602,26 @@ void launch_update_d(int K, int rule, hipStream_t st, float *D, const NmfWork &w
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
   }
+  const bool ex = extrap && rule == kModeNV && has_obj && w.dprev;
+  if (ex) anls_beta_kernel<<<1, 1, 0, st>>>(w.ctrl, iter, K * K, f_ref, tol, bf16, bias);
   switch (K) {
 #define HSN_K(KK)                                                                                                 \
   case KK:                                                                                                        \
     if (rule == kModeMU)                                                                                          \
       update_d_kernel<KK, kModeMU><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
-                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias, w.part_gd16); \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias, w.part_gd16, \
+                                                               ex ? w.dprev : nullptr); \
     else if (rule == kModeHALS)                                                                                   \
       update_d_kernel<KK, kModeHALS><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                          \
                                                                  w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd, \
-                                                                 w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias, w.part_gd16); \
+                                                                 w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias, w.part_gd16, \
+                                                               ex ? w.dprev : nullptr); \
     else                                                                                                          \
       update_d_kernel<KK, kModeNV><<<nb, kUpdThreads, 0, st>>>(D, w.part_nd, n_wg, n_k,                            \
                                                                w.ctrl, iter, has_obj, f_ref, tol, w.hist, w.gd,   \
-                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias, w.part_gd16); \
+                                                               w.chol, next_chol, w.part_gd, img, ldb_img, bf16, bias, w.part_gd16, \
+                                                               ex ? w.dprev : nullptr); \
     break;
     HSN_K(1) HSN_K(2) HSN_K(3) HSN_K(4) HSN_K(5) HSN_K(6) HSN_K(7) HSN_K(8)
 #undef HSN_K
@@ -647,6 +697,8 @@ void launch_batched_rows(int K, int n_blocks, hipStream_t st, const BatchInst *d
 __global__ void nmf_resume_kernel(NmfCtrl *__restrict__ ctrl) { ctrl->stop_at = INT_MAX; }
 
 void launch_nmf_resume(hipStream_t st, NmfCtrl *ctrl) { nmf_resume_kernel<<<1, 1, 0, st>>>(ctrl); }
+
+
 
 // After a float32 round that confirms a stop of the bfloat16 rounds: the
 // calibration that makes the estimate of the last bfloat16 objective equal

@@ -43,7 +43,7 @@ class NmfOpts(C.Structure):
                 ("max_iter", C.c_int), ("check_every", C.c_int), ("polish_rounds", C.c_int),
                 ("polish_algo", C.c_int), ("polish_bf16_rounds", C.c_int), ("rel_obj_tol", C.c_double),
                 ("f_ref", C.c_double), ("mlp", C.c_void_p), ("mlp_pooled", C.c_void_p), ("bf16_bias", C.c_void_p),
-                ("mlp_fallback_rel", C.c_double)]
+                ("mlp_fallback_rel", C.c_double), ("anls_extrapolate", C.c_int)]
 
 
 class TrainOpts(C.Structure):
@@ -347,7 +347,7 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
                      polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0,
                      init: int = INIT_USER, mlp: Optional["Mlp"] = None, history_cap: int = 4096,
                      mlp_pooled: Optional[torch.Tensor] = None, bf16_bias: Optional[torch.Tensor] = None,
-                     mlp_fallback_rel: float = 0.0) -> dict:
+                     mlp_fallback_rel: float = 0.0, anls_extrapolate: bool = False) -> dict:
     """Runs eq. (4) in place on V [N_p][K] and D [N_k][K] (float32, device).  bf16_bias: the f64
     device scalar -||p - p_bf16||^2 (hsn_normalize want_bias) for the stop test of the
     polish rounds on p_bf16.  mlp_fallback_rel > 0: a learned start whose first objective is
@@ -367,7 +367,7 @@ def hsn_subspace_nmf(p: Optional[torch.Tensor], p_bf16: Optional[torch.Tensor], 
     _opt(bf16_bias, "bf16_bias", torch.float64, shape=(), device=V.device)
     opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo,
                    polish_bf16_rounds, rel_obj_tol, f_ref, mlp.handle if mlp is not None else None,
-                   _ptr(mlp_pooled), _ptr(bf16_bias), float(mlp_fallback_rel))
+                   _ptr(mlp_pooled), _ptr(bf16_bias), float(mlp_fallback_rel), int(bool(anls_extrapolate)))
     hist = (C.c_double * max(history_cap, 1))()
     stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0, 0, 0)
     ldp = p.stride(0) if p is not None else 0
@@ -503,7 +503,8 @@ def hsn_fhr_step(y: torch.Tensor, yo: torch.Tensor, V: torch.Tensor, D: torch.Te
                  bufs: Optional[dict] = None, algo: int = ALGO_MU, precision: int = PREC_FP32, max_iter: int = 100,
                  check_every: int = 10, polish_rounds: int = 0, polish_algo: int = ALGO_ANLS,
                  polish_bf16_rounds: int = 0, rel_obj_tol: float = 0.0, f_ref: float = 0.0, init: int = INIT_USER,
-                 mlp: Optional["Mlp"] = None, history_cap: int = 4096, mlp_fallback_rel: float = 0.0):
+                 mlp: Optional["Mlp"] = None, history_cap: int = 4096, mlp_fallback_rel: float = 0.0,
+                 anls_extrapolate: bool = False):
     """The whole FHR path of one scan in one C call: counts y [N_v][N_r][N_c][N_k] and y^o (uint16 bits
     as int16) -> V, D in place, x [N_r][N_c][N_c][K], and x^h over vox x bins (None if vox is None).
     bufs: optional dict that keeps the intermediates (p, pooled) and outputs (x, xh) between calls."""
@@ -536,7 +537,7 @@ def hsn_fhr_step(y: torch.Tensor, yo: torch.Tensor, V: torch.Tensor, D: torch.Te
     xh = bufs.get("xh") if vox is not None else None
     opts = NmfOpts(k, algo, precision, init, max_iter, check_every, polish_rounds, polish_algo, polish_bf16_rounds,
                    rel_obj_tol, f_ref, mlp.handle if mlp is not None else None, None, None,
-                   float(mlp_fallback_rel))
+                   float(mlp_fallback_rel), int(bool(anls_extrapolate)))
     hist = (C.c_double * max(history_cap, 1))()
     stats = NmfStats(0, 0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)), history_cap, 0, 0.0, 0, 0)
     keep = (C.c_double * n_v)(*[float(a) for a in angles]) if angles is not None else None

@@ -209,6 +209,8 @@ def main(argv=None):
     ap.add_argument("--mid", action="store_true", help="also compare on the mid workload (1024 bins pooled)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--unseen-library", type=int, default=None,
+                    help="also compare on held-out scans of this material library (not seen in training)")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     X, T, t = make_training_set(a.phantoms, joint=not a.per_scan, log=log)
@@ -217,15 +219,25 @@ def main(argv=None):
     log(f"training: {a.epochs} epochs in {t_train:.2f} s, loss {hist[0]:.4g} -> {hist[-1]:.4g}")
     if a.out:
         hsn.hsn_mlp_save(m, a.out)
+    def summarise(rows):
+        cw = np.array([[r["cold_iters"], r["warm_iters"], r["cold_ms"], r["warm_ms"]] for r in rows], float)
+        return dict(cold_iters_mean=cw[:, 0].mean(), warm_iters_mean=cw[:, 1].mean(),
+                    cold_ms_mean=cw[:, 2].mean(), warm_ms_mean=cw[:, 3].mean(),
+                    cold_ms_median=float(np.median(cw[:, 2])), warm_ms_median=float(np.median(cw[:, 3])),
+                    warm_reached=int(sum(r["warm_rel"] <= 1e-4 for r in rows)),
+                    cold_reached=int(sum(r["cold_rel"] <= 1e-4 for r in rows)), held_out=len(rows))
+
     rows = compare_held_out(m, a.held_out)
     for r in rows:
         log(json.dumps(r))
-    cw = np.array([[r["cold_iters"], r["warm_iters"], r["cold_ms"], r["warm_ms"]] for r in rows], float)
     summary = dict(spectra=int(X.shape[0]), epochs=a.epochs, train_s=t_train, loss_first=hist[0],
-                   loss_last=hist[-1], cold_iters_mean=cw[:, 0].mean(), warm_iters_mean=cw[:, 1].mean(),
-                   cold_ms_mean=cw[:, 2].mean(), warm_ms_mean=cw[:, 3].mean(),
-                   warm_reached=int(sum(r["warm_rel"] <= 1e-4 for r in rows)),
-                   cold_reached=int(sum(r["cold_rel"] <= 1e-4 for r in rows)), held_out=len(rows), **t)
+                   loss_last=hist[-1], library_seed=LIBRARY_SEED, **summarise(rows), **t)
+    rows_unseen = None
+    if a.unseen_library is not None:
+        rows_unseen = compare_held_out(m, a.held_out, library_seed=a.unseen_library)
+        for r in rows_unseen:
+            log("unseen library: " + json.dumps(r))
+        summary["unseen_library"] = dict(library_seed=a.unseen_library, **summarise(rows_unseen))
     if a.mid:
         scan = synth.make_scan(n_mat=N_MAT, seed=MID_SEED, library_seed=LIBRARY_SEED, **MID_GEOMETRY)
         p, pb = scan_to_device(scan)
@@ -241,7 +253,7 @@ def main(argv=None):
     log(json.dumps(summary))
     if a.json:
         with open(a.json, "w") as f:
-            json.dump(dict(summary=summary, rows=rows, loss=hist), f, indent=1)
+            json.dump(dict(summary=summary, rows=rows, rows_unseen_library=rows_unseen, loss=hist), f, indent=1)
 
 
 if __name__ == "__main__":

@@ -274,3 +274,55 @@ def test_zero_column_in_d_stays_finite(hsn):
         assert np.all(np.isfinite(Vg)) and np.all(np.isfinite(Dg))
         assert rel_fro(Vg, V1) <= 1e-5 and rel_fro(Dg, D1) <= 1e-5
         assert abs(st["history"][0] - fh) <= 1e-5 * fh
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_extrapolated_anls_rounds_against_oracle(hsn, passes):
+    # Eight extrapolated ANLS rounds (fused pass or two-pass form) from a
+    # seeded start against the oracle's run of the same rule: the objective
+    # of every round within 1e-5, V and D within 1e-4 (float32 factors
+    # between exact float64 solves, carried through the extrapolation).
+    g = np.random.Generator(np.random.PCG64(95))
+    n_p, n_k, k = 1500, 300, 4
+    p = _as32(np.maximum(g.uniform(0, 1, (n_p, k)) @ g.uniform(0, 1, (k, n_k))
+                         + 0.05 * g.standard_normal((n_p, n_k)), 0))
+    V0, D0 = synth.random_factors(n_p, n_k, k, 96)
+    V0, D0 = _as32(V0), _as32(D0)
+    Vr, Dr, hr = onmf.anls_extrapolated_run(p, V0, D0, 8)
+    hsn.hsn_nmf_set_launch(passes)
+    try:
+        V = to_dev(V0, torch.float32)
+        D = to_dev(D0, torch.float32)
+        st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, max_iter=0, polish_rounds=8,
+                                  polish_algo=hsn.ALGO_ANLS, anls_extrapolate=True)
+    finally:
+        hsn.hsn_nmf_set_launch(0)
+    h = np.array(st["history"])
+    ev, ed = rel_fro(V.cpu().numpy(), Vr), rel_fro(D.cpu().numpy(), Dr)
+    show("extrapolated anls", passes=passes, V=ev, D=ed, h=float(np.max(np.abs(h - hr) / hr)))
+    assert h.shape == hr.shape and np.all(np.abs(h - hr) <= 1e-5 * hr)
+    assert ev <= 1e-4 and ed <= 1e-4
+
+
+def test_extrapolated_anls_reaches_reference_in_fewer_rounds(hsn):
+    # The tiny scan's stationary reference f*: with the stop test at 1e-4 the
+    # extrapolated rounds stop within the tolerance in fewer rounds than the
+    # plain ones, and the returned factors are at least as good as the last
+    # reported objective.
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "nmf_tiny_stationary.json")) as fh:
+        f_star = json.load(fh)["f_star"]
+    p = _tiny_p()
+    n_p, n_k = p.shape
+    V0, D0 = synth.random_factors(n_p, n_k, 3, 10)
+    rounds = {}
+    for ex in (False, True):
+        V = to_dev(_as32(V0), torch.float32)
+        D = to_dev(_as32(D0), torch.float32)
+        st = hsn.hsn_subspace_nmf(_p_dev(p), None, n_k, V, D, max_iter=0, polish_rounds=3000,
+                                  polish_algo=hsn.ALGO_ANLS, rel_obj_tol=1e-4, f_ref=f_star, anls_extrapolate=ex)
+        f_end = onmf.objective(p.astype(np.float64), V.cpu().numpy().astype(np.float64),
+                               D.cpu().numpy().astype(np.float64))
+        show("  stop", extrapolate=ex, rounds=st["polish_done"], rel=st["rel_obj"])
+        assert st["rel_obj"] <= 1e-4 and f_end <= st["objective"] * (1 + 1e-6)
+        rounds[ex] = st["polish_done"]
+    assert rounds[True] < rounds[False]

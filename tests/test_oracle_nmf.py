@@ -257,3 +257,54 @@ def test_stationary_reference_is_a_kkt_point():
     assert max(nmf.kkt_residual(P, Va, Da)) > 1e-6
     _, V1, D1 = nmf.stationary_reference(P, V0, D0, max_rounds=1, refine=False)
     assert max(nmf.kkt_residual(P, V1, D1)) > 1e-4
+
+
+def test_extrapolated_anls_without_weight_is_plain_anls():
+    # beta0 = 0 keeps the weight at 0: every round is a plain ANLS round.
+    P = _noisy_lowrank(11, 60, 30, 3)
+    V0, D0 = synth.random_factors(60, 30, 3, 12)
+    V, D = V0.copy(), D0.copy()
+    hist = []
+    for _ in range(6):
+        V, D, fh, _ = nmf.anls_round(P, V, D)
+        hist.append(fh)
+    Ve, De, he = nmf.anls_extrapolated_run(P, V0, D0, 6, beta0=0.0)
+    assert np.array_equal(Ve, V) and np.array_equal(De, D)
+    assert np.array_equal(he, np.array(hist))
+
+
+def test_extrapolated_anls_accelerates_to_the_stationary_point():
+    # The small noisy scan where plain ANLS is still 1.6e-3 above the
+    # KKT-pinned stationary reference after 400 rounds: the extrapolated
+    # rounds get within 1e-4 of it in about 110 rounds, while plain ANLS after
+    # 150 rounds is still more than ten times as far, and they end near a
+    # KKT point.
+    sc = synth.make_scan(n_views=12, n_rows=1, n_cols=24, n_bins=48, n_mat=3, flux=1e4, seed=5)
+    from oracle.normalize import normalize
+    P, _, _ = normalize(sc.y, sc.yo)
+    V0, D0 = synth.random_factors(P.shape[0], P.shape[1], 3, 7)
+    fs, _, _ = nmf.stationary_reference(P, V0, D0, max_rounds=50)
+    Ve, De, he = nmf.anls_extrapolated_run(P, V0, D0, 220)
+    hit = np.nonzero((he - fs) / fs <= 1e-4)[0]
+    assert hit.size and hit[0] < 150, hit[:1]
+    V, D = V0.copy(), D0.copy()
+    hp = []
+    for _ in range(150):
+        V, D, fh, _ = nmf.anls_round(P, V, D)
+        hp.append(fh)
+    assert (min(hp) - fs) / fs > 1e-3
+    assert max(nmf.kkt_residual(P, Ve, De)) <= 1e-3
+
+
+def test_extrapolated_anls_stop_keeps_the_exact_d():
+    # With a stop test the run ends at the first objective within the
+    # tolerance and returns that round's exact D, no worse than the recorded
+    # objective.
+    P = _noisy_lowrank(13, 70, 35, 3)
+    V0, D0 = synth.random_factors(70, 35, 3, 14)
+    _, _, h = nmf.anls_extrapolated_run(P, V0, D0, 60)
+    f_ref = h.min() * (1 - 1e-9)
+    V, D, hs = nmf.anls_extrapolated_run(P, V0, D0, 60, f_ref=f_ref, tol=1e-3)
+    assert (hs[-1] - f_ref) / f_ref <= 1e-3 and np.all((hs[:-1] - f_ref) / f_ref > 1e-3)
+    assert nmf.objective(P, V, D) <= hs[-1] * (1 + 1e-12)
+    assert np.array_equal(D, nmf.nnls_rows(V.T @ V, P.T @ V))
