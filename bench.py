@@ -513,6 +513,7 @@ def main():
         "nmf": {"vpb_per_s": vpb / (nmf_ms * 1e-3), "ms": nmf_ms, "anls_rounds": recs[-1]["polish_done"],
                 "anls_rounds_bf16": recs[-1]["polish_bf16_done"], "rel_obj": recs[-1]["rel_obj"],
                 "reached": reached, "fell_back": any(r["fell_back"] for r in recs), "f_star": f_star,
+                "history_last_step": recs[-1]["history"],
                 "references": refs,
                 "f_star_note": "lowest objective of the float32 extrapolated-ANLS reference runs; their "
                                "last-100-round relative decrease bounds how far from stationary they ended"},

@@ -280,50 +280,46 @@ __global__ __launch_bounds__(kVoxThreads) void backproject_kernel(const float *_
 // a dependent gather per step.  Here a block copies the rows it shares (the
 // slice image for A, the slice's sinogram rows for A^T) into LDS in bands
 // and takes the taps from there, while the next band's global loads are in
-// flight.  Staged rows are channel-planar (channel q of pixel t of staged
-// row i at q * plane + i * ldp + pad + t), so the two taps of a lane are
-// neighbouring words and neighbouring lanes read neighbouring words; the
-// plane stride is a compile-time constant, so each tap is one LDS read with
-// an immediate offset.  Rows carry zero pixels (bins) on both sides and a
-// tap index is clamped into them: no bounds tests or weight masks in the
-// inner loops.  A clamped tap reads 0 where the gather kernels apply weight
-// 0, so with one thread per ray (split 1) both paths give the same values
-// bit for bit.
+// flight.  Staged rows keep the global layout (the K channels of a pixel
+// contiguous): pixel t of staged row i starts at i * rp + (pad + t) K, rp =
+// (n + 2 pad) K, so a band is copied with 16-byte loads and stores and the
+// 2 K values of a tap pair (pixels t0, t0 + 1) lie within 2 K words of one
+// address: one address per step, the channel offsets are immediates.  pad
+// zero pixels (bins) on both sides (2 for even K, 4 for odd K, which keeps
+// each row's data 16-byte aligned) and a tap index clamped into them: no
+// bounds tests or weight masks in the inner loops.  A clamped tap reads 0
+// where the gather kernels apply weight 0, so with one thread per ray
+// (split 1) both paths give the same values bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int kLdsMaxThreads = 1024;
-constexpr int kStageFloats = 15360;  // 60 KB of channel planes
-constexpr int kStagePad = 2;         // zero pixels (bins) on each side of a staged row
-constexpr int kCopyFloats = 8;       // floats each thread copies per band
-
-// Plane stride of the staged rows (floats).
-template <int K>
-__host__ __device__ constexpr int lds_plane() { return (kStageFloats / K) / 4 * 4; }
+constexpr int kStageFloats = 15360;  // 60 KB of staged rows
+constexpr int kCopyFloats = 16;      // floats each thread copies per band
 
 template <int K>
-__device__ __forceinline__ int planar_offset(int row, int col, int ldp) {
-  const int pix = col / K, q = col - pix * K;
-  return q * lds_plane<K>() + row * ldp + kStagePad + pix;
-}
+__host__ __device__ constexpr int stage_pad() { return (2 * K) % 4 == 0 ? 2 : 4; }
+template <int K>
+__host__ __device__ constexpr int stage_rp(int n) { return (n + 2 * stage_pad<K>()) * K; }
 
 // One thread's part of a band copy: up to kCopyFloats floats of `rows`
-// rows of `width` interleaved floats each (row i at src + i * src_ld), at
-// band-local flat positions t + u * nt (scalar) or 4 (t + u * nt) + j
-// (float4, VEC), written channel-planar.  load() issues the global loads
-// into registers; store() writes them to LDS, so a band's loads can be in
-// flight while the previous band is used.
+// rows of `width` floats each (row i at src + i * src_ld), at band-local
+// flat positions t + u * nt (scalar) or 4 (t + u * nt) + j (float4, VEC).
+// load() issues the global loads into registers; store() writes them to
+// the staged rows (pitch rp, data from pad K on), so a band's loads can be
+// in flight while the previous band is used.
 template <int K, bool VEC>
 struct BandCopy {
-  int width, ldp;
-  int row4[2], col4[2];
+  static constexpr int U4 = kCopyFloats / 4;
+  int width, rp;
+  int row4[U4], col4[U4];
   float buf[kCopyFloats];
 
-  __device__ __forceinline__ void init(int w, int ld) {
+  __device__ __forceinline__ void init(int w, int rpitch) {
     width = w;
-    ldp = ld;
+    rp = rpitch;
     if constexpr (VEC) {
       const int w4 = w / 4;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < U4; ++u) {
         const int f = int(threadIdx.x) + u * int(blockDim.x);
         row4[u] = f / w4;
         col4[u] = 4 * (f - row4[u] * w4);
@@ -333,7 +329,7 @@ struct BandCopy {
   __device__ __forceinline__ void load(const float *__restrict__ src, size_t src_ld, int rows) {
     if constexpr (VEC) {
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < U4; ++u) {
         if (row4[u] < rows) {
           const float4 v = *reinterpret_cast<const float4 *>(src + size_t(row4[u]) * src_ld + col4[u]);
           buf[4 * u] = v.x;
@@ -351,45 +347,43 @@ struct BandCopy {
       }
     }
   }
-  __device__ __forceinline__ void store(float *__restrict__ planes, int rows) const {
+  __device__ __forceinline__ void store(float *__restrict__ rows_lds, int rows) const {
+    constexpr int P0 = stage_pad<K>() * K;
     if constexpr (VEC) {
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        if (row4[u] < rows) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) planes[planar_offset<K>(row4[u], col4[u] + j, ldp)] = buf[4 * u + j];
-        }
+      for (int u = 0; u < U4; ++u) {
+        if (row4[u] < rows)
+          *reinterpret_cast<float4 *>(rows_lds + row4[u] * rp + P0 + col4[u]) =
+              make_float4(buf[4 * u], buf[4 * u + 1], buf[4 * u + 2], buf[4 * u + 3]);
       }
     } else {
 #pragma unroll
       for (int u = 0; u < kCopyFloats; ++u) {
         const int e = int(threadIdx.x) + u * int(blockDim.x);
         const int r = e / width, c = e - r * width;
-        if (r < rows) planes[planar_offset<K>(r, c, ldp)] = buf[u];
+        if (r < rows) rows_lds[r * rp + P0 + c] = buf[u];
       }
     }
   }
 };
 
-// Both taps of every channel at staged pixel p: a[q] = p[q plane],
-// b[q] = p[q plane + 1].
+// Both taps of every channel at staged pixel p: a[q] = p[q], b[q] = p[K + q].
 template <int K>
-__device__ __forceinline__ void planar_taps(const float *p, float (&a)[K], float (&b)[K]) {
+__device__ __forceinline__ void pixel_taps(const float *p, float (&a)[K], float (&b)[K]) {
 #pragma unroll
   for (int q = 0; q < K; ++q) {
-    a[q] = p[q * lds_plane<K>()];
-    b[q] = p[q * lds_plane<K>() + 1];
+    a[q] = p[q];
+    b[q] = p[K + q];
   }
 }
 
-// Zeroes the pad pixels of `rows` staged rows in every channel plane.
+// Zeroes the pad pixels of `rows` staged rows (n data pixels each).
 template <int K>
-__device__ __forceinline__ void zero_pads(float *__restrict__ planes, int ldp, int n, int rows) {
-  constexpr int PP = 2 * kStagePad;
-  for (int e = threadIdx.x; e < K * rows * PP; e += blockDim.x) {
-    const int q = e / (rows * PP), rest = e - q * (rows * PP);
-    const int row = rest / PP, k = rest - row * PP;
-    planes[q * lds_plane<K>() + row * ldp + (k < kStagePad ? k : n + k)] = 0.0f;
+__device__ __forceinline__ void zero_pads(float *__restrict__ rows_lds, int rp, int n, int rows) {
+  constexpr int PW = stage_pad<K>() * K;  // floats of one side's pad
+  for (int e = threadIdx.x; e < rows * 2 * PW; e += blockDim.x) {
+    const int row = e / (2 * PW), k = e - row * (2 * PW);
+    rows_lds[row * rp + (k < PW ? k : n * K + k)] = 0.0f;
   }
 }
 
@@ -428,8 +422,8 @@ __global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
     const float *__restrict__ x, const float *__restrict__ xT, float *__restrict__ s,
     const ViewGeom *__restrict__ geom, const double *__restrict__ groups, int n_groups, int vb, int split,
     int n_slices, int n, int band_rows, float alpha, float beta, double *__restrict__ sumsq) {
-  extern __shared__ __align__(16) float stage[];  // K planes of band_rows staged rows; then the copies' sums
-  constexpr int LP = lds_plane<K>();
+  extern __shared__ __align__(16) float stage[];  // band_rows staged rows; then the copies' sums
+  constexpr int PAD = stage_pad<K>();
   const int per_group = kViewGroup / vb;
   const BlockSlot bs = block_slot(blockIdx.x, n_slices, n_groups * per_group);
   if (bs.slice >= n_slices) return;
@@ -444,7 +438,7 @@ __global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
     return;
   }
   const bool steep = fabs(geom[v_first].sn) > fabs(geom[v_first].cs);
-  const int ldp = n + 2 * kStagePad;
+  const int rp = stage_rp<K>(n);
   const int t1 = int(blockDim.x) / split;
   const int sp = int(threadIdx.x) / t1, slot = int(threadIdx.x) - sp * t1;
   const int vi = slot / n, c = slot - vi * n;
@@ -454,17 +448,17 @@ __global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
     view = int(groups[gi * kViewGroup + sub * vb + vi]);
     if (view >= 0) ry = ray_setup(geom[view], c, n);
   }
-  zero_pads<K>(stage, ldp, n, band_rows);
+  zero_pads<K>(stage, rp, n, band_rows);
   const float *img = (steep ? xT : x) + size_t(r) * n * n * K;
   BandCopy<K, VEC> cp;
-  cp.init(n * K, ldp);
+  cp.init(n * K, rp);
   int rows = min(band_rows, n);
   cp.load(img, size_t(n) * K, rows);
   float acc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0.0f;
   const int64_t dUs = ry.dU * split;
-  const int bstep = ldp * split;
+  const int bstep = rp * split;
   for (int m0 = 0; m0 < n; m0 += band_rows) {
     __syncthreads();  // the previous band is no longer read
     cp.store(stage, rows);
@@ -474,11 +468,11 @@ __global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
     const int mb = max(ry.m_lo, m0), me = min(ry.m_hi, m0 + rows - 1);
     int m = m0 + sp + ((max(mb - m0 - sp, 0) + split - 1) / split) * split;  // first own row >= mb
     int64_t U = ry.U0 + int64_t(m) * ry.dU;
-    int base = (m - m0) * ldp + kStagePad;
+    int base = (m - m0) * rp + PAD * K;
     for (; m <= me; m += split, U += dUs, base += bstep) {
-      const int t0 = min(max(int(U >> 32), -kStagePad), n + kStagePad - 2);
+      const int t0 = min(max(int(U >> 32), -PAD), n + PAD - 2);
       float a0[K], a1[K];
-      planar_taps<K>(stage + (base + t0), a0, a1);
+      pixel_taps<K>(stage + (base + t0 * K), a0, a1);
       const float w1 = float(uint32_t(U)) * ry.s1;
       const float w0 = ry.inv_w - w1;
 #pragma unroll
@@ -542,7 +536,8 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
   const int r = bs.slice;
   StagedView *gv = reinterpret_cast<StagedView *>(stage);
   float *planes = stage + geom_stage_bytes(view_chunk) / 4;
-  const int ldp = n + 2 * kStagePad;
+  constexpr int PAD = stage_pad<K>();
+  const int rp = stage_rp<K>(n);
   const int64_t H = int64_t(n - 1) << 31;
   const int db = 2 * (nt / n);  // b_j step between a thread's voxels (VPT > 1)
   int vox[VPT];
@@ -554,7 +549,7 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
     const int w = w0i + e * nt;
     vox[e] = w < n * n ? w : -1;
   }
-  zero_pads<K>(planes, ldp, n, view_chunk);
+  zero_pads<K>(planes, rp, n, view_chunk);
   float acc[VPT][K];
 #pragma unroll
   for (int e = 0; e < VPT; ++e)
@@ -563,7 +558,7 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
   const size_t view_stride = size_t(n_slices) * n * K;
   const float *sr = s + size_t(r) * n * K;
   BandCopy<K, VEC> cp;
-  cp.init(n * K, ldp);
+  cp.init(n * K, rp);
   int nv = min(view_chunk, n_views);
   cp.load(sr, view_stride, nv);
   ViewGeom gn{};
@@ -589,15 +584,15 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
       cp.load(sr + size_t(v0 + view_chunk) * view_stride, view_stride, nv_next);
       if (int(threadIdx.x) < nv_next) gn = geom[v0 + view_chunk + threadIdx.x];
     }
-    int base = kStagePad;
-    for (int vl = 0; vl < nv; ++vl, base += ldp) {
+    int base = PAD * K;
+    for (int vl = 0; vl < nv; ++vl, base += rp) {
       const StagedView sv = gv[vl];
       int64_t U = int64_t(a) * sv.C + (int64_t(b0) * sv.S + H);
 #pragma unroll
       for (int e = 0; e < VPT; ++e, U += sv.D) {
-        const int c0 = min(max(int(U >> 32), -kStagePad), n + kStagePad - 2);
+        const int c0 = min(max(int(U >> 32), -PAD), n + PAD - 2);
         float a0[K], a1[K];
-        planar_taps<K>(planes + (base + c0), a0, a1);
+        pixel_taps<K>(planes + (base + c0 * K), a0, a1);
         float w0, w1;
         vox_weights(uint32_t(U), sv.iw, sv.iw2, sv.c1, w0, w1);
 #pragma unroll
@@ -1176,24 +1171,25 @@ struct ProjLaunch {
 };
 
 int round64(int64_t v) { return int((v + 63) / 64 * 64); }
-int64_t staged_ldp(const hsn_geom *g) { return g->n_cols + 2 * kStagePad; }
-int64_t plane_of(int k) {
-  switch (k) {
-    case 1: return lds_plane<1>();
-    case 2: return lds_plane<2>();
-    case 3: return lds_plane<3>();
-    case 4: return lds_plane<4>();
-    case 5: return lds_plane<5>();
-    case 6: return lds_plane<6>();
-    case 7: return lds_plane<7>();
-    default: return lds_plane<8>();
+// Row pitch (floats) of the staged rows for the geometry's K.
+int64_t staged_rp(const hsn_geom *g) {
+  const int n = int(g->n_cols);
+  switch (g->k) {
+    case 1: return stage_rp<1>(n);
+    case 2: return stage_rp<2>(n);
+    case 3: return stage_rp<3>(n);
+    case 4: return stage_rp<4>(n);
+    case 5: return stage_rp<5>(n);
+    case 6: return stage_rp<6>(n);
+    case 7: return stage_rp<7>(n);
+    default: return stage_rp<8>(n);
   }
 }
 
 ProjLaunch plan_project(const hsn_ctx *ctx, const hsn_geom *g, int n_groups) {
   ProjLaunch L;
-  const int64_t n = g->n_cols, K = g->k, ldp = staged_ldp(g), LP = plane_of(g->k);
-  if (ctx->proj_views < 0 || ldp > LP || n > kLdsMaxThreads) {
+  const int64_t n = g->n_cols, K = g->k, rp = staged_rp(g);
+  if (ctx->proj_views < 0 || rp > kStageFloats || n > kLdsMaxThreads) {
     L.threads = kRayThreads;
     L.grid = project_grid(g);
     L.partials = size_t(g->n_slices) * g->n_views * ((n + kRayThreads - 1) / kRayThreads);
@@ -1222,7 +1218,8 @@ ProjLaunch plan_project(const hsn_ctx *ctx, const hsn_geom *g, int n_groups) {
   }
   while (split > 1 && split * t1 > kLdsMaxThreads) split /= 2;
   const int nt = split * t1;
-  const int64_t band = std::max<int64_t>(1, std::min<int64_t>({n, LP / ldp, int64_t(kCopyFloats) * nt / (n * K)}));
+  const int64_t band =
+      std::max<int64_t>(1, std::min<int64_t>({n, kStageFloats / rp, int64_t(kCopyFloats) * nt / (n * K)}));
   L.lds = true;
   L.vb = vb;
   L.split = split;
@@ -1230,14 +1227,14 @@ ProjLaunch plan_project(const hsn_ctx *ctx, const hsn_geom *g, int n_groups) {
   L.rows = int(band);
   L.grid = slot_grid(g->n_slices, int64_t(n_groups) * (kViewGroup / vb));
   L.partials = size_t(blocks(vb));
-  L.lds_bytes = sizeof(float) * size_t(std::max<int64_t>((K - 1) * LP + band * ldp, split > 1 ? int64_t(nt) * K : 0));
+  L.lds_bytes = sizeof(float) * size_t(std::max<int64_t>(band * rp, split > 1 ? int64_t(nt) * K : 0));
   return L;
 }
 
 ProjLaunch plan_backproject(const hsn_ctx *ctx, const hsn_geom *g) {
   ProjLaunch L;
-  const int64_t n = g->n_cols, K = g->k, ldp = staged_ldp(g), LP = plane_of(g->k);
-  if (ctx->proj_voxels < 0 || ldp > LP || n * K > int64_t(kCopyFloats) * kLdsMaxThreads) {
+  const int64_t n = g->n_cols, K = g->k, rp = staged_rp(g);
+  if (ctx->proj_voxels < 0 || rp > kStageFloats || n * K > int64_t(kCopyFloats) * kLdsMaxThreads) {
     L.threads = kVoxThreads;
     L.grid = backproject_grid(g);
     L.partials = size_t(g->n_slices) * n * ((n + kVoxThreads - 1) / kVoxThreads);
@@ -1263,7 +1260,7 @@ ProjLaunch plan_backproject(const hsn_ctx *ctx, const hsn_geom *g) {
   // must span whole image rows.
   if (nt % n != 0) vpt = 1;
   const int64_t vc = std::max<int64_t>(
-      1, std::min<int64_t>({int64_t(g->n_views), LP / ldp, int64_t(kMaxViewChunk), int64_t(nt),
+      1, std::min<int64_t>({int64_t(g->n_views), kStageFloats / rp, int64_t(kMaxViewChunk), int64_t(nt),
                             int64_t(kCopyFloats) * nt / (n * K)}));
   L.lds = true;
   L.vpt = vpt;
@@ -1271,7 +1268,7 @@ ProjLaunch plan_backproject(const hsn_ctx *ctx, const hsn_geom *g) {
   L.rows = int(vc);
   L.grid = slot_grid(g->n_slices, per_slice(vpt));
   L.partials = size_t(g->n_slices) * per_slice(vpt);
-  L.lds_bytes = size_t(geom_stage_bytes(int(vc))) + sizeof(float) * size_t((K - 1) * LP + vc * ldp);
+  L.lds_bytes = size_t(geom_stage_bytes(int(vc))) + sizeof(float) * size_t(vc * rp);
   return L;
 }
 
