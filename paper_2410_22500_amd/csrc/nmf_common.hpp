@@ -53,6 +53,8 @@ struct NmfCtrl {
   // weight, its cap, the previous round's objective and the weight this
   // round's D update applies (0: no extrapolation)
   double beta, beta_bar, e_prev, beta_use;
+  int e_prev_bf16;  // e_prev came from a step on p_bf16 (1), on p (0), none yet (-1)
+  int pad2;
   double gvo[65];   // G_V = V^T V (K*K) and the objective of the last pass, reduced
 };
 

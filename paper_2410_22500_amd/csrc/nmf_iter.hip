@@ -168,6 +168,7 @@ __device__ __forceinline__ void nmf_init_body(const float *__restrict__ D, int n
     ctrl->beta_bar = 1.0;
     ctrl->e_prev = INFINITY;
     ctrl->beta_use = 0.0;
+    ctrl->e_prev_bf16 = -1;
   }
   block_gram_d<K>(D, n_k, false, red, g_s);
   if (t < K * K) GD[t] = g_s[t];
@@ -563,7 +564,11 @@ __global__ void anls_beta_kernel(NmfCtrl *__restrict__ ctrl, int iter, int obj_i
   const bool stop = !isfinite(ob) || (f_ref > 0.0 && (ob - f_ref) / f_ref <= tol);
   double use = 0.0;
   if (!stop) {
-    if (ob <= ctrl->e_prev) {
+    if (ctrl->e_prev_bf16 >= 0 && ctrl->e_prev_bf16 != (bf16 ? 1 : 0)) {
+      // the previous objective was measured on the other copy of p: not
+      // comparable, so the weight stays and is used
+      use = ctrl->beta;
+    } else if (ob <= ctrl->e_prev) {
       ctrl->beta = fmin(ctrl->beta_bar, kExtrapGrow * ctrl->beta);
       ctrl->beta_bar = fmin(1.0, kExtrapCapGrow * ctrl->beta_bar);
       use = ctrl->beta;
@@ -573,6 +578,7 @@ __global__ void anls_beta_kernel(NmfCtrl *__restrict__ ctrl, int iter, int obj_i
     }
   }
   ctrl->e_prev = ob;
+  ctrl->e_prev_bf16 = bf16 ? 1 : 0;
   ctrl->beta_use = use;
 }
 
