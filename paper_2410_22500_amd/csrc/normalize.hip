@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
     const uint16_t *__restrict__ y, const uint16_t *__restrict__ yo, int64_t n_v, int64_t vc, int64_t n_pix, int nk,
     const float *__restrict__ b, float floor_, int clip, float *__restrict__ p, int64_t ldp,
     uint16_t *__restrict__ pb, int64_t ldb, void *__restrict__ pooled, double *__restrict__ partial) {
-  __shared__ float rowbuf[POOL ? kPoolMaxBins : 1];
+  __shared__ __attribute__((aligned(16))) float rowbuf[POOL ? kPoolMaxBins : 4];
   // Thread t takes chunk t % cpw of row t / cpw of the group, cpw = the
   // chunks of the widest output row (the padded bfloat16 row when there is
   // one), as normalize_kernel does; chunks past the bins only zero the pad.
@@ -268,7 +268,12 @@ __global__ __launch_bounds__(kThreads) void normalize_u16_kernel(
       }
       if constexpr (POOL != 0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) rowbuf[rr * nk + k0 + e] = hsn::bf16_bits_to_f32(hsn::f32_to_bf16_bits(out[e]));
+        for (int e = 0; e < 8; ++e) out[e] = hsn::bf16_bits_to_f32(hsn::f32_to_bf16_bits(out[e]));
+        // two 16-byte stores per chunk (eight 4-byte stores 32 bytes apart
+        // across the lanes fall on the same banks)
+        float4 *rb = reinterpret_cast<float4 *>(rowbuf + rr * nk + k0);
+        rb[0] = make_float4(out[0], out[1], out[2], out[3]);
+        rb[1] = make_float4(out[4], out[5], out[6], out[7]);
       }
     }
     if constexpr (POOL != 0) {
