@@ -441,7 +441,23 @@ __global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
   const int rp = stage_rp<K>(n);
   const int t1 = int(blockDim.x) / split;
   const int sp = int(threadIdx.x) / t1, slot = int(threadIdx.x) - sp * t1;
-  const int vi = slot / n, c = slot - vi * n;
+  // Ray slot -> (view vi, column c).  Neighbouring rays of one view are
+  // 1/max(|cos|, |sin|) in [1, 1.41] pixels apart, so 32 of them (a
+  // half-wave, one LDS pass) span up to 45 pixels and pixels 32 apart meet
+  // in one of the 32 banks.  With an even vb and n % 16 == 0 a half-wave
+  // instead takes 16 rays of each of two views of the group: their taps lie
+  // within about 30 pixels (the views are close in angle), and for odd K
+  // the pitch of K floats per pixel puts distinct pixels of such a window
+  // in distinct banks.  Each ray's arithmetic is the same either way.
+  int vi, c;
+  if ((vb & 1) == 0 && (n & 15) == 0) {
+    const int pi = slot / (2 * n), rr = slot - pi * (2 * n);
+    vi = 2 * pi + ((rr >> 4) & 1);
+    c = ((rr >> 5) << 4) + (rr & 15);
+  } else {
+    vi = slot / n;
+    c = slot - vi * n;
+  }
   int view = -1;
   Ray ry{0, 0, 0, -1, 0.0f, 0.0f};
   if (vi < vb) {
@@ -467,12 +483,15 @@ __global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
     if (rows_next > 0) cp.load(img + size_t(m0 + band_rows) * n * K, size_t(n) * K, rows_next);
     const int mb = max(ry.m_lo, m0), me = min(ry.m_hi, m0 + rows - 1);
     int m = m0 + sp + ((max(mb - m0 - sp, 0) + split - 1) / split) * split;  // first own row >= mb
-    int64_t U = ry.U0 + int64_t(m) * ry.dU;
-    int base = (m - m0) * rp + PAD * K;
-    for (; m <= me; m += split, U += dUs, base += bstep) {
-      const int t0 = min(max(int(U >> 32), -PAD), n + PAD - 2);
+    // U carries PAD in its integer part: the high word is the staged pixel
+    // index of tap t0 (t0 + PAD), clamped into the pads; the LDS offset is
+    // a 24-bit multiply-add.
+    int64_t U = ry.U0 + int64_t(m) * ry.dU + (int64_t(PAD) << 32);
+    unsigned base = unsigned((m - m0) * rp);
+    for (; m <= me; m += split, U += dUs, base += unsigned(bstep)) {
+      const int tp = min(max(int(U >> 32), 0), n + 2 * PAD - 2);
       float a0[K], a1[K];
-      pixel_taps<K>(stage + (base + t0 * K), a0, a1);
+      pixel_taps<K>(stage + (base + __umul24(unsigned(tp), unsigned(K))), a0, a1);
       const float w1 = float(uint32_t(U)) * ry.s1;
       const float w0 = ry.inv_w - w1;
 #pragma unroll
@@ -538,7 +557,7 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
   float *planes = stage + geom_stage_bytes(view_chunk) / 4;
   constexpr int PAD = stage_pad<K>();
   const int rp = stage_rp<K>(n);
-  const int64_t H = int64_t(n - 1) << 31;
+  const int64_t H = (int64_t(n - 1) << 31) + (int64_t(PAD) << 32);
   const int db = 2 * (nt / n);  // b_j step between a thread's voxels (VPT > 1)
   int vox[VPT];
   const int w0i = bs.rest * per_block + int(threadIdx.x);
@@ -584,15 +603,17 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
       cp.load(sr + size_t(v0 + view_chunk) * view_stride, view_stride, nv_next);
       if (int(threadIdx.x) < nv_next) gn = geom[v0 + view_chunk + threadIdx.x];
     }
-    int base = PAD * K;
-    for (int vl = 0; vl < nv; ++vl, base += rp) {
+    // H carries PAD in its integer part: the high word of U is the staged
+    // bin index of tap c0 (c0 + PAD), clamped into the pads.
+    unsigned base = 0;
+    for (int vl = 0; vl < nv; ++vl, base += unsigned(rp)) {
       const StagedView sv = gv[vl];
       int64_t U = int64_t(a) * sv.C + (int64_t(b0) * sv.S + H);
 #pragma unroll
       for (int e = 0; e < VPT; ++e, U += sv.D) {
-        const int c0 = min(max(int(U >> 32), -PAD), n + PAD - 2);
+        const int cp0 = min(max(int(U >> 32), 0), n + 2 * PAD - 2);
         float a0[K], a1[K];
-        pixel_taps<K>(planes + (base + c0 * K), a0, a1);
+        pixel_taps<K>(planes + (base + __umul24(unsigned(cp0), unsigned(K))), a0, a1);
         float w0, w1;
         vox_weights(uint32_t(U), sv.iw, sv.iw2, sv.c1, w0, w1);
 #pragma unroll
