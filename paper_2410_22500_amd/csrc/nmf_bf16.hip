@@ -334,10 +334,14 @@ __device__ __forceinline__ void pass_bf16_body(const uint16_t *__restrict__ Pb, 
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
           const int bin0 = 32 * (s0 + i) + 16 * hh;
-          s16x4 a2;
-          const char *col = tileL + 2 * (bin0 + (lane & 15));
-#pragma unroll
-          for (int q = 0; q < 4; ++q) a2[q] = *reinterpret_cast<const short *>(col + (4 * (lane >> 4) + q) * pitch);
+          // P^T operand, lane (g, n) = (lane >> 4, lane & 15): rows 4 g .. 4 g + 3
+          // of bin bin0 + n, by one transposed 8-byte read: lane
+          // (g, j, m) = (lane >> 4, (lane >> 2) & 3, lane & 3) addresses bins
+          // bin0 + 4 m .. + 3 of row 4 g + j, and within each 16 lanes the read
+          // hands lane n element j of lane 4 j + n / 4, item n % 4.
+          const s16x4 a2 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+              (__attribute__((address_space(3))) s16x4 *)(tileL + (4 * (lane >> 4) + ((lane >> 2) & 3)) * pitch +
+                                                          2 * (bin0 + 4 * (lane & 3))));
           acc2[2 * i + hh] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, b2, acc2[2 * i + hh], 0, 0, 0);
           if (RECON) {
             const uint4 b3 = db3g[(bin0 / 16) * 64 + lane];
