@@ -106,7 +106,7 @@ __device__ __forceinline__ void pass_bf16_body(const uint16_t *__restrict__ Pb, 
   const Bf16Lds L = bf16_lds_layout(ldb, K, MODE == kModeANLS);
   char *tileL = smem + L.tile;
   uint4 *db1L = reinterpret_cast<uint4 *>(smem + L.db1);
-  float *red = reinterpret_cast<float *>(smem + L.red);        // [8][16][16]
+  float *red = reinterpret_cast<float *>(smem + L.red);        // [8][16][16], [wave][col][row]
   uint16_t *vsp = reinterpret_cast<uint16_t *>(smem + L.vsp);  // [16][16]  [V_hi | V_lo]
   float *vnw = reinterpret_cast<float *>(smem + L.vnw);        // [16][8]
   float *vold = reinterpret_cast<float *>(smem + L.vold);      // [16][K] V of the tile before the update
@@ -215,8 +215,8 @@ __device__ __forceinline__ void pass_bf16_body(const uint16_t *__restrict__ Pb, 
         }
       }
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) red[(w * 16 + 4 * (lane >> 4) + i) * 16 + (lane & 15)] = acc1[i];
+    // column-major per wave (red[w][col][row]): the lane's four rows are one 16-byte store
+    *reinterpret_cast<f32x4 *>(red + (w * 16 + (lane & 15)) * 16 + 4 * (lane >> 4)) = acc1;
     __syncthreads();
     }
 
@@ -236,7 +236,7 @@ __device__ __forceinline__ void pass_bf16_body(const uint16_t *__restrict__ Pb, 
         const int r = t / K, j = t - (t / K) * K;
         float s = 0.0f;
 #pragma unroll
-        for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + r) * 16 + j] + red[(ww * 16 + r) * 16 + 8 + j];
+        for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + j) * 16 + r] + red[(ww * 16 + 8 + j) * 16 + r];
         hsum[r * 8 + j] = s;
       }
       __syncthreads();
@@ -267,7 +267,7 @@ __device__ __forceinline__ void pass_bf16_body(const uint16_t *__restrict__ Pb, 
         for (int j = 0; j < K; ++j) {
           float s = 0.0f;
 #pragma unroll
-          for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + r) * 16 + j] + red[(ww * 16 + r) * 16 + 8 + j];
+          for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + j) * 16 + r] + red[(ww * 16 + 8 + j) * 16 + r];
           h[j] = s;
           x[j] = (row < n_p) ? double(vold[r * K + j]) : 0.0;
         }
@@ -286,7 +286,7 @@ __device__ __forceinline__ void pass_bf16_body(const uint16_t *__restrict__ Pb, 
       const int64_t row = row0 + r;
       float s = 0.0f;
 #pragma unroll
-      for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + r) * 16 + j] + red[(ww * 16 + r) * 16 + 8 + j];
+      for (int ww = 0; ww < kBWaves; ++ww) s += red[(ww * 16 + j) * 16 + r] + red[(ww * 16 + 8 + j) * 16 + r];
       float vn = 0.0f;
       if (row < n_p) {
         float vr[K];
@@ -312,9 +312,10 @@ __device__ __forceinline__ void pass_bf16_body(const uint16_t *__restrict__ Pb, 
       for (int r = 0; r < kBRows; ++r) s = fmaf(vnw[r * 8 + i], vnw[r * 8 + j], s);
       gv += double(s);
     }
-    s16x4 b2;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) b2[q] = short(vsp[(4 * (lane >> 4) + q) * 16 + (lane & 15)]);
+    // [V_hi | V_lo] operand, lane (g, n): rows 4 g .. 4 g + 3 of column n, by
+    // one transposed 8-byte read (lane addressing as for P^T below)
+    const s16x4 b2 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+        (__attribute__((address_space(3))) s16x4 *)(vsp + (4 * (lane >> 4) + ((lane >> 2) & 3)) * 16 + 4 * (lane & 3)));
     bf16x8 a3;
     // the reconstruction objective (MU, HALS); an ANLS pass has its objective
     // from the row solves

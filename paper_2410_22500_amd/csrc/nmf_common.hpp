@@ -289,11 +289,15 @@ __device__ __forceinline__ double nnls_enum_group(const double *__restrict__ gin
   double best_q = 0.0;
   int best_m = 0;
   for (int m = l; m < (1 << K); m += 32) {
-    if (m == 0 || isnan(ginv[m])) continue;
-    bool feasible = true;
+    // no branch before the loads: the empty support (the default) and a
+    // singular G[S,S] (NaN first entry) are simply never feasible
+    bool feasible = m != 0 && !isnan(ginv[m]);
     double q = 0.0;
-    // one row of z at a time (rolled): few registers live beside the pass's own
-#pragma unroll 1
+    // all rows of z at once for K <= 6 (the tri(K) inverse entries are
+    // loaded together, one latency); one row at a time (rolled) beyond,
+    // where they would take too many registers beside the pass's own
+    constexpr int kRowUnroll = K <= 6 ? K : 1;
+#pragma unroll kRowUnroll
     for (int i = 0; i < K; ++i) {
       double s = 0.0, hi = 0.0;
 #pragma unroll
