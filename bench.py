@@ -50,8 +50,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="full", choices=["full", "mid", "tiny", "batched"],
-                    help="full / mid / tiny: the whole path on one scan; batched: 32 uneven decompositions")
+    ap.add_argument("--workload", default="full", choices=["full", "mid", "tiny", "batched", "ksweep"],
+                    help="full / mid / tiny: the whole path on one scan; batched: 32 uneven decompositions; "
+                         "ksweep: the subspace size study on the mid scan (K = N_m .. 2 N_m)")
     ap.add_argument("--mlp-scans", type=int, default=None, help="training scans (default 348; 40 with --quick)")
     ap.add_argument("--quick", action="store_true",
                     help="short set-up and no comparison paths or CPU baseline (for profiler runs)")
@@ -217,6 +218,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "ksweep":
+        run_ksweep(args)
         return
     if args.counters:
         counter_run(args)
@@ -651,6 +655,82 @@ def fbp_comparison(sc, y, yo, mlp, V, D, learned_kw, f_star, x_cgls):
             "paper_table_ii": {"dhr_min": 817.44, "fhr_fbp_min": 23.62, "fhr_mbir_min": 62.96, "snr_dhr_db": -2.33,
                                "snr_fhr_fbp_db": 26.34, "snr_fhr_mbir_db": 42.13,
                                "note": "simulated data, whole pipelines on the paper's hardware: context only"}}
+
+
+KSWEEP_ROUNDS = 60
+
+
+def run_ksweep(args):
+    """Subspace size study (Section V-D: N_s = beta N_m; the paper finds beta = 1 enough on simulated
+    data, 2 on measured data): on the mid scan (N_m = 4 materials), for K = N_m .. min(2 N_m, 8),
+    the plain method (NNDSVDa, 200 MU, 60 extrapolated ANLS rounds: a fixed schedule, since each K has
+    its own optimum), 20 CGLS iterations on the K channels, and the semi-supervised material tail
+    (Alg. 2 with the phantom's pure-material voxels as masks).  Reports, per K, the relative NMF
+    residual f / ||p||^2, the times, SNR_FMD (eq. 12) of the material images, SNR_FHR (eq. 11) of the
+    rehydrated reconstruction and the error of the estimated material spectra D^m against the
+    generator's (relative Frobenius)."""
+    import torch
+    import synth
+    from paper_2410_22500_amd import hsn
+
+    dev = torch.device("cuda:0")
+    sc = synth.config_scan("mid")
+    n_m, n_k = sc.n_mat, sc.n_bins
+    n_v, n_r, n_c = sc.n_views, sc.n_rows, sc.n_cols
+    n_p, n_x = sc.n_p, sc.n_rows * sc.n_cols * sc.n_cols
+    y = torch.from_numpy(sc.y.view(np.int16)).to(dev)
+    yo = torch.from_numpy(sc.yo.view(np.int16)).to(dev)
+    p, _, _, psq = hsn.hsn_normalize(y, yo)
+    psq = float(psq)
+    frac = synth.volume_fractions(sc.objs, n_c, n_r, n_m).reshape(n_x, n_m)
+    lab = np.where(frac.max(axis=-1) >= 0.999, frac.argmax(axis=-1), -1).astype(np.int32)
+    lab_d = torch.from_numpy(lab).to(dev)
+    g = np.arange(n_c) - (n_c - 1) / 2.0
+    fov = np.broadcast_to(np.sqrt(g[None, :] ** 2 + g[:, None] ** 2) < n_c / 2.0 - 2.0, (n_r, n_c, n_c)).reshape(n_x)
+    regions = [torch.from_numpy(np.nonzero(lab == m)[0]).to(dev) for m in range(n_m)]
+    bg = torch.from_numpy(np.nonzero((frac.sum(axis=1) == 0) & fov)[0]).to(dev)
+    mu = torch.from_numpy(np.asarray(sc.mu, np.float64)).to(dev)  # [n_k][n_m], the generator's spectra
+    log(f"ksweep: mid scan N_v={n_v} N_r={n_r} N_c={n_c} N_k={n_k} N_m={n_m}; "
+        f"pure voxels per material {[int(r.numel()) for r in regions]}, background {int(bg.numel())}")
+
+    def timed(fn):  # the second of two runs (the first allocates workspaces)
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1)
+
+    rows = []
+    for K in range(n_m, min(2 * n_m, 8) + 1):
+        V = torch.empty((n_p, K), dtype=torch.float32, device=dev)
+        D = torch.empty((n_k, K), dtype=torch.float32, device=dev)
+        st, nmf_ms = timed(lambda: hsn.hsn_subspace_nmf(
+            p, None, n_k, V, D, algo=hsn.ALGO_MU, max_iter=BULK, check_every=BULK, polish_rounds=KSWEEP_ROUNDS,
+            polish_algo=hsn.ALGO_ANLS, init=hsn.INIT_NNDSVDA, anls_extrapolate=True))
+        xs, cgls_ms = timed(lambda: hsn.hsn_cgls(V.view(n_v, n_r, n_c, K), CGLS_ITERS))
+        (T, xm, Dm), fmd_ms = timed(lambda: hsn.hsn_fmd(xs.view(n_x, K), lab_d, n_m, D))
+        xmd = xm.double()
+        snr_fmd = float(10.0 * torch.log10(torch.stack(
+            [(xmd[r, m].mean() / xmd[bg, m].std(unbiased=False)) ** 2 for m, r in enumerate(regions)]).mean()))
+        Dd, xsd = D.double(), xs.view(n_x, K).double()
+        sig = torch.stack([(xsd[r] @ Dd.T).mean(dim=0) for r in regions])  # [n_m][n_k]
+        sd = (xsd[bg] @ Dd.T).std(dim=0, unbiased=False)
+        snr_fhr = float(10.0 * torch.log10(((sig / sd) ** 2).mean()))
+        mu_err = float(torch.linalg.norm(Dm.double() - mu) / torch.linalg.norm(mu))
+        row = {"K": K, "beta": K / n_m, "rel_resid": st["objective"] / psq, "anls_rounds": st["polish_done"],
+               "nmf_ms": nmf_ms, "cgls_ms": cgls_ms, "fmd_ms": fmd_ms, "snr_fmd_db": snr_fmd, "snr_fhr_db": snr_fhr,
+               "mu_rel_err": mu_err}
+        rows.append(row)
+        log(f"ksweep K={K}: f/|p|^2 {row['rel_resid']:.4e}, NMF {nmf_ms:.1f} ms, CGLS {cgls_ms:.1f} ms, "
+            f"SNR_FMD {snr_fmd:.2f} dB, SNR_FHR {snr_fhr:.2f} dB, spectra error {mu_err:.3e}")
+    print(json.dumps({"metric": "k_sweep", "unit": "per K", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+                      "config": {"workload": f"ksweep: mid scan, {n_r} slices x {n_c}^2, {n_v} views, {n_k} bins, "
+                                             f"{n_m} materials; K = {n_m} .. {rows[-1]['K']}",
+                                 "schedule": f"NNDSVDa, {BULK} MU, {KSWEEP_ROUNDS} extrapolated ANLS rounds, "
+                                             f"CGLS {CGLS_ITERS}, FMD with pure-voxel masks"},
+                      "rows": rows}), flush=True)
 
 
 def run_batched(args):
