@@ -335,8 +335,9 @@ hsn_status hsn_backproject(hsn_ctx *ctx, const hsn_geom *g, const float *s, floa
  * from the caches.  Other values: HSN_ERR_INVALID_ARG.  With split 1 (and
  * for A^T always) the staged and gather kernels give the same float32
  * values bit for bit; split > 1 changes the order of the sums per ray.
- * Geometries whose staged row does not fit 61 KB of LDS ((n_cols + 4) k
- * floats, 8 pad pixels for odd k), or n_cols > 1024 for A, use the gather
+ * Geometries whose staged row does not fit 60 KB of LDS ((n_cols + 2 pad) k
+ * floats, pad = 2 pixels for k = 2 or 4 and 4 otherwise, rounded up to a
+ * multiple of 4 for k >= 5), or n_cols > 1024 for A, use the gather
  * kernels whatever is set.
  */
 hsn_status hsn_projector_set_launch(hsn_ctx *ctx, int views, int split, int voxels, int threads);

@@ -293,36 +293,81 @@ __global__ __launch_bounds__(kVoxThreads) void backproject_kernel(const float *_
 // ---------------------------------------------------------------------------
 constexpr int kLdsMaxThreads = 1024;
 constexpr int kStageFloats = 15360;  // 60 KB of staged rows
-constexpr int kCopyFloats = 16;      // floats each thread copies per band
+constexpr int kCopyFloats = 16;      // floats each thread copies per band (K <= 4)
 
+// Staged layout of a row of n pixels (A: image pixels; A^T: detector bins)
+// with K channels, pad zero pixels on both sides.
+//  K <= 4: pixel t's channels at (pad + t) K, one run per row.
+//  K >= 5: two parts: channels 0..3 of pixel t at (pad + t) 4 (16-byte
+//   aligned, so the first four channels of a tap pair are two 16-byte
+//   reads), channels 4..K-1 at b0 + (pad + t) (K - 4), b0 = (n + 2 pad) 4.
+//   With a pitch of K words a tap pair's 2 K words need 2 K / 2 paired
+//   4-byte reads, and for even K two pixels 16 apart share a bank.
+// pad: 2 (K = 2, 4) or 4 pixels, which keeps each part's data 16-byte
+// aligned.
 template <int K>
-__host__ __device__ constexpr int stage_pad() { return (2 * K) % 4 == 0 ? 2 : 4; }
+__host__ __device__ constexpr int stage_ka() { return K >= 5 ? 4 : K; }
 template <int K>
-__host__ __device__ constexpr int stage_rp(int n) { return (n + 2 * stage_pad<K>()) * K; }
+__host__ __device__ constexpr int stage_kb() { return K >= 5 ? K - 4 : 0; }
+template <int K>
+__host__ __device__ constexpr int stage_pad() { return (K <= 4 && (2 * K) % 4 == 0) ? 2 : 4; }
+// Row pitch: K >= 5 rounds it up to whole 16-byte units, so every staged
+// row (and both its parts) starts 16-byte aligned whatever n is.
+template <int K>
+__host__ __device__ constexpr int stage_rp(int n) {
+  return K >= 5 ? ((n + 2 * stage_pad<K>()) * K + 3) / 4 * 4 : (n + 2 * stage_pad<K>()) * K;
+}
+template <int K>
+__host__ __device__ constexpr int stage_b0(int n) { return (n + 2 * stage_pad<K>()) * stage_ka<K>(); }
+// Floats each thread copies per band: a group of four pixels (K >= 5) or kCopyFloats.
+template <int K>
+__host__ __device__ constexpr int copy_floats() { return K >= 5 ? 4 * K : kCopyFloats; }
+// Staged offset (within its row) of float c of a source row of n K floats.
+template <int K>
+__device__ __forceinline__ int stage_pos(int c, int n) {
+  constexpr int PAD = stage_pad<K>();
+  if constexpr (K <= 4) {
+    return PAD * K + c;
+  } else {
+    const int t = c / K, q = c - t * K;
+    return q < 4 ? (PAD + t) * 4 + q : stage_b0<K>(n) + (PAD + t) * (K - 4) + (q - 4);
+  }
+}
 
-// One thread's part of a band copy: up to kCopyFloats floats of `rows`
-// rows of `width` floats each (row i at src + i * src_ld), at band-local
-// flat positions t + u * nt (scalar) or 4 (t + u * nt) + j (float4, VEC).
-// load() issues the global loads into registers; store() writes them to
-// the staged rows (pitch rp, data from pad K on), so a band's loads can be
-// in flight while the previous band is used.
+// One thread's part of a band copy of `rows` source rows of n K floats
+// (row i at src + i * src_ld) into staged rows of pitch rp.  Scalar: the
+// floats t + u * nt of the band, u < copy_floats.  VEC, K <= 4: the
+// float4s t + u * nt.  VEC, K >= 5: the group of pixels 4 t .. 4 t + 3 of
+// the band (K float4 loads; its four 4-channel runs and its (K - 4)-channel
+// runs, contiguous, as K float4 stores).  load() issues the global loads
+// into registers; store() writes them to the staged rows, so a band's loads
+// can be in flight while the previous band is used.
 template <int K, bool VEC>
 struct BandCopy {
-  static constexpr int U4 = kCopyFloats / 4;
-  int width, rp;
-  int row4[U4], col4[U4];
-  float buf[kCopyFloats];
+  static constexpr int CF = copy_floats<K>();
+  static constexpr bool SPLIT = K >= 5;
+  static constexpr int U4 = SPLIT ? 1 : CF / 4;
+  int n, width, rp;
+  int row4[U4], col4[U4];  // SPLIT: the group's row and first pixel
+  float buf[CF];
 
-  __device__ __forceinline__ void init(int w, int rpitch) {
-    width = w;
+  __device__ __forceinline__ void init(int npix, int rpitch) {
+    n = npix;
+    width = npix * K;
     rp = rpitch;
     if constexpr (VEC) {
-      const int w4 = w / 4;
+      if constexpr (SPLIT) {
+        const int g = int(threadIdx.x), gpr = npix / 4;
+        row4[0] = g / gpr;
+        col4[0] = 4 * (g - row4[0] * gpr);
+      } else {
+        const int w4 = width / 4;
 #pragma unroll
-      for (int u = 0; u < U4; ++u) {
-        const int f = int(threadIdx.x) + u * int(blockDim.x);
-        row4[u] = f / w4;
-        col4[u] = 4 * (f - row4[u] * w4);
+        for (int u = 0; u < U4; ++u) {
+          const int f = int(threadIdx.x) + u * int(blockDim.x);
+          row4[u] = f / w4;
+          col4[u] = 4 * (f - row4[u] * w4);
+        }
       }
     }
   }
@@ -331,16 +376,20 @@ struct BandCopy {
 #pragma unroll
       for (int u = 0; u < U4; ++u) {
         if (row4[u] < rows) {
-          const float4 v = *reinterpret_cast<const float4 *>(src + size_t(row4[u]) * src_ld + col4[u]);
-          buf[4 * u] = v.x;
-          buf[4 * u + 1] = v.y;
-          buf[4 * u + 2] = v.z;
-          buf[4 * u + 3] = v.w;
+          const float *p = src + size_t(row4[u]) * src_ld + (SPLIT ? col4[u] * K : col4[u]);
+#pragma unroll
+          for (int i = 0; i < (SPLIT ? K : 1); ++i) {
+            const float4 v = *reinterpret_cast<const float4 *>(p + 4 * i);
+            buf[4 * (u + i)] = v.x;
+            buf[4 * (u + i) + 1] = v.y;
+            buf[4 * (u + i) + 2] = v.z;
+            buf[4 * (u + i) + 3] = v.w;
+          }
         }
       }
     } else {
 #pragma unroll
-      for (int u = 0; u < kCopyFloats; ++u) {
+      for (int u = 0; u < CF; ++u) {
         const int e = int(threadIdx.x) + u * int(blockDim.x);
         const int r = e / width, c = e - r * width;
         if (r < rows) buf[u] = src[size_t(r) * src_ld + c];
@@ -348,42 +397,98 @@ struct BandCopy {
     }
   }
   __device__ __forceinline__ void store(float *__restrict__ rows_lds, int rows) const {
-    constexpr int P0 = stage_pad<K>() * K;
-    if constexpr (VEC) {
+    constexpr int PAD = stage_pad<K>();
+    if constexpr (VEC && SPLIT) {
+      constexpr int KB = K - 4;
+      if (row4[0] < rows) {
+        float *d = rows_lds + row4[0] * rp;
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          *reinterpret_cast<float4 *>(d + (PAD + col4[0] + p) * 4) =
+              make_float4(buf[p * K], buf[p * K + 1], buf[p * K + 2], buf[p * K + 3]);
+        float bv[4 * KB];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int j = 0; j < KB; ++j) bv[p * KB + j] = buf[p * K + 4 + j];
+        float *db = d + stage_b0<K>(n) + (PAD + col4[0]) * KB;
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+          *reinterpret_cast<float4 *>(db + 4 * i) = make_float4(bv[4 * i], bv[4 * i + 1], bv[4 * i + 2], bv[4 * i + 3]);
+      }
+    } else if constexpr (VEC) {
 #pragma unroll
       for (int u = 0; u < U4; ++u) {
         if (row4[u] < rows)
-          *reinterpret_cast<float4 *>(rows_lds + row4[u] * rp + P0 + col4[u]) =
+          *reinterpret_cast<float4 *>(rows_lds + row4[u] * rp + PAD * K + col4[u]) =
               make_float4(buf[4 * u], buf[4 * u + 1], buf[4 * u + 2], buf[4 * u + 3]);
       }
     } else {
 #pragma unroll
-      for (int u = 0; u < kCopyFloats; ++u) {
+      for (int u = 0; u < CF; ++u) {
         const int e = int(threadIdx.x) + u * int(blockDim.x);
         const int r = e / width, c = e - r * width;
-        if (r < rows) rows_lds[r * rp + P0 + c] = buf[u];
+        if (r < rows) rows_lds[r * rp + stage_pos<K>(c, n)] = buf[u];
       }
     }
   }
 };
 
-// Both taps of every channel at staged pixel p: a[q] = p[q], b[q] = p[K + q].
+// Both taps of every channel at staged pixel index tp (t0 + pad) of the
+// staged row at `row`: a[q] = channel q of pixel tp, b[q] of pixel tp + 1.
 template <int K>
-__device__ __forceinline__ void pixel_taps(const float *p, float (&a)[K], float (&b)[K]) {
+__device__ __forceinline__ void pixel_taps(const float *row, unsigned tp, unsigned b0, float (&a)[K], float (&b)[K]) {
+  if constexpr (K <= 4) {
+    const float *p = row + __umul24(tp, unsigned(K));
 #pragma unroll
-  for (int q = 0; q < K; ++q) {
-    a[q] = p[q];
-    b[q] = p[K + q];
+    for (int q = 0; q < K; ++q) {
+      a[q] = p[q];
+      b[q] = p[K + q];
+    }
+  } else {
+    constexpr int KB = K - 4;
+    const float4 *pa = static_cast<const float4 *>(__builtin_assume_aligned(row + 4 * tp, 16));
+    const float4 x = pa[0], y = pa[1];
+    a[0] = x.x; a[1] = x.y; a[2] = x.z; a[3] = x.w;
+    b[0] = y.x; b[1] = y.y; b[2] = y.z; b[3] = y.w;
+    const float *pb = row + (b0 + tp * unsigned(KB));
+    if constexpr (KB == 4) {
+      const float4 *p4 = static_cast<const float4 *>(__builtin_assume_aligned(pb, 16));
+      const float4 u = p4[0], v = p4[1];
+      a[4] = u.x; a[5] = u.y; a[6] = u.z; a[7] = u.w;
+      b[4] = v.x; b[5] = v.y; b[6] = v.z; b[7] = v.w;
+    } else if constexpr (KB == 2) {
+      const float2 *p2 = static_cast<const float2 *>(__builtin_assume_aligned(pb, 8));
+      const float2 u = p2[0], v = p2[1];
+      a[4] = u.x; a[5] = u.y;
+      b[4] = v.x; b[5] = v.y;
+    } else {
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        a[4 + j] = pb[j];
+        b[4 + j] = pb[KB + j];
+      }
+    }
   }
 }
 
 // Zeroes the pad pixels of `rows` staged rows (n data pixels each).
 template <int K>
 __device__ __forceinline__ void zero_pads(float *__restrict__ rows_lds, int rp, int n, int rows) {
-  constexpr int PW = stage_pad<K>() * K;  // floats of one side's pad
-  for (int e = threadIdx.x; e < rows * 2 * PW; e += blockDim.x) {
-    const int row = e / (2 * PW), k = e - row * (2 * PW);
-    rows_lds[row * rp + (k < PW ? k : n * K + k)] = 0.0f;
+  constexpr int PAD = stage_pad<K>(), KA = stage_ka<K>(), KB = stage_kb<K>();
+  constexpr int PWA = PAD * KA, PWB = PAD * KB;  // floats of one side's pad, each part
+  constexpr int PW = 2 * (PWA + PWB);
+  const int b0 = stage_b0<K>(n);
+  for (int e = threadIdx.x; e < rows * PW; e += blockDim.x) {
+    const int row = e / PW, k = e - row * PW;
+    int off;
+    if (k < 2 * PWA) {
+      off = k < PWA ? k : n * KA + k;
+    } else {
+      const int k2 = k - 2 * PWA;
+      off = b0 + (k2 < PWB ? k2 : n * KB + k2);
+    }
+    rows_lds[row * rp + off] = 0.0f;
   }
 }
 
@@ -466,8 +571,9 @@ __global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
   }
   zero_pads<K>(stage, rp, n, band_rows);
   const float *img = (steep ? xT : x) + size_t(r) * n * n * K;
+  const unsigned sb0 = unsigned(stage_b0<K>(n));
   BandCopy<K, VEC> cp;
-  cp.init(n * K, rp);
+  cp.init(n, rp);
   int rows = min(band_rows, n);
   cp.load(img, size_t(n) * K, rows);
   float acc[K];
@@ -491,7 +597,7 @@ __global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
     for (; m <= me; m += split, U += dUs, base += unsigned(bstep)) {
       const int tp = min(max(int(U >> 32), 0), n + 2 * PAD - 2);
       float a0[K], a1[K];
-      pixel_taps<K>(stage + (base + __umul24(unsigned(tp), unsigned(K))), a0, a1);
+      pixel_taps<K>(stage + base, unsigned(tp), sb0, a0, a1);
       const float w1 = float(uint32_t(U)) * ry.s1;
       const float w0 = ry.inv_w - w1;
 #pragma unroll
@@ -569,6 +675,7 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
     vox[e] = w < n * n ? w : -1;
   }
   zero_pads<K>(planes, rp, n, view_chunk);
+  const unsigned sb0 = unsigned(stage_b0<K>(n));
   float acc[VPT][K];
 #pragma unroll
   for (int e = 0; e < VPT; ++e)
@@ -577,7 +684,7 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
   const size_t view_stride = size_t(n_slices) * n * K;
   const float *sr = s + size_t(r) * n * K;
   BandCopy<K, VEC> cp;
-  cp.init(n * K, rp);
+  cp.init(n, rp);
   int nv = min(view_chunk, n_views);
   cp.load(sr, view_stride, nv);
   ViewGeom gn{};
@@ -613,7 +720,7 @@ __global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
       for (int e = 0; e < VPT; ++e, U += sv.D) {
         const int cp0 = min(max(int(U >> 32), 0), n + 2 * PAD - 2);
         float a0[K], a1[K];
-        pixel_taps<K>(planes + (base + __umul24(unsigned(cp0), unsigned(K))), a0, a1);
+        pixel_taps<K>(planes + base, unsigned(cp0), sb0, a0, a1);
         float w0, w1;
         vox_weights(uint32_t(U), sv.iw, sv.iw2, sv.c1, w0, w1);
 #pragma unroll
@@ -1192,6 +1299,11 @@ struct ProjLaunch {
 };
 
 int round64(int64_t v) { return int((v + 63) / 64 * 64); }
+// Floats each thread copies per band (copy_floats for the geometry's K).
+int64_t copy_floats_k(int64_t k) { return k >= 5 ? 4 * k : kCopyFloats; }
+// The band copy moves float4s: whole source rows of n K floats (K <= 4),
+// groups of four pixels (K >= 5).
+bool copy_vec(int64_t k, int64_t n) { return k >= 5 ? n % 4 == 0 : (n * k) % 4 == 0; }
 // Row pitch (floats) of the staged rows for the geometry's K.
 int64_t staged_rp(const hsn_geom *g) {
   const int n = int(g->n_cols);
@@ -1240,7 +1352,7 @@ ProjLaunch plan_project(const hsn_ctx *ctx, const hsn_geom *g, int n_groups) {
   while (split > 1 && split * t1 > kLdsMaxThreads) split /= 2;
   const int nt = split * t1;
   const int64_t band =
-      std::max<int64_t>(1, std::min<int64_t>({n, kStageFloats / rp, int64_t(kCopyFloats) * nt / (n * K)}));
+      std::max<int64_t>(1, std::min<int64_t>({n, kStageFloats / rp, copy_floats_k(K) * nt / (n * K)}));
   L.lds = true;
   L.vb = vb;
   L.split = split;
@@ -1255,14 +1367,14 @@ ProjLaunch plan_project(const hsn_ctx *ctx, const hsn_geom *g, int n_groups) {
 ProjLaunch plan_backproject(const hsn_ctx *ctx, const hsn_geom *g) {
   ProjLaunch L;
   const int64_t n = g->n_cols, K = g->k, rp = staged_rp(g);
-  if (ctx->proj_voxels < 0 || rp > kStageFloats || n * K > int64_t(kCopyFloats) * kLdsMaxThreads) {
+  if (ctx->proj_voxels < 0 || rp > kStageFloats || n * K > copy_floats_k(K) * kLdsMaxThreads) {
     L.threads = kVoxThreads;
     L.grid = backproject_grid(g);
     L.partials = size_t(g->n_slices) * n * ((n + kVoxThreads - 1) / kVoxThreads);
     return L;
   }
   int nt = ctx->proj_threads > 0 ? ctx->proj_threads : kLdsMaxThreads;
-  nt = std::max<int>({64, round64((n * K + kCopyFloats - 1) / kCopyFloats), std::min<int>(nt, round64(n * n))});
+  nt = std::max<int>({64, round64((n * K + copy_floats_k(K) - 1) / copy_floats_k(K)), std::min<int>(nt, round64(n * n))});
   nt = std::min(nt, kLdsMaxThreads);
   auto per_slice = [&](int vpt) { return (n * n + int64_t(vpt) * nt - 1) / (int64_t(vpt) * nt); };
   int vpt = ctx->proj_voxels;
@@ -1282,7 +1394,7 @@ ProjLaunch plan_backproject(const hsn_ctx *ctx, const hsn_geom *g) {
   if (nt % n != 0) vpt = 1;
   const int64_t vc = std::max<int64_t>(
       1, std::min<int64_t>({int64_t(g->n_views), kStageFloats / rp, int64_t(kMaxViewChunk), int64_t(nt),
-                            int64_t(kCopyFloats) * nt / (n * K)}));
+                            copy_floats_k(K) * nt / (n * K)}));
   L.lds = true;
   L.vpt = vpt;
   L.threads = nt;
@@ -1304,7 +1416,7 @@ void launch_project(const ProjLaunch &L, const float *x, const float *xT, float 
                                                       alpha, beta, sumsq);
     return;
   }
-  const bool vec4 = (n * K) % 4 == 0 && aligned16(x) && (!xT || aligned16(xT));
+  const bool vec4 = copy_vec(K, n) && aligned16(x) && (!xT || aligned16(xT));
   if (vec4)
     project_lds_kernel<K, true><<<L.grid, L.threads, L.lds_bytes, st>>>(
         x, xT, s, gt.views, gt.groups, gt.n_groups, L.vb, L.split, int(g->n_slices), n, L.rows, alpha, beta, sumsq);
@@ -1317,7 +1429,7 @@ template <int K, int VPT>
 void launch_backproject_lds(const ProjLaunch &L, const float *s, float *x, const GeomTab &gt, const hsn_geom *g,
                             float alpha, float beta, double *sumsq, hipStream_t st) {
   const int n = int(g->n_cols);
-  const bool vec4 = (n * K) % 4 == 0 && aligned16(s);
+  const bool vec4 = copy_vec(K, n) && aligned16(s);
   if (vec4)
     backproject_lds_kernel<K, VPT, true><<<L.grid, L.threads, L.lds_bytes, st>>>(
         s, x, gt.views, int(g->n_views), int(g->n_slices), n, L.rows, alpha, beta, sumsq);
