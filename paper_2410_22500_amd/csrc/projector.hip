@@ -522,8 +522,13 @@ __device__ __forceinline__ void block_sumsq_n(const float (&v)[S][K], const bool
 // block (thread = copy * t1 + slot, t1 = blockDim.x / split), copy sp takes
 // the band rows m with (m - m0) % split == sp, and the copies' sums are
 // added in copy order at the end.
+// Occupancy: K <= 5 (not 4) with float4 staging fits 64 VGPRs with a few
+// spills outside the tap loop, so two 1024-thread blocks share a CU and one
+// block's band copy and barriers overlap the other's taps (K = 5 at full
+// size: 1.95 -> 1.56 ms); K = 4 and K >= 6 would spill inside the loop.
 template <int K, bool VEC>
-__global__ __launch_bounds__(kLdsMaxThreads) void project_lds_kernel(
+__global__ __launch_bounds__(kLdsMaxThreads) __attribute__((amdgpu_waves_per_eu((VEC && K <= 5 && K != 4) ? 8 : 4)))
+void project_lds_kernel(
     const float *__restrict__ x, const float *__restrict__ xT, float *__restrict__ s,
     const ViewGeom *__restrict__ geom, const double *__restrict__ groups, int n_groups, int vb, int split,
     int n_slices, int n, int band_rows, float alpha, float beta, double *__restrict__ sumsq) {
