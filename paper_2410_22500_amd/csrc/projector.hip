@@ -17,8 +17,8 @@
 // the adjoint evaluates them in float64; the forward ray starts in float64
 // and steps in 32.32 fixed point, integer steps that are exact, so a
 // position is off by less than (m + 1) 2^-33 px after m steps.  Weights
-// and channel sums are float32.  All K channels of a pixel or bin are
-// contiguous, so each tap is one vector load.
+// and channel sums are float32.  In global memory all K channels of a pixel
+// or bin are contiguous, so a gather kernel's tap is one vector load.
 #include "common.hpp"
 
 #include <algorithm>
@@ -280,16 +280,13 @@ __global__ __launch_bounds__(kVoxThreads) void backproject_kernel(const float *_
 // a dependent gather per step.  Here a block copies the rows it shares (the
 // slice image for A, the slice's sinogram rows for A^T) into LDS in bands
 // and takes the taps from there, while the next band's global loads are in
-// flight.  Staged rows keep the global layout (the K channels of a pixel
-// contiguous): pixel t of staged row i starts at i * rp + (pad + t) K, rp =
-// (n + 2 pad) K, so a band is copied with 16-byte loads and stores and the
-// 2 K values of a tap pair (pixels t0, t0 + 1) lie within 2 K words of one
-// address: one address per step, the channel offsets are immediates.  pad
-// zero pixels (bins) on both sides (2 for even K, 4 for odd K, which keeps
-// each row's data 16-byte aligned) and a tap index clamped into them: no
-// bounds tests or weight masks in the inner loops.  A clamped tap reads 0
-// where the gather kernels apply weight 0, so with one thread per ray
-// (split 1) both paths give the same values bit for bit.
+// flight.  The staged layout (stage_* below) keeps a tap pair's channels
+// (pixels t0, t0 + 1) at one or two addresses with immediate offsets, and
+// band copies as 16-byte loads and stores.  Pad zero pixels (bins) on both
+// sides and a tap index clamped into them: no bounds tests or weight masks
+// in the inner loops.  A clamped tap reads 0 where the gather kernels apply
+// weight 0, so with one thread per ray (split 1) both paths give the same
+// values bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int kLdsMaxThreads = 1024;
 constexpr int kStageFloats = 15360;  // 60 KB of staged rows
