@@ -316,20 +316,19 @@ __global__ __launch_bounds__(256) void mlp_rows_kernel(RowsArgs a) {
   if (threadIdx.x == 0) a.part_loss[blockIdx.x] = redl[0] + redl[1] + redl[2] + redl[3];
 }
 
-// Inference of the bfloat16 network with two 16-row tiles per wave: every
-// weight fragment read from L2 feeds two MFMAs (half the weight traffic of
-// mlp_rows_kernel, which reads all weights for every 16 rows).  Per row the
+// Inference of the bfloat16 network with three 16-row tiles per wave: every
+// weight fragment read from L2 feeds three MFMAs (a third of the weight
+// traffic of mlp_rows_kernel, which reads all weights for every 16 rows).  Per row the
 // arithmetic and the MFMA order are those of mlp_rows_kernel<uint16_t, K,
 // false>, so both give the same outputs.  A wave's h1 and then h2 share one
 // LDS tile pair (a wave's LDS accesses are performed in order).
-constexpr int kTilesW = 2;
+constexpr int kTilesW = 3;
 constexpr int kRowsB2 = kWaves * kTilesW * kRowsW;
 
-// Four waves per SIMD (at most 128 registers, no spills): a CU holds four
-// workgroups, 1024 on the chip, so the mid workload's 960 row blocks run in
-// one round instead of 768 plus a quarter-full second round at three.
+// Three waves per SIMD (at most 168 registers, no spills; 51 KB of LDS per
+// workgroup): a CU holds three workgroups.
 template <int K>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mlp_infer2_kernel(RowsArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mlp_infer2_kernel(RowsArgs a) {
   using T = uint16_t;
   using M = Mma<T>;
   constexpr int E = M::E, KS = M::KS;
