@@ -187,9 +187,12 @@ def test_projector_mid_config_shape(hsn):
 
 # Geometries for the launch-shape checks: n * k not a multiple of 4 (scalar
 # staging), n not a multiple of 64, view groups padded at both
-# orientations, custom angles mixing flat and steep views, one slice.
+# orientations, custom angles mixing flat and steep views, one slice; for
+# k >= 5 (two staged parts) n a multiple of 4 (grouped float4 copies) and
+# not (scalar copies), with both parts' read widths (k = 5, 6, 7, 8).
 _SHAPES = [(37, 11, 3, 3, None), (64, 60, 4, 9, None), (50, 13, 5, 2, None),
-           (24, 6, 8, 1, [0.0, 0.3, 1.2, 1.9, 2.6, 3.0]), (128, 9, 1, 8, None), (19, 5, 7, 2, None)]
+           (24, 6, 8, 1, [0.0, 0.3, 1.2, 1.9, 2.6, 3.0]), (128, 9, 1, 8, None), (19, 5, 7, 2, None),
+           (40, 9, 6, 3, None), (42, 7, 6, 2, None), (64, 12, 5, 3, None)]
 
 
 @pytest.mark.parametrize("n,n_views,k,n_r,angles", _SHAPES)
