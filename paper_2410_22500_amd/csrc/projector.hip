@@ -794,7 +794,9 @@ enum { kGamma = 0, kAlphaOff = 16, kBetaOff = 24 };
 // from the A^T partial sums (gamma = st[gsel], the new value goes to
 // st[1 - gsel]), x += alpha p with the old p, then p = sv + beta p, pT = p^T.
 // mode 4: mode 3 without the x update (the MBIR direction step, whose
-// partials are <r, r> of the CG step kernel).
+// partials are <r, r> of the CG step kernel).  mode 5: mode 3 with alpha
+// and beta already formed in st (by the scalar kernel, when the partials
+// are too many for every block to sum).
 template <int K>
 __global__ __launch_bounds__(256) void xpby_transpose_kernel(float *__restrict__ p, float *__restrict__ pT,
                                                              const float *__restrict__ sv,
@@ -817,6 +819,12 @@ __global__ __launch_bounds__(256) void xpby_transpose_kernel(float *__restrict__
     }
     if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && int(threadIdx.x) < K)
       st[kGamma + 8 * (1 - gsel) + threadIdx.x] = tot[threadIdx.x];
+  } else if (mode == 5) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      cf[q] = float(st[kBetaOff + q]);
+      al[q] = float(st[kAlphaOff + q]);
+    }
   } else {
 #pragma unroll
     for (int q = 0; q < K; ++q) {
@@ -832,11 +840,11 @@ __global__ __launch_bounds__(256) void xpby_transpose_kernel(float *__restrict__
       float val[K];
       if (mode == 0) {  // plain transpose of p
         load_k<K>(p + o, val);
-      } else {          // p = sv + coef * p (modes 1, 3), p = sv (mode 2)
+      } else {          // p = sv + coef * p (modes 1, 3, 4, 5), p = sv (mode 2)
         float a[K], b[K];
         load_k<K>(sv + o, a);
         if (mode != 2) load_k<K>(p + o, b);
-        if (mode == 3) {
+        if (mode == 3 || mode == 5) {
           float xv[K];
           load_k<K>(x + o, xv);
 #pragma unroll
@@ -1456,7 +1464,8 @@ void launch_backproject(const ProjLaunch &L, const float *s, float *x, const Geo
 }
 
 // mode 0: pT = p^T; mode 1: p = sv + coef p, pT = p^T; mode 2: p = sv, pT = p^T;
-// mode 3: the fused CGLS direction step, mode 4: the MBIR one (see xpby_transpose_kernel).
+// mode 3: the fused CGLS direction step, mode 4: the MBIR one, mode 5: the CGLS one with formed
+// scalars (see xpby_transpose_kernel).
 template <int K>
 void launch_xpby_t(float *p, float *pT, const float *sv, const double *coef, const hsn_geom *g, int mode,
                    hipStream_t st, float *x = nullptr, const double *partial = nullptr, int nblk = 0,
@@ -1633,7 +1642,9 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
                                                                         gsel);
     } else {
       cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_proj), K, kAlpha, scal, gsel, nullptr);
-      chan_axpy2_kernel<<<blocks(nx * K + ns * K), eb, 0, st>>>(x, p, nx * K, r, q, ns * K, scal + kAlphaOff, K);
+      // r -= alpha q here; x += alpha p goes with the direction step (mode 5),
+      // which reads p anyway
+      chan_axpy2_kernel<<<blocks(ns * K), eb, 0, st>>>(x, p, 0, r, q, ns * K, scal + kAlphaOff, K);
     }
     hsn::prof_begin(ctx, HSN_KERN_BACKPROJECT, st);
     HSN_DISPATCH_K(K, launch_backproject, LB, r, sv, gt, g, 1.0f, 0.0f, partial, st);
@@ -1642,14 +1653,14 @@ extern "C" hsn_status hsn_cgls(hsn_ctx *ctx, const hsn_geom *g, const float *sin
       HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, nullptr, g, 3, st, x, partial, int(nb_back), scal, gsel);
     } else {
       cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, int(nb_back), K, kBeta, scal, gsel, nullptr);
-      HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, scal + kBetaOff, g, 1, st);
+      HSN_DISPATCH_K(K, launch_xpby_t, p, pT, sv, nullptr, g, 5, st, x, nullptr, 0, scal, gsel);
     }
     if (resid) {
       HSN_DISPATCH_K(K, launch_dot, r, r, ns, partial, st);
       cgls_scalar_kernel<<<1, 256, 0, st>>>(partial, kDotBlocks, K, kResid, scal, 0, resid + size_t(it + 1) * K);
     }
   }
-  // The fused path adds alpha p to x in the direction step, which the last
+  // Both paths add alpha p to x in the direction step, which the last
   // iteration still runs; nothing is left to add here.
   HSN_LAUNCHED(ctx);
   return HSN_OK;
