@@ -650,8 +650,13 @@ constexpr int kMaxViewChunk = 64;
 // the column i and lie blockDim.x / n rows apart: their positions differ by
 // the integer step D.  The slice's sinogram rows pass through LDS in chunks
 // of view_chunk views, with the chunk's geometry.
+// Occupancy: K = 5, 4 voxels per thread, float4 staging fits 76 VGPRs
+// without spills, so three 512-thread blocks (each 42 KB of LDS at the full
+// shape) share a CU (K = 5 at full size: 1.35 ms with one 1024-thread block,
+// 1.27 ms with three of 512; plan_backproject picks 512 threads for K = 5).
 template <int K, int VPT, bool VEC>
-__global__ __launch_bounds__(kLdsMaxThreads) void backproject_lds_kernel(
+__global__ __launch_bounds__(kLdsMaxThreads) __attribute__((amdgpu_waves_per_eu((VEC && VPT == 4 && K == 5) ? 6 : 4)))
+void backproject_lds_kernel(
     const float *__restrict__ s, float *__restrict__ x, const ViewGeom *__restrict__ geom, int n_views,
     int n_slices, int n, int view_chunk, float alpha, float beta, double *__restrict__ sumsq) {
   extern __shared__ __align__(16) float stage[];
@@ -1383,7 +1388,9 @@ ProjLaunch plan_backproject(const hsn_ctx *ctx, const hsn_geom *g) {
     L.partials = size_t(g->n_slices) * n * ((n + kVoxThreads - 1) / kVoxThreads);
     return L;
   }
-  int nt = ctx->proj_threads > 0 ? ctx->proj_threads : kLdsMaxThreads;
+  // default block: 512 threads for K = 5 (three blocks per CU, see
+  // backproject_lds_kernel), else the largest
+  int nt = ctx->proj_threads > 0 ? ctx->proj_threads : (K == 5 ? 512 : kLdsMaxThreads);
   nt = std::max<int>({64, round64((n * K + copy_floats_k(K) - 1) / copy_floats_k(K)), std::min<int>(nt, round64(n * n))});
   nt = std::min(nt, kLdsMaxThreads);
   auto per_slice = [&](int vpt) { return (n * n + int64_t(vpt) * nt - 1) / (int64_t(vpt) * nt); };
